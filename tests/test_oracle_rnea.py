@@ -1,0 +1,217 @@
+"""Pins for the oracle's inverse dynamics (Alg. 4) and its VJP.
+
+The paper prints no numeric RNEA example, so the oracle is pinned to what
+mechanics fixes: a pendulum and the textbook planar two-link arm in closed
+form; gravity torques equal to the gradient of potential energy; the
+acceleration-linear part equal to M(q) qdd with M the Hessian of kinetic
+energy (computed from forward kinematics, not from the recursion); the
+quadratic scaling of velocity terms; the power identity qd . tau = dE/dt;
+and, for the VJP, central finite differences and the dot-product test.
+"""
+import numpy as np
+import pytest
+
+from paper_2603_05493_amd import synth
+from tests import energy
+
+
+def _pendulum(l=0.7, m=1.3, ixx=0.02):
+    rb = synth.serial_chain(1, 1, seed=0)
+    rb.axis[1] = [1.0, 0.0, 0.0]
+    rb.fixed_p[1] = [0.0, 0.0, 0.0]
+    rb.mass[:] = [0.0, m]
+    rb.com[1] = [0.0, 0.0, -l]
+    rb.inertia[1] = np.diag([ixx, 0.03, 0.04])
+    return rb
+
+
+def test_pendulum_closed_form(oracle):
+    rb = _pendulum()
+    rng = np.random.default_rng(1)
+    q, qd, qdd = (rng.uniform(-3, 3, size=(20, 1)) for _ in range(3))
+    tau = oracle.rnea(rb, q, qd, qdd)
+    m, l, ixx, g = rb.mass[1], -rb.com[1, 2], rb.inertia[1, 0, 0], -rb.gravity[2]
+    ref = (ixx + m * l * l) * qdd + m * g * l * np.sin(q)
+    np.testing.assert_allclose(tau, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_planar_2r_textbook(oracle):
+    """Two-link planar arm (Spong, Robot Modeling and Control): M, C, g in closed form."""
+    rb = synth.planar_2r()
+    m1, m2 = rb.mass[1], rb.mass[2]
+    l1 = rb.fixed_p[2, 0]
+    lc1, lc2 = rb.com[1, 0], rb.com[2, 0]
+    I1, I2 = rb.inertia[1, 2, 2], rb.inertia[2, 2, 2]
+    g = -rb.gravity[1]
+    rng = np.random.default_rng(2)
+    q, qd, qdd = (rng.uniform(-2, 2, size=(32, 2)) for _ in range(3))
+    tau = oracle.rnea(rb, q, qd, qdd)
+    q1, q2 = q[:, 0], q[:, 1]
+    c2, s2 = np.cos(q2), np.sin(q2)
+    M11 = m1 * lc1 ** 2 + m2 * (l1 ** 2 + lc2 ** 2 + 2 * l1 * lc2 * c2) + I1 + I2
+    M12 = m2 * (lc2 ** 2 + l1 * lc2 * c2) + I2
+    M22 = m2 * lc2 ** 2 + I2
+    h = -m2 * l1 * lc2 * s2
+    g1 = (m1 * lc1 + m2 * l1) * g * np.cos(q1) + m2 * lc2 * g * np.cos(q1 + q2)
+    g2 = m2 * lc2 * g * np.cos(q1 + q2)
+    t1 = M11 * qdd[:, 0] + M12 * qdd[:, 1] + h * (2 * qd[:, 0] * qd[:, 1] + qd[:, 1] ** 2) + g1
+    t2 = M12 * qdd[:, 0] + M22 * qdd[:, 1] - h * qd[:, 0] ** 2 + g2
+    np.testing.assert_allclose(tau, np.stack([t1, t2], 1), rtol=1e-10, atol=1e-10)
+
+
+def _small_robots():
+    return [synth.serial_chain(4, 1, seed=6, random_fixed_rotation=True),
+            synth.random_tree(6, 1, seed=8, random_fixed_rotation=True)]
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_gravity_torque_is_potential_gradient(oracle, idx):
+    rb = _small_robots()[idx]
+    st = synth.states(rb, 3, seed=4)
+    z = np.zeros_like(st.q)
+    tau = oracle.rnea(rb, st.q, z, z)
+    h = 1e-6
+    for b in range(3):
+        grad = np.array([(energy.potential(oracle, rb, st.q[b] + h * e) -
+                          energy.potential(oracle, rb, st.q[b] - h * e)) / (2 * h)
+                         for e in np.eye(rb.n_dof)])
+        # float32-rounded inputs: axes unit and fixed rotations orthonormal to ~1e-7,
+        # so the physical identity holds to that level
+        np.testing.assert_allclose(tau[b], grad, rtol=1e-6, atol=1e-7)
+
+
+def test_humanoid_gravity_torque_is_potential_gradient(oracle):
+    rb = synth.humanoid48(seed=2)
+    st = synth.states(rb, 1, seed=5, q_range=1.5)
+    z = np.zeros_like(st.q)
+    tau = oracle.rnea(rb, st.q, z, z)[0]
+    h = 1e-6
+    grad = np.array([(energy.potential(oracle, rb, st.q[0] + h * e) -
+                      energy.potential(oracle, rb, st.q[0] - h * e)) / (2 * h)
+                     for e in np.eye(rb.n_dof)])
+    np.testing.assert_allclose(tau, grad, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_inertial_part_is_kinetic_energy_hessian(oracle, idx):
+    rb = _small_robots()[idx]
+    st = synth.states(rb, 2, seed=7)
+    z = np.zeros_like(st.q)
+    dtau = oracle.rnea(rb, st.q, st.qd, st.qdd) - oracle.rnea(rb, st.q, st.qd, z)
+    for b in range(2):
+        M = energy.mass_matrix(oracle, rb, st.q[b])
+        assert np.all(np.linalg.eigvalsh(M) > 0)
+        np.testing.assert_allclose(dtau[b], M @ st.qdd[b], rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_velocity_terms_are_quadratic(oracle, idx):
+    rb = _small_robots()[idx]
+    st = synth.states(rb, 5, seed=9)
+    z = np.zeros_like(st.q)
+    g = oracle.rnea(rb, st.q, z, z)
+    t1 = oracle.rnea(rb, st.q, st.qd, z) - g
+    t2 = oracle.rnea(rb, st.q, 2 * st.qd, z) - g
+    np.testing.assert_allclose(t2, 4 * t1, rtol=1e-10, atol=1e-10)
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_power_identity(oracle, idx):
+    """qd . tau = d/dt (KE + PE) along q(t) = q + qd t + qdd t^2 / 2."""
+    rb = _small_robots()[idx]
+    st = synth.states(rb, 2, seed=10)
+    tau = oracle.rnea(rb, st.q, st.qd, st.qdd)
+    ht = 1e-4
+    for b in range(2):
+        q, qd, qdd = st.q[b], st.qd[b], st.qdd[b]
+
+        def E(t):
+            qt, qdt = q + qd * t + 0.5 * qdd * t * t, qd + qdd * t
+            return energy.kinetic(oracle, rb, qt, qdt) + energy.potential(oracle, rb, qt)
+
+        dE = (E(ht) - E(-ht)) / (2 * ht)
+        assert abs(qd @ tau[b] - dE) < 1e-6 * max(1.0, abs(dE))
+
+
+def _vjp_robots():
+    mim = synth.serial_chain(5, 1, seed=12, random_fixed_rotation=True)
+    mim.joint_index = np.array([-1, 0, 1, 1, 2, 3], dtype=np.int32)
+    mim.joint_mult = np.array([1.0, 1.0, 1.0, -0.7, 1.3, 1.0])
+    mim.joint_offset = np.array([0.0, 0.0, 0.0, 0.2, -0.1, 0.0])
+    return [synth.serial_chain(7, 1, seed=11, random_fixed_rotation=True),
+            synth.random_tree(9, 1, seed=13, random_fixed_rotation=True),
+            mim, synth.humanoid48(seed=3)]
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2, 3])
+def test_vjp_matches_central_fd(oracle, idx):
+    rb = _vjp_robots()[idx]
+    B = 3
+    st = synth.states(rb, B, seed=14, q_range=1.5)
+    w = synth.weights((B, rb.n_dof), seed=15)
+    gq, gqd, gqdd = oracle.rnea_vjp(rb, st.q, st.qd, st.qdd, w)
+    h = 1e-6
+    n = rb.n_dof
+    for which, ana in ((0, gq), (1, gqd), (2, gqdd)):
+        fd = np.zeros((B, n))
+        for j in range(n):
+            args_p = [st.q.copy(), st.qd.copy(), st.qdd.copy()]
+            args_m = [st.q.copy(), st.qd.copy(), st.qdd.copy()]
+            args_p[which][:, j] += h
+            args_m[which][:, j] -= h
+            fd[:, j] = np.sum(w * (oracle.rnea(rb, *args_p) - oracle.rnea(rb, *args_m)), 1) / (2 * h)
+        np.testing.assert_allclose(ana, fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+
+
+def test_vjp_dot_product(oracle):
+    """<taub, J xdot> = <J^T taub, xdot> with J xdot from a directional central difference."""
+    rb = synth.random_tree(10, 1, seed=16, random_fixed_rotation=True)
+    st = synth.states(rb, 4, seed=17)
+    rng = np.random.default_rng(18)
+    w = rng.normal(size=st.q.shape)
+    dq, dqd, dqdd = (rng.normal(size=st.q.shape) for _ in range(3))
+    gq, gqd, gqdd = oracle.rnea_vjp(rb, st.q, st.qd, st.qdd, w)
+    h = 1e-6
+    jv = (oracle.rnea(rb, st.q + h * dq, st.qd + h * dqd, st.qdd + h * dqdd) -
+          oracle.rnea(rb, st.q - h * dq, st.qd - h * dqd, st.qdd - h * dqdd)) / (2 * h)
+    lhs = np.sum(w * jv, 1)
+    rhs = np.sum(gq * dq + gqd * dqd + gqdd * dqdd, 1)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-7)
+
+
+def test_external_force_gradient(oracle):
+    rb = synth.serial_chain(4, 1, seed=19)
+    st = synth.states(rb, 2, seed=20)
+    rng = np.random.default_rng(21)
+    fext = rng.normal(size=(2, rb.n_links, 6))
+    w = rng.normal(size=st.q.shape)
+    _, _, _, gfe = oracle.rnea_vjp(rb, st.q, st.qd, st.qdd, w, fext=fext, want_fext=True)
+    h = 1e-6
+    idx = [(1, 0), (2, 4), (4, 2), (3, 5)]
+    for (k, i) in idx:
+        fp, fm = fext.copy(), fext.copy()
+        fp[:, k, i] += h
+        fm[:, k, i] -= h
+        fd = np.sum(w * (oracle.rnea(rb, st.q, st.qd, st.qdd, fp) -
+                         oracle.rnea(rb, st.q, st.qd, st.qdd, fm)), 1) / (2 * h)
+        np.testing.assert_allclose(gfe[:, k, i], fd, rtol=1e-6, atol=1e-9)
+
+
+def test_mimic_torque_is_virtual_work(oracle):
+    """Coupled links: tau_j = sum_k m_k tau_k of the expanded robot (virtual work)."""
+    rb = synth.serial_chain(4, 1, seed=22)
+    mim = synth.serial_chain(4, 1, seed=22)
+    mim.joint_index = np.array([-1, 0, 1, 1, 2], dtype=np.int32)
+    mim.joint_mult = np.array([1.0, 1.0, 1.0, -0.5, 2.0])
+    mim.joint_offset = np.array([0.0, 0.0, 0.0, 0.25, 0.0])
+    st = synth.states(mim, 4, seed=23)
+    m = np.array([1.0, 1.0, -0.5, 2.0])
+    off = np.array([0.0, 0.0, 0.25, 0.0])
+    sel = np.array([0, 1, 1, 2])
+    qx = st.q[:, sel] * m + off
+    tx = oracle.rnea(rb, qx, st.qd[:, sel] * m, st.qdd[:, sel] * m)
+    tm = oracle.rnea(mim, st.q, st.qd, st.qdd)
+    ref = np.zeros_like(tm)
+    for k in range(4):
+        ref[:, sel[k]] += m[k] * tx[:, k]
+    np.testing.assert_allclose(tm, ref, rtol=1e-12, atol=1e-12)
