@@ -1,0 +1,223 @@
+/*
+ * wb.h -- C ABI of the MI355X whole-body library (libwb.so).
+ *
+ * Batched forward kinematics, recursive Newton-Euler inverse dynamics and
+ * map-reduce self-collision, with their adjoints, for a kinematic tree whose
+ * topology, joint axes, fixed transforms, inertias and collision spheres are
+ * given at run time (cuRoboV2, arXiv 2603.05493: Sec. 3 states the problem,
+ * Sec. 6.1 forward kinematics and Alg. 1 its gradient, Sec. 6.2 the
+ * self-collision map-reduce, Sec. 6.3 with Alg. 4 and Alg. 5 the RNEA and its
+ * vector-Jacobian product).
+ *
+ * Conventions shared by every call
+ *   - Arithmetic is FP32 on the GPU.
+ *   - Batched arrays are structure-of-arrays with the state index fastest:
+ *     an array documented as [k][B] holds element (i, b) at i*B + b.  All
+ *     such pointers are device pointers owned by the caller; the library
+ *     never allocates, frees or synchronizes inside a launch call, so every
+ *     launch call may be captured into a HIP graph.
+ *   - Every launch call enqueues its kernels on the given stream and returns
+ *     immediately; results are valid once the stream reaches that point.
+ *   - Every call returns WB_OK or an error code; wb_last_error() returns a
+ *     thread-local description of the last failure.  Launch calls validate
+ *     sizes and pointers (non-null, 4-byte aligned) before enqueuing
+ *     anything; NaN or Inf inputs are not checked and propagate.
+ *   - B = 0 is valid and enqueues nothing.
+ *
+ * Frames.  Link 0 is the fixed root at the world identity.  Link k >= 1 is
+ * placed at parent_T_k(q) = [fixed_R_k | fixed_p_k] * Rot(axis_k, theta_k)
+ * with theta_k = joint_mult_k * q[joint_index_k] + joint_offset_k (mimic
+ * joints share an actuated index; Sec. 6 "mimic joints"), the axis given in
+ * the child frame.  A link pose is 12 floats: the world rotation R
+ * (row-major 3x3) then the world position p.  Spatial vectors are
+ * Featherstone [angular; linear] in link coordinates (Sec. 6.3).
+ */
+#ifndef WB_H
+#define WB_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum wb_status {
+    WB_OK = 0,
+    WB_ERR_INVALID_ARG = 1,   /* null/misaligned pointer, bad size, bad option  */
+    WB_ERR_INVALID_TREE = 2,  /* descriptor is not a valid rooted tree / sphere set */
+    WB_ERR_UNSUPPORTED = 3,   /* valid but beyond what the kernels handle        */
+    WB_ERR_HIP = 4            /* a HIP runtime call failed (message has details) */
+};
+
+enum wb_joint_type { WB_JOINT_FIXED = 0, WB_JOINT_REVOLUTE = 1 };
+
+/* Limits of this build (WB_ERR_UNSUPPORTED beyond them). */
+#define WB_MAX_LINKS 1024
+#define WB_MAX_SPHERES_PER_LINK 8
+
+/*
+ * Robot description (runtime robot binding, Sec. 6.3 "Our RNEA
+ * Implementation": topology, inertias and joint types supplied at run time).
+ * All pointers are host pointers, read during wb_robot_create only.
+ *   n_links        L >= 1, including the fixed root link 0.
+ *   parent[L]      parent[0] = -1, 0 <= parent[k] < k for k >= 1.
+ *   joint_type[L]  WB_JOINT_FIXED or WB_JOINT_REVOLUTE; link 0 must be fixed.
+ *   joint_index[L] actuated joint of each revolute link, -1 for fixed links;
+ *                  the actuated indices used must be exactly 0..n-1 (n = DoF).
+ *   joint_mult[L], joint_offset[L]  mimic multiplier and offset (NULL = 1, 0).
+ *   axis[L][3]     unit joint axis in the child frame (|axis| = 1 within 1e-4).
+ *   fixed_R[L][9], fixed_p[L][3]  fixed transform parent->joint frame
+ *                  (fixed_R orthonormal within 1e-4).
+ *   mass[L], com[L][3], inertia[L][9]  mass, centre of mass in link frame,
+ *                  symmetric rotational inertia about the CoM in link axes.
+ *   n_spheres      S >= 0; sphere_link[S] nondecreasing link indices;
+ *   sphere[S][4]   centre (link frame) and radius (> 0) of each sphere;
+ *                  at most WB_MAX_SPHERES_PER_LINK spheres per link.
+ *   allow[L][L]    symmetric link-pair allow matrix for self-collision, or
+ *                  NULL for the default: every pair of distinct links that
+ *                  are not parent and child (Sec. 6.2 checks all sphere pairs
+ *                  whose links are not adjacent).  Same-link pairs are never
+ *                  checked.
+ *   gravity[3]     gravity vector in the world frame (e.g. 0, 0, -9.81).
+ */
+typedef struct wb_robot_desc {
+    int32_t n_links;
+    const int32_t *parent;
+    const int32_t *joint_type;
+    const int32_t *joint_index;
+    const float *joint_mult;
+    const float *joint_offset;
+    const float *axis;
+    const float *fixed_R;
+    const float *fixed_p;
+    const float *mass;
+    const float *com;
+    const float *inertia;
+    int32_t n_spheres;
+    const int32_t *sphere_link;
+    const float *sphere;
+    const uint8_t *allow;
+    float gravity[3];
+} wb_robot_desc;
+
+/* Derived sizes of a robot. */
+typedef struct wb_robot_info {
+    int32_t n_links;          /* L */
+    int32_t n_dof;            /* n */
+    int32_t n_spheres;        /* S */
+    int32_t max_depth;        /* deepest link's distance from the root */
+    int64_t n_pairs;          /* checked sphere pairs P */
+    int32_t n_blocks;         /* checked link pairs (a < b) carrying spheres */
+    int32_t max_spheres_per_link;
+} wb_robot_info;
+
+typedef struct wb_robot wb_robot;   /* opaque; owns a device copy of the tables */
+
+const char *wb_last_error(void);
+
+/* ---------------------------------------------------------------- host only
+ * These never touch a GPU. */
+
+/* Validate a description and report its derived sizes. */
+int wb_desc_analyze(const wb_robot_desc *desc, wb_robot_info *info);
+
+/* Write the checked sphere pairs, numbered lexicographically in (s, t) with
+ * s < t: s[P], t[P] (host arrays of info.n_pairs entries).  The pair index
+ * returned as argmax by wb_self_collision refers to this numbering.  The list
+ * is rebuilt from the link-block tables the kernels use. */
+int wb_desc_pairs(const wb_robot_desc *desc, int32_t *s, int32_t *t);
+
+/* ------------------------------------------------------------- robot object */
+
+/* Validate, derive the kernel tables and copy them to the current HIP device.
+ * The robot is usable on that device only.  *out is owned by the caller and
+ * released with wb_robot_destroy. */
+int wb_robot_create(const wb_robot_desc *desc, wb_robot **out);
+int wb_robot_destroy(wb_robot *robot);
+int wb_robot_get_info(const wb_robot *robot, wb_robot_info *info);
+
+/* Scratch needed by wb_fk_backward and wb_rnea_backward for B states, in
+ * bytes (caller-allocated device memory, 256-byte aligned, reusable across
+ * calls on one stream). */
+int wb_workspace_bytes(const wb_robot *robot, int64_t B, size_t *bytes);
+/* Size of the RNEA forward cache for B states: [L][18][B] floats holding,
+ * per link, spatial velocity v (6), acceleration a (6) and the accumulated
+ * force F (6) of Alg. 4 (the cache of Sec. 6.3 "Memory layout", unpadded). */
+int wb_rnea_cache_bytes(const wb_robot *robot, int64_t B, size_t *bytes);
+
+/* ---------------------------------------------------------------- forward */
+
+/* Forward kinematics (Sec. 6.1).  q[n][B] joint positions ->
+ *   link_pose[L][12][B] (required; also serves as the traversal storage),
+ *   spheres[S][3][B] world sphere centres (NULL to skip). */
+int wb_fk(const wb_robot *robot, int64_t B, const float *q, float *link_pose, float *spheres,
+          hipStream_t stream);
+
+/* Inverse dynamics by RNEA (Alg. 4).  q, qd, qdd [n][B] -> tau[n][B].
+ * f_ext must be NULL in this build (external link forces are not supported:
+ * WB_ERR_UNSUPPORTED).  cache[L][18][B] (required) receives v, a and the
+ * accumulated link forces for wb_rnea_backward. */
+int wb_rnea(const wb_robot *robot, int64_t B, const float *q, const float *qd, const float *qdd,
+            const float *f_ext, float *tau, float *cache, hipStream_t stream);
+
+/* Self-collision map-reduce (Sec. 6.2).  spheres[S][3][B] -> per state
+ *   max_pen[B]  largest r_s + r_t - |c_s - c_t| over the checked pairs
+ *               (-inf when the robot has no checked pair),
+ *   argmax[B]   lowest pair index attaining it (-1 when there is none),
+ *   n_coll[B]   number of pairs with positive penetration.
+ * Any of the three outputs may be NULL to skip it (not all three). */
+int wb_self_collision(const wb_robot *robot, int64_t B, const float *spheres, float *max_pen,
+                      int32_t *argmax, int32_t *n_coll, hipStream_t stream);
+
+/* -------------------------------------------------------------- adjoints */
+
+/* Adjoint of the hinge cost h = max(0, max_pen + margin) at the most
+ * penetrating pair: g_spheres[S][3][B] is overwritten with zeros except the
+ * two spheres of pair argmax[b], which receive -/+ g_cost[b] * u with u the
+ * unit vector from sphere t to sphere s, when max_pen[b] + margin > 0 (and
+ * zero otherwise, including coincident centres). */
+int wb_self_collision_backward(const wb_robot *robot, int64_t B, const float *spheres,
+                               const int32_t *argmax, const float *max_pen, float margin,
+                               const float *g_cost, float *g_spheres, hipStream_t stream);
+
+/* Adjoint of forward kinematics (Alg. 1): gradients on link poses
+ * g_link_pose[L][12][B] and/or sphere centres g_spheres[S][3][B] (either may
+ * be NULL, not both) -> g_q[n][B] (overwritten).  link_pose is the output of
+ * wb_fk for the same q, or NULL to recompute the transforms from q inside
+ * the kernel.  workspace: wb_workspace_bytes(robot, B). */
+int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float *link_pose,
+                   const float *g_link_pose, const float *g_spheres, float *g_q, void *workspace,
+                   hipStream_t stream);
+
+/* Vector-Jacobian product of RNEA (the role of Alg. 5): g_tau[n][B] ->
+ * g_q, g_qd, g_qdd [n][B] (overwritten).  cache is the one written by
+ * wb_rnea for the same q, qd, qdd.  Transforms are recomputed from q.
+ * workspace: wb_workspace_bytes(robot, B). */
+int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const float *qd,
+                     const float *qdd, const float *cache, const float *g_tau, float *g_q,
+                     float *g_qd, float *g_qdd, void *workspace, hipStream_t stream);
+
+/* ------------------------------------------------ cost head and update step
+ * The per-state scalar costs of the trajectory-optimization iteration
+ * (Sec. 3, Eq. 1 and the torque / self-collision constraints as penalties):
+ *   cost[b] = (w ? sum_j w[j][b] tau[j][b] : torque_weight * sum_j tau^2)
+ *           + hinge_weight * max(0, max_pen[b] + margin)
+ *   g_tau   = w ? w : 2 * torque_weight * tau
+ *   g_maxpen[b] = hinge_weight * (max_pen[b] + margin > 0)
+ * w may be NULL; max_pen may be NULL (no hinge term, g_maxpen untouched);
+ * cost and g_maxpen may be NULL. */
+int wb_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float torque_weight,
+                 const float *max_pen, float margin, float hinge_weight, float *cost,
+                 float *g_tau, float *g_maxpen, hipStream_t stream);
+
+/* Gradient step in place: q -= lr * (g_q + g_q2), qd -= lr * g_qd,
+ * qdd -= lr * g_qdd, all [n][B]; g_q2 may be NULL. */
+int wb_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd, const float *g_q,
+                const float *g_q2, const float *g_qd, const float *g_qdd, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WB_H */

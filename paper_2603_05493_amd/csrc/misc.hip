@@ -1,0 +1,103 @@
+// Small per-state kernels of the optimizer iteration: the hinge adjoint of
+// self-collision, the cost head and the gradient step.  All are one state
+// per lane over [k][B] arrays (coalesced in B).
+#include "spatial.h"
+
+namespace wb {
+
+// Hinge h = max(0, max_pen + margin) at the most penetrating pair: its
+// subgradient moves the two spheres of that pair apart along their centre
+// line (cuRoboV2 Sec. 6.2 reduces to one most-penetrating pair per state).
+__global__ void __launch_bounds__(256) k_sc_backward(DevRobot rb, int64_t B, const float *__restrict__ sph,
+                                                     const int32_t *__restrict__ argmax,
+                                                     const float *__restrict__ max_pen, float margin,
+                                                     const float *__restrict__ g_cost,
+                                                     float *__restrict__ g_sph) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    for (int i = 0; i < rb.S * 3; ++i) g_sph[(int64_t)i * B + b] = 0.0f;
+    const int p = argmax[b];
+    if (p < 0 || p >= rb.n_pairs || !(max_pen[b] + margin > 0.0f)) return;
+    const int s = rb.pair_s[p], t = rb.pair_t[p];
+    const float *cs = sph + (int64_t)s * 3 * B + b;
+    const float *ct = sph + (int64_t)t * 3 * B + b;
+    const V3 d = v3(cs[0] - ct[0], cs[B] - ct[B], cs[2 * B] - ct[2 * B]);
+    const float n = sqrtf(dot(d, d));
+    if (!(n > 0.0f)) return;
+    const float g = g_cost[b] / n;
+    float *gs = g_sph + (int64_t)s * 3 * B + b;
+    float *gt = g_sph + (int64_t)t * 3 * B + b;
+    gs[0] = -g * d.x; gs[B] = -g * d.y; gs[2 * B] = -g * d.z;
+    gt[0] = g * d.x;  gt[B] = g * d.y;  gt[2 * B] = g * d.z;
+}
+
+__global__ void __launch_bounds__(256) k_cost_head(int64_t B, int n, const float *__restrict__ tau,
+                                                   const float *__restrict__ w, float tw,
+                                                   const float *__restrict__ max_pen, float margin,
+                                                   float hw, float *__restrict__ cost,
+                                                   float *__restrict__ g_tau, float *__restrict__ g_mp) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float c = 0.0f;
+    for (int j = 0; j < n; ++j) {
+        const int64_t o = (int64_t)j * B + b;
+        const float t = tau[o];
+        if (w) {
+            c = __builtin_fmaf(w[o], t, c);
+            if (g_tau) g_tau[o] = w[o];
+        } else {
+            c = __builtin_fmaf(tw * t, t, c);
+            if (g_tau) g_tau[o] = 2.0f * tw * t;
+        }
+    }
+    if (max_pen) {
+        const float h = max_pen[b] + margin;
+        c += hw * fmaxf(h, 0.0f);
+        if (g_mp) g_mp[b] = h > 0.0f ? hw : 0.0f;
+    }
+    if (cost) cost[b] = c;
+}
+
+__global__ void __launch_bounds__(256) k_sgd_step(int64_t total, float lr, float *__restrict__ q,
+                                                  float *__restrict__ qd, float *__restrict__ qdd,
+                                                  const float *__restrict__ g_q, const float *__restrict__ g_q2,
+                                                  const float *__restrict__ g_qd,
+                                                  const float *__restrict__ g_qdd) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const float gq = g_q[i] + (g_q2 ? g_q2[i] : 0.0f);
+    q[i] -= lr * gq;
+    qd[i] -= lr * g_qd[i];
+    qdd[i] -= lr * g_qdd[i];
+}
+
+hipError_t launch_self_collision_backward(const DevRobot &rb, int64_t B, const float *spheres,
+                                          const int32_t *argmax, const float *max_pen,
+                                          float margin, const float *g_cost, float *g_sph,
+                                          hipStream_t s) {
+    if (B == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sc_backward, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, rb, B, spheres,
+                       argmax, max_pen, margin, g_cost, g_sph);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float tw,
+                            const float *max_pen, float margin, float hw, float *cost,
+                            float *g_tau, float *g_maxpen, hipStream_t s) {
+    if (B == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cost_head, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, B, n, tau, w, tw,
+                       max_pen, margin, hw, cost, g_tau, g_maxpen);
+    return hipGetLastError();
+}
+
+hipError_t launch_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd,
+                           const float *g_q, const float *g_q2, const float *g_qd,
+                           const float *g_qdd, hipStream_t s) {
+    const int64_t total = B * (int64_t)n;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sgd_step, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total, lr, q, qd,
+                       qdd, g_q, g_q2, g_qd, g_qdd);
+    return hipGetLastError();
+}
+
+}  // namespace wb

@@ -1,0 +1,525 @@
+// Host side of libwb: descriptor validation, derived kernel tables, device
+// upload and the extern "C" entry points declared in include/wb.h.
+#include "wb.h"
+#include "wb_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(WB_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Everything derived from a descriptor, in host memory.
+struct Tables {
+    int L = 0, n = 0, S = 0, nmax = 1, max_depth = 0, simple = 1;
+    std::vector<wb::LinkF> lf;
+    std::vector<wb::LinkI> li;
+    std::vector<float4> sph;
+    std::vector<int32_t> sph_link, sph_slot;
+    std::vector<float> slot_r;
+    std::vector<int32_t> blocks;      // padded to a multiple of 64
+    int n_blocks = 0;
+    std::vector<int32_t> pair_off, pair_cnt, pair_s, pair_t;
+    int64_t n_pairs = 0;
+    float g[3] = {0, 0, 0};
+};
+
+bool finite_all(const float *p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+int build_tables(const wb_robot_desc *d, Tables &T) {
+    if (!d) return fail(WB_ERR_INVALID_ARG, "descriptor is null");
+    const int L = d->n_links;
+    if (L < 1) return fail(WB_ERR_INVALID_TREE, "n_links must be >= 1 (got %d)", L);
+    if (L > WB_MAX_LINKS) return fail(WB_ERR_UNSUPPORTED, "n_links %d exceeds %d", L, WB_MAX_LINKS);
+    if (!d->parent || !d->joint_type || !d->joint_index || !d->axis || !d->fixed_R || !d->fixed_p ||
+        !d->mass || !d->com || !d->inertia)
+        return fail(WB_ERR_INVALID_ARG, "a required per-link array is null");
+    const int S = d->n_spheres;
+    if (S < 0) return fail(WB_ERR_INVALID_ARG, "n_spheres must be >= 0");
+    if (S > 0 && (!d->sphere_link || !d->sphere)) return fail(WB_ERR_INVALID_ARG, "sphere arrays are null");
+    if (!finite_all(d->axis, 3 * (size_t)L) || !finite_all(d->fixed_R, 9 * (size_t)L) ||
+        !finite_all(d->fixed_p, 3 * (size_t)L) || !finite_all(d->mass, L) || !finite_all(d->com, 3 * (size_t)L) ||
+        !finite_all(d->inertia, 9 * (size_t)L) || !finite_all(d->gravity, 3) ||
+        (S > 0 && !finite_all(d->sphere, 4 * (size_t)S)) ||
+        (d->joint_mult && !finite_all(d->joint_mult, L)) || (d->joint_offset && !finite_all(d->joint_offset, L)))
+        return fail(WB_ERR_INVALID_ARG, "descriptor holds a non-finite value");
+
+    // Topology.
+    if (d->parent[0] != -1) return fail(WB_ERR_INVALID_TREE, "parent[0] must be -1");
+    if (d->joint_type[0] != WB_JOINT_FIXED) return fail(WB_ERR_INVALID_TREE, "link 0 (root) must be fixed");
+    T.L = L;
+    T.lf.assign(L, wb::LinkF{});
+    T.li.assign(L, wb::LinkI{});
+    int max_j = -1;
+    for (int k = 0; k < L; ++k) {
+        const int p = d->parent[k];
+        if (k > 0 && (p < 0 || p >= k))
+            return fail(WB_ERR_INVALID_TREE, "parent[%d] = %d must satisfy 0 <= parent < %d", k, p, k);
+        const int jt = d->joint_type[k];
+        if (jt != WB_JOINT_FIXED && jt != WB_JOINT_REVOLUTE)
+            return fail(WB_ERR_INVALID_TREE, "joint_type[%d] = %d is not fixed/revolute", k, jt);
+        const int ji = d->joint_index[k];
+        if (jt == WB_JOINT_FIXED && ji != -1)
+            return fail(WB_ERR_INVALID_TREE, "fixed link %d must have joint_index -1", k);
+        if (jt == WB_JOINT_REVOLUTE && ji < 0)
+            return fail(WB_ERR_INVALID_TREE, "revolute link %d has joint_index %d", k, ji);
+        if (ji > max_j) max_j = ji;
+        wb::LinkI &I = T.li[k];
+        I.parent = p;
+        I.revolute = jt == WB_JOINT_REVOLUTE;
+        I.jidx = ji;
+        I.depth = k == 0 ? 0 : T.li[p].depth + 1;
+        if (I.depth > T.max_depth) T.max_depth = I.depth;
+        wb::LinkF &F = T.lf[k];
+        const float *ax = d->axis + 3 * k;
+        if (I.revolute) {
+            const double nrm = std::sqrt((double)ax[0] * ax[0] + (double)ax[1] * ax[1] + (double)ax[2] * ax[2]);
+            if (std::fabs(nrm - 1.0) > 1e-4) return fail(WB_ERR_INVALID_TREE, "axis of link %d is not unit (|a| = %g)", k, nrm);
+        }
+        memcpy(F.axis, ax, 3 * sizeof(float));
+        const float *R = d->fixed_R + 9 * k;
+        double orth = 0.0;
+        bool ident = true;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0.0;
+                for (int t = 0; t < 3; ++t) s += (double)R[3 * t + i] * R[3 * t + j];
+                orth = std::fmax(orth, std::fabs(s - (i == j ? 1.0 : 0.0)));
+                if (R[3 * i + j] != (i == j ? 1.0f : 0.0f)) ident = false;
+            }
+        if (orth > 1e-4) return fail(WB_ERR_INVALID_TREE, "fixed_R of link %d is not orthonormal", k);
+        memcpy(F.fR, R, 9 * sizeof(float));
+        I.fR_identity = ident;
+        memcpy(F.fp, d->fixed_p + 3 * k, 3 * sizeof(float));
+        F.mult = d->joint_mult ? d->joint_mult[k] : 1.0f;
+        F.offset = d->joint_offset ? d->joint_offset[k] : 0.0f;
+        if (d->mass[k] < 0.0f) return fail(WB_ERR_INVALID_ARG, "mass of link %d is negative", k);
+        F.mass = d->mass[k];
+        memcpy(F.com, d->com + 3 * k, 3 * sizeof(float));
+        const float *In = d->inertia + 9 * k;
+        const float sc = std::fabs(In[0]) + std::fabs(In[4]) + std::fabs(In[8]) + 1e-30f;
+        if (std::fabs(In[1] - In[3]) > 1e-5f * sc || std::fabs(In[2] - In[6]) > 1e-5f * sc ||
+            std::fabs(In[5] - In[7]) > 1e-5f * sc)
+            return fail(WB_ERR_INVALID_ARG, "inertia of link %d is not symmetric", k);
+        F.I[0] = In[0]; F.I[1] = In[4]; F.I[2] = In[8];
+        F.I[3] = 0.5f * (In[1] + In[3]); F.I[4] = 0.5f * (In[2] + In[6]); F.I[5] = 0.5f * (In[5] + In[7]);
+    }
+    T.n = max_j + 1;
+    std::vector<int> uses(T.n, 0);
+    for (int k = 0; k < L; ++k) {
+        if (T.li[k].jidx >= 0) ++uses[T.li[k].jidx];
+        if (T.li[k].revolute && (T.lf[k].mult != 1.0f || T.lf[k].offset != 0.0f)) T.simple = 0;
+    }
+    for (int j = 0; j < T.n; ++j) {
+        if (uses[j] == 0) return fail(WB_ERR_INVALID_TREE, "actuated joint index %d is used by no link", j);
+        if (uses[j] > 1) T.simple = 0;
+    }
+    for (int k = 1; k < L; ++k)
+        if (d->parent[k] != k - 1) T.li[d->parent[k]].far_child = 1;
+
+    // Spheres.
+    T.S = S;
+    std::vector<int> count(L, 0);
+    for (int k = 0; k < L; ++k) T.li[k].sph_first = 0;
+    for (int s = 0; s < S; ++s) {
+        const int l = d->sphere_link[s];
+        if (l < 0 || l >= L) return fail(WB_ERR_INVALID_TREE, "sphere %d is on missing link %d", s, l);
+        if (s > 0 && l < d->sphere_link[s - 1])
+            return fail(WB_ERR_INVALID_TREE, "sphere_link must be nondecreasing (sphere %d)", s);
+        if (!(d->sphere[4 * s + 3] > 0.0f)) return fail(WB_ERR_INVALID_ARG, "sphere %d radius must be > 0", s);
+        if (count[l] == 0) T.li[l].sph_first = s;
+        ++count[l];
+    }
+    int nmax = 1;
+    for (int k = 0; k < L; ++k) {
+        T.li[k].sph_count = count[k];
+        if (count[k] == 0) T.li[k].sph_first = 0;
+        if (count[k] > nmax) nmax = count[k];
+    }
+    if (nmax > WB_MAX_SPHERES_PER_LINK)
+        return fail(WB_ERR_UNSUPPORTED, "%d spheres on one link exceeds %d", nmax, WB_MAX_SPHERES_PER_LINK);
+    T.nmax = nmax;
+    if ((size_t)(L + 1) * nmax * sizeof(float4) > 65536)
+        return fail(WB_ERR_UNSUPPORTED, "(links + 1) x spheres-per-link slots (%d x %d) exceed the 64 KB LDS tile",
+                    L + 1, nmax);
+    T.sph.resize(S);
+    T.sph_link.resize(S);
+    T.sph_slot.resize(S);
+    for (int s = 0; s < S; ++s) {
+        const float *x = d->sphere + 4 * s;
+        T.sph[s] = make_float4(x[0], x[1], x[2], x[3]);
+        const int l = d->sphere_link[s];
+        T.sph_link[s] = l;
+        T.sph_slot[s] = l * nmax + (s - T.li[l].sph_first);
+    }
+    T.slot_r.assign((size_t)(L + 1) * nmax, -1e30f);
+    for (int s = 0; s < S; ++s) T.slot_r[T.sph_slot[s]] = T.sph[s].w;
+
+    // Link-pair allow rule and blocks.
+    if (d->allow) {
+        for (int a = 0; a < L; ++a)
+            for (int b = 0; b < L; ++b)
+                if ((d->allow[a * L + b] != 0) != (d->allow[b * L + a] != 0))
+                    return fail(WB_ERR_INVALID_ARG, "allow matrix is not symmetric at (%d, %d)", a, b);
+    }
+    auto allowed = [&](int a, int b) {
+        if (a == b) return false;
+        if (d->allow) return d->allow[a * L + b] != 0;
+        return d->parent[b] != a && d->parent[a] != b;
+    };
+    T.blocks.clear();
+    T.pair_cnt.assign((size_t)L * L, 0);
+    std::vector<int64_t> partners(L, 0);
+    for (int a = 0; a < L; ++a) {
+        int64_t run = 0;
+        for (int b = a + 1; b < L; ++b) {
+            if (!allowed(a, b)) continue;
+            T.pair_cnt[(size_t)a * L + b] = (int32_t)run;
+            run += count[b];
+            if (count[a] > 0 && count[b] > 0) T.blocks.push_back((a << 16) | b);
+        }
+        partners[a] = run;
+    }
+    T.n_blocks = (int)T.blocks.size();
+    while (T.blocks.size() % 64) T.blocks.push_back((L << 16) | L);
+    T.pair_off.resize(S);
+    int64_t off = 0;
+    for (int s = 0; s < S; ++s) {
+        if (off > INT32_MAX) return fail(WB_ERR_UNSUPPORTED, "more than 2^31 sphere pairs");
+        T.pair_off[s] = (int32_t)off;
+        off += partners[T.sph_link[s]];
+    }
+    if (off > INT32_MAX) return fail(WB_ERR_UNSUPPORTED, "more than 2^31 sphere pairs");
+    T.n_pairs = off;
+    // Pair list rebuilt from the block tables (the numbering the kernels use).
+    T.pair_s.assign(off, -1);
+    T.pair_t.assign(off, -1);
+    for (int i = 0; i < T.n_blocks; ++i) {
+        const int a = T.blocks[i] >> 16, b = T.blocks[i] & 0xffff;
+        for (int s = T.li[a].sph_first; s < T.li[a].sph_first + count[a]; ++s)
+            for (int t = T.li[b].sph_first; t < T.li[b].sph_first + count[b]; ++t) {
+                const int64_t idx = (int64_t)T.pair_off[s] + T.pair_cnt[(size_t)a * L + b] + (t - T.li[b].sph_first);
+                if (idx < 0 || idx >= off || T.pair_s[idx] != -1)
+                    return fail(WB_ERR_INVALID_TREE, "internal: pair numbering is inconsistent");
+                T.pair_s[idx] = s;
+                T.pair_t[idx] = t;
+            }
+    }
+    for (int c = 0; c < 3; ++c) T.g[c] = d->gravity[c];
+    return WB_OK;
+}
+
+void fill_info(const Tables &T, wb_robot_info *info) {
+    info->n_links = T.L;
+    info->n_dof = T.n;
+    info->n_spheres = T.S;
+    info->max_depth = T.max_depth;
+    info->n_pairs = T.n_pairs;
+    info->n_blocks = T.n_blocks;
+    info->max_spheres_per_link = T.nmax;
+}
+
+bool aligned4(const void *p) { return ((uintptr_t)p & 3) == 0; }
+
+}  // namespace
+
+struct wb_robot {
+    Tables T;
+    wb::DevRobot dev{};
+    void *dmem = nullptr;
+    int device = -1;
+};
+
+namespace {
+
+template <typename V>
+size_t append(std::vector<char> &blob, const V &v) {
+    size_t off = (blob.size() + 255) & ~(size_t)255;
+    blob.resize(off + v.size() * sizeof(typename V::value_type));
+    if (!v.empty()) memcpy(blob.data() + off, v.data(), v.size() * sizeof(typename V::value_type));
+    return off;
+}
+
+int check_robot(const wb_robot *r) {
+    if (!r || !r->dmem) return fail(WB_ERR_INVALID_ARG, "robot handle is null or destroyed");
+    return WB_OK;
+}
+
+int check_B(int64_t B) {
+    if (B < 0 || B > INT32_MAX) return fail(WB_ERR_INVALID_ARG, "batch size %lld out of range", (long long)B);
+    return WB_OK;
+}
+
+int check_ptr(const void *p, const char *name, bool required) {
+    if (!p) return required ? fail(WB_ERR_INVALID_ARG, "%s is null", name) : WB_OK;
+    if (!aligned4(p)) return fail(WB_ERR_INVALID_ARG, "%s is not 4-byte aligned", name);
+    return WB_OK;
+}
+
+#define WB_TRY(x)                    \
+    do {                             \
+        int _rc = (x);               \
+        if (_rc != WB_OK) return _rc; \
+    } while (0)
+
+int finish(hipError_t e, const char *what) { return e == hipSuccess ? WB_OK : hip_fail(e, what); }
+
+}  // namespace
+
+extern "C" {
+
+const char *wb_last_error(void) { return g_err.c_str(); }
+
+int wb_desc_analyze(const wb_robot_desc *desc, wb_robot_info *info) {
+    if (!info) return fail(WB_ERR_INVALID_ARG, "info is null");
+    Tables T;
+    WB_TRY(build_tables(desc, T));
+    fill_info(T, info);
+    return WB_OK;
+}
+
+int wb_desc_pairs(const wb_robot_desc *desc, int32_t *s, int32_t *t) {
+    Tables T;
+    WB_TRY(build_tables(desc, T));
+    if (T.n_pairs > 0 && (!s || !t)) return fail(WB_ERR_INVALID_ARG, "output arrays are null");
+    if (T.n_pairs > 0) {
+        memcpy(s, T.pair_s.data(), T.n_pairs * sizeof(int32_t));
+        memcpy(t, T.pair_t.data(), T.n_pairs * sizeof(int32_t));
+    }
+    return WB_OK;
+}
+
+int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
+    if (!out) return fail(WB_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    wb_robot *r = new wb_robot();
+    int rc = build_tables(desc, r->T);
+    if (rc != WB_OK) {
+        delete r;
+        return rc;
+    }
+    const Tables &T = r->T;
+    std::vector<char> blob;
+    const size_t o_lf = append(blob, T.lf), o_li = append(blob, T.li), o_sph = append(blob, T.sph);
+    const size_t o_sl = append(blob, T.sph_link), o_ss = append(blob, T.sph_slot);
+    const size_t o_sr = append(blob, T.slot_r), o_bl = append(blob, T.blocks);
+    const size_t o_po = append(blob, T.pair_off), o_pc = append(blob, T.pair_cnt);
+    const size_t o_ps = append(blob, T.pair_s), o_pt = append(blob, T.pair_t);
+    blob.resize(blob.size() + 256);
+    hipError_t e = hipGetDevice(&r->device);
+    if (e == hipSuccess) e = hipMalloc(&r->dmem, blob.size());
+    if (e == hipSuccess) e = hipMemcpy(r->dmem, blob.data(), blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (r->dmem) (void)hipFree(r->dmem);
+        delete r;
+        return hip_fail(e, "uploading the robot tables");
+    }
+    char *base = static_cast<char *>(r->dmem);
+    wb::DevRobot &D = r->dev;
+    D.L = T.L; D.n = T.n; D.S = T.S; D.nmax = T.nmax;
+    D.n_blocks = T.n_blocks; D.n_blocks_pad = (int)T.blocks.size();
+    D.max_depth = T.max_depth; D.simple_joints = T.simple;
+    D.n_pairs = T.n_pairs;
+    D.gx = T.g[0]; D.gy = T.g[1]; D.gz = T.g[2];
+    D.lf = reinterpret_cast<const wb::LinkF *>(base + o_lf);
+    D.li = reinterpret_cast<const wb::LinkI *>(base + o_li);
+    D.sph = reinterpret_cast<const float4 *>(base + o_sph);
+    D.sph_link = reinterpret_cast<const int32_t *>(base + o_sl);
+    D.sph_slot = reinterpret_cast<const int32_t *>(base + o_ss);
+    D.slot_r = reinterpret_cast<const float *>(base + o_sr);
+    D.blocks = reinterpret_cast<const int32_t *>(base + o_bl);
+    D.pair_off = reinterpret_cast<const int32_t *>(base + o_po);
+    D.pair_cnt = reinterpret_cast<const int32_t *>(base + o_pc);
+    D.pair_s = reinterpret_cast<const int32_t *>(base + o_ps);
+    D.pair_t = reinterpret_cast<const int32_t *>(base + o_pt);
+    *out = r;
+    return WB_OK;
+}
+
+int wb_robot_destroy(wb_robot *robot) {
+    if (!robot) return WB_OK;
+    hipError_t e = hipSuccess;
+    if (robot->dmem) e = hipFree(robot->dmem);
+    robot->dmem = nullptr;
+    delete robot;
+    return finish(e, "freeing the robot tables");
+}
+
+int wb_robot_get_info(const wb_robot *robot, wb_robot_info *info) {
+    WB_TRY(check_robot(robot));
+    if (!info) return fail(WB_ERR_INVALID_ARG, "info is null");
+    fill_info(robot->T, info);
+    return WB_OK;
+}
+
+int wb_workspace_bytes(const wb_robot *robot, int64_t B, size_t *bytes) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    if (!bytes) return fail(WB_ERR_INVALID_ARG, "bytes is null");
+    *bytes = (size_t)wb::workspace_floats_per_state(robot->T.L) * (size_t)B * sizeof(float);
+    return WB_OK;
+}
+
+int wb_rnea_cache_bytes(const wb_robot *robot, int64_t B, size_t *bytes) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    if (!bytes) return fail(WB_ERR_INVALID_ARG, "bytes is null");
+    *bytes = (size_t)robot->T.L * 18 * (size_t)B * sizeof(float);
+    return WB_OK;
+}
+
+int wb_fk(const wb_robot *robot, int64_t B, const float *q, float *link_pose, float *spheres,
+          hipStream_t stream) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    if (B == 0) return WB_OK;
+    WB_TRY(check_ptr(q, "q", robot->T.n > 0));
+    WB_TRY(check_ptr(link_pose, "link_pose", true));
+    WB_TRY(check_ptr(spheres, "spheres", false));
+    return finish(wb::launch_fk(robot->dev, B, q, link_pose, spheres, stream), "wb_fk launch");
+}
+
+int wb_rnea(const wb_robot *robot, int64_t B, const float *q, const float *qd, const float *qdd,
+            const float *f_ext, float *tau, float *cache, hipStream_t stream) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    if (f_ext) return fail(WB_ERR_UNSUPPORTED, "external link forces are not supported in this build");
+    if (B == 0) return WB_OK;
+    const bool need = robot->T.n > 0;
+    WB_TRY(check_ptr(q, "q", need));
+    WB_TRY(check_ptr(qd, "qd", need));
+    WB_TRY(check_ptr(qdd, "qdd", need));
+    WB_TRY(check_ptr(tau, "tau", need));
+    WB_TRY(check_ptr(cache, "cache", true));
+    return finish(wb::launch_rnea(robot->dev, B, q, qd, qdd, tau, cache, stream), "wb_rnea launch");
+}
+
+int wb_self_collision(const wb_robot *robot, int64_t B, const float *spheres, float *max_pen,
+                      int32_t *argmax, int32_t *n_coll, hipStream_t stream) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    if (!max_pen && !argmax && !n_coll) return fail(WB_ERR_INVALID_ARG, "all outputs are null");
+    if (B == 0) return WB_OK;
+    WB_TRY(check_ptr(spheres, "spheres", robot->T.S > 0));
+    WB_TRY(check_ptr(max_pen, "max_pen", false));
+    WB_TRY(check_ptr(argmax, "argmax", false));
+    WB_TRY(check_ptr(n_coll, "n_coll", false));
+    return finish(wb::launch_self_collision(robot->dev, B, spheres, max_pen, argmax, n_coll, stream),
+                  "wb_self_collision launch");
+}
+
+int wb_self_collision_backward(const wb_robot *robot, int64_t B, const float *spheres,
+                               const int32_t *argmax, const float *max_pen, float margin,
+                               const float *g_cost, float *g_spheres, hipStream_t stream) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    if (!std::isfinite(margin)) return fail(WB_ERR_INVALID_ARG, "margin is not finite");
+    if (B == 0) return WB_OK;
+    WB_TRY(check_ptr(spheres, "spheres", robot->T.S > 0));
+    WB_TRY(check_ptr(argmax, "argmax", true));
+    WB_TRY(check_ptr(max_pen, "max_pen", true));
+    WB_TRY(check_ptr(g_cost, "g_cost", true));
+    WB_TRY(check_ptr(g_spheres, "g_spheres", robot->T.S > 0));
+    return finish(wb::launch_self_collision_backward(robot->dev, B, spheres, argmax, max_pen, margin, g_cost,
+                                                     g_spheres, stream),
+                  "wb_self_collision_backward launch");
+}
+
+int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float *link_pose,
+                   const float *g_link_pose, const float *g_spheres, float *g_q, void *workspace,
+                   hipStream_t stream) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    if (!g_link_pose && !g_spheres) return fail(WB_ERR_INVALID_ARG, "both gradient inputs are null");
+    if (B == 0) return WB_OK;
+    WB_TRY(check_ptr(q, "q", robot->T.n > 0));
+    WB_TRY(check_ptr(link_pose, "link_pose", false));
+    WB_TRY(check_ptr(g_link_pose, "g_link_pose", false));
+    WB_TRY(check_ptr(g_spheres, "g_spheres", false));
+    WB_TRY(check_ptr(g_q, "g_q", robot->T.n > 0));
+    WB_TRY(check_ptr(workspace, "workspace", true));
+    return finish(wb::launch_fk_backward(robot->dev, B, q, link_pose, g_link_pose, g_spheres, g_q,
+                                         static_cast<float *>(workspace), stream),
+                  "wb_fk_backward launch");
+}
+
+int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const float *qd,
+                     const float *qdd, const float *cache, const float *g_tau, float *g_q,
+                     float *g_qd, float *g_qdd, void *workspace, hipStream_t stream) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    if (B == 0) return WB_OK;
+    const bool need = robot->T.n > 0;
+    WB_TRY(check_ptr(q, "q", need));
+    WB_TRY(check_ptr(qd, "qd", need));
+    WB_TRY(check_ptr(qdd, "qdd", need));
+    WB_TRY(check_ptr(cache, "cache", true));
+    WB_TRY(check_ptr(g_tau, "g_tau", need));
+    WB_TRY(check_ptr(g_q, "g_q", need));
+    WB_TRY(check_ptr(g_qd, "g_qd", need));
+    WB_TRY(check_ptr(g_qdd, "g_qdd", need));
+    WB_TRY(check_ptr(workspace, "workspace", true));
+    return finish(wb::launch_rnea_backward(robot->dev, B, q, qd, qdd, cache, g_tau, g_q, g_qd, g_qdd,
+                                           static_cast<float *>(workspace), stream),
+                  "wb_rnea_backward launch");
+}
+
+int wb_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float torque_weight,
+                 const float *max_pen, float margin, float hinge_weight, float *cost, float *g_tau,
+                 float *g_maxpen, hipStream_t stream) {
+    WB_TRY(check_B(B));
+    if (n < 0) return fail(WB_ERR_INVALID_ARG, "n must be >= 0");
+    if (!std::isfinite(torque_weight) || !std::isfinite(margin) || !std::isfinite(hinge_weight))
+        return fail(WB_ERR_INVALID_ARG, "weights and margin must be finite");
+    if (B == 0) return WB_OK;
+    WB_TRY(check_ptr(tau, "tau", n > 0));
+    WB_TRY(check_ptr(w, "w", false));
+    WB_TRY(check_ptr(max_pen, "max_pen", false));
+    WB_TRY(check_ptr(cost, "cost", false));
+    WB_TRY(check_ptr(g_tau, "g_tau", false));
+    WB_TRY(check_ptr(g_maxpen, "g_maxpen", false));
+    return finish(wb::launch_cost_head(B, n, tau, w, torque_weight, max_pen, margin, hinge_weight, cost, g_tau,
+                                       g_maxpen, stream),
+                  "wb_cost_head launch");
+}
+
+int wb_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd, const float *g_q,
+                const float *g_q2, const float *g_qd, const float *g_qdd, hipStream_t stream) {
+    WB_TRY(check_B(B));
+    if (n < 0) return fail(WB_ERR_INVALID_ARG, "n must be >= 0");
+    if (!std::isfinite(lr)) return fail(WB_ERR_INVALID_ARG, "lr must be finite");
+    if (B == 0 || n == 0) return WB_OK;
+    WB_TRY(check_ptr(q, "q", true));
+    WB_TRY(check_ptr(qd, "qd", true));
+    WB_TRY(check_ptr(qdd, "qdd", true));
+    WB_TRY(check_ptr(g_q, "g_q", true));
+    WB_TRY(check_ptr(g_q2, "g_q2", false));
+    WB_TRY(check_ptr(g_qd, "g_qd", true));
+    WB_TRY(check_ptr(g_qdd, "g_qdd", true));
+    return finish(wb::launch_sgd_step(B, n, lr, q, qd, qdd, g_q, g_q2, g_qd, g_qdd, stream), "wb_sgd_step launch");
+}
+
+}  // extern "C"

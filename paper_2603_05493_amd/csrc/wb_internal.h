@@ -1,0 +1,86 @@
+// Internal structures shared by the host code and the HIP kernels of libwb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace wb {
+
+// Per-link float record, 32 floats (128 bytes) so a uniform link index turns
+// into one scalar-cache fetch in lane-per-state kernels.
+struct LinkF {
+    float axis[3];     // 0
+    float fR[9];       // 3   row-major fixed rotation
+    float fp[3];       // 12  fixed translation (child joint origin in parent frame)
+    float mult;        // 15
+    float offset;      // 16
+    float mass;        // 17
+    float com[3];      // 18
+    float I[6];        // 21  xx yy zz xy xz yz about the CoM, link axes
+    float pad[5];      // 27
+};
+static_assert(sizeof(LinkF) == 128, "LinkF layout");
+
+// Per-link integer record.
+struct LinkI {
+    int32_t parent;
+    int32_t revolute;  // 1 if the link has a revolute joint
+    int32_t jidx;      // actuated joint, -1 if fixed
+    int32_t sph_first;
+    int32_t sph_count;
+    int32_t depth;
+    int32_t fR_identity;  // fixed rotation is exactly the identity
+    int32_t far_child;    // has a child other than link k+1
+};
+static_assert(sizeof(LinkI) == 32, "LinkI layout");
+
+// Device view of a robot, passed by value to kernels.
+struct DevRobot {
+    int32_t L, n, S, nmax;        // nmax: sphere slots per link (max spheres on a link)
+    int32_t n_blocks, n_blocks_pad, max_depth, simple_joints;  // simple: one link per actuated joint, mult 1, offset 0
+    int64_t n_pairs;
+    float gx, gy, gz, pad0;
+    const LinkF *__restrict__ lf;         // [L]
+    const LinkI *__restrict__ li;         // [L]
+    const float4 *__restrict__ sph;       // [S] local centre + radius
+    const int32_t *__restrict__ sph_link; // [S]
+    const int32_t *__restrict__ sph_slot; // [S] padded slot a*nmax + (s - first sphere of a)
+    const float *__restrict__ slot_r;     // [(L+1)*nmax] radius of slot (a,i), -1e30 for empty slots
+    const int32_t *__restrict__ blocks;   // [n_blocks_pad] packed (a<<16)|b, padding = (L<<16)|L
+    const int32_t *__restrict__ pair_off; // [S] index of sphere s's first pair
+    const int32_t *__restrict__ pair_cnt; // [L*L] pairs of a sphere on link a with links a<b'<b
+    const int32_t *__restrict__ pair_s;   // [P]
+    const int32_t *__restrict__ pair_t;   // [P]
+};
+
+// Kernel launchers (each defined next to its kernels).
+hipError_t launch_fk(const DevRobot &rb, int64_t B, const float *q, float *pose, float *spheres,
+                     hipStream_t s);
+hipError_t launch_fk_backward(const DevRobot &rb, int64_t B, const float *q, const float *pose,
+                              const float *g_pose, const float *g_sph, float *g_q, float *ws,
+                              hipStream_t s);
+hipError_t launch_rnea(const DevRobot &rb, int64_t B, const float *q, const float *qd,
+                       const float *qdd, float *tau, float *cache, hipStream_t s);
+hipError_t launch_rnea_backward(const DevRobot &rb, int64_t B, const float *q, const float *qd,
+                                const float *qdd, const float *cache, const float *g_tau,
+                                float *g_q, float *g_qd, float *g_qdd, float *ws, hipStream_t s);
+hipError_t launch_self_collision(const DevRobot &rb, int64_t B, const float *spheres,
+                                 float *max_pen, int32_t *argmax, int32_t *n_coll, hipStream_t s);
+hipError_t launch_self_collision_backward(const DevRobot &rb, int64_t B, const float *spheres,
+                                          const int32_t *argmax, const float *max_pen,
+                                          float margin, const float *g_cost, float *g_sph,
+                                          hipStream_t s);
+hipError_t launch_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float tw,
+                            const float *max_pen, float margin, float hw, float *cost,
+                            float *g_tau, float *g_maxpen, hipStream_t s);
+hipError_t launch_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd,
+                           const float *g_q, const float *g_q2, const float *g_qd,
+                           const float *g_qdd, hipStream_t s);
+
+// States per workgroup of the self-collision kernel (LDS tile).
+int self_collision_tile(int L, int nmax);
+
+// Workspace floats per state needed by the backward kernels.
+inline int64_t workspace_floats_per_state(int L) { return (int64_t)L * 18 + 8; }
+
+}  // namespace wb

@@ -1,0 +1,314 @@
+"""Python binding of libwb: the C-ABI calls under the same names, taking torch
+tensors for device memory and the current HIP stream, plus
+``torch.autograd.Function`` wrappers.
+
+Only argument marshalling happens here; every step runs in the HIP kernels
+of libwb.  Batched tensors are [k, B] float32, contiguous, on the robot's
+device (state index fastest), exactly as the C ABI documents.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import WbRobotDesc, WbRobotInfo, check, lib
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _chk(t: Optional[torch.Tensor], name: str, shape=None, dtype=torch.float32, device=None):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+class Robot:
+    """A robot description bound to libwb.
+
+    ``desc`` is any object with the fields of ``synth.Robot``.  The host
+    tables (validation, pair numbering) need no GPU; ``to_device`` uploads
+    the kernel tables to the current HIP device.
+    """
+
+    def __init__(self, desc):
+        f = lambda a: np.ascontiguousarray(np.asarray(a), dtype=np.float32)
+        i = lambda a: np.ascontiguousarray(np.asarray(a), dtype=np.int32)
+        L = int(np.asarray(desc.parent).shape[0])
+        S = int(np.asarray(desc.sphere_link).shape[0])
+        sph = np.concatenate([np.asarray(desc.sphere_pos, dtype=np.float64).reshape(S, 3),
+                              np.asarray(desc.sphere_r, dtype=np.float64).reshape(S, 1)], 1)
+        self._keep = dict(
+            parent=i(desc.parent), joint_type=i(desc.joint_type), joint_index=i(desc.joint_index),
+            joint_mult=f(desc.joint_mult), joint_offset=f(desc.joint_offset), axis=f(desc.axis),
+            fixed_R=f(desc.fixed_R).reshape(L, 9), fixed_p=f(desc.fixed_p), mass=f(desc.mass),
+            com=f(desc.com), inertia=f(desc.inertia).reshape(L, 9), sphere_link=i(desc.sphere_link),
+            sphere=f(sph) if S else np.zeros((1, 4), np.float32),
+        )
+        allow = getattr(desc, "allow", None)
+        self._allow = None if allow is None else np.ascontiguousarray(allow, dtype=np.uint8)
+        k = self._keep
+        fp = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        g = np.asarray(desc.gravity, dtype=np.float32)
+        self.desc = WbRobotDesc(
+            L, ip(k["parent"]), ip(k["joint_type"]), ip(k["joint_index"]), fp(k["joint_mult"]),
+            fp(k["joint_offset"]), fp(k["axis"]), fp(k["fixed_R"]), fp(k["fixed_p"]), fp(k["mass"]),
+            fp(k["com"]), fp(k["inertia"]), S, ip(k["sphere_link"]), fp(k["sphere"]),
+            self._allow.ctypes.data_as(C.POINTER(C.c_uint8)) if self._allow is not None else None,
+            (C.c_float * 3)(*g.tolist()),
+        )
+        inf = WbRobotInfo()
+        check(lib().wb_desc_analyze(C.byref(self.desc), C.byref(inf)))
+        self.n_links, self.n_dof, self.n_spheres = inf.n_links, inf.n_dof, inf.n_spheres
+        self.max_depth, self.n_pairs, self.n_blocks = inf.max_depth, inf.n_pairs, inf.n_blocks
+        self.max_spheres_per_link = inf.max_spheres_per_link
+        self.handle = None
+        self.device = None
+
+    def pairs(self) -> Tuple[np.ndarray, np.ndarray]:
+        P = self.n_pairs
+        s = np.empty(max(P, 1), np.int32)
+        t = np.empty(max(P, 1), np.int32)
+        check(lib().wb_desc_pairs(C.byref(self.desc), s.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  t.ctypes.data_as(C.POINTER(C.c_int32))))
+        return s[:P], t[:P]
+
+    def to_device(self, device=None) -> "Robot":
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        with torch.cuda.device(dev):
+            h = C.c_void_p()
+            check(lib().wb_robot_create(C.byref(self.desc), C.byref(h)))
+        self.handle, self.device = h, dev
+        return self
+
+    def workspace_bytes(self, B: int) -> int:
+        n = C.c_size_t()
+        check(lib().wb_workspace_bytes(self.handle, B, C.byref(n)))
+        return n.value
+
+    def rnea_cache_bytes(self, B: int) -> int:
+        n = C.c_size_t()
+        check(lib().wb_rnea_cache_bytes(self.handle, B, C.byref(n)))
+        return n.value
+
+    def workspace(self, B: int) -> torch.Tensor:
+        return torch.empty(max(self.workspace_bytes(B) // 4, 1), dtype=torch.float32, device=self.device)
+
+    def close(self):
+        if self.handle is not None:
+            check(lib().wb_robot_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _empty(shape, robot: Robot, dtype=torch.float32):
+    return torch.empty(shape, dtype=dtype, device=robot.device)
+
+
+# ------------------------------------------------------------------ the ABI
+
+def wb_fk(robot: Robot, q: torch.Tensor, link_pose=None, spheres=None, want_spheres=True):
+    n, B = robot.n_dof, q.shape[-1]
+    L, S = robot.n_links, robot.n_spheres
+    link_pose = _empty((L, 12, B), robot) if link_pose is None else link_pose
+    if spheres is None and want_spheres:
+        spheres = _empty((S, 3, B), robot)
+    _chk(q, "q", (n, B), device=robot.device)
+    _chk(link_pose, "link_pose", (L, 12, B), device=robot.device)
+    _chk(spheres, "spheres", (S, 3, B), device=robot.device)
+    check(lib().wb_fk(robot.handle, B, _p(q), _p(link_pose), _p(spheres), _stream()))
+    return link_pose, spheres
+
+
+def wb_rnea(robot: Robot, q, qd, qdd, tau=None, cache=None):
+    n, B, L = robot.n_dof, q.shape[-1], robot.n_links
+    tau = _empty((n, B), robot) if tau is None else tau
+    cache = _empty((L, 18, B), robot) if cache is None else cache
+    for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (tau, "tau")):
+        _chk(t, nm, (n, B), device=robot.device)
+    _chk(cache, "cache", (L, 18, B), device=robot.device)
+    check(lib().wb_rnea(robot.handle, B, _p(q), _p(qd), _p(qdd), None, _p(tau), _p(cache), _stream()))
+    return tau, cache
+
+
+def wb_self_collision(robot: Robot, spheres, max_pen=None, argmax=None, n_coll=None):
+    S, B = robot.n_spheres, spheres.shape[-1]
+    max_pen = _empty((B,), robot) if max_pen is None else max_pen
+    argmax = _empty((B,), robot, torch.int32) if argmax is None else argmax
+    n_coll = _empty((B,), robot, torch.int32) if n_coll is None else n_coll
+    _chk(spheres, "spheres", (S, 3, B), device=robot.device)
+    _chk(max_pen, "max_pen", (B,), device=robot.device)
+    _chk(argmax, "argmax", (B,), torch.int32, device=robot.device)
+    _chk(n_coll, "n_coll", (B,), torch.int32, device=robot.device)
+    check(lib().wb_self_collision(robot.handle, B, _p(spheres), _p(max_pen), _p(argmax), _p(n_coll),
+                                  _stream()))
+    return max_pen, argmax, n_coll
+
+
+def wb_self_collision_backward(robot: Robot, spheres, argmax, max_pen, margin: float, g_cost,
+                               g_spheres=None):
+    S, B = robot.n_spheres, spheres.shape[-1]
+    g_spheres = _empty((S, 3, B), robot) if g_spheres is None else g_spheres
+    _chk(spheres, "spheres", (S, 3, B), device=robot.device)
+    _chk(argmax, "argmax", (B,), torch.int32, device=robot.device)
+    _chk(max_pen, "max_pen", (B,), device=robot.device)
+    _chk(g_cost, "g_cost", (B,), device=robot.device)
+    _chk(g_spheres, "g_spheres", (S, 3, B), device=robot.device)
+    check(lib().wb_self_collision_backward(robot.handle, B, _p(spheres), _p(argmax), _p(max_pen),
+                                           float(margin), _p(g_cost), _p(g_spheres), _stream()))
+    return g_spheres
+
+
+def wb_fk_backward(robot: Robot, q, g_spheres=None, g_link_pose=None, link_pose=None, g_q=None,
+                   workspace=None):
+    n, B, L, S = robot.n_dof, q.shape[-1], robot.n_links, robot.n_spheres
+    g_q = _empty((n, B), robot) if g_q is None else g_q
+    workspace = robot.workspace(B) if workspace is None else workspace
+    _chk(q, "q", (n, B), device=robot.device)
+    _chk(g_spheres, "g_spheres", (S, 3, B), device=robot.device)
+    _chk(g_link_pose, "g_link_pose", (L, 12, B), device=robot.device)
+    _chk(link_pose, "link_pose", (L, 12, B), device=robot.device)
+    _chk(g_q, "g_q", (n, B), device=robot.device)
+    if workspace.numel() * workspace.element_size() < robot.workspace_bytes(B):
+        raise ValueError("workspace too small")
+    check(lib().wb_fk_backward(robot.handle, B, _p(q), _p(link_pose), _p(g_link_pose), _p(g_spheres),
+                               _p(g_q), _p(workspace), _stream()))
+    return g_q
+
+
+def wb_rnea_backward(robot: Robot, q, qd, qdd, cache, g_tau, g_q=None, g_qd=None, g_qdd=None,
+                     workspace=None):
+    n, B, L = robot.n_dof, q.shape[-1], robot.n_links
+    g_q = _empty((n, B), robot) if g_q is None else g_q
+    g_qd = _empty((n, B), robot) if g_qd is None else g_qd
+    g_qdd = _empty((n, B), robot) if g_qdd is None else g_qdd
+    workspace = robot.workspace(B) if workspace is None else workspace
+    for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (g_tau, "g_tau"), (g_q, "g_q"), (g_qd, "g_qd"),
+                  (g_qdd, "g_qdd")):
+        _chk(t, nm, (n, B), device=robot.device)
+    _chk(cache, "cache", (L, 18, B), device=robot.device)
+    if workspace.numel() * workspace.element_size() < robot.workspace_bytes(B):
+        raise ValueError("workspace too small")
+    check(lib().wb_rnea_backward(robot.handle, B, _p(q), _p(qd), _p(qdd), _p(cache), _p(g_tau), _p(g_q),
+                                 _p(g_qd), _p(g_qdd), _p(workspace), _stream()))
+    return g_q, g_qd, g_qdd
+
+
+def wb_cost_head(tau, w=None, torque_weight=0.0, max_pen=None, margin=0.0, hinge_weight=0.0,
+                 cost=None, g_tau=None, g_maxpen=None):
+    n, B = tau.shape
+    dev = tau.device
+    cost = torch.empty(B, dtype=torch.float32, device=dev) if cost is None else cost
+    g_tau = torch.empty_like(tau) if g_tau is None else g_tau
+    if max_pen is not None and g_maxpen is None:
+        g_maxpen = torch.empty(B, dtype=torch.float32, device=dev)
+    for t, nm, shp in ((tau, "tau", (n, B)), (w, "w", (n, B)), (max_pen, "max_pen", (B,)), (cost, "cost", (B,)),
+                       (g_tau, "g_tau", (n, B)), (g_maxpen, "g_maxpen", (B,))):
+        _chk(t, nm, shp, device=dev)
+    check(lib().wb_cost_head(B, n, _p(tau), _p(w), float(torque_weight), _p(max_pen), float(margin),
+                             float(hinge_weight), _p(cost), _p(g_tau), _p(g_maxpen), _stream()))
+    return cost, g_tau, g_maxpen
+
+
+def wb_sgd_step(lr: float, q, qd, qdd, g_q, g_qd, g_qdd, g_q2=None):
+    n, B = q.shape
+    for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (g_q, "g_q"), (g_qd, "g_qd"), (g_qdd, "g_qdd"),
+                  (g_q2, "g_q2")):
+        _chk(t, nm, (n, B), device=q.device)
+    check(lib().wb_sgd_step(B, n, float(lr), _p(q), _p(qd), _p(qdd), _p(g_q), _p(g_q2), _p(g_qd),
+                            _p(g_qdd), _stream()))
+
+
+# ------------------------------------------------------------- autograd
+
+class ForwardKinematics(torch.autograd.Function):
+    """q [n,B] -> sphere centres [S,3,B]; backward runs wb_fk_backward."""
+
+    @staticmethod
+    def forward(ctx, q, robot: Robot):
+        q = q.contiguous()
+        pose, sph = wb_fk(robot, q)
+        ctx.robot = robot
+        ctx.save_for_backward(q, pose)
+        return sph
+
+    @staticmethod
+    def backward(ctx, g_sph):
+        q, pose = ctx.saved_tensors
+        g_q = wb_fk_backward(ctx.robot, q, g_spheres=g_sph.contiguous(), link_pose=pose)
+        return g_q, None
+
+
+class SelfCollision(torch.autograd.Function):
+    """spheres [S,3,B] -> max penetration [B] (argmax and counts as extra,
+    non-differentiable outputs); the gradient flows through the argmax pair."""
+
+    @staticmethod
+    def forward(ctx, sph, robot: Robot):
+        sph = sph.contiguous()
+        mp, am, nc = wb_self_collision(robot, sph)
+        ctx.robot = robot
+        ctx.save_for_backward(sph, am, mp)
+        ctx.mark_non_differentiable(am, nc)
+        return mp, am, nc
+
+    @staticmethod
+    def backward(ctx, g_mp, g_am, g_nc):
+        sph, am, mp = ctx.saved_tensors
+        # an effectively infinite margin makes the hinge transparent: d max_pen / d spheres
+        g = wb_self_collision_backward(ctx.robot, sph, am, mp, 3.0e38, g_mp.contiguous())
+        return g, None
+
+
+class InverseDynamics(torch.autograd.Function):
+    """(q, qd, qdd) [n,B] -> tau [n,B]; backward runs wb_rnea_backward."""
+
+    @staticmethod
+    def forward(ctx, q, qd, qdd, robot: Robot):
+        q, qd, qdd = q.contiguous(), qd.contiguous(), qdd.contiguous()
+        tau, cache = wb_rnea(robot, q, qd, qdd)
+        ctx.robot = robot
+        ctx.save_for_backward(q, qd, qdd, cache)
+        return tau
+
+    @staticmethod
+    def backward(ctx, g_tau):
+        q, qd, qdd, cache = ctx.saved_tensors
+        g_q, g_qd, g_qdd = wb_rnea_backward(ctx.robot, q, qd, qdd, cache, g_tau.contiguous())
+        return g_q, g_qd, g_qdd, None
+
+
+def forward_kinematics(robot, q):
+    return ForwardKinematics.apply(q, robot)
+
+
+def self_collision(robot, spheres):
+    return SelfCollision.apply(spheres, robot)
+
+
+def inverse_dynamics(robot, q, qd, qdd):
+    return InverseDynamics.apply(q, qd, qdd, robot)

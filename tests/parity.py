@@ -1,0 +1,79 @@
+"""Helpers shared by the GPU parity tests: layout conversion, the per-state
+normwise error measure, the ambiguity band for integer decisions, and the
+oracle's composition of the whole-body iteration (FK -> self-collision ->
+hinge, RNEA -> torque cost, and their adjoints).
+
+Tolerances (FP32 device arithmetic against the FP64 oracle):
+  * every float output, per state: ||x - x_ref||_inf / max(||x_ref||_inf, floor)
+    <= 1e-4 ("1e-4 relative", read normwise per output and state);
+  * distances (sphere centres, link positions, max penetration) are scaled by
+    the state's robot extent max_s |c_s| instead, since r_s + r_t - d
+    cancels near contact;
+  * argmax pair and collision counts are exact wherever the oracle's
+    decision is farther than DELTA = 1e-5 m from a tie (about ten times the
+    FP32 position error of an 18-deep chain); counts must lie in
+    [#{pen > DELTA}, #{pen > -DELTA}].
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+TOL = 1e-4
+DELTA = 1e-5
+
+
+def dev(a_Bk: np.ndarray) -> torch.Tensor:
+    """State-major [B, ...] numpy -> device [..., B] float32 contiguous."""
+    a = np.asarray(a_Bk, dtype=np.float32)
+    return torch.from_numpy(np.ascontiguousarray(np.moveaxis(a, 0, -1))).cuda()
+
+
+def host(t: torch.Tensor) -> np.ndarray:
+    """Device [..., B] -> state-major numpy float64 [B, ...]."""
+    return np.moveaxis(t.detach().cpu().numpy().astype(np.float64), -1, 0)
+
+
+def normwise(x: np.ndarray, ref: np.ndarray, floor: float = 1e-12) -> np.ndarray:
+    B = x.shape[0]
+    d = np.abs(x - ref).reshape(B, -1).max(1)
+    s = np.maximum(np.abs(ref).reshape(B, -1).max(1), floor)
+    return d / s
+
+
+def scaled(x: np.ndarray, ref: np.ndarray, extent: np.ndarray) -> np.ndarray:
+    B = x.shape[0]
+    return np.abs(x - ref).reshape(B, -1).max(1) / np.maximum(extent, 1e-3)
+
+
+def extent(c_ref: np.ndarray) -> np.ndarray:
+    return np.linalg.norm(c_ref, axis=-1).max(-1)
+
+
+def unambiguous(pens: np.ndarray, delta: float = DELTA) -> np.ndarray:
+    """States whose maximum pair beats every other pair by at least delta."""
+    if pens.shape[1] < 2:
+        return np.ones(pens.shape[0], bool)
+    part = -np.partition(-pens, 1, axis=1)[:, :2]
+    return (part[:, 0] - part[:, 1]) >= delta
+
+
+def count_band(pens: np.ndarray, delta: float = DELTA):
+    return (pens > delta).sum(1), (pens > -delta).sum(1)
+
+
+def oracle_iteration(O, rb, q, qd, qdd, w=None, torque_weight=1e-3, margin=0.01, hinge_weight=1.0):
+    """FP64 reference of one iteration: costs and the gradient of
+    sum_b cost_b with respect to q, qd, qdd (state-major arrays)."""
+    R, p, c = O.fk(rb, q)
+    mp, am, nc = O.self_collision(rb, c)
+    tau = O.rnea(rb, q, qd, qdd)
+    g_tau = w if w is not None else 2.0 * torque_weight * tau
+    tcost = np.sum(w * tau, 1) if w is not None else torque_weight * np.sum(tau * tau, 1)
+    h = np.maximum(0.0, mp + margin)
+    cost = tcost + hinge_weight * h
+    g_c = O.self_collision_backward(rb, c, am, mp, margin, np.full(q.shape[0], hinge_weight))
+    gq_fk = O.fk_backward(rb, q, g_spheres=g_c)
+    gq, gqd, gqdd = O.rnea_vjp(rb, q, qd, qdd, g_tau)
+    return dict(R=R, p=p, c=c, max_pen=mp, argmax=am, n_coll=nc, tau=tau, cost=cost,
+                g_q=gq + gq_fk, g_q_fk=gq_fk, g_q_rnea=gq, g_qd=gqd, g_qdd=gqdd, g_spheres=g_c)

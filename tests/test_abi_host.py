@@ -1,0 +1,142 @@
+"""Host-only checks of libwb (no GPU needed): the library loads and exports
+every entry point the header declares, descriptors are validated with the
+documented error codes, and the pair numbering rebuilt from the kernels'
+link-block tables equals the oracle's lexicographic enumeration exactly."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2603_05493_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_2603_05493_amd import _abi
+    _abi.lib()
+    return _abi
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "wb.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(wb_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_exports_every_declared_symbol(abi):
+    lib = abi.lib()
+    names = _header_functions()
+    assert len(names) >= 15
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert set(abi.declared_symbols()) == set(names)
+
+
+def _robot(rb):
+    from paper_2603_05493_amd.wb import Robot
+    return Robot(rb)
+
+
+@pytest.mark.parametrize("factory", [lambda: synth.serial_chain(7, 5, seed=0),
+                                     lambda: synth.humanoid48(seed=0),
+                                     lambda: synth.random_tree(48, 6, seed=3),
+                                     lambda: synth.random_tree(23, 6, seed=2),
+                                     lambda: synth.random_tree(12, 3, seed=1)])
+def test_pair_numbering_matches_oracle(abi, oracle, factory):
+    rb = factory()
+    r = _robot(rb)
+    s, t = r.pairs()
+    so, to = oracle.pairs(rb)
+    np.testing.assert_array_equal(s, so)
+    np.testing.assert_array_equal(t, to)
+    assert r.n_pairs == len(so)
+
+
+def test_sizes_of_the_workloads(abi):
+    r = _robot(synth.humanoid48(seed=0))
+    assert (r.n_links, r.n_dof, r.n_spheres, r.max_spheres_per_link) == (49, 48, 240, 5)
+    assert r.n_pairs == 27040
+    assert [_robot(synth.random_tree(n, 6, seed=i)).n_pairs
+            for i, (n, _) in enumerate(synth.UNEVEN_TREES)] == [756, 2376, 9108, 40608]
+
+
+def test_explicit_allow_matrix(abi, oracle):
+    rb = synth.random_tree(9, 2, seed=4)
+    L = rb.n_links
+    rng = np.random.default_rng(5)
+    allow = np.triu((rng.uniform(size=(L, L)) < 0.5).astype(np.uint8), 1)
+    rb.allow = allow + allow.T
+    s, t = _robot(rb).pairs()
+    so, to = oracle.pairs(rb)
+    np.testing.assert_array_equal(s, so)
+    np.testing.assert_array_equal(t, to)
+
+
+def _expect(abi, code, mutate):
+    rb = synth.serial_chain(4, 2, seed=1)
+    mutate(rb)
+    from paper_2603_05493_amd.wb import Robot
+    with pytest.raises(abi.WbError) as e:
+        Robot(rb)
+    assert e.value.code == code, str(e.value)
+
+
+def test_rejects_bad_descriptors(abi):
+    E = abi
+    _expect(E, E.WB_ERR_INVALID_TREE, lambda rb: rb.parent.__setitem__(2, 3))      # parent after child
+    _expect(E, E.WB_ERR_INVALID_TREE, lambda rb: rb.parent.__setitem__(3, 3))      # self loop / cycle
+    _expect(E, E.WB_ERR_INVALID_TREE, lambda rb: rb.parent.__setitem__(0, 0))      # root has a parent
+    _expect(E, E.WB_ERR_INVALID_TREE, lambda rb: rb.axis.__setitem__(2, [1.0, 1.0, 0.0]))  # non-unit axis
+    _expect(E, E.WB_ERR_INVALID_TREE, lambda rb: rb.sphere_link.__setitem__(-1, 7))  # missing link
+    _expect(E, E.WB_ERR_INVALID_TREE, lambda rb: rb.sphere_link.__setitem__(0, 3))   # not sorted
+    _expect(E, E.WB_ERR_INVALID_TREE, lambda rb: rb.joint_index.__setitem__(3, 1))   # joint 2 unused
+    _expect(E, E.WB_ERR_INVALID_TREE, lambda rb: rb.joint_type.__setitem__(0, 1))    # jointed root
+    _expect(E, E.WB_ERR_INVALID_TREE, lambda rb: rb.fixed_R.__setitem__(1, 2 * np.eye(3)))
+    _expect(E, E.WB_ERR_INVALID_ARG, lambda rb: rb.sphere_r.__setitem__(0, -0.1))
+    _expect(E, E.WB_ERR_INVALID_ARG, lambda rb: rb.mass.__setitem__(1, np.nan))
+    _expect(E, E.WB_ERR_INVALID_ARG, lambda rb: rb.inertia.__setitem__(1, np.array([[1, 2, 0], [0, 1, 0], [0, 0, 1.0]])))
+
+
+def test_rejects_unsupported_sizes(abi):
+    rb = synth.serial_chain(3, 9, seed=0)                 # nine spheres on one link
+    from paper_2603_05493_amd.wb import Robot
+    with pytest.raises(abi.WbError) as e:
+        Robot(rb)
+    assert e.value.code == abi.WB_ERR_UNSUPPORTED
+
+
+def test_asymmetric_allow_rejected(abi):
+    rb = synth.serial_chain(3, 1, seed=0)
+    a = np.zeros((4, 4), np.uint8)
+    a[0, 2] = 1
+    rb.allow = a
+    from paper_2603_05493_amd.wb import Robot
+    with pytest.raises(abi.WbError) as e:
+        Robot(rb)
+    assert e.value.code == abi.WB_ERR_INVALID_ARG
+
+
+def test_null_descriptor_and_outputs(abi):
+    lib = abi.lib()
+    info = abi.WbRobotInfo()
+    assert lib.wb_desc_analyze(None, C.byref(info)) == abi.WB_ERR_INVALID_ARG
+    assert "null" in lib.wb_last_error().decode()
+    r = _robot(synth.serial_chain(2, 1))
+    assert lib.wb_desc_analyze(C.byref(r.desc), None) == abi.WB_ERR_INVALID_ARG
+    h = C.c_void_p()
+    assert lib.wb_robot_create(None, C.byref(h)) == abi.WB_ERR_INVALID_ARG
+    assert lib.wb_robot_create(C.byref(r.desc), None) == abi.WB_ERR_INVALID_ARG
+
+
+def test_launch_calls_reject_null_robot(abi):
+    lib = abi.lib()
+    assert lib.wb_fk(None, 4, None, None, None, None) == abi.WB_ERR_INVALID_ARG
+    assert lib.wb_self_collision(None, 4, None, None, None, None, None) == abi.WB_ERR_INVALID_ARG
+    assert lib.wb_cost_head(-1, 3, None, None, 0.0, None, 0.0, 0.0, None, None, None, None) == \
+        abi.WB_ERR_INVALID_ARG
+    # B = 0 with no pointers is a valid no-op for the robot-free kernels
+    assert lib.wb_sgd_step(0, 3, 0.1, None, None, None, None, None, None, None, None) == abi.WB_OK
