@@ -111,6 +111,7 @@ typedef struct wb_robot_info {
     int64_t n_pairs;          /* checked sphere pairs P */
     int32_t n_blocks;         /* checked link pairs (a < b) carrying spheres */
     int32_t max_spheres_per_link;
+    int32_t fused_supported;  /* 1 if wb_wholebody_step accepts this robot */
 } wb_robot_info;
 
 typedef struct wb_robot wb_robot;   /* opaque; owns a device copy of the tables */
@@ -216,6 +217,28 @@ int wb_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float t
  * qdd -= lr * g_qdd, all [n][B]; g_q2 may be NULL. */
 int wb_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd, const float *g_q,
                 const float *g_q2, const float *g_qd, const float *g_qdd, hipStream_t stream);
+
+/* ------------------------------------------------------ fused iteration
+ * One trajectory-optimizer iteration of the whole-body terms (Sec. 3, the
+ * six-step loop: kinematics and inverse dynamics, the self-collision cost,
+ * the backward pass through both, and the update) in a single launch:
+ *   FK (Sec. 6.1) -> self-collision (Sec. 6.2) -> RNEA (Alg. 4) -> cost head
+ *   (as wb_cost_head) -> hinge, FK and RNEA adjoints -> optional step.
+ * Nothing intermediate is written to device memory.
+ *   q, qd, qdd [n][B]  inputs; when lr != 0 they are updated in place:
+ *                      x -= lr * d(cost)/dx for x in (q, qd, qdd).
+ *   w [n][B] or NULL   torque cost weights (NULL: torque_weight * ||tau||^2).
+ *   tau [n][B], cost [B], max_pen [B], argmax [B], n_coll [B],
+ *   g_q, g_qd, g_qdd [n][B]   optional outputs (NULL to skip); the gradients
+ *                      are those of cost[b] (FK through the hinge plus RNEA),
+ *                      evaluated before the step.
+ * Results agree with the separate calls (same definitions, same tolerance;
+ * floating-point sums are ordered differently).  Needs n_links <= 64 and
+ * no mimic joints (wb_robot_info.fused_supported), else WB_ERR_UNSUPPORTED. */
+int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, float *qdd, const float *w,
+                      float torque_weight, float margin, float hinge_weight, float lr, float *tau,
+                      float *cost, float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q,
+                      float *g_qd, float *g_qdd, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,7 @@ class WbRobotInfo(C.Structure):
     _fields_ = [
         ("n_links", C.c_int32), ("n_dof", C.c_int32), ("n_spheres", C.c_int32),
         ("max_depth", C.c_int32), ("n_pairs", C.c_int64), ("n_blocks", C.c_int32),
-        ("max_spheres_per_link", C.c_int32),
+        ("max_spheres_per_link", C.c_int32), ("fused_supported", C.c_int32),
     ]
 
 
@@ -63,6 +63,8 @@ _SIGS = {
     "wb_cost_head": [C.c_int64, C.c_int32, _vp, _vp, C.c_float, _vp, C.c_float, C.c_float, _vp, _vp,
                      _vp, _vp],
     "wb_sgd_step": [C.c_int64, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "wb_wholebody_step": [_vp, C.c_int64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float,
+                          _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
 }
 
 _lib = None

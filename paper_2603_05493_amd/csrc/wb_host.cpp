@@ -41,12 +41,63 @@ struct Tables {
     std::vector<int32_t> pair_off, pair_cnt, pair_s, pair_t;
     int64_t n_pairs = 0;
     float g[3] = {0, 0, 0};
+    // fused-kernel lane tables (depth-first lane order)
+    int fused = 0, jsteps = 0;
+    std::vector<int32_t> f_li;
+    std::vector<float> f_lf;
+    std::vector<float4> f_sph;
 };
 
 bool finite_all(const float *p, size_t n) {
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(p[i])) return false;
     return true;
+}
+
+// Lane tables of the fused kernel: links in depth-first pre-order so every
+// subtree is a contiguous lane range.
+void build_fused(Tables &T) {
+    const int L = T.L;
+    T.fused = 0;
+    if (L > 64 || !T.simple) return;
+    std::vector<std::vector<int>> kids(L);
+    for (int k = 1; k < L; ++k) kids[T.li[k].parent].push_back(k);
+    std::vector<int> perm, stack{0};
+    while (!stack.empty()) {
+        const int k = stack.back();
+        stack.pop_back();
+        perm.push_back(k);
+        for (auto it = kids[k].rbegin(); it != kids[k].rend(); ++it) stack.push_back(*it);
+    }
+    std::vector<int> lane_of(L), size(L, 1);
+    for (int i = 0; i < L; ++i) lane_of[perm[i]] = i;
+    for (int k = L - 1; k >= 1; --k) size[T.li[k].parent] += size[k];
+    T.f_li.assign(8 * 64, 0);
+    T.f_lf.assign(25 * 64, 0.0f);
+    T.f_sph.assign((size_t)WB_MAX_SPHERES_PER_LINK * 64, make_float4(0, 0, 0, 0));
+    for (int i = 0; i < L; ++i) {
+        const int k = perm[i];
+        const wb::LinkI &I = T.li[k];
+        const wb::LinkF &F = T.lf[k];
+        T.f_li[0 * 64 + i] = k;
+        T.f_li[1 * 64 + i] = k == 0 ? -1 : lane_of[I.parent];
+        T.f_li[2 * 64 + i] = i + size[k] - 1;
+        T.f_li[3 * 64 + i] = I.jidx;
+        T.f_li[4 * 64 + i] = I.sph_count;
+        T.f_li[5 * 64 + i] = I.revolute;
+        T.f_li[6 * 64 + i] = I.fR_identity;
+        for (int c = 0; c < 3; ++c) T.f_lf[(0 + c) * 64 + i] = F.axis[c];
+        for (int c = 0; c < 9; ++c) T.f_lf[(3 + c) * 64 + i] = k == 0 ? (c % 4 == 0 ? 1.0f : 0.0f) : F.fR[c];
+        for (int c = 0; c < 3; ++c) T.f_lf[(12 + c) * 64 + i] = k == 0 ? 0.0f : F.fp[c];
+        T.f_lf[15 * 64 + i] = F.mass;
+        for (int c = 0; c < 3; ++c) T.f_lf[(16 + c) * 64 + i] = F.com[c];
+        for (int c = 0; c < 6; ++c) T.f_lf[(19 + c) * 64 + i] = F.I[c];
+        for (int j = 0; j < I.sph_count; ++j) T.f_sph[(size_t)j * 64 + i] = T.sph[I.sph_first + j];
+    }
+    int js = 0;
+    while ((1 << js) < T.max_depth + 1) ++js;
+    T.jsteps = js;
+    T.fused = 1;
 }
 
 int build_tables(const wb_robot_desc *d, Tables &T) {
@@ -229,6 +280,7 @@ int build_tables(const wb_robot_desc *d, Tables &T) {
             }
     }
     for (int c = 0; c < 3; ++c) T.g[c] = d->gravity[c];
+    build_fused(T);
     return WB_OK;
 }
 
@@ -240,6 +292,7 @@ void fill_info(const Tables &T, wb_robot_info *info) {
     info->n_pairs = T.n_pairs;
     info->n_blocks = T.n_blocks;
     info->max_spheres_per_link = T.nmax;
+    info->fused_supported = T.fused;
 }
 
 bool aligned4(const void *p) { return ((uintptr_t)p & 3) == 0; }
@@ -249,6 +302,7 @@ bool aligned4(const void *p) { return ((uintptr_t)p & 3) == 0; }
 struct wb_robot {
     Tables T;
     wb::DevRobot dev{};
+    wb::DevFused fz{};
     void *dmem = nullptr;
     int device = -1;
 };
@@ -328,6 +382,7 @@ int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
     const size_t o_sr = append(blob, T.slot_r), o_bl = append(blob, T.blocks);
     const size_t o_po = append(blob, T.pair_off), o_pc = append(blob, T.pair_cnt);
     const size_t o_ps = append(blob, T.pair_s), o_pt = append(blob, T.pair_t);
+    const size_t o_fi = append(blob, T.f_li), o_ff = append(blob, T.f_lf), o_fs = append(blob, T.f_sph);
     blob.resize(blob.size() + 256);
     hipError_t e = hipGetDevice(&r->device);
     if (e == hipSuccess) e = hipMalloc(&r->dmem, blob.size());
@@ -355,6 +410,12 @@ int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
     D.pair_cnt = reinterpret_cast<const int32_t *>(base + o_pc);
     D.pair_s = reinterpret_cast<const int32_t *>(base + o_ps);
     D.pair_t = reinterpret_cast<const int32_t *>(base + o_pt);
+    wb::DevFused &Fz = r->fz;
+    Fz.supported = T.fused;
+    Fz.jsteps = T.jsteps;
+    Fz.li = reinterpret_cast<const int32_t *>(base + o_fi);
+    Fz.lf = reinterpret_cast<const float *>(base + o_ff);
+    Fz.lsph = reinterpret_cast<const float4 *>(base + o_fs);
     *out = r;
     return WB_OK;
 }
@@ -421,8 +482,8 @@ int wb_self_collision(const wb_robot *robot, int64_t B, const float *spheres, fl
                       int32_t *argmax, int32_t *n_coll, hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
-    if (!max_pen && !argmax && !n_coll) return fail(WB_ERR_INVALID_ARG, "all outputs are null");
     if (B == 0) return WB_OK;
+    if (!max_pen && !argmax && !n_coll) return fail(WB_ERR_INVALID_ARG, "all outputs are null");
     WB_TRY(check_ptr(spheres, "spheres", robot->T.S > 0));
     WB_TRY(check_ptr(max_pen, "max_pen", false));
     WB_TRY(check_ptr(argmax, "argmax", false));
@@ -453,8 +514,8 @@ int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float
                    hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
-    if (!g_link_pose && !g_spheres) return fail(WB_ERR_INVALID_ARG, "both gradient inputs are null");
     if (B == 0) return WB_OK;
+    if (!g_link_pose && !g_spheres) return fail(WB_ERR_INVALID_ARG, "both gradient inputs are null");
     WB_TRY(check_ptr(q, "q", robot->T.n > 0));
     WB_TRY(check_ptr(link_pose, "link_pose", false));
     WB_TRY(check_ptr(g_link_pose, "g_link_pose", false));
@@ -520,6 +581,43 @@ int wb_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd,
     WB_TRY(check_ptr(g_qd, "g_qd", true));
     WB_TRY(check_ptr(g_qdd, "g_qdd", true));
     return finish(wb::launch_sgd_step(B, n, lr, q, qd, qdd, g_q, g_q2, g_qd, g_qdd, stream), "wb_sgd_step launch");
+}
+
+int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, float *qdd, const float *w,
+                      float torque_weight, float margin, float hinge_weight, float lr, float *tau, float *cost,
+                      float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q, float *g_qd, float *g_qdd,
+                      hipStream_t stream) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    if (!robot->fz.supported)
+        return fail(WB_ERR_UNSUPPORTED, "the fused iteration needs <= 64 links and no mimic joints");
+    if (!std::isfinite(torque_weight) || !std::isfinite(margin) || !std::isfinite(hinge_weight) || !std::isfinite(lr))
+        return fail(WB_ERR_INVALID_ARG, "weights, margin and lr must be finite");
+    if (B == 0) return WB_OK;
+    const bool need = robot->T.n > 0;
+    WB_TRY(check_ptr(q, "q", need));
+    WB_TRY(check_ptr(qd, "qd", need));
+    WB_TRY(check_ptr(qdd, "qdd", need));
+    WB_TRY(check_ptr(w, "w", false));
+    WB_TRY(check_ptr(tau, "tau", false));
+    WB_TRY(check_ptr(cost, "cost", false));
+    WB_TRY(check_ptr(max_pen, "max_pen", false));
+    WB_TRY(check_ptr(argmax, "argmax", false));
+    WB_TRY(check_ptr(n_coll, "n_coll", false));
+    WB_TRY(check_ptr(g_q, "g_q", false));
+    WB_TRY(check_ptr(g_qd, "g_qd", false));
+    WB_TRY(check_ptr(g_qdd, "g_qdd", false));
+    wb::FusedArgs a{};
+    a.rb = robot->dev;
+    a.fz = robot->fz;
+    a.B = B;
+    a.chunk = 16;
+    a.jsteps = robot->fz.jsteps;
+    a.q = q; a.qd = qd; a.qdd = qdd; a.w = w;
+    a.torque_weight = torque_weight; a.margin = margin; a.hinge_weight = hinge_weight; a.lr = lr;
+    a.tau = tau; a.cost = cost; a.max_pen = max_pen; a.argmax = argmax; a.n_coll = n_coll;
+    a.g_q = g_q; a.g_qd = g_qd; a.g_qdd = g_qdd;
+    return finish(wb::launch_fused(a, stream), "wb_wholebody_step launch");
 }
 
 }  // extern "C"

@@ -53,6 +53,38 @@ struct DevRobot {
     const int32_t *__restrict__ pair_t;   // [P]
 };
 
+// Per-lane tables of the fused kernel: lane i holds link perm[i] in
+// depth-first pre-order.  Structure of arrays, 64 entries per field.
+//   li[f*64 + i]: f = 0 link, 1 parent lane (-1 root), 2 last lane of the
+//                 subtree, 3 joint index (-1 fixed), 4 sphere count,
+//                 5 revolute, 6 fixed rotation is the identity
+//   lf[f*64 + i]: f = 0..2 axis, 3..11 fixed R, 12..14 fixed p, 15 mass,
+//                 16..18 CoM, 19..24 inertia (xx yy zz xy xz yz)
+//   lsph[j*64 + i]: local centre and radius of the link's j-th sphere
+struct DevFused {
+    int32_t supported;   // L <= 64 and one link per actuated joint without mimic scaling
+    int32_t jsteps;      // pointer-jumping steps, ceil(log2(max_depth + 1))
+    const int32_t *__restrict__ li;
+    const float *__restrict__ lf;
+    const float4 *__restrict__ lsph;
+};
+
+// Arguments of the fused iteration kernel (by value).
+struct FusedArgs {
+    DevRobot rb;
+    DevFused fz;
+    int64_t B;
+    int32_t chunk, jsteps;        // states per workgroup, pointer-jumping steps
+    float *q, *qd, *qdd;          // [n][B], updated in place when lr != 0
+    const float *w;               // [n][B] or null
+    float torque_weight, margin, hinge_weight, lr;
+    float *tau, *cost, *max_pen;
+    int32_t *argmax, *n_coll;
+    float *g_q, *g_qd, *g_qdd;
+};
+
+hipError_t launch_fused(const FusedArgs &a, hipStream_t s);
+
 // Kernel launchers (each defined next to its kernels).
 hipError_t launch_fk(const DevRobot &rb, int64_t B, const float *q, float *pose, float *spheres,
                      hipStream_t s);

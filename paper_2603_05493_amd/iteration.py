@@ -12,8 +12,9 @@ module runs the whole-body part of that loop on a batch of B states:
     optional gradient step on (q, qd, qdd)
 
 ``PlainIteration`` issues one launch per operation through the C ABI (the
-"plain launch" form); every buffer is allocated once, so ``run`` can be
-captured into a HIP graph with ``torch.cuda.graph``.
+"plain launch" form); ``FusedIteration`` runs the same iteration as one
+kernel (``wb_wholebody_step``).  Every buffer is allocated once, so ``run``
+can be captured into a HIP graph with ``torch.cuda.graph``.
 """
 from __future__ import annotations
 
@@ -56,3 +57,28 @@ class PlainIteration:
                             self.workspace)
         if step and self.lr != 0.0:
             wb.wb_sgd_step(self.lr, q, qd, qdd, self.g_q, self.g_qd, self.g_qdd, g_q2=self.g_q_fk)
+
+
+class FusedIteration:
+    """The iteration as a single launch; same costs, gradients and step."""
+
+    def __init__(self, robot: wb.Robot, B: int, w: Optional[torch.Tensor] = None,
+                 torque_weight: float = 1e-3, margin: float = 0.01, hinge_weight: float = 1.0,
+                 lr: float = 0.0, outputs: bool = True):
+        if not robot.fused_supported:
+            raise ValueError("robot not supported by the fused iteration (needs <= 64 links, no mimic joints)")
+        self.robot, self.B = robot, B
+        self.w, self.tw, self.margin, self.hw, self.lr = w, torque_weight, margin, hinge_weight, lr
+        n = robot.n_dof
+        e = lambda *shape, dt=torch.float32: torch.empty(shape, dtype=dt, device=robot.device)
+        self.cost, self.max_pen = e(B), e(B)
+        self.argmax, self.n_coll = e(B, dt=torch.int32), e(B, dt=torch.int32)
+        self.tau = e(n, B) if outputs else None
+        self.g_q = e(n, B) if outputs else None
+        self.g_qd = e(n, B) if outputs else None
+        self.g_qdd = e(n, B) if outputs else None
+
+    def run(self, q: torch.Tensor, qd: torch.Tensor, qdd: torch.Tensor, step: bool = True) -> None:
+        wb.wb_wholebody_step(self.robot, q, qd, qdd, self.w, self.tw, self.margin, self.hw,
+                             self.lr if step else 0.0, self.tau, self.cost, self.max_pen, self.argmax,
+                             self.n_coll, self.g_q, self.g_qd, self.g_qdd)

@@ -211,9 +211,10 @@ def serial_chain(n_dof: int = 7, spheres_per_link: int = 5, seed: int = 0,
 
 def random_tree(n_dof: int, spheres_per_link: int = 6, seed: int = 0,
                 min_children: int = 1, max_children: int = 3,
-                random_fixed_rotation: bool = False) -> Robot:
+                random_fixed_rotation: bool = False, dfs_order: bool = True) -> Robot:
     """Random tree: breadth-first growth, each node taking 1-3 children, then
-    renumbered in depth-first pre-order.  Geometry and inertia as the chain."""
+    renumbered in depth-first pre-order (or kept in breadth-first order).
+    Geometry and inertia as the chain."""
     rng = np.random.default_rng(seed)
     parent_bfs = [-1]
     frontier = [0]
@@ -227,7 +228,7 @@ def random_tree(n_dof: int, spheres_per_link: int = 6, seed: int = 0,
                 parent_bfs.append(node)
                 nxt.append(len(parent_bfs) - 1)
         frontier = nxt if nxt else [len(parent_bfs) - 1]
-    order = _dfs_preorder(parent_bfs)
+    order = _dfs_preorder(parent_bfs) if dfs_order else list(range(len(parent_bfs)))
     new_of = {old: i for i, old in enumerate(order)}
     parent = [-1] + [new_of[parent_bfs[old]] for old in order[1:]]
     L = n_dof + 1
@@ -334,6 +335,22 @@ def humanoid48(seed: int = 0, n_spheres: int = 240) -> Robot:
         sr.append(r)
     return _finish("humanoid48", seed, parent, axis, fixed_R, fixed_p, mass, com, inertia,
                    sl, np.concatenate(sp), np.concatenate(sr))
+
+
+def with_fixed_links(rb: Robot, links) -> Robot:
+    """Turn the given links' joints into fixed joints (actuated indices renumbered)."""
+    fixed = set(int(k) for k in links)
+    jt = rb.joint_type.copy()
+    ji = np.full_like(rb.joint_index, -1)
+    nxt = 0
+    for k in range(rb.n_links):
+        if k in fixed or k == 0:
+            jt[k] = JOINT_FIXED
+        else:
+            ji[k] = nxt
+            nxt += 1
+    rb.joint_type, rb.joint_index = jt, ji
+    return rb
 
 
 def planar_2r(l1: float = 0.5, l2: float = 0.4, m1: float = 1.0, m2: float = 0.7,

@@ -81,6 +81,7 @@ class Robot:
         self.n_links, self.n_dof, self.n_spheres = inf.n_links, inf.n_dof, inf.n_spheres
         self.max_depth, self.n_pairs, self.n_blocks = inf.max_depth, inf.n_pairs, inf.n_blocks
         self.max_spheres_per_link = inf.max_spheres_per_link
+        self.fused_supported = bool(inf.fused_supported)
         self.handle = None
         self.device = None
 
@@ -241,6 +242,25 @@ def wb_sgd_step(lr: float, q, qd, qdd, g_q, g_qd, g_qdd, g_q2=None):
         _chk(t, nm, (n, B), device=q.device)
     check(lib().wb_sgd_step(B, n, float(lr), _p(q), _p(qd), _p(qdd), _p(g_q), _p(g_q2), _p(g_qd),
                             _p(g_qdd), _stream()))
+
+
+def wb_wholebody_step(robot: Robot, q, qd, qdd, w=None, torque_weight=0.0, margin=0.0, hinge_weight=0.0,
+                      lr=0.0, tau=None, cost=None, max_pen=None, argmax=None, n_coll=None, g_q=None,
+                      g_qd=None, g_qdd=None):
+    """One fused iteration (FK, self-collision, RNEA, cost head, adjoints,
+    optional in-place step on q, qd, qdd).  Outputs left as None are skipped."""
+    n, B = robot.n_dof, q.shape[-1]
+    for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (w, "w"), (tau, "tau"), (g_q, "g_q"), (g_qd, "g_qd"),
+                  (g_qdd, "g_qdd")):
+        _chk(t, nm, (n, B), device=robot.device)
+    _chk(cost, "cost", (B,), device=robot.device)
+    _chk(max_pen, "max_pen", (B,), device=robot.device)
+    _chk(argmax, "argmax", (B,), torch.int32, device=robot.device)
+    _chk(n_coll, "n_coll", (B,), torch.int32, device=robot.device)
+    check(lib().wb_wholebody_step(robot.handle, B, _p(q), _p(qd), _p(qdd), _p(w), float(torque_weight),
+                                  float(margin), float(hinge_weight), float(lr), _p(tau), _p(cost),
+                                  _p(max_pen), _p(argmax), _p(n_coll), _p(g_q), _p(g_qd), _p(g_qdd),
+                                  _stream()))
 
 
 # ------------------------------------------------------------- autograd

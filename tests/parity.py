@@ -62,6 +62,37 @@ def count_band(pens: np.ndarray, delta: float = DELTA):
     return (pens > delta).sum(1), (pens > -delta).sum(1)
 
 
+def cost_scale(ref, w, torque_weight, margin, floor=1e-3):
+    """Magnitude the FP32 cost is accumulated from: sum |w tau| (or c tau^2) + hinge."""
+    tau = ref["tau"]
+    t = np.abs(w * tau).sum(1) if w is not None else torque_weight * (tau * tau).sum(1)
+    return np.maximum(t + np.maximum(0.0, ref["max_pen"] + margin), floor)
+
+
+def fk_grad_floor(ref, hinge_weight=1.0):
+    """Floor for the hinge's FK gradient: 1 % of the magnitude of the terms it
+    sums (extent x hinge weight).  For joints above both spheres of the pair
+    the exact gradient is zero (the force is along the pair's centre line), so
+    FP32 leaves rounding noise of order eps * |c| * |g| there."""
+    return 1e-2 * float(np.median(extent(ref["c"]))) * hinge_weight
+
+
+HINGE_D0 = 1e-2   # m: below this pair distance the hinge direction is ill-conditioned
+
+
+def hinge_conditioning(ref, rb):
+    """Amplification of centre errors into the hinge direction, HINGE_D0 / d at the argmax pair."""
+    from oracle import oracle as O
+    s, t = O.pairs(rb)
+    am = ref["argmax"]
+    c = ref["c"]
+    cond = np.ones(len(am))
+    for b in np.where(am >= 0)[0]:
+        d = np.linalg.norm(c[b, s[am[b]]] - c[b, t[am[b]]])
+        cond[b] = HINGE_D0 / max(d, 1e-9)
+    return cond
+
+
 def oracle_iteration(O, rb, q, qd, qdd, w=None, torque_weight=1e-3, margin=0.01, hinge_weight=1.0):
     """FP64 reference of one iteration: costs and the gradient of
     sum_b cost_b with respect to q, qd, qdd (state-major arrays)."""

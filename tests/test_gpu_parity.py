@@ -148,9 +148,15 @@ def _check_iteration(O, rb, st, label, w=None, torque_weight=1e-3, margin=0.01, 
     pens = O.self_collision_pens(rb, ref["c"])
     ok = P.unambiguous(pens) & (np.abs(ref["max_pen"] + margin) >= P.DELTA)
     g = lambda t: sub(P.host(t))
-    e_cost = P.normwise(g(it.cost)[:, None], ref["cost"][:, None], floor=1e-3)[ok].max()
+    cscale = P.cost_scale(ref, w, torque_weight, margin)
+    e_cost = (np.abs(g(it.cost) - ref["cost"]) / cscale)[ok].max()
     e_gq = P.normwise(g(it.g_q) + g(it.g_q_fk), ref["g_q"], floor=1e-6)[ok].max()
-    e_gqfk = P.normwise(g(it.g_q_fk), ref["g_q_fk"], floor=1e-6)[ok].max()
+    # the hinge direction u = (c_s - c_t)/d carries FP32 position error / d
+    cond = P.hinge_conditioning(ref, rb)
+    e_gqfk_all = P.normwise(g(it.g_q_fk), ref["g_q_fk"], floor=P.fk_grad_floor(ref))
+    well = ok & (cond <= 1.0)
+    e_gqfk = e_gqfk_all[well].max() if well.any() else 0.0
+    assert np.all(e_gqfk_all[ok] <= P.TOL * np.maximum(cond[ok], 1.0))
     e_gqd = P.normwise(g(it.g_qd), ref["g_qd"], floor=1e-6).max()
     e_gqdd = P.normwise(g(it.g_qdd), ref["g_qdd"], floor=1e-6).max()
     _log(label + " fwd+bwd", e_cost=e_cost, e_gq=e_gq, e_gq_fk=e_gqfk, e_gqd=e_gqd, e_gqdd=e_gqdd,
