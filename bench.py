@@ -33,6 +33,24 @@ PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3   # needs packed FP32, which this build disables
 
 
+# HBM traffic of the fused kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# (profiles/k_fused_step_humanoid48_B24576_hbm_counters.md), scaled by a copy
+# calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
+# it was measured with; reported as null once they change.
+TRAFFIC_MEASURED = {"sources_sha1": "55235200a7b39c95ebaaac392d8c2e90d09464a5", "states": 24576,
+                    "bytes_per_launch": 28606.8 * 1024}
+FUSED_SOURCES = ("fused.hip", "sweep.h", "spatial.h", "wb_internal.h")
+
+
+def fused_sources_sha1() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in FUSED_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_05493_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def algorithmic_flop_per_state(L: int, S: int, P: int, n: int) -> float:
     """Work model of one iteration per state (FMA = 2 FLOP): FK 135/link +
     18/sphere; pair sweep 11/pair; RNEA 290/link; VJP 860/link with
@@ -51,6 +69,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="fused_graph,plain_graph,plain")
+    ap.add_argument("--no-uneven", dest="uneven", action="store_false",
+                    help="skip the uneven multi-tree batch measurement")
     return ap.parse_args()
 
 
@@ -86,6 +106,8 @@ def main():
     rb = synth.humanoid48(seed=0)
     st = synth.states(rb, B, seed=1, q_range=1.5)
     robot = wb.Robot(rb).to_device("cuda:0")
+    from paper_2603_05493_amd import tune
+    tune.apply(robot, tune.load())
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a.T.astype(np.float32))).cuda()
     q0, qd0, qdd0 = d(st.q), d(st.qd), d(st.qdd)
     lr = 1e-3
@@ -142,10 +164,10 @@ def main():
         return dt, kernel_ms
 
     for form in forms:
-        if form == "plain":
-            res[form] = timed_eager(form)[0]
-        else:
+        if form.endswith("_graph"):
             res[form] = timed_graph(form)
+        else:
+            res[form] = timed_eager(form)[0]
     fused_ms = None
     if robot.fused_supported and any(f.startswith("fused") for f in forms):
         _, fused_ms = timed_eager("fused", events=True)
@@ -175,14 +197,82 @@ def main():
         out["speedup_vs_plain_launch"] = res["plain"] / res[head]
     if fused_ms is not None:
         achieved = flop / (fused_ms * 1e-3) / 1e12
+        traffic = None
+        if fused_sources_sha1() == TRAFFIC_MEASURED["sources_sha1"] and B == TRAFFIC_MEASURED["states"]:
+            traffic = TRAFFIC_MEASURED["bytes_per_launch"]
+        alg_bytes = B * (6 * 4 * n + 16)
         out["roofline"] = {"bound": "alu", "kernel": "k_fused_step", "achieved": achieved,
                            "peak": PEAK_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / PEAK_FP32_NONPACKED_TFLOPS,
                            "frac_of_published_packed_peak": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
-                           "kernel_ms": fused_ms, "flop_per_launch": flop, "traffic": None}
+                           "kernel_ms": fused_ms, "flop_per_launch": flop, "traffic": traffic,
+                           "algorithmic_bytes_per_launch": alg_bytes,
+                           "hbm_gbps_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9}
+    if args.uneven:
+        out["uneven_batch"] = bench_uneven(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(rb, st, args.cpu_sample)
     print(json.dumps(out))
+
+
+def bench_uneven(args):
+    """Random trees of 7/12/23/48 DoF with 8192/4096/2048/1024 states: one
+    persistent plan launch (tuned shapes) replayed from a HIP graph, against
+    one plain launch sequence per tree."""
+    import torch
+    from paper_2603_05493_amd import synth, tune, wb
+    from paper_2603_05493_amd.iteration import PlainIteration, PlanIteration
+
+    jobs = synth.uneven_trees(seed=0)
+    table = tune.load()
+    robots, states = [], []
+    for i, (rb, B) in enumerate(jobs):
+        r = wb.Robot(rb).to_device("cuda:0")
+        tune.apply(r, table)
+        robots.append(r)
+        st = synth.states(rb, B, seed=10 + i)
+        d = lambda a: torch.from_numpy(np.ascontiguousarray(a.T.astype(np.float32))).cuda()
+        states.append((d(st.q), d(st.qd), d(st.qdd)))
+    Bs = [B for _, B in jobs]
+    total = sum(Bs)
+    kw = dict(torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=0.0)
+
+    plan = PlanIteration(robots, Bs, outputs=False, **kw)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.run(states)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run(states)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_plan = (time.perf_counter() - t0) / args.steps
+
+    plains = [PlainIteration(r, B, **kw) for r, B in zip(robots, Bs)]
+    for _ in range(args.warmup):
+        for it, s in zip(plains, states):
+            it.run(*s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for it, s in zip(plains, states):
+            it.run(*s)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.steps
+    return {"trees": [f"{rb.name}x{B}" for rb, B in jobs], "states": total,
+            "plan_graph": {"states_per_s": total / t_plan, "ms_per_step": t_plan * 1e3,
+                           "items": plan.plan.n_items, "workgroups": plan.plan.n_workgroups},
+            "plain_per_tree": {"states_per_s": total / t_plain, "ms_per_step": t_plain * 1e3},
+            "speedup": t_plain / t_plan,
+            "shapes": [r.get_tune() for r in robots]}
 
 
 if __name__ == "__main__":

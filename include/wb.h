@@ -240,6 +240,55 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, flo
                       float *cost, float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q,
                       float *g_qd, float *g_qdd, hipStream_t stream);
 
+/* Launch shape of the fused iteration for one robot (the paper dispatches
+ * FK differently by robot size, Sec. 6.1 "adaptive kernel dispatch"; here the
+ * shape is a per-topology tuning record, chosen by measurement).
+ *   lanes_per_state  16, 32 or 64 lanes of a 64-wide wavefront per state
+ *                    (>= the robot's links); 64 / lanes_per_state states run
+ *                    side by side in one wavefront.
+ *   states_per_item  states per workgroup work item (1..4096).
+ *   ns_per_state     measured cost of one state, used to balance uneven
+ *                    batches (0 = use the built-in cost model).
+ * wb_robot_create sets a default; wb_robot_set_tune validates and replaces it
+ * (WB_ERR_INVALID_ARG for an invalid shape). */
+typedef struct wb_tune {
+    int32_t lanes_per_state;
+    int32_t states_per_item;
+    float ns_per_state;
+} wb_tune;
+int wb_robot_set_tune(wb_robot *robot, const wb_tune *tune);
+int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune);
+
+/* ------------------------------------------------ uneven multi-robot batches
+ * A plan runs the fused iteration for several robots, each with its own
+ * batch size, in one persistent launch (suitable for HIP graph capture; the
+ * paper captures its whole iteration in CUDA graphs, Sec. 7.2).  The plan
+ * owns a static work list of (robot, state range) items balanced over the
+ * workgroups by cost (longest first), using each robot's tune record.
+ *   wb_plan_create: robots[n_trees] (created on one device, each
+ *     fused_supported), B[n_trees] states per robot, tune[n_trees] or NULL
+ *     (each robot's current record); 1 <= n_trees <= 16.  Allocates the
+ *     plan's device tables; the plan does not own the robots, which must
+ *     outlive it.  WB_ERR_UNSUPPORTED if the LDS of a workgroup would exceed
+ *     64 KB.
+ *   wb_plan_run: io[n_trees] holds each robot's device buffers with the
+ *     meaning and layout of wb_wholebody_step; the scalars are shared.
+ *     Never allocates or synchronizes. */
+typedef struct wb_tree_io {
+    float *q, *qd, *qdd;
+    const float *w;
+    float *tau, *cost, *max_pen;
+    int32_t *argmax, *n_coll;
+    float *g_q, *g_qd, *g_qdd;
+} wb_tree_io;
+typedef struct wb_plan wb_plan;
+int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_trees, const wb_tune *tune,
+                   wb_plan **out);
+int wb_plan_run(const wb_plan *plan, const wb_tree_io *io, float torque_weight, float margin,
+                float hinge_weight, float lr, hipStream_t stream);
+int wb_plan_get_info(const wb_plan *plan, int32_t *n_items, int32_t *n_workgroups);
+int wb_plan_destroy(wb_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,15 @@ class WbRobotInfo(C.Structure):
     ]
 
 
+class WbTune(C.Structure):
+    _fields_ = [("lanes_per_state", C.c_int32), ("states_per_item", C.c_int32), ("ns_per_state", C.c_float)]
+
+
+class WbTreeIO(C.Structure):
+    _fields_ = [(nm, _vp) for nm in ("q", "qd", "qdd", "w", "tau", "cost", "max_pen", "argmax", "n_coll",
+                                     "g_q", "g_qd", "g_qdd")]
+
+
 class WbError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"wb error {code}: {msg}")
@@ -65,6 +74,12 @@ _SIGS = {
     "wb_sgd_step": [C.c_int64, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "wb_wholebody_step": [_vp, C.c_int64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float,
                           _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "wb_robot_set_tune": [_vp, C.POINTER(WbTune)],
+    "wb_robot_get_tune": [_vp, C.POINTER(WbTune)],
+    "wb_plan_create": [C.POINTER(_vp), C.POINTER(C.c_int64), C.c_int32, C.POINTER(WbTune), C.POINTER(_vp)],
+    "wb_plan_run": [_vp, C.POINTER(WbTreeIO), C.c_float, C.c_float, C.c_float, C.c_float, _vp],
+    "wb_plan_get_info": [_vp, _i32p, _i32p],
+    "wb_plan_destroy": [_vp],
 }
 
 _lib = None

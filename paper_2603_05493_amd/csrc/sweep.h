@@ -115,6 +115,63 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const float4 *P,
     cnt_out = cnt;
 }
 
+// The same sweep by a group of G < 64 lanes (64/G states per wavefront).
+// Blocks are dealt to the group's lanes; the pair count is a per-lane
+// counter summed over the group at the end.
+template <int NMAX>
+__device__ __forceinline__ void sweep_group(const DevRobot &rb, const float4 *P, int glane, int G, float &M_out,
+                                            int &key_out, unsigned &cnt_out) {
+    float best = -INFINITY;
+    int best_blk = -1;
+    bool tie = false;
+    unsigned cnt = 0;
+    const int nb = (rb.n_blocks + G - 1) / G * G;
+    for (int base = 0; base < nb; base += G) {
+        const int blk = base + glane;
+        const int ab = rb.blocks[blk];
+        const int a = ab >> 16, bb = ab & 0xffff;
+        float4 A[NMAX], Bv[NMAX];
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+            A[i] = P[a * NMAX + i];
+            Bv[i] = P[bb * NMAX + i];
+        }
+        float m = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i)
+#pragma unroll
+            for (int j = 0; j < NMAX; ++j) {
+                const float pen = pair_pen(A[i], Bv[j]);
+                m = fmaxf(m, pen);
+                cnt += pen > 0.0f ? 1u : 0u;
+            }
+        if (m > best) {
+            best = m;
+            best_blk = blk;
+            tie = false;
+        } else if (m == best) {
+            tie = true;
+        }
+    }
+    float M = best;
+    for (int o = G >> 1; o > 0; o >>= 1) M = fmaxf(M, __shfl_xor(M, o, G));
+    int key = INT_MAX;
+    if (best == M && M > -INFINITY) {
+        if (!tie) {
+            key = block_min_key<NMAX>(rb, P, best_blk, M);
+        } else {
+            for (int blk = glane; blk < nb; blk += G) key = min(key, block_min_key<NMAX>(rb, P, blk, M));
+        }
+    }
+    for (int o = G >> 1; o > 0; o >>= 1) {
+        key = min(key, __shfl_xor(key, o, G));
+        cnt += __shfl_xor(cnt, o, G);
+    }
+    M_out = M;
+    key_out = key;
+    cnt_out = cnt;
+}
+
 // Pair index (lexicographic in (s, t)) of a sphere key s*S + t.
 __device__ __forceinline__ int32_t pair_index(const DevRobot &rb, int key) {
     if (key == INT_MAX) return -1;

@@ -3,6 +3,7 @@
 #include "wb.h"
 #include "wb_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -303,9 +304,35 @@ struct wb_robot {
     Tables T;
     wb::DevRobot dev{};
     wb::DevFused fz{};
+    wb_tune tune{};
     void *dmem = nullptr;
     int device = -1;
 };
+
+namespace {
+
+// Default launch shape of the fused iteration: the narrowest group of lanes
+// per state that holds every link (16, 32 or 64), 16 states per workgroup.
+wb_tune default_tune(int L) {
+    wb_tune t{};
+    t.lanes_per_state = L <= 16 ? 16 : (L <= 32 ? 32 : 64);
+    t.states_per_item = 16;
+    t.ns_per_state = 0.0f;
+    return t;
+}
+
+int check_tune(const wb_tune &t, int L) {
+    const int g = t.lanes_per_state;
+    if (g != 16 && g != 32 && g != 64) return fail(WB_ERR_INVALID_ARG, "lanes_per_state must be 16, 32 or 64");
+    if (g < L) return fail(WB_ERR_INVALID_ARG, "lanes_per_state %d is below the %d links", g, L);
+    if (t.states_per_item < 1 || t.states_per_item > 4096)
+        return fail(WB_ERR_INVALID_ARG, "states_per_item must be in [1, 4096]");
+    if (!(t.ns_per_state >= 0.0f) || !std::isfinite(t.ns_per_state))
+        return fail(WB_ERR_INVALID_ARG, "ns_per_state must be finite and >= 0");
+    return WB_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -416,6 +443,7 @@ int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
     Fz.li = reinterpret_cast<const int32_t *>(base + o_fi);
     Fz.lf = reinterpret_cast<const float *>(base + o_ff);
     Fz.lsph = reinterpret_cast<const float4 *>(base + o_fs);
+    r->tune = default_tune(T.L);
     *out = r;
     return WB_OK;
 }
@@ -611,13 +639,241 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, flo
     a.rb = robot->dev;
     a.fz = robot->fz;
     a.B = B;
-    a.chunk = 16;
-    a.jsteps = robot->fz.jsteps;
-    a.q = q; a.qd = qd; a.qdd = qdd; a.w = w;
-    a.torque_weight = torque_weight; a.margin = margin; a.hinge_weight = hinge_weight; a.lr = lr;
-    a.tau = tau; a.cost = cost; a.max_pen = max_pen; a.argmax = argmax; a.n_coll = n_coll;
-    a.g_q = g_q; a.g_qd = g_qd; a.g_qdd = g_qdd;
+    a.chunk = robot->tune.states_per_item;
+    a.lanes_per_state = robot->tune.lanes_per_state;
+    a.io = wb::TreeIO{q, qd, qdd, w, tau, cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd};
+    a.k = wb::StepScalars{torque_weight, margin, hinge_weight, lr};
     return finish(wb::launch_fused(a, stream), "wb_wholebody_step launch");
+}
+
+int wb_robot_set_tune(wb_robot *robot, const wb_tune *tune) {
+    WB_TRY(check_robot(robot));
+    if (!tune) return fail(WB_ERR_INVALID_ARG, "tune is null");
+    WB_TRY(check_tune(*tune, robot->T.L));
+    robot->tune = *tune;
+    return WB_OK;
+}
+
+int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune) {
+    WB_TRY(check_robot(robot));
+    if (!tune) return fail(WB_ERR_INVALID_ARG, "tune is null");
+    *tune = robot->tune;
+    return WB_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ plans
+
+struct wb_plan {
+    int n_trees = 0, nmax = 1, n_wg = 0, n_items = 0, device = -1;
+    size_t lds = 0;
+    std::vector<int64_t> B;
+    std::vector<int> n_dof;
+    void *dmem = nullptr;
+    const wb::PlanTree *d_trees = nullptr;
+    const wb::PlanItem *d_items = nullptr;
+    const int32_t *d_item_start = nullptr;
+};
+
+namespace {
+
+// Relative cost of one state under a launch shape (used when no measured
+// time is given): sweep block iterations x pairs per block x ~14 issue slots,
+// plus the link-parallel dynamics, shared by the 64/G states of a wavefront.
+double model_cost(const Tables &T, const wb_tune &t, int nmax) {
+    const int G = t.lanes_per_state;
+    const double iters = (double)((T.n_blocks + G - 1) / G);
+    const double slots = iters * nmax * nmax * 14.0 + 1500.0 + 200.0 * T.jsteps;
+    return slots * G / 64.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_trees, const wb_tune *tune,
+                   wb_plan **out) {
+    if (!out) return fail(WB_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (!robots || !B) return fail(WB_ERR_INVALID_ARG, "robots or B is null");
+    if (n_trees < 1 || n_trees > WB_PLAN_MAX_TREES)
+        return fail(WB_ERR_INVALID_ARG, "n_trees must be in [1, %d]", WB_PLAN_MAX_TREES);
+    int nmax = 1, device = -1;
+    std::vector<wb_tune> tunes(n_trees);
+    for (int i = 0; i < n_trees; ++i) {
+        WB_TRY(check_robot(robots[i]));
+        WB_TRY(check_B(B[i]));
+        if (!robots[i]->fz.supported)
+            return fail(WB_ERR_UNSUPPORTED, "tree %d: the fused iteration needs <= 64 links and no mimic joints", i);
+        if (device >= 0 && robots[i]->device != device)
+            return fail(WB_ERR_INVALID_ARG, "all robots of a plan must live on one device");
+        device = robots[i]->device;
+        nmax = std::max(nmax, robots[i]->T.nmax);
+        tunes[i] = tune ? tune[i] : robots[i]->tune;
+        WB_TRY(check_tune(tunes[i], robots[i]->T.L));
+    }
+    size_t lds = 0;
+    for (int i = 0; i < n_trees; ++i) {
+        const size_t per_wave = (size_t)(64 / tunes[i].lanes_per_state) * (robots[i]->T.L + 1) * nmax * sizeof(float4);
+        lds = std::max(lds, 4 * per_wave);
+    }
+    if (lds > 65536) return fail(WB_ERR_UNSUPPORTED, "plan needs %zu bytes of LDS per workgroup (> 64 KB)", lds);
+
+    // Work items: contiguous state ranges of one tree, balanced over the
+    // workgroups of one persistent wave of the launch (longest item first).
+    struct Item {
+        wb::PlanItem it;
+        double cost;
+    };
+    std::vector<Item> items;
+    for (int i = 0; i < n_trees; ++i) {
+        const int c = tunes[i].states_per_item;
+        const double per = tunes[i].ns_per_state > 0.0f ? tunes[i].ns_per_state
+                                                         : model_cost(robots[i]->T, tunes[i], nmax);
+        for (int64_t b0 = 0; b0 < B[i]; b0 += c) {
+            const int cnt = (int)std::min<int64_t>(c, B[i] - b0);
+            items.push_back({wb::PlanItem{b0, i, cnt}, per * cnt});
+        }
+    }
+    int cus = 256;
+    {
+        int dev_cus = 0;
+        if (hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+            dev_cus > 0)
+            cus = dev_cus;
+    }
+    const int n_wg = (int)std::min<size_t>(items.size(), (size_t)cus * 2);
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+    std::vector<double> load(n_wg, 0.0);
+    std::vector<std::vector<wb::PlanItem>> per_wg(n_wg);
+    for (const Item &x : items) {
+        int best = 0;
+        for (int w = 1; w < n_wg; ++w)
+            if (load[w] < load[best]) best = w;
+        load[best] += x.cost;
+        per_wg[best].push_back(x.it);
+    }
+    std::vector<wb::PlanItem> flat;
+    std::vector<int32_t> start(n_wg + 1, 0);
+    for (int w = 0; w < n_wg; ++w) {
+        start[w] = (int32_t)flat.size();
+        for (const auto &it : per_wg[w]) flat.push_back(it);
+    }
+    start[n_wg] = (int32_t)flat.size();
+
+    // Per-tree slot tables for the plan's slots per link.
+    std::vector<std::vector<float>> slot_r(n_trees);
+    std::vector<std::vector<int32_t>> sph_slot(n_trees);
+    for (int i = 0; i < n_trees; ++i) {
+        const Tables &T = robots[i]->T;
+        slot_r[i].assign((size_t)(T.L + 1) * nmax, -1e30f);
+        sph_slot[i].resize(T.S);
+        for (int s = 0; s < T.S; ++s) {
+            const int l = T.sph_link[s];
+            sph_slot[i][s] = l * nmax + (s - T.li[l].sph_first);
+            slot_r[i][sph_slot[i][s]] = T.sph[s].w;
+        }
+    }
+    std::vector<char> blob;
+    std::vector<wb::PlanTree> trees(n_trees);
+    const size_t o_items = append(blob, flat), o_start = append(blob, start);
+    std::vector<size_t> o_sr(n_trees), o_ss(n_trees);
+    for (int i = 0; i < n_trees; ++i) {
+        o_sr[i] = append(blob, slot_r[i]);
+        o_ss[i] = append(blob, sph_slot[i]);
+    }
+    const size_t o_trees = append(blob, trees);
+    blob.resize(blob.size() + 256);
+    wb_plan *p = new wb_plan();
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != device) e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMalloc(&p->dmem, blob.size());
+    if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "allocating the plan");
+    }
+    char *base = static_cast<char *>(p->dmem);
+    for (int i = 0; i < n_trees; ++i) {
+        wb::PlanTree &t = trees[i];
+        t.rb = robots[i]->dev;
+        t.rb.nmax = nmax;
+        t.rb.slot_r = reinterpret_cast<const float *>(base + o_sr[i]);
+        t.rb.sph_slot = reinterpret_cast<const int32_t *>(base + o_ss[i]);
+        t.fz = robots[i]->fz;
+        t.B = B[i];
+        t.lanes_per_state = tunes[i].lanes_per_state;
+        t.pad = 0;
+    }
+    memcpy(blob.data() + o_trees, trees.data(), trees.size() * sizeof(wb::PlanTree));
+    e = hipMemcpy(p->dmem, blob.data(), blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p->dmem);
+        delete p;
+        return hip_fail(e, "uploading the plan");
+    }
+    p->n_trees = n_trees;
+    p->nmax = nmax;
+    p->n_wg = n_wg;
+    p->n_items = (int)flat.size();
+    p->device = device;
+    p->lds = lds;
+    p->B.assign(B, B + n_trees);
+    for (int i = 0; i < n_trees; ++i) p->n_dof.push_back(robots[i]->T.n);
+    p->d_trees = reinterpret_cast<const wb::PlanTree *>(base + o_trees);
+    p->d_items = reinterpret_cast<const wb::PlanItem *>(base + o_items);
+    p->d_item_start = reinterpret_cast<const int32_t *>(base + o_start);
+    *out = p;
+    return WB_OK;
+}
+
+int wb_plan_run(const wb_plan *plan, const wb_tree_io *io, float torque_weight, float margin, float hinge_weight,
+                float lr, hipStream_t stream) {
+    if (!plan || !plan->dmem) return fail(WB_ERR_INVALID_ARG, "plan is null or destroyed");
+    if (!io) return fail(WB_ERR_INVALID_ARG, "io is null");
+    if (!std::isfinite(torque_weight) || !std::isfinite(margin) || !std::isfinite(hinge_weight) || !std::isfinite(lr))
+        return fail(WB_ERR_INVALID_ARG, "weights, margin and lr must be finite");
+    wb::PlanArgs a{};
+    a.trees = plan->d_trees;
+    a.items = plan->d_items;
+    a.item_start = plan->d_item_start;
+    a.k = wb::StepScalars{torque_weight, margin, hinge_weight, lr};
+    for (int i = 0; i < plan->n_trees; ++i) {
+        const wb_tree_io &x = io[i];
+        const bool need = plan->B[i] > 0 && plan->n_dof[i] > 0;
+        WB_TRY(check_ptr(x.q, "io.q", need));
+        WB_TRY(check_ptr(x.qd, "io.qd", need));
+        WB_TRY(check_ptr(x.qdd, "io.qdd", need));
+        WB_TRY(check_ptr(x.w, "io.w", false));
+        WB_TRY(check_ptr(x.tau, "io.tau", false));
+        WB_TRY(check_ptr(x.cost, "io.cost", false));
+        WB_TRY(check_ptr(x.max_pen, "io.max_pen", false));
+        WB_TRY(check_ptr(x.argmax, "io.argmax", false));
+        WB_TRY(check_ptr(x.n_coll, "io.n_coll", false));
+        WB_TRY(check_ptr(x.g_q, "io.g_q", false));
+        WB_TRY(check_ptr(x.g_qd, "io.g_qd", false));
+        WB_TRY(check_ptr(x.g_qdd, "io.g_qdd", false));
+        a.io[i] = wb::TreeIO{x.q, x.qd, x.qdd, x.w, x.tau, x.cost, x.max_pen, x.argmax, x.n_coll, x.g_q, x.g_qd, x.g_qdd};
+    }
+    return finish(wb::launch_plan(a, plan->nmax, plan->n_wg, plan->lds, stream), "wb_plan_run launch");
+}
+
+int wb_plan_get_info(const wb_plan *plan, int32_t *n_items, int32_t *n_workgroups) {
+    if (!plan || !plan->dmem) return fail(WB_ERR_INVALID_ARG, "plan is null or destroyed");
+    if (n_items) *n_items = plan->n_items;
+    if (n_workgroups) *n_workgroups = plan->n_wg;
+    return WB_OK;
+}
+
+int wb_plan_destroy(wb_plan *plan) {
+    if (!plan) return WB_OK;
+    hipError_t e = hipSuccess;
+    if (plan->dmem) e = hipFree(plan->dmem);
+    plan->dmem = nullptr;
+    delete plan;
+    return finish(e, "freeing the plan");
 }
 
 }  // extern "C"

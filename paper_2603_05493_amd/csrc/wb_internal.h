@@ -69,21 +69,55 @@ struct DevFused {
     const float4 *__restrict__ lsph;
 };
 
-// Arguments of the fused iteration kernel (by value).
-struct FusedArgs {
-    DevRobot rb;
-    DevFused fz;
-    int64_t B;
-    int32_t chunk, jsteps;        // states per workgroup, pointer-jumping steps
+// Device pointers of one robot's batch in a fused iteration.
+struct TreeIO {
     float *q, *qd, *qdd;          // [n][B], updated in place when lr != 0
     const float *w;               // [n][B] or null
-    float torque_weight, margin, hinge_weight, lr;
-    float *tau, *cost, *max_pen;
+    float *tau, *cost, *max_pen;  // optional outputs
     int32_t *argmax, *n_coll;
     float *g_q, *g_qd, *g_qdd;
 };
 
+// Scalars of the cost head and the step.
+struct StepScalars {
+    float torque_weight, margin, hinge_weight, lr;
+};
+
+// Arguments of the single-robot fused kernel (by value).
+struct FusedArgs {
+    DevRobot rb;
+    DevFused fz;
+    TreeIO io;
+    StepScalars k;
+    int64_t B;
+    int32_t chunk;            // states per workgroup
+    int32_t lanes_per_state;  // G: 16, 32 or 64
+};
+
+// One robot of an uneven batch, and one unit of work of the persistent launch.
+struct PlanTree {
+    DevRobot rb;              // tables re-derived for the plan's slots per link
+    DevFused fz;
+    int64_t B;
+    int32_t lanes_per_state;
+    int32_t pad;
+};
+struct PlanItem {
+    int64_t b0;
+    int32_t tree, count;
+};
+
+#define WB_PLAN_MAX_TREES 16
+struct PlanArgs {
+    const PlanTree *trees;
+    const PlanItem *items;        // grouped by workgroup
+    const int32_t *item_start;    // [n_wg + 1]
+    StepScalars k;
+    TreeIO io[WB_PLAN_MAX_TREES];
+};
+
 hipError_t launch_fused(const FusedArgs &a, hipStream_t s);
+hipError_t launch_plan(const PlanArgs &a, int nmax, int n_wg, size_t lds, hipStream_t s);
 
 // Kernel launchers (each defined next to its kernels).
 hipError_t launch_fk(const DevRobot &rb, int64_t B, const float *q, float *pose, float *spheres,

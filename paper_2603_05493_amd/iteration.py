@@ -59,6 +59,28 @@ class PlainIteration:
             wb.wb_sgd_step(self.lr, q, qd, qdd, self.g_q, self.g_qd, self.g_qdd, g_q2=self.g_q_fk)
 
 
+class PlanIteration:
+    """Several robots, each with its own batch, in one persistent launch."""
+
+    def __init__(self, robots, Bs, tunes=None, torque_weight: float = 1e-3, margin: float = 0.01,
+                 hinge_weight: float = 1.0, lr: float = 0.0, outputs: bool = True, ws=None):
+        self.plan = wb.Plan(robots, Bs, tunes)
+        self.tw, self.margin, self.hw, self.lr = torque_weight, margin, hinge_weight, lr
+        self.bufs = []
+        for i, (r, B) in enumerate(zip(robots, Bs)):
+            e = lambda *shape, dt=torch.float32: torch.empty(shape, dtype=dt, device=r.device)
+            d = {"cost": e(B), "max_pen": e(B), "argmax": e(B, dt=torch.int32), "n_coll": e(B, dt=torch.int32)}
+            if outputs:
+                d.update(tau=e(r.n_dof, B), g_q=e(r.n_dof, B), g_qd=e(r.n_dof, B), g_qdd=e(r.n_dof, B))
+            if ws is not None and ws[i] is not None:
+                d["w"] = ws[i]
+            self.bufs.append(d)
+
+    def run(self, states, step: bool = True) -> None:
+        ios = [dict(q=q, qd=qd, qdd=qdd, **b) for (q, qd, qdd), b in zip(states, self.bufs)]
+        self.plan.run(ios, self.tw, self.margin, self.hw, self.lr if step else 0.0)
+
+
 class FusedIteration:
     """The iteration as a single launch; same costs, gradients and step."""
 

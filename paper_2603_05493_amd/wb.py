@@ -111,6 +111,24 @@ class Robot:
         check(lib().wb_rnea_cache_bytes(self.handle, B, C.byref(n)))
         return n.value
 
+    def set_tune(self, lanes_per_state: int, states_per_item: int, ns_per_state: float = 0.0) -> None:
+        t = _abi.WbTune(int(lanes_per_state), int(states_per_item), float(ns_per_state))
+        check(lib().wb_robot_set_tune(self.handle, C.byref(t)))
+
+    def get_tune(self) -> dict:
+        t = _abi.WbTune()
+        check(lib().wb_robot_get_tune(self.handle, C.byref(t)))
+        return {"lanes_per_state": t.lanes_per_state, "states_per_item": t.states_per_item,
+                "ns_per_state": t.ns_per_state}
+
+    def topology_key(self) -> str:
+        """Hash of what the launch shape depends on: topology, spheres per link."""
+        import hashlib
+        k = self._keep
+        counts = np.bincount(k["sphere_link"], minlength=self.n_links) if self.n_spheres else np.zeros(1)
+        h = hashlib.sha1(k["parent"].tobytes() + k["joint_type"].tobytes() + counts.astype(np.int32).tobytes())
+        return f"L{self.n_links}_S{self.n_spheres}_{h.hexdigest()[:12]}"
+
     def workspace(self, B: int) -> torch.Tensor:
         return torch.empty(max(self.workspace_bytes(B) // 4, 1), dtype=torch.float32, device=self.device)
 
@@ -261,6 +279,56 @@ def wb_wholebody_step(robot: Robot, q, qd, qdd, w=None, torque_weight=0.0, margi
                                   float(margin), float(hinge_weight), float(lr), _p(tau), _p(cost),
                                   _p(max_pen), _p(argmax), _p(n_coll), _p(g_q), _p(g_qd), _p(g_qdd),
                                   _stream()))
+
+
+class Plan:
+    """An uneven batch of robots run by one persistent launch (wb_plan_*)."""
+
+    def __init__(self, robots, B, tunes=None):
+        self.robots, self.B = list(robots), [int(b) for b in B]
+        n = len(self.robots)
+        handles = (C.c_void_p * n)(*[r.handle.value for r in self.robots])
+        bs = (C.c_int64 * n)(*self.B)
+        tn = None
+        if tunes is not None:
+            tn = (_abi.WbTune * n)(*[_abi.WbTune(int(t["lanes_per_state"]), int(t["states_per_item"]),
+                                                 float(t.get("ns_per_state", 0.0))) for t in tunes])
+        h = C.c_void_p()
+        check(lib().wb_plan_create(C.cast(handles, C.POINTER(C.c_void_p)), bs, n, tn, C.byref(h)))
+        self.handle = h
+        ni, nw = C.c_int32(), C.c_int32()
+        check(lib().wb_plan_get_info(h, C.byref(ni), C.byref(nw)))
+        self.n_items, self.n_workgroups = ni.value, nw.value
+
+    def run(self, ios, torque_weight=0.0, margin=0.0, hinge_weight=0.0, lr=0.0):
+        """ios: one dict per robot with keys q, qd, qdd and optional w, tau,
+        cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd (device tensors)."""
+        n = len(self.robots)
+        arr = (_abi.WbTreeIO * n)()
+        for i, (r, b, io) in enumerate(zip(self.robots, self.B, ios)):
+            nd = r.n_dof
+            for key in ("q", "qd", "qdd", "w", "tau", "g_q", "g_qd", "g_qdd"):
+                _chk(io.get(key), key, (nd, b), device=r.device)
+            for key in ("cost", "max_pen"):
+                _chk(io.get(key), key, (b,), device=r.device)
+            for key in ("argmax", "n_coll"):
+                _chk(io.get(key), key, (b,), torch.int32, device=r.device)
+            for key, _ in _abi.WbTreeIO._fields_:
+                t = io.get(key)
+                setattr(arr[i], key, None if t is None else t.data_ptr())
+        check(lib().wb_plan_run(self.handle, arr, float(torque_weight), float(margin), float(hinge_weight),
+                                float(lr), _stream()))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            check(lib().wb_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------- autograd
