@@ -154,8 +154,9 @@ __device__ __forceinline__ void load_lane(LaneConst<NMAX> &C, const DevFused &fz
 // a valid state and store nothing.
 template <int NMAX, bool FULL>
 __device__ __forceinline__ void iterate_state(const DevRobot &rb, int jsteps, const LaneConst<NMAX> &C,
-                                              const TreeIO &io, const StepScalars &k, float4 *P, int G,
-                                              int glane, int64_t B, int64_t b, bool valid) {
+                                              const TreeIO &io, const StepScalars &k, float4 *P, float4 *Bd,
+                                              int *list, int G, int grp, int glane, int64_t B, int64_t b,
+                                              bool valid) {
     const int64_t jo = (int64_t)C.jidx * B + b;
     float th = 0.f, thd = 0.f, thdd = 0.f;
     if (C.revolute) {
@@ -198,11 +199,12 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, int jsteps, co
         }
     wave_sync();
     // ---- self-collision
+    link_bounds<NMAX>(rb, P, Bd, glane, G);
+    wave_sync();
     float M;
     int key;
     unsigned cnt;
-    if (FULL) sweep_state<NMAX>(rb, P, glane, M, key, cnt);
-    else sweep_group<NMAX>(rb, P, glane, G, M, key, cnt);
+    sweep_state<NMAX, FULL>(rb, P, Bd, list, glane, G, grp, M, key, cnt);
     const float hmarg = M + k.margin;
     const bool hinge_on = key != INT_MAX && hmarg > 0.f && k.hinge_weight != 0.f;
     SV W = zsv();
@@ -301,7 +303,9 @@ __device__ __forceinline__ void run_states(const DevRobot &rb, const DevFused &f
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int per_wave = 64 / G, grp = lane / G, glane = lane - grp * G;
     const int SL = (rb.L + 1) * NMAX;
-    float4 *P = lds_wave + grp * SL;
+    float4 *P = lds_wave + grp * (int)(group_lds_bytes(rb.L, NMAX) / 16);
+    float4 *Bd = P + SL;
+    int *list = reinterpret_cast<int *>(Bd + rb.L + 1);
     wave_sync();
     for (int i = glane; i < SL; i += G) P[i] = make_float4(0.f, 0.f, 0.f, rb.slot_r[i]);
     LaneConst<NMAX> C;
@@ -310,8 +314,8 @@ __device__ __forceinline__ void run_states(const DevRobot &rb, const DevFused &f
         const int s = base + grp;
         const bool valid = s < count;
         const int64_t b = b0 + (valid ? s : base);
-        if (G == 64) iterate_state<NMAX, true>(rb, fz.jsteps, C, io, k, P, 64, glane, B, b, valid);
-        else iterate_state<NMAX, false>(rb, fz.jsteps, C, io, k, P, G, glane, B, b, valid);
+        if (G == 64) iterate_state<NMAX, true>(rb, fz.jsteps, C, io, k, P, Bd, list, 64, 0, glane, B, b, valid);
+        else iterate_state<NMAX, false>(rb, fz.jsteps, C, io, k, P, Bd, list, G, grp, glane, B, b, valid);
     }
 }
 
@@ -320,7 +324,7 @@ __global__ void __launch_bounds__(256) k_fused_step(FusedArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
     const int G = A.lanes_per_state;
-    const int SLW = (64 / G) * (A.rb.L + 1) * NMAX;
+    const int SLW = (64 / G) * (int)(group_lds_bytes(A.rb.L, NMAX) / 16);
     // XCD-aware chunk order: consecutive chunks stay on one XCD's L2.
     const int nwg = gridDim.x, x = blockIdx.x & 7, y = blockIdx.x >> 3;
     const int qd8 = nwg >> 3, rd8 = nwg & 7;
@@ -343,14 +347,15 @@ __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
         const PlanItem item = A.items[it];
         const PlanTree T = ldu(A.trees + item.tree);
         const int G = T.lanes_per_state;
-        const int SLW = (64 / G) * (T.rb.L + 1) * NMAX;
-        run_states<NMAX>(T.rb, T.fz, A.io[item.tree], A.k, lds + wave * SLW, G, T.B, item.b0, item.count);
+        // a fixed region per wave: waves of one workgroup may be on different trees
+        run_states<NMAX>(T.rb, T.fz, A.io[item.tree], A.k, lds + wave * A.wave_stride, G, T.B, item.b0,
+                         item.count);
     }
 }
 
 template <int NMAX>
 static hipError_t launch_fused_t(const FusedArgs &a, hipStream_t s) {
-    const size_t lds = (size_t)4 * (64 / a.lanes_per_state) * (a.rb.L + 1) * NMAX * sizeof(float4);
+    const size_t lds = (size_t)4 * (64 / a.lanes_per_state) * group_lds_bytes(a.rb.L, NMAX);
     const unsigned nwg = (unsigned)((a.B + a.chunk - 1) / a.chunk);
     hipLaunchKernelGGL(k_fused_step<NMAX>, dim3(nwg), dim3(256), lds, s, a);
     return hipGetLastError();

@@ -5,6 +5,7 @@
 
 namespace wb {
 
+// LDS: TS states x [(L+1)*NMAX slots | (L+1) link bounds], then 4 lists.
 template <int NMAX>
 __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, int TS,
                                                         const float *__restrict__ sph,
@@ -13,9 +14,13 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, 
                                                         int32_t *__restrict__ n_coll) {
     extern __shared__ float4 lds[];
     const int SL = (rb.L + 1) * NMAX;
+    const int SLB = SL + rb.L + 1;
     const int64_t b0 = (int64_t)blockIdx.x * TS;
     const int tid = threadIdx.x;
-    for (int i = tid; i < TS * SL; i += 256) lds[i] = make_float4(0.f, 0.f, 0.f, rb.slot_r[i % SL]);
+    for (int i = tid; i < TS * SLB; i += 256) {
+        const int st = i / SLB, o = i - st * SLB;
+        lds[i] = make_float4(0.f, 0.f, 0.f, o < SL ? rb.slot_r[o] : -1e30f);
+    }
     __syncthreads();
     const int n3 = rb.S * 3;
     for (int i = tid; i < n3 * TS; i += 256) {
@@ -23,19 +28,25 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, 
         const int64_t b = b0 + st;
         if (b < B) {
             const int s = sc / 3, c = sc - 3 * s;
-            reinterpret_cast<float *>(&lds[st * SL + rb.sph_slot[s]])[c] = sph[(int64_t)sc * B + b];
+            reinterpret_cast<float *>(&lds[st * SLB + rb.sph_slot[s]])[c] = sph[(int64_t)sc * B + b];
         }
     }
     __syncthreads();
 
     const int wave = tid >> 6, lane = tid & 63;
+    int *list = reinterpret_cast<int *>(lds + TS * SLB) + wave * (SWEEP_LIST_BYTES / 4);
     for (int st = wave; st < TS; st += 4) {
         const int64_t b = b0 + st;
         if (b >= B) break;
+        float4 *P = lds + st * SLB;
+        float4 *Bd = P + SL;
+        link_bounds<NMAX>(rb, P, Bd, lane, 64);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         float M;
         int key;
         unsigned cnt;
-        sweep_state<NMAX>(rb, lds + st * SL, lane, M, key, cnt);
+        sweep_state<NMAX, true>(rb, P, Bd, list, lane, 64, 0, M, key, cnt);
         if (lane == 0) {
             if (max_pen) max_pen[b] = M;
             if (argmax) argmax[b] = pair_index(rb, key);
@@ -45,8 +56,8 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, 
 }
 
 int self_collision_tile(int L, int nmax) {
-    const int bytes_per_state = (L + 1) * nmax * (int)sizeof(float4);
-    int ts = 65536 / bytes_per_state;
+    const int per_state = (int)state_lds_bytes(L, nmax);
+    int ts = (65536 - 4 * SWEEP_LIST_BYTES) / per_state;
     if (ts > 16) ts = 16;
     if (ts >= 4) ts &= ~3;
     if (ts < 1) ts = 1;
@@ -57,7 +68,7 @@ template <int NMAX>
 static hipError_t launch_sc(const DevRobot &rb, int64_t B, const float *sph, float *mp, int32_t *am,
                             int32_t *nc, hipStream_t s) {
     const int TS = self_collision_tile(rb.L, NMAX);
-    const size_t lds = (size_t)TS * (rb.L + 1) * NMAX * sizeof(float4);
+    const size_t lds = (size_t)TS * state_lds_bytes(rb.L, NMAX) + 4 * SWEEP_LIST_BYTES;
     dim3 grid((unsigned)((B + TS - 1) / TS));
     hipLaunchKernelGGL(k_self_collision<NMAX>, grid, dim3(256), lds, s, rb, B, TS, sph, mp, am, nc);
     return hipGetLastError();

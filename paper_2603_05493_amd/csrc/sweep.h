@@ -1,29 +1,42 @@
-// The self-collision pair sweep of one state by one wavefront (cuRoboV2
-// Sec. 6.2, the "map" over pair blocks and the "reduce" to the most
-// penetrating pair), shared by the standalone and the fused kernels.
+// The self-collision pair sweep of one state by a group of G lanes of a
+// wavefront (cuRoboV2 Sec. 6.2: the "map" over pair blocks and the "reduce"
+// to the most penetrating pair), shared by the standalone and fused kernels.
 //
 // The checked pair set is a union of dense link blocks: every allowed link
 // pair (a < b) contributes all spheres of a times all spheres of b.  The
 // state's sphere centres sit in LDS, padded to NMAX slots per link (empty
 // slots carry radius -1e30, so they can neither be the maximum nor count as
-// a collision), plus one all-empty row that the block list is padded with to
-// a multiple of 64.  Each lane owns whole link blocks: it loads the
-// NMAX + NMAX centres of its block into registers once and evaluates
-// NMAX * NMAX pairs, so the control flow of the sweep is uniform.
+// a collision), plus one all-empty row for padding blocks.  A lane owns a
+// whole link block: it loads the NMAX + NMAX centres into registers once and
+// evaluates NMAX * NMAX pairs.
 //
-// Reduce: the pair count accumulates on the scalar unit from a ballot of
-// pen > 0 per pair; the maximum is a per-lane running max per block plus a
-// wave shuffle reduction.  The lowest pair index attaining the maximum is
-// recovered exactly: each lane remembers the block where its running max was
-// set and whether another of its blocks tied it; lanes holding the wave
-// maximum re-evaluate that block (or, after a tie, all their blocks) with the
-// same arithmetic and report the lowest (s, t) whose penetration equals it.
+// Broad phase (exact): each link gets a bounding sphere (centroid C_a of its
+// sphere centres, reach R_a = max |c - C_a| + r), and no pair of block (a, b)
+// can penetrate more than bound = R_a + R_b - |C_a - C_b|.  A seed, the
+// exact maximum of the block with the largest bound, is a lower bound of the
+// state's maximum M.  Blocks with bound < min(seed, 0) - eps therefore hold
+// no pair that is the maximum, ties it, or collides; they are skipped.  eps
+// covers the FP32 rounding of both the bound and the pair penetrations (all
+// computed from the same FP32 centres), so the result is identical to the
+// full sweep.  Survivors are compacted into an LDS list per chunk of blocks
+// so the pair loop stays lane-dense.
+//
+// Reduce: the pair count is a scalar ballot popcount per pair (one state per
+// wavefront) or a per-lane counter summed over the group; the maximum is a
+// per-lane running max per block plus a group shuffle reduction.  The lowest
+// pair index attaining the maximum is recovered exactly: lanes holding the
+// maximum re-evaluate the block where their running max was set with the
+// same arithmetic and report the lowest (s, t) whose penetration equals it;
+// if any lane saw two of its blocks tie the maximum, the group rescans every
+// block instead.
 #pragma once
 
 #include <climits>
 #include "spatial.h"
 
 namespace wb {
+
+constexpr int SWEEP_CHUNK = 256;   // blocks per compaction chunk (list entries per group)
 
 // Penetration depth of one sphere pair; .w is the radius.  Written with
 // explicit fused multiply-adds so every evaluation rounds identically.
@@ -33,15 +46,23 @@ __device__ __forceinline__ float pair_pen(float4 A, float4 Bv) {
     return (A.w + Bv.w) - __builtin_amdgcn_sqrtf(d2);
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+__device__ __forceinline__ float group_max(float v, int G) {
+    for (int o = G >> 1; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, G));
     return v;
 }
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+__device__ __forceinline__ int group_min(int v, int G) {
+    for (int o = G >> 1; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, G));
     return v;
+}
+__device__ __forceinline__ unsigned group_sum(unsigned v, int G) {
+    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+__device__ __forceinline__ float block_bound(const float4 *Bd, int ab) {
+    const float4 A = Bd[ab >> 16], Bv = Bd[ab & 0xffff];
+    const float dx = A.x - Bv.x, dy = A.y - Bv.y, dz = A.z - Bv.z;
+    return (A.w + Bv.w) - __builtin_amdgcn_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
 }
 
 template <int NMAX>
@@ -60,116 +81,145 @@ __device__ __forceinline__ int block_min_key(const DevRobot &rb, const float4 *P
     return INT_MAX;
 }
 
-
-// Sweep one state's checked pairs.  P points at the state's padded sphere
-// slots in LDS ((L+1)*NMAX float4, .w = radius).  Called by all 64 lanes of
-// the wavefront; every lane returns the state's maximum penetration M, the
-// sphere key s*S + t of the lowest pair attaining it (INT_MAX if none) and
-// the count of pairs with positive penetration.
+// Bounding sphere of every link's (non-empty) sphere slots, into Bd[0..L).
 template <int NMAX>
-__device__ __forceinline__ void sweep_state(const DevRobot &rb, const float4 *P, int lane, float &M_out,
-                                            int &key_out, unsigned &cnt_out) {
-    float best = -INFINITY;
-    int best_blk = -1;
-    bool tie = false;
-    unsigned cnt = 0;
-    for (int base = 0; base < rb.n_blocks_pad; base += 64) {
-        const int blk = base + lane;
-        const int ab = rb.blocks[blk];
-        const int a = ab >> 16, bb = ab & 0xffff;
-        float4 A[NMAX], Bv[NMAX];
+__device__ __forceinline__ void link_bounds(const DevRobot &rb, const float4 *P, float4 *Bd, int glane, int G) {
+    for (int a = glane; a < rb.L; a += G) {
+        float cx = 0.f, cy = 0.f, cz = 0.f, n = 0.f;
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) {
-            A[i] = P[a * NMAX + i];
-            Bv[i] = P[bb * NMAX + i];
-        }
-        float m = -INFINITY;
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i)
-#pragma unroll
-            for (int j = 0; j < NMAX; ++j) {
-                const float pen = pair_pen(A[i], Bv[j]);
-                m = fmaxf(m, pen);
-                cnt += (unsigned)__popcll(__ballot(pen > 0.0f));
+            const float4 s = P[a * NMAX + i];
+            if (s.w > -1e29f) {
+                cx += s.x;
+                cy += s.y;
+                cz += s.z;
+                n += 1.f;
             }
-        if (m > best) {
-            best = m;
-            best_blk = blk;
-            tie = false;
-        } else if (m == best) {
-            tie = true;
         }
-    }
-    const float M = wave_max(best);
-    int key = INT_MAX;
-    if (best == M && M > -INFINITY) {
-        if (!tie) {
-            key = block_min_key<NMAX>(rb, P, best_blk, M);
-        } else {
-            for (int blk = lane; blk < rb.n_blocks_pad; blk += 64)
-                key = min(key, block_min_key<NMAX>(rb, P, blk, M));
+        float R = -1e30f;
+        if (n > 0.f) {
+            const float inv = 1.f / n;
+            cx *= inv;
+            cy *= inv;
+            cz *= inv;
+#pragma unroll
+            for (int i = 0; i < NMAX; ++i) {
+                const float4 s = P[a * NMAX + i];
+                if (s.w > -1e29f) {
+                    const float dx = s.x - cx, dy = s.y - cy, dz = s.z - cz;
+                    R = fmaxf(R, __builtin_amdgcn_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) + s.w);
+                }
+            }
         }
+        Bd[a] = make_float4(cx, cy, cz, R);
     }
-    M_out = M;
-    key_out = wave_min(key);
-    cnt_out = cnt;
 }
 
-// The same sweep by a group of G < 64 lanes (64/G states per wavefront).
-// Blocks are dealt to the group's lanes; the pair count is a per-lane
-// counter summed over the group at the end.
-template <int NMAX>
-__device__ __forceinline__ void sweep_group(const DevRobot &rb, const float4 *P, int glane, int G, float &M_out,
-                                            int &key_out, unsigned &cnt_out) {
+// Sweep one state.  P: the state's (L+1)*NMAX sphere slots; Bd: its link
+// bounding spheres (link_bounds); list: SWEEP_CHUNK ints of LDS scratch for
+// this group.  Every lane of the group returns the maximum penetration M,
+// the sphere key s*S + t of the lowest pair attaining it (INT_MAX if none)
+// and the number of pairs with positive penetration.  FULL: G == 64.
+template <int NMAX, bool FULL>
+__device__ __forceinline__ void sweep_state(const DevRobot &rb, const float4 *P, const float4 *Bd, int *list,
+                                            int glane, int G, int grp, float &M_out, int &key_out,
+                                            unsigned &cnt_out) {
+    const int nb = (rb.n_blocks + G - 1) / G * G;
+    const uint64_t gmask = FULL ? ~0ull : ((1ull << G) - 1ull);
+    const int gshift = FULL ? 0 : grp * G;
+    // extent of the robot in this state, for the rounding margin
+    float ext = 0.f;
+    for (int a = glane; a < rb.L; a += G) {
+        const float4 c = Bd[a];
+        if (c.w > -1e29f) ext = fmaxf(ext, sqrtf(c.x * c.x + c.y * c.y + c.z * c.z) + c.w);
+    }
+    const float eps = 4e-6f * (1.f + group_max(ext, G));
+    // seed: exact maximum of the block with the largest bound
+    float bmax = -INFINITY;
+    int bblk = INT_MAX;
+    for (int base = 0; base < nb; base += G) {
+        const int blk = base + glane;
+        if (blk < rb.n_blocks) {
+            const float bd = block_bound(Bd, rb.blocks[blk]);
+            if (bd > bmax) {
+                bmax = bd;
+                bblk = blk;
+            }
+        }
+    }
+    const float gbmax = group_max(bmax, G);
+    const int cand = group_min(bmax == gbmax ? bblk : INT_MAX, G);
+    float seed = -INFINITY;
+    if (cand != INT_MAX) {
+        const int ab = rb.blocks[cand];
+        const int a = ab >> 16, bb = ab & 0xffff;
+        for (int j = glane; j < NMAX * NMAX; j += G) {
+            const int i = j / NMAX, k = j - i * NMAX;
+            seed = fmaxf(seed, pair_pen(P[a * NMAX + i], P[bb * NMAX + k]));
+        }
+    }
+    const float theta = fminf(group_max(seed, G), 0.f) - eps;
+
     float best = -INFINITY;
     int best_blk = -1;
     bool tie = false;
     unsigned cnt = 0;
-    const int nb = (rb.n_blocks + G - 1) / G * G;
-    for (int base = 0; base < nb; base += G) {
-        const int blk = base + glane;
-        const int ab = rb.blocks[blk];
-        const int a = ab >> 16, bb = ab & 0xffff;
-        float4 A[NMAX], Bv[NMAX];
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-            A[i] = P[a * NMAX + i];
-            Bv[i] = P[bb * NMAX + i];
+    for (int c0 = 0; c0 < nb; c0 += SWEEP_CHUNK) {
+        const int cend = min(c0 + SWEEP_CHUNK, nb);
+        int nl = 0;
+        for (int base = c0; base < cend; base += G) {
+            const int blk = base + glane;
+            const bool surv = blk < rb.n_blocks && block_bound(Bd, rb.blocks[blk]) >= theta;
+            const uint64_t m = (__ballot(surv) >> gshift) & gmask;
+            if (surv) list[nl + __popcll(m & ((1ull << glane) - 1ull))] = blk;
+            nl += __popcll(m);
         }
-        float m = -INFINITY;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int j = 0; j < nl; j += G) {
+            const int idx = j + glane;
+            const int blk = idx < nl ? list[idx] : -1;
+            const int ab = blk >= 0 ? rb.blocks[blk] : ((rb.L << 16) | rb.L);
+            const int a = ab >> 16, bb = ab & 0xffff;
+            float4 A[NMAX], Bv[NMAX];
 #pragma unroll
-        for (int i = 0; i < NMAX; ++i)
-#pragma unroll
-            for (int j = 0; j < NMAX; ++j) {
-                const float pen = pair_pen(A[i], Bv[j]);
-                m = fmaxf(m, pen);
-                cnt += pen > 0.0f ? 1u : 0u;
+            for (int i = 0; i < NMAX; ++i) {
+                A[i] = P[a * NMAX + i];
+                Bv[i] = P[bb * NMAX + i];
             }
-        if (m > best) {
-            best = m;
-            best_blk = blk;
-            tie = false;
-        } else if (m == best) {
-            tie = true;
+            float m = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < NMAX; ++i)
+#pragma unroll
+                for (int k = 0; k < NMAX; ++k) {
+                    const float pen = pair_pen(A[i], Bv[k]);
+                    m = fmaxf(m, pen);
+                    if (FULL) cnt += (unsigned)__popcll(__ballot(pen > 0.0f));
+                    else cnt += pen > 0.0f ? 1u : 0u;
+                }
+            if (m > best) {
+                best = m;
+                best_blk = blk;
+                tie = false;
+            } else if (m == best) {
+                tie = true;
+            }
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
-    float M = best;
-    for (int o = G >> 1; o > 0; o >>= 1) M = fmaxf(M, __shfl_xor(M, o, G));
+    const float M = group_max(best, G);
     int key = INT_MAX;
-    if (best == M && M > -INFINITY) {
-        if (!tie) {
-            key = block_min_key<NMAX>(rb, P, best_blk, M);
-        } else {
-            for (int blk = glane; blk < nb; blk += G) key = min(key, block_min_key<NMAX>(rb, P, blk, M));
-        }
-    }
-    for (int o = G >> 1; o > 0; o >>= 1) {
-        key = min(key, __shfl_xor(key, o, G));
-        cnt += __shfl_xor(cnt, o, G);
+    const bool holder = best == M && M > -INFINITY && best_blk >= 0;
+    const int rescan = group_min((holder && tie) ? 0 : 1, G) == 0;
+    if (rescan) {
+        for (int blk = glane; blk < nb; blk += G) key = min(key, block_min_key<NMAX>(rb, P, blk, M));
+    } else if (holder) {
+        key = block_min_key<NMAX>(rb, P, best_blk, M);
     }
     M_out = M;
-    key_out = key;
-    cnt_out = cnt;
+    key_out = group_min(key, G);
+    cnt_out = FULL ? cnt : group_sum(cnt, G);
 }
 
 // Pair index (lexicographic in (s, t)) of a sphere key s*S + t.

@@ -214,7 +214,7 @@ int build_tables(const wb_robot_desc *d, Tables &T) {
     if (nmax > WB_MAX_SPHERES_PER_LINK)
         return fail(WB_ERR_UNSUPPORTED, "%d spheres on one link exceeds %d", nmax, WB_MAX_SPHERES_PER_LINK);
     T.nmax = nmax;
-    if ((size_t)(L + 1) * nmax * sizeof(float4) > 65536)
+    if (wb::state_lds_bytes(L, nmax) + 4 * wb::SWEEP_LIST_BYTES > 65536)
         return fail(WB_ERR_UNSUPPORTED, "(links + 1) x spheres-per-link slots (%d x %d) exceed the 64 KB LDS tile",
                     L + 1, nmax);
     T.sph.resize(S);
@@ -715,7 +715,7 @@ int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_tr
     }
     size_t lds = 0;
     for (int i = 0; i < n_trees; ++i) {
-        const size_t per_wave = (size_t)(64 / tunes[i].lanes_per_state) * (robots[i]->T.L + 1) * nmax * sizeof(float4);
+        const size_t per_wave = (size_t)(64 / tunes[i].lanes_per_state) * wb::group_lds_bytes(robots[i]->T.L, nmax);
         lds = std::max(lds, 4 * per_wave);
     }
     if (lds > 65536) return fail(WB_ERR_UNSUPPORTED, "plan needs %zu bytes of LDS per workgroup (> 64 KB)", lds);
@@ -839,6 +839,7 @@ int wb_plan_run(const wb_plan *plan, const wb_tree_io *io, float torque_weight, 
     a.trees = plan->d_trees;
     a.items = plan->d_items;
     a.item_start = plan->d_item_start;
+    a.wave_stride = (int32_t)(plan->lds / 4 / 16);
     a.k = wb::StepScalars{torque_weight, margin, hinge_weight, lr};
     for (int i = 0; i < plan->n_trees; ++i) {
         const wb_tree_io &x = io[i];

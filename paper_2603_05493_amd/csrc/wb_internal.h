@@ -112,6 +112,7 @@ struct PlanArgs {
     const PlanTree *trees;
     const PlanItem *items;        // grouped by workgroup
     const int32_t *item_start;    // [n_wg + 1]
+    int32_t wave_stride;          // float4s of LDS per wave (the largest over the plan's trees)
     StepScalars k;
     TreeIO io[WB_PLAN_MAX_TREES];
 };
@@ -142,6 +143,14 @@ hipError_t launch_cost_head(int64_t B, int32_t n, const float *tau, const float 
 hipError_t launch_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd,
                            const float *g_q, const float *g_q2, const float *g_qd,
                            const float *g_qdd, hipStream_t s);
+
+// LDS of one state's sweep: (L+1)*nmax sphere slots and L+1 link bounding
+// spheres (float4 each); plus, per sweeping group, a list of 256 block ids.
+constexpr int SWEEP_LIST_BYTES = 256 * 4;
+__host__ __device__ inline size_t state_lds_bytes(int L, int nmax) { return (size_t)(L + 1) * (nmax + 1) * 16; }
+__host__ __device__ inline size_t group_lds_bytes(int L, int nmax) {
+    return state_lds_bytes(L, nmax) + SWEEP_LIST_BYTES;
+}
 
 // States per workgroup of the self-collision kernel (LDS tile).
 int self_collision_tile(int L, int nmax);

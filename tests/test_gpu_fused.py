@@ -158,3 +158,22 @@ def test_fused_deterministic():
         outs.append([t.clone() for t in (it.cost, it.max_pen, it.argmax, it.n_coll, it.tau, it.g_q)])
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+def test_fused_no_collision_regime(oracle):
+    rb = synth.humanoid48(seed=4)
+    rb.sphere_r = synth._f32(rb.sphere_r * 0.3)
+    check_fused(oracle, rb, synth.states(rb, 1500, seed=7, q_range=1.5), "humanoid_small_r")
+
+
+def test_fused_exact_tie_takes_lowest_pair():
+    from paper_2603_05493_amd.iteration import FusedIteration
+    from tests.test_gpu_parity import _tie_robot
+    rb = _tie_robot()
+    r = _robot(rb)
+    B = 70
+    it = FusedIteration(r, B)
+    z = torch.zeros((3, B), device="cuda")
+    it.run(z, z.clone(), z.clone(), step=False)
+    torch.cuda.synchronize()
+    assert np.all(it.argmax.cpu().numpy() == 1) and np.all(it.n_coll.cpu().numpy() == 2)

@@ -287,3 +287,42 @@ def test_bitwise_deterministic():
                                          it.g_qd, it.g_qdd)])
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+def _small_radius_humanoid():
+    rb = synth.humanoid48(seed=4)
+    rb.sphere_r = synth._f32(rb.sphere_r * 0.3)
+    return rb
+
+
+def test_forward_no_collision_regime(oracle):
+    """Mostly negative maxima: the broad phase's threshold comes from the seed."""
+    rb = _small_radius_humanoid()
+    _check_forward(oracle, rb, synth.states(rb, 1500, seed=7, q_range=1.5), "humanoid_small_r")
+
+
+def _tie_robot():
+    """Root with three children; spheres at the child origins make the pairs
+    (1,3) and (2,3) exact mirror images, so their penetrations tie in FP32."""
+    L = 4
+    z = np.zeros((L, 3))
+    fp = np.array([[0, 0, 0], [0.125, 0, 0], [-0.125, 0, 0], [0, 0, 0.0625]])
+    axis = np.tile([0.0, 0.0, 1.0], (L, 1))
+    inertia = np.tile(np.eye(3) * 1e-3, (L, 1, 1))
+    return synth._finish("tie", 0, [-1, 0, 0, 0], axis, np.tile(np.eye(3), (L, 1, 1)), fp,
+                         np.ones(L), z, inertia, [1, 2, 3], np.zeros((3, 3)), np.full(3, 0.0875))
+
+
+def test_exact_tie_takes_lowest_pair(oracle):
+    wb = _wb()
+    rb = _tie_robot()
+    r = _dev_robot(rb)
+    B = 130
+    q = torch.zeros((3, B), device="cuda")
+    pose, sph = wb.wb_fk(r, q)
+    mp, am, nc = wb.wb_self_collision(r, sph)
+    torch.cuda.synchronize()
+    s, t = oracle.pairs(rb)
+    pens = oracle.self_collision_pens(rb, np.zeros((1, 3, 3)) + P.host(sph)[:1])
+    assert pens[0, 0] < pens[0, 1] == pens[0, 2]          # pairs (1,2), (1,3), (2,3)
+    assert np.all(am.cpu().numpy() == 1) and np.all(nc.cpu().numpy() == 2)
