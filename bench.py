@@ -3,12 +3,15 @@ forward + backward + gradient step) on the optimizer-shaped 48-DoF humanoid
 workload (512 seeds x 48 timesteps = 24576 states, cost 1e-3 ||tau||^2 +
 hinge(max_pen + 0.01 m)), synthetic seeded robot and states.
 
-One "step" is one optimizer iteration over the whole batch.  Three forms are
+One "step" is one optimizer iteration over the whole batch.  Four forms are
 timed on the same inputs:
-  fused_graph  the iteration as one kernel (wb_wholebody_step) replayed from
-               a HIP graph -- the reported value;
-  plain_graph  one launch per operation, captured in a HIP graph;
-  plain        one launch per operation, issued eagerly (the "plain launch").
+  fused_graph   K iterations of the fused kernel (wb_wholebody_step) with the
+                gradient step, captured in one HIP graph with a snapshot of
+                state, gradient and cost every 10th iteration; the timed
+                region is one replay (exactly K steps) -- the reported value;
+  fused_graph1  a one-iteration graph of the same kernel, replayed K times;
+  plain_graph   one launch per operation, captured in a HIP graph;
+  plain         one launch per operation, issued eagerly (the "plain launch").
 The roofline object covers the fused kernel, timed with HIP events on its
 stream over an eager timed loop; the CPU baseline is the FP64 oracle on a
 bounded sample of the same workload.
@@ -39,7 +42,7 @@ PEAK_FP32_PUBLISHED_TFLOPS = 157.3   # needs packed FP32, which this build disab
 # it was measured with; reported as null once they change.
 TRAFFIC_MEASURED = {"sources_sha1": "55235200a7b39c95ebaaac392d8c2e90d09464a5", "states": 24576,
                     "bytes_per_launch": 28606.8 * 1024}
-FUSED_SOURCES = ("fused.hip", "sweep.h", "spatial.h", "wb_internal.h")
+FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h")
 
 
 def fused_sources_sha1() -> str:
@@ -68,7 +71,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=24576)
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="fused_graph,plain_graph,plain")
+    ap.add_argument("--forms", default="fused_graph,fused_graph1,plain_graph,plain")
     ap.add_argument("--no-uneven", dest="uneven", action="store_false",
                     help="skip the uneven multi-tree batch measurement")
     return ap.parse_args()
@@ -99,7 +102,7 @@ def main():
         sys.exit(2)
     import torch
     from paper_2603_05493_amd import synth, wb
-    from paper_2603_05493_amd.iteration import FusedIteration, PlainIteration
+    from paper_2603_05493_amd.iteration import FusedIteration, OptimizerGraph, PlainIteration
 
     torch.cuda.set_device(0)
     B = args.batch
@@ -118,6 +121,20 @@ def main():
     def make(form):
         return FusedIteration(robot, B, outputs=False, **kw) if form.startswith("fused") else \
             PlainIteration(robot, B, **kw)
+
+    def timed_optimizer_graph():
+        q, qd, qdd = q0.clone(), qd0.clone(), qdd0.clone()
+        og = OptimizerGraph(robot, q, qd, qdd, iters=args.steps, every=10, **kw)
+        for _ in range(args.warmup):
+            og.lean.run(q, qd, qdd)
+        og.capture()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        og.replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        assert torch.isfinite(q).all() and torch.isfinite(og.hist["cost"]).all()
+        return dt
 
     def timed_graph(form):
         q, qd, qdd = q0.clone(), qd0.clone(), qdd0.clone()
@@ -164,7 +181,9 @@ def main():
         return dt, kernel_ms
 
     for form in forms:
-        if form.endswith("_graph"):
+        if form == "fused_graph":
+            res[form] = timed_optimizer_graph()
+        elif "_graph" in form:
             res[form] = timed_graph(form)
         else:
             res[form] = timed_eager(form)[0]

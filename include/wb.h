@@ -233,8 +233,10 @@ int wb_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd,
  *                      are those of cost[b] (FK through the hinge plus RNEA),
  *                      evaluated before the step.
  * Results agree with the separate calls (same definitions, same tolerance;
- * floating-point sums are ordered differently).  Needs n_links <= 64 and
- * no mimic joints (wb_robot_info.fused_supported), else WB_ERR_UNSUPPORTED. */
+ * floating-point sums are ordered differently).  Needs n_links <= 64, no
+ * mimic joints, and the per-state sweep tables of a 256-lane workgroup
+ * within 64 KB of LDS (wb_robot_info.fused_supported), else
+ * WB_ERR_UNSUPPORTED. */
 int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, float *qdd, const float *w,
                       float torque_weight, float margin, float hinge_weight, float lr, float *tau,
                       float *cost, float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q,
@@ -250,7 +252,9 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, flo
  *   ns_per_state     measured cost of one state, used to balance uneven
  *                    batches (0 = use the built-in cost model).
  * wb_robot_create sets a default; wb_robot_set_tune validates and replaces it
- * (WB_ERR_INVALID_ARG for an invalid shape). */
+ * (WB_ERR_INVALID_ARG for an invalid shape, WB_ERR_UNSUPPORTED when
+ * 64 / lanes_per_state states per wavefront would not fit 64 KB of LDS per
+ * workgroup). */
 typedef struct wb_tune {
     int32_t lanes_per_state;
     int32_t states_per_item;

@@ -46,10 +46,6 @@ __device__ __forceinline__ SV shfl_sv(SV x, int src, int G) {
     return sv(v3(__shfl(x.w.x, src, G), __shfl(x.w.y, src, G), __shfl(x.w.z, src, G)),
               v3(__shfl(x.l.x, src, G), __shfl(x.l.y, src, G), __shfl(x.l.z, src, G)));
 }
-__device__ __forceinline__ SV shfl_up_sv(SV x, int d, int G) {
-    return sv(v3(__shfl_up(x.w.x, d, G), __shfl_up(x.w.y, d, G), __shfl_up(x.w.z, d, G)),
-              v3(__shfl_up(x.l.x, d, G), __shfl_up(x.l.y, d, G), __shfl_up(x.l.z, d, G)));
-}
 __device__ __forceinline__ SV zsv() { return sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f)); }
 
 // Sum of x over the path from the root to this lane's link.
@@ -67,33 +63,47 @@ __device__ __forceinline__ SV path_sum(SV x, int parent_lane, int glane, int ste
     return x;
 }
 
-// Sum of x over this lane's subtree (group lanes [glane, sub_end]); lanes
-// outside the robot must hold zero.
+// Sum of x over this lane's subtree (group lanes [glane, sub_end]): the
+// difference of two values of the group's inclusive scan.  Lanes outside the
+// robot must hold zero.
 __device__ __forceinline__ SV subtree_sum(SV x, int glane, int sub_end, int G) {
-    for (int d = 1; d < G; d <<= 1) {
-        const SV t = shfl_up_sv(x, d, G);
-        if (glane >= d) x += t;
-    }
-    const SV hi = shfl_sv(x, sub_end, G);
-    const SV lo = shfl_sv(x, glane > 0 ? glane - 1 : 0, G);
+    const SV s = sv(v3(group_scan(x.w.x, G), group_scan(x.w.y, G), group_scan(x.w.z, G)),
+                    v3(group_scan(x.l.x, G), group_scan(x.l.y, G), group_scan(x.l.z, G)));
+    const SV hi = shfl_sv(s, sub_end, G);
+    const SV lo = sv(v3(lane_prev(s.w.x), lane_prev(s.w.y), lane_prev(s.w.z)),
+                     v3(lane_prev(s.l.x), lane_prev(s.l.y), lane_prev(s.l.z)));
     return glane > 0 ? hi - lo : hi;
 }
 
-// World-frame spatial inertia product: CoM cw (world), mass m, rotational
-// inertia Ic about the CoM in link axes with world rotation R.
+// World-frame spatial inertia of a link: mass m, CoM cw and the rotational
+// inertia about the CoM in world axes, Iw = R Ic R^T (xx yy zz xy xz yz).
 struct WInertia {
     float m;
     V3 cw;
-    M3 R;
     float I[6];
 };
 __device__ __forceinline__ SV iw_apply(const WInertia &J, SV u) {
     const V3 h = J.m * (u.l + cross(u.w, J.cw));
-    const V3 wl = mulT(J.R, u.w);
-    const V3 Iw = v3(J.I[0] * wl.x + J.I[3] * wl.y + J.I[4] * wl.z,
-                     J.I[3] * wl.x + J.I[1] * wl.y + J.I[5] * wl.z,
-                     J.I[4] * wl.x + J.I[5] * wl.y + J.I[2] * wl.z);
-    return sv(mul(J.R, Iw) + cross(J.cw, h), h);
+    const V3 Iw = v3(J.I[0] * u.w.x + J.I[3] * u.w.y + J.I[4] * u.w.z,
+                     J.I[3] * u.w.x + J.I[1] * u.w.y + J.I[5] * u.w.z,
+                     J.I[4] * u.w.x + J.I[5] * u.w.y + J.I[2] * u.w.z);
+    return sv(Iw + cross(J.cw, h), h);
+}
+// R Ic R^T for a symmetric Ic given as xx yy zz xy xz yz.
+__device__ __forceinline__ void rotate_inertia(const M3 &R, const float *Ic, float *Iw) {
+    float T[9];   // R Ic
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float r0 = R.m[3 * i], r1 = R.m[3 * i + 1], r2 = R.m[3 * i + 2];
+        T[3 * i + 0] = r0 * Ic[0] + r1 * Ic[3] + r2 * Ic[4];
+        T[3 * i + 1] = r0 * Ic[3] + r1 * Ic[1] + r2 * Ic[5];
+        T[3 * i + 2] = r0 * Ic[4] + r1 * Ic[5] + r2 * Ic[2];
+    }
+    const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+        Iw[e] = T[3 * ii[e]] * R.m[3 * jj[e]] + T[3 * ii[e] + 1] * R.m[3 * jj[e] + 1] +
+                T[3 * ii[e] + 2] * R.m[3 * jj[e] + 2];
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -101,81 +111,45 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Per-lane link constants of one robot.
-template <int NMAX>
-struct LaneConst {
-    bool act, revolute, fr_ident;
-    int link, parent_lane, sub_end, jidx, nsph;
-    V3 axis, fp, com;
-    M3 fR;
-    float m, I[6];
-    float4 loc[NMAX];
-};
-
-template <int NMAX>
-__device__ __forceinline__ void load_lane(LaneConst<NMAX> &C, const DevFused &fz, int L, int glane) {
-    C.act = glane < L;
-    const int i = glane;
-    C.link = C.act ? fz.li[0 * 64 + i] : 0;
-    C.parent_lane = C.act ? fz.li[1 * 64 + i] : -1;
-    C.sub_end = C.act ? fz.li[2 * 64 + i] : glane;
-    C.jidx = C.act ? fz.li[3 * 64 + i] : -1;
-    C.nsph = C.act ? fz.li[4 * 64 + i] : 0;
-    C.revolute = C.act && fz.li[5 * 64 + i] != 0;
-    C.fr_ident = !C.act || fz.li[6 * 64 + i] != 0;
-    C.axis = v3(0.f, 0.f, 1.f);
-    C.fp = v3(0.f, 0.f, 0.f);
-    C.com = v3(0.f, 0.f, 0.f);
-#pragma unroll
-    for (int t = 0; t < 9; ++t) C.fR.m[t] = (t % 4 == 0) ? 1.f : 0.f;
-    C.m = 0.f;
-#pragma unroll
-    for (int t = 0; t < 6; ++t) C.I[t] = 0.f;
-#pragma unroll
-    for (int j = 0; j < NMAX; ++j) C.loc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (C.act) {
-        const float *lf = fz.lf;
-        C.axis = v3(lf[0 * 64 + i], lf[1 * 64 + i], lf[2 * 64 + i]);
-#pragma unroll
-        for (int t = 0; t < 9; ++t) C.fR.m[t] = lf[(3 + t) * 64 + i];
-        C.fp = v3(lf[12 * 64 + i], lf[13 * 64 + i], lf[14 * 64 + i]);
-        C.m = lf[15 * 64 + i];
-        C.com = v3(lf[16 * 64 + i], lf[17 * 64 + i], lf[18 * 64 + i]);
-#pragma unroll
-        for (int t = 0; t < 6; ++t) C.I[t] = lf[(19 + t) * 64 + i];
-#pragma unroll
-        for (int j = 0; j < NMAX; ++j) C.loc[j] = fz.lsph[j * 64 + i];
-    }
-}
-
 // The whole iteration for one state per group of G lanes.  Every lane of
 // the wavefront calls this (group-local shuffles need all lanes); `valid`
 // is false for groups past the end of the batch, which compute on a copy of
-// a valid state and store nothing.
+// a valid state and store nothing.  The lane's link constants are read from
+// the lane tables at the point of use in every state (they stay in the L1
+// cache), so that no register holds them across the sweep.
 template <int NMAX, bool FULL>
-__device__ __forceinline__ void iterate_state(const DevRobot &rb, int jsteps, const LaneConst<NMAX> &C,
+__device__ __forceinline__ void iterate_state(const DevRobot &rb, const int *tab, const DevFused &fz,
                                               const TreeIO &io, const StepScalars &k, float4 *P, float4 *Bd,
                                               int *list, int G, int grp, int glane, int64_t B, int64_t b,
                                               bool valid) {
-    const int64_t jo = (int64_t)C.jidx * B + b;
+    int gl = glane;
+    asm volatile("" : "+v"(gl));   // keeps the table reads inside the state loop
+    const int *li = fz.li;
+    const float *lf = fz.lf;
+    const bool act = glane < rb.L;
+    const int parent_lane = li[1 * 64 + gl];
+    const bool revolute = li[5 * 64 + gl] != 0;
+    const int64_t jo = (int64_t)li[3 * 64 + gl] * B + b;
     float th = 0.f, thd = 0.f, thdd = 0.f;
-    if (C.revolute) {
+    if (revolute) {
         th = io.q[jo];
         thd = io.qd[jo];
         thdd = io.qdd[jo];
     }
     // ---- forward kinematics
-    M3 R = C.fR;
-    V3 p = C.fp;
-    if (C.revolute) {
+    M3 R;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) R.m[t] = lf[(3 + t) * 64 + gl];
+    V3 p = v3(lf[12 * 64 + gl], lf[13 * 64 + gl], lf[14 * 64 + gl]);
+    if (revolute) {
         float s, c;
         sincosf(th, &s, &c);
-        const M3 Jr = axis_angle(C.axis, s, c);
-        R = C.fr_ident ? Jr : matmul(C.fR, Jr);
+        const M3 Jr = axis_angle(v3(lf[0 * 64 + gl], lf[1 * 64 + gl], lf[2 * 64 + gl]), s, c);
+        R = li[6 * 64 + gl] ? Jr : matmul(R, Jr);
     }
     {
-        int anc = C.parent_lane;
-        for (int st = 0; st < jsteps; ++st) {
+        int anc = parent_lane;
+        for (int st = 0; st < fz.jsteps; ++st) {
             const int src = anc < 0 ? glane : anc;
             M3 Ra;
 #pragma unroll
@@ -190,24 +164,29 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, int jsteps, co
         }
     }
     // ---- sphere centres into the group's LDS slots
-    wave_sync();
+    const int link = li[0 * 64 + gl];
+    {
+        const int nsph = li[4 * 64 + gl];
+        wave_sync();
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j)
-        if (j < C.nsph) {
-            const V3 c = mul(R, v3(C.loc[j].x, C.loc[j].y, C.loc[j].z)) + p;
-            P[C.link * NMAX + j] = make_float4(c.x, c.y, c.z, C.loc[j].w);
-        }
-    wave_sync();
+        for (int j = 0; j < NMAX; ++j)
+            if (j < nsph) {
+                const float4 loc = fz.lsph[j * 64 + gl];
+                const V3 c = mul(R, v3(loc.x, loc.y, loc.z)) + p;
+                P[link * NMAX + j] = make_float4(c.x, c.y, c.z, loc.w);
+            }
+        wave_sync();
+    }
     // ---- self-collision
     link_bounds<NMAX>(rb, P, Bd, glane, G);
     wave_sync();
     float M;
     int key;
     unsigned cnt;
-    sweep_state<NMAX, FULL>(rb, P, Bd, list, glane, G, grp, M, key, cnt);
+    sweep_state<NMAX, FULL>(rb, tab, P, Bd, list, glane, G, grp, M, key, cnt);
     const float hmarg = M + k.margin;
     const bool hinge_on = key != INT_MAX && hmarg > 0.f && k.hinge_weight != 0.f;
-    SV W = zsv();
+    SV W = zsv();   // adjoint of the lane's joint rotation, before the subtree sum
     if (hinge_on) {
         const int s = key / rb.S, t = key - s * rb.S;
         const float4 cs = P[rb.sph_slot[s]], ct = P[rb.sph_slot[t]];
@@ -215,36 +194,39 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, int jsteps, co
         const float n = sqrtf(dot(d, d));
         if (n > 0.f) {
             const V3 g = (k.hinge_weight / n) * d;   // gradient on c_t; -g on c_s
-            if (C.act && C.link == rb.sph_link[s]) W += sv(cross(v3(cs.x, cs.y, cs.z), -g), -g);
-            if (C.act && C.link == rb.sph_link[t]) W += sv(cross(v3(ct.x, ct.y, ct.z), g), g);
+            if (act && link == rb.sph_link[s]) W += sv(cross(v3(cs.x, cs.y, cs.z), -g), -g);
+            if (act && link == rb.sph_link[t]) W += sv(cross(v3(ct.x, ct.y, ct.z), g), g);
         }
     }
-    // ---- world axes and inertias
+    // ---- world axis and inertia
     SV S = zsv();
-    if (C.revolute) {
-        const V3 sw = mul(R, C.axis);
+    if (revolute) {
+        const V3 sw = mul(R, v3(lf[0 * 64 + gl], lf[1 * 64 + gl], lf[2 * 64 + gl]));
         S = sv(sw, cross(p, sw));
     }
     WInertia J;
-    J.m = C.m;
+    {
+        J.m = lf[15 * 64 + gl];
+        J.cw = mul(R, v3(lf[16 * 64 + gl], lf[17 * 64 + gl], lf[18 * 64 + gl])) + p;
+        float Ic[6];
 #pragma unroll
-    for (int t = 0; t < 6; ++t) J.I[t] = C.I[t];
-    J.R = R;
-    J.cw = mul(R, C.com) + p;
+        for (int t = 0; t < 6; ++t) Ic[t] = lf[(19 + t) * 64 + gl];
+        rotate_inertia(R, Ic, J.I);
+    }
+    const int sub_end = li[2 * 64 + gl];
     // ---- RNEA forward
     const SV Sqd = thd * S;
-    const SV v = path_sum(Sqd, C.parent_lane, glane, jsteps, G);
-    const SV cterm = thdd * S + crm(v, Sqd);
-    SV a = path_sum(cterm, C.parent_lane, glane, jsteps, G);
-    if (C.act) a += sv(v3(0.f, 0.f, 0.f), v3(-rb.gx, -rb.gy, -rb.gz));
+    const SV v = path_sum(Sqd, parent_lane, glane, fz.jsteps, G);
+    SV a = path_sum(thdd * S + crm(v, Sqd), parent_lane, glane, fz.jsteps, G);
+    if (act) a += sv(v3(0.f, 0.f, 0.f), v3(-rb.gx, -rb.gy, -rb.gz));
     const SV Ia = iw_apply(J, a), Iv = iw_apply(J, v);
-    SV f = Ia + crf(v, Iv);
-    if (!C.act) f = zsv();
-    const SV F = subtree_sum(f, glane, C.sub_end, G);
-    const float tau = C.revolute ? dot(S, F) : 0.f;
+    SV F = Ia + crf(v, Iv);
+    if (!act) F = zsv();
+    F = subtree_sum(F, glane, sub_end, G);
+    const float tau = revolute ? dot(S, F) : 0.f;
     // ---- cost head
     float tcost = 0.f, taub = 0.f;
-    if (C.revolute) {
+    if (revolute) {
         if (io.w) {
             const float wj = io.w[jo];
             tcost = wj * tau;
@@ -254,28 +236,32 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, int jsteps, co
             taub = 2.f * k.torque_weight * tau;
         }
     }
-    for (int o = G >> 1; o > 0; o >>= 1) tcost += __shfl_xor(tcost, o, G);
-    // ---- VJP
-    const SV fb = path_sum(taub * S, C.parent_lane, glane, jsteps, G);
-    const SV ab = iw_apply(J, fb);
+    tcost = group_reduce_sum(tcost, G);
+    // ---- VJP, with the terms of W added as soon as their factors exist
+    W += taub * crf(S, F);
+    const SV fb = path_sum(taub * S, parent_lane, glane, fz.jsteps, G);
+    SV ab = iw_apply(J, fb);
+    W = W - (crf(fb, Ia) + crf(a, ab));
     const SV vxfb = crm(v, fb);
     const SV Ivxfb = iw_apply(J, vxfb);
     SV vb = zsv() - (crf(fb, Iv) + Ivxfb);
-    const SV Acc = subtree_sum(C.act ? ab : zsv(), glane, C.sub_end, G);
+    W += crf(vxfb, Iv) + crf(v, Ivxfb);
+    if (!act) ab = zsv();
+    const SV Acc = subtree_sum(ab, glane, sub_end, G);
     vb += crf(Sqd, Acc);
-    if (!C.act) vb = zsv();
+    if (!act) vb = zsv();
     const SV vxA = crf(v, Acc);
     const float thdd_b = dot(S, Acc);
-    const SV V = subtree_sum(vb, glane, C.sub_end, G);
+    W += thdd * crf(S, Acc) - thd * crf(S, vxA);
+    const SV V = subtree_sum(vb, glane, sub_end, G);
     const float thd_b = dot(S, V) - dot(S, vxA);
-    const SV Sb = taub * F + thdd * Acc - thd * vxA + thd * V;
-    W += crf(S, Sb) - crf(fb, Ia) - crf(a, ab) + crf(vxfb, Iv) + crf(v, Ivxfb);
-    if (!C.act) W = zsv();
-    const SV Ws = subtree_sum(W, glane, C.sub_end, G);
+    W += thd * crf(S, V);
+    if (!act) W = zsv();
+    const SV Ws = subtree_sum(W, glane, sub_end, G);
     const float th_b = dot(S, Ws);
     // ---- outputs and the gradient step
     if (!valid) return;
-    if (C.revolute) {
+    if (revolute) {
         if (io.tau) io.tau[jo] = tau;
         if (io.g_q) io.g_q[jo] = th_b;
         if (io.g_qd) io.g_qd[jo] = thd_b;
@@ -295,27 +281,26 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, int jsteps, co
 }
 
 // Process `count` states starting at b0 of one robot with the 4 waves of
-// this workgroup, 64/G states per wavefront at a time.
+// this workgroup, 64/G states per wavefront at a time; tab is the robot's
+// block table staged in LDS.
 template <int NMAX>
-__device__ __forceinline__ void run_states(const DevRobot &rb, const DevFused &fz, const TreeIO &io,
+__device__ __forceinline__ void run_states(const DevRobot &rb, const int *tab, const DevFused &fz, const TreeIO &io,
                                            const StepScalars &k, float4 *lds_wave, int G, int64_t B,
                                            int64_t b0, int count) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int per_wave = 64 / G, grp = lane / G, glane = lane - grp * G;
     const int SL = (rb.L + 1) * NMAX;
-    float4 *P = lds_wave + grp * (int)(group_lds_bytes(rb.L, NMAX) / 16);
+    float4 *P = lds_wave + grp * (int)(group_lds_bytes(rb.L, NMAX, rb.list_cap) / 16);
     float4 *Bd = P + SL;
     int *list = reinterpret_cast<int *>(Bd + rb.L + 1);
     wave_sync();
     for (int i = glane; i < SL; i += G) P[i] = make_float4(0.f, 0.f, 0.f, rb.slot_r[i]);
-    LaneConst<NMAX> C;
-    load_lane<NMAX>(C, fz, rb.L, glane);
     for (int base = wave * per_wave; base < count; base += 4 * per_wave) {
         const int s = base + grp;
         const bool valid = s < count;
         const int64_t b = b0 + (valid ? s : base);
-        if (G == 64) iterate_state<NMAX, true>(rb, fz.jsteps, C, io, k, P, Bd, list, 64, 0, glane, B, b, valid);
-        else iterate_state<NMAX, false>(rb, fz.jsteps, C, io, k, P, Bd, list, G, grp, glane, B, b, valid);
+        if (G == 64) iterate_state<NMAX, true>(rb, tab, fz, io, k, P, Bd, list, 64, 0, glane, B, b, valid);
+        else iterate_state<NMAX, false>(rb, tab, fz, io, k, P, Bd, list, G, grp, glane, B, b, valid);
     }
 }
 
@@ -324,7 +309,7 @@ __global__ void __launch_bounds__(256) k_fused_step(FusedArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
     const int G = A.lanes_per_state;
-    const int SLW = (64 / G) * (int)(group_lds_bytes(A.rb.L, NMAX) / 16);
+    const int SLW = (64 / G) * (int)(group_lds_bytes(A.rb.L, NMAX, A.rb.list_cap) / 16);
     // XCD-aware chunk order: consecutive chunks stay on one XCD's L2.
     const int nwg = gridDim.x, x = blockIdx.x & 7, y = blockIdx.x >> 3;
     const int qd8 = nwg >> 3, rd8 = nwg & 7;
@@ -332,7 +317,10 @@ __global__ void __launch_bounds__(256) k_fused_step(FusedArgs A) {
     const int64_t b0 = (int64_t)chunk * A.chunk;
     const int64_t rem = A.B - b0;
     const int count = rem < A.chunk ? (int)rem : A.chunk;
-    run_states<NMAX>(A.rb, A.fz, A.io, A.k, lds + wave * SLW, G, A.B, b0, count);
+    int *tab = reinterpret_cast<int *>(lds + 4 * SLW);
+    for (int i = threadIdx.x; i < A.rb.n_blocks; i += 256) tab[i] = A.rb.blocks[i];
+    __syncthreads();
+    run_states<NMAX>(A.rb, tab, A.fz, A.io, A.k, lds + wave * SLW, G, A.B, b0, count);
 }
 
 // Persistent launch over an uneven batch of robots: workgroup w processes
@@ -343,19 +331,27 @@ __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
     const int w = blockIdx.x;
+    int *tab = reinterpret_cast<int *>(lds + 4 * A.wave_stride);
+    int staged = -1;   // tree whose block table is in LDS
     for (int it = A.item_start[w]; it < A.item_start[w + 1]; ++it) {
         const PlanItem item = A.items[it];
         const PlanTree T = ldu(A.trees + item.tree);
         const int G = T.lanes_per_state;
-        // a fixed region per wave: waves of one workgroup may be on different trees
-        run_states<NMAX>(T.rb, T.fz, A.io[item.tree], A.k, lds + wave * A.wave_stride, G, T.B, item.b0,
+        if (item.tree != staged) {
+            __syncthreads();   // every wave is done with the previous table
+            for (int i = threadIdx.x; i < T.rb.n_blocks; i += 256) tab[i] = T.rb.blocks[i];
+            __syncthreads();
+            staged = item.tree;
+        }
+        // a fixed region per wave, sized for the plan's largest tree
+        run_states<NMAX>(T.rb, tab, T.fz, A.io[item.tree], A.k, lds + wave * A.wave_stride, G, T.B, item.b0,
                          item.count);
     }
 }
 
 template <int NMAX>
 static hipError_t launch_fused_t(const FusedArgs &a, hipStream_t s) {
-    const size_t lds = (size_t)4 * (64 / a.lanes_per_state) * group_lds_bytes(a.rb.L, NMAX);
+    const size_t lds = fused_lds_bytes(a.rb.L, NMAX, a.rb.list_cap, a.lanes_per_state, a.rb.n_blocks_pad);
     const unsigned nwg = (unsigned)((a.B + a.chunk - 1) / a.chunk);
     hipLaunchKernelGGL(k_fused_step<NMAX>, dim3(nwg), dim3(256), lds, s, a);
     return hipGetLastError();

@@ -5,8 +5,9 @@
 
 namespace wb {
 
-// LDS: TS states x [(L+1)*NMAX slots | (L+1) link bounds], then 4 lists.
-template <int NMAX>
+// LDS: TS states x [(L+1)*NMAX slots | (L+1) link bounds], then 4 lists of
+// rb.list_cap ints (one per wavefront), then (TAB_LDS) the block table.
+template <int NMAX, bool TAB_LDS>
 __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, int TS,
                                                         const float *__restrict__ sph,
                                                         float *__restrict__ max_pen,
@@ -17,6 +18,13 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, 
     const int SLB = SL + rb.L + 1;
     const int64_t b0 = (int64_t)blockIdx.x * TS;
     const int tid = threadIdx.x;
+    int *lists = reinterpret_cast<int *>(lds + TS * SLB);
+    const int *tab = rb.blocks;
+    if (TAB_LDS) {
+        int *t = lists + 4 * rb.list_cap;
+        for (int i = tid; i < rb.n_blocks; i += 256) t[i] = rb.blocks[i];
+        tab = t;
+    }
     for (int i = tid; i < TS * SLB; i += 256) {
         const int st = i / SLB, o = i - st * SLB;
         lds[i] = make_float4(0.f, 0.f, 0.f, o < SL ? rb.slot_r[o] : -1e30f);
@@ -34,7 +42,7 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, 
     __syncthreads();
 
     const int wave = tid >> 6, lane = tid & 63;
-    int *list = reinterpret_cast<int *>(lds + TS * SLB) + wave * (SWEEP_LIST_BYTES / 4);
+    int *list = lists + wave * rb.list_cap;
     for (int st = wave; st < TS; st += 4) {
         const int64_t b = b0 + st;
         if (b >= B) break;
@@ -46,7 +54,7 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, 
         float M;
         int key;
         unsigned cnt;
-        sweep_state<NMAX, true>(rb, P, Bd, list, lane, 64, 0, M, key, cnt);
+        sweep_state<NMAX, true>(rb, tab, P, Bd, list, lane, 64, 0, M, key, cnt);
         if (lane == 0) {
             if (max_pen) max_pen[b] = M;
             if (argmax) argmax[b] = pair_index(rb, key);
@@ -55,22 +63,42 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, 
     }
 }
 
-int self_collision_tile(int L, int nmax) {
-    const int per_state = (int)state_lds_bytes(L, nmax);
-    int ts = (65536 - 4 * SWEEP_LIST_BYTES) / per_state;
+// States per workgroup that fit the LDS limit next to `fixed` bytes.
+static int sc_tile(size_t per_state, size_t fixed) {
+    int ts = (int)((LDS_LIMIT - fixed) / per_state);
     if (ts > 16) ts = 16;
     if (ts >= 4) ts &= ~3;
     if (ts < 1) ts = 1;
     return ts;
 }
 
+int self_collision_tile(int L, int nmax, int list_cap) {
+    return sc_tile(state_lds_bytes(L, nmax), (size_t)16 * list_cap);
+}
+
+// The block table goes to LDS when one state, the four lists and the table
+// fit; otherwise the lists shrink to fit beside one state and the table is
+// read from device memory.
 template <int NMAX>
-static hipError_t launch_sc(const DevRobot &rb, int64_t B, const float *sph, float *mp, int32_t *am,
+static hipError_t launch_sc(const DevRobot &rb0, int64_t B, const float *sph, float *mp, int32_t *am,
                             int32_t *nc, hipStream_t s) {
-    const int TS = self_collision_tile(rb.L, NMAX);
-    const size_t lds = (size_t)TS * state_lds_bytes(rb.L, NMAX) + 4 * SWEEP_LIST_BYTES;
-    dim3 grid((unsigned)((B + TS - 1) / TS));
-    hipLaunchKernelGGL(k_self_collision<NMAX>, grid, dim3(256), lds, s, rb, B, TS, sph, mp, am, nc);
+    DevRobot rb = rb0;
+    const size_t per_state = state_lds_bytes(rb.L, NMAX);
+    const size_t tab = tab_lds_bytes(rb.n_blocks_pad);
+    dim3 block(256);
+    if (per_state + (size_t)16 * rb.list_cap + tab <= LDS_LIMIT) {
+        const int TS = sc_tile(per_state, (size_t)16 * rb.list_cap + tab);
+        const size_t lds = (size_t)TS * per_state + (size_t)16 * rb.list_cap + tab;
+        dim3 grid((unsigned)((B + TS - 1) / TS));
+        hipLaunchKernelGGL((k_self_collision<NMAX, true>), grid, block, lds, s, rb, B, TS, sph, mp, am, nc);
+    } else {
+        const int room = (int)((LDS_LIMIT - per_state) / 16) / 64 * 64;
+        if (room < rb.list_cap) rb.list_cap = room;
+        const int TS = self_collision_tile(rb.L, NMAX, rb.list_cap);
+        const size_t lds = (size_t)TS * per_state + (size_t)16 * rb.list_cap;
+        dim3 grid((unsigned)((B + TS - 1) / TS));
+        hipLaunchKernelGGL((k_self_collision<NMAX, false>), grid, block, lds, s, rb, B, TS, sph, mp, am, nc);
+    }
     return hipGetLastError();
 }
 

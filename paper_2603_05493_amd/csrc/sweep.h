@@ -6,9 +6,7 @@
 // pair (a < b) contributes all spheres of a times all spheres of b.  The
 // state's sphere centres sit in LDS, padded to NMAX slots per link (empty
 // slots carry radius -1e30, so they can neither be the maximum nor count as
-// a collision), plus one all-empty row for padding blocks.  A lane owns a
-// whole link block: it loads the NMAX + NMAX centres into registers once and
-// evaluates NMAX * NMAX pairs.
+// a collision), plus one all-empty row for padding.
 //
 // Broad phase (exact): each link gets a bounding sphere (centroid C_a of its
 // sphere centres, reach R_a = max |c - C_a| + r), and no pair of block (a, b)
@@ -18,25 +16,32 @@
 // no pair that is the maximum, ties it, or collides; they are skipped.  eps
 // covers the FP32 rounding of both the bound and the pair penetrations (all
 // computed from the same FP32 centres), so the result is identical to the
-// full sweep.  Survivors are compacted into an LDS list per chunk of blocks
-// so the pair loop stays lane-dense.
+// full sweep.
+//
+// The bounds go to the group's LDS list once; the survivors' link pairs are
+// compacted in place into the same list (a survivor's list position never
+// exceeds its block index), and the pair loop runs over rows -- (block,
+// sphere slot of the first link) against the NMAX slots of the second link
+// -- so that the lanes stay dense whatever the number of survivors.  Robots
+// with more blocks than the list holds are swept in chunks, recomputing the
+// bounds.  The block table itself is read from LDS where the caller has
+// staged it, so no step of the sweep waits on device memory.
 //
 // Reduce: the pair count is a scalar ballot popcount per pair (one state per
 // wavefront) or a per-lane counter summed over the group; the maximum is a
-// per-lane running max per block plus a group shuffle reduction.  The lowest
-// pair index attaining the maximum is recovered exactly: lanes holding the
-// maximum re-evaluate the block where their running max was set with the
-// same arithmetic and report the lowest (s, t) whose penetration equals it;
-// if any lane saw two of its blocks tie the maximum, the group rescans every
+// per-lane running max plus a group reduction.  The lowest pair index
+// attaining the maximum is recovered exactly: lanes holding the maximum
+// re-evaluate the row where their running max was set with the same
+// arithmetic and report the lowest (s, t) whose penetration equals it; if
+// any lane saw two of its rows tie the maximum, the group rescans every
 // block instead.
 #pragma once
 
 #include <climits>
+#include "lanes.h"
 #include "spatial.h"
 
 namespace wb {
-
-constexpr int SWEEP_CHUNK = 256;   // blocks per compaction chunk (list entries per group)
 
 // Penetration depth of one sphere pair; .w is the radius.  Written with
 // explicit fused multiply-adds so every evaluation rounds identically.
@@ -46,39 +51,32 @@ __device__ __forceinline__ float pair_pen(float4 A, float4 Bv) {
     return (A.w + Bv.w) - __builtin_amdgcn_sqrtf(d2);
 }
 
-__device__ __forceinline__ float group_max(float v, int G) {
-    for (int o = G >> 1; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, G));
-    return v;
-}
-__device__ __forceinline__ int group_min(int v, int G) {
-    for (int o = G >> 1; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, G));
-    return v;
-}
-__device__ __forceinline__ unsigned group_sum(unsigned v, int G) {
-    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-    return v;
-}
-
 __device__ __forceinline__ float block_bound(const float4 *Bd, int ab) {
     const float4 A = Bd[ab >> 16], Bv = Bd[ab & 0xffff];
     const float dx = A.x - Bv.x, dy = A.y - Bv.y, dz = A.z - Bv.z;
     return (A.w + Bv.w) - __builtin_amdgcn_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
 }
 
+// Lowest sphere key s*S + t in row i of link pair ab = (a << 16) | b whose
+// penetration equals M.
 template <int NMAX>
-__device__ __forceinline__ int block_min_key(const DevRobot &rb, const float4 *P, int blk, float M) {
-    const int ab = rb.blocks[blk];
+__device__ __forceinline__ int row_min_key(const DevRobot &rb, const float4 *P, int ab, int i, float M) {
     const int a = ab >> 16, bb = ab & 0xffff;
     if (a >= rb.L) return INT_MAX;
-    const int fa = rb.li[a].sph_first, fb = rb.li[bb].sph_first;
+    const float4 A = P[a * NMAX + i];
+    const int s = rb.li[a].sph_first + i, fb = rb.li[bb].sph_first;
 #pragma unroll
-    for (int i = 0; i < NMAX; ++i) {
-        const float4 A = P[a * NMAX + i];
-#pragma unroll
-        for (int j = 0; j < NMAX; ++j)
-            if (pair_pen(A, P[bb * NMAX + j]) == M) return (fa + i) * rb.S + (fb + j);
-    }
+    for (int j = 0; j < NMAX; ++j)
+        if (pair_pen(A, P[bb * NMAX + j]) == M) return s * rb.S + (fb + j);
     return INT_MAX;
+}
+
+template <int NMAX>
+__device__ __forceinline__ int block_min_key(const DevRobot &rb, const float4 *P, int ab, float M) {
+    int key = INT_MAX;
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) key = min(key, row_min_key<NMAX>(rb, P, ab, i, M));
+    return key;
 }
 
 // Bounding sphere of every link's (non-empty) sphere slots, into Bd[0..L).
@@ -115,91 +113,120 @@ __device__ __forceinline__ void link_bounds(const DevRobot &rb, const float4 *P,
     }
 }
 
-// Sweep one state.  P: the state's (L+1)*NMAX sphere slots; Bd: its link
-// bounding spheres (link_bounds); list: SWEEP_CHUNK ints of LDS scratch for
-// this group.  Every lane of the group returns the maximum penetration M,
+// Sweep one state.  tab: the robot's block table (rb.blocks or an LDS copy);
+// P: the state's (L+1)*NMAX sphere slots; Bd: its link bounding spheres
+// (link_bounds); list: rb.list_cap ints of LDS scratch for this group.  Every lane of the group returns the maximum penetration M,
 // the sphere key s*S + t of the lowest pair attaining it (INT_MAX if none)
 // and the number of pairs with positive penetration.  FULL: G == 64.
 template <int NMAX, bool FULL>
-__device__ __forceinline__ void sweep_state(const DevRobot &rb, const float4 *P, const float4 *Bd, int *list,
+__device__ __forceinline__ void sweep_state(const DevRobot &rb, const int *tab, const float4 *P, const float4 *Bd,
+                                            int *list,
                                             int glane, int G, int grp, float &M_out, int &key_out,
                                             unsigned &cnt_out) {
-    const int nb = (rb.n_blocks + G - 1) / G * G;
+    const int n = rb.n_blocks;
+    const int nb = (n + G - 1) / G * G;
+    const int cap = rb.list_cap;
+    const bool one_chunk = nb <= cap;
+    float *bnd = reinterpret_cast<float *>(list);
     const uint64_t gmask = FULL ? ~0ull : ((1ull << G) - 1ull);
     const int gshift = FULL ? 0 : grp * G;
+    const uint64_t below = (1ull << glane) - 1ull;
     // extent of the robot in this state, for the rounding margin
     float ext = 0.f;
     for (int a = glane; a < rb.L; a += G) {
         const float4 c = Bd[a];
-        if (c.w > -1e29f) ext = fmaxf(ext, sqrtf(c.x * c.x + c.y * c.y + c.z * c.z) + c.w);
+        if (c.w > -1e29f)
+            ext = fmaxf(ext, __builtin_amdgcn_sqrtf(__builtin_fmaf(c.x, c.x, __builtin_fmaf(c.y, c.y, c.z * c.z))) + c.w);
     }
-    const float eps = 4e-6f * (1.f + group_max(ext, G));
-    // seed: exact maximum of the block with the largest bound
+    const float eps = 4e-6f * (1.f + group_reduce_max(ext, G));
+    // every block's bound (kept in the list when it fits) and the block with
+    // the largest bound, two blocks per lane per step
     float bmax = -INFINITY;
     int bblk = INT_MAX;
-    for (int base = 0; base < nb; base += G) {
-        const int blk = base + glane;
-        if (blk < rb.n_blocks) {
-            const float bd = block_bound(Bd, rb.blocks[blk]);
-            if (bd > bmax) {
-                bmax = bd;
-                bblk = blk;
-            }
+    for (int base = 0; base < nb; base += 2 * G) {
+        const int k0 = base + glane, k1 = k0 + G;
+        const bool v0 = k0 < n, v1 = k1 < n;
+        const int ab0 = v0 ? tab[k0] : 0, ab1 = v1 ? tab[k1] : 0;
+        const float d0 = v0 ? block_bound(Bd, ab0) : -INFINITY;
+        const float d1 = v1 ? block_bound(Bd, ab1) : -INFINITY;
+        if (one_chunk) {
+            if (v0) bnd[k0] = d0;
+            if (v1) bnd[k1] = d1;
+        }
+        if (d0 > bmax) {
+            bmax = d0;
+            bblk = k0;
+        }
+        if (d1 > bmax) {
+            bmax = d1;
+            bblk = k1;
         }
     }
-    const float gbmax = group_max(bmax, G);
-    const int cand = group_min(bmax == gbmax ? bblk : INT_MAX, G);
+    const float gbmax = group_reduce_max(bmax, G);
+    const int cand = group_reduce_min(bmax == gbmax ? bblk : INT_MAX, G);
+    // seed: exact maximum of that block
     float seed = -INFINITY;
     if (cand != INT_MAX) {
-        const int ab = rb.blocks[cand];
+        const int ab = tab[cand];
         const int a = ab >> 16, bb = ab & 0xffff;
         for (int j = glane; j < NMAX * NMAX; j += G) {
             const int i = j / NMAX, k = j - i * NMAX;
             seed = fmaxf(seed, pair_pen(P[a * NMAX + i], P[bb * NMAX + k]));
         }
     }
-    const float theta = fminf(group_max(seed, G), 0.f) - eps;
+    const float theta = fminf(group_reduce_max(seed, G), 0.f) - eps;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 
     float best = -INFINITY;
-    int best_blk = -1;
+    int best_code = -1;   // link pair * NMAX + row of the running maximum
     bool tie = false;
     unsigned cnt = 0;
-    for (int c0 = 0; c0 < nb; c0 += SWEEP_CHUNK) {
-        const int cend = min(c0 + SWEEP_CHUNK, nb);
+    for (int c0 = 0; c0 < nb; c0 += cap) {
+        const int cend = min(c0 + cap, nb);
+        // compaction of the chunk's surviving link pairs into list[0, nl)
         int nl = 0;
-        for (int base = c0; base < cend; base += G) {
-            const int blk = base + glane;
-            const bool surv = blk < rb.n_blocks && block_bound(Bd, rb.blocks[blk]) >= theta;
-            const uint64_t m = (__ballot(surv) >> gshift) & gmask;
-            if (surv) list[nl + __popcll(m & ((1ull << glane) - 1ull))] = blk;
-            nl += __popcll(m);
+        for (int base = c0; base < cend; base += 2 * G) {
+            const int k0 = base + glane, k1 = k0 + G;
+            const bool v0 = k0 < n, v1 = k1 < cend && k1 < n;
+            const int ab0 = v0 ? tab[k0] : 0, ab1 = v1 ? tab[k1] : 0;
+            bool s0, s1;
+            if (one_chunk) {
+                s0 = v0 && bnd[k0] >= theta;
+                s1 = v1 && bnd[k1] >= theta;
+            } else {
+                s0 = v0 && block_bound(Bd, ab0) >= theta;
+                s1 = v1 && block_bound(Bd, ab1) >= theta;
+            }
+            const uint64_t m0 = (__ballot(s0) >> gshift) & gmask;
+            const uint64_t m1 = (__ballot(s1) >> gshift) & gmask;
+            const int n0 = __popcll(m0);
+            if (s0) list[nl + __popcll(m0 & below)] = ab0;
+            if (s1) list[nl + n0 + __popcll(m1 & below)] = ab1;
+            nl += n0 + __popcll(m1);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        for (int j = 0; j < nl; j += G) {
-            const int idx = j + glane;
-            const int blk = idx < nl ? list[idx] : -1;
-            const int ab = blk >= 0 ? rb.blocks[blk] : ((rb.L << 16) | rb.L);
+        // pair loop over rows (list entry j / NMAX, slot j % NMAX)
+        const int items = nl * NMAX;
+        for (int j0 = 0; j0 < items; j0 += G) {
+            const int it = j0 + glane;
+            const bool ok = it < items;
+            const int e = it / NMAX, row = it - e * NMAX;
+            const int ab = ok ? list[e] : ((rb.L << 16) | rb.L);
             const int a = ab >> 16, bb = ab & 0xffff;
-            float4 A[NMAX], Bv[NMAX];
-#pragma unroll
-            for (int i = 0; i < NMAX; ++i) {
-                A[i] = P[a * NMAX + i];
-                Bv[i] = P[bb * NMAX + i];
-            }
+            const float4 A = P[a * NMAX + row];
             float m = -INFINITY;
 #pragma unroll
-            for (int i = 0; i < NMAX; ++i)
-#pragma unroll
-                for (int k = 0; k < NMAX; ++k) {
-                    const float pen = pair_pen(A[i], Bv[k]);
-                    m = fmaxf(m, pen);
-                    if (FULL) cnt += (unsigned)__popcll(__ballot(pen > 0.0f));
-                    else cnt += pen > 0.0f ? 1u : 0u;
-                }
+            for (int k = 0; k < NMAX; ++k) {
+                const float pen = pair_pen(A, P[bb * NMAX + k]);
+                m = fmaxf(m, pen);
+                if (FULL) cnt += (unsigned)__popcll(__ballot(pen > 0.0f));
+                else cnt += pen > 0.0f ? 1u : 0u;
+            }
             if (m > best) {
                 best = m;
-                best_blk = blk;
+                best_code = ok ? ab * NMAX + row : -1;
                 tie = false;
             } else if (m == best) {
                 tie = true;
@@ -208,18 +235,19 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const float4 *P,
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
-    const float M = group_max(best, G);
+    const float M = group_reduce_max(best, G);
     int key = INT_MAX;
-    const bool holder = best == M && M > -INFINITY && best_blk >= 0;
-    const int rescan = group_min((holder && tie) ? 0 : 1, G) == 0;
+    const bool holder = best == M && M > -INFINITY && best_code >= 0;
+    const bool rescan = group_reduce_min((holder && tie) ? 0 : 1, G) == 0;
     if (rescan) {
-        for (int blk = glane; blk < nb; blk += G) key = min(key, block_min_key<NMAX>(rb, P, blk, M));
+        for (int blk = glane; blk < n; blk += G) key = min(key, block_min_key<NMAX>(rb, P, tab[blk], M));
     } else if (holder) {
-        key = block_min_key<NMAX>(rb, P, best_blk, M);
+        const int ab = best_code / NMAX;
+        key = row_min_key<NMAX>(rb, P, ab, best_code - ab * NMAX, M);
     }
     M_out = M;
-    key_out = group_min(key, G);
-    cnt_out = FULL ? cnt : group_sum(cnt, G);
+    key_out = group_reduce_min(key, G);
+    cnt_out = FULL ? cnt : group_reduce_sum_u(cnt, G);
 }
 
 // Pair index (lexicographic in (s, t)) of a sphere key s*S + t.

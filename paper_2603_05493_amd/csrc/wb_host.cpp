@@ -39,6 +39,7 @@ struct Tables {
     std::vector<float> slot_r;
     std::vector<int32_t> blocks;      // padded to a multiple of 64
     int n_blocks = 0;
+    int list_cap = 64;                // ints of the sweep's per-group LDS list
     std::vector<int32_t> pair_off, pair_cnt, pair_s, pair_t;
     int64_t n_pairs = 0;
     float g[3] = {0, 0, 0};
@@ -61,6 +62,8 @@ void build_fused(Tables &T) {
     const int L = T.L;
     T.fused = 0;
     if (L > 64 || !T.simple) return;
+    const int g_default = L <= 16 ? 16 : (L <= 32 ? 32 : 64);
+    if (wb::fused_lds_bytes(L, T.nmax, T.list_cap, g_default, (int)T.blocks.size()) > wb::LDS_LIMIT) return;
     std::vector<std::vector<int>> kids(L);
     for (int k = 1; k < L; ++k) kids[T.li[k].parent].push_back(k);
     std::vector<int> perm, stack{0};
@@ -94,6 +97,15 @@ void build_fused(Tables &T) {
         for (int c = 0; c < 3; ++c) T.f_lf[(16 + c) * 64 + i] = F.com[c];
         for (int c = 0; c < 6; ++c) T.f_lf[(19 + c) * 64 + i] = F.I[c];
         for (int j = 0; j < I.sph_count; ++j) T.f_sph[(size_t)j * 64 + i] = T.sph[I.sph_first + j];
+    }
+    // lanes past the robot: an empty massless link with no parent and no joint
+    for (int i = L; i < 64; ++i) {
+        T.f_li[0 * 64 + i] = -1;
+        T.f_li[1 * 64 + i] = -1;
+        T.f_li[2 * 64 + i] = i;
+        T.f_li[3 * 64 + i] = -1;
+        T.f_li[6 * 64 + i] = 1;
+        for (int c = 0; c < 9; c += 4) T.f_lf[(3 + c) * 64 + i] = 1.0f;
     }
     int js = 0;
     while ((1 << js) < T.max_depth + 1) ++js;
@@ -214,7 +226,7 @@ int build_tables(const wb_robot_desc *d, Tables &T) {
     if (nmax > WB_MAX_SPHERES_PER_LINK)
         return fail(WB_ERR_UNSUPPORTED, "%d spheres on one link exceeds %d", nmax, WB_MAX_SPHERES_PER_LINK);
     T.nmax = nmax;
-    if (wb::state_lds_bytes(L, nmax) + 4 * wb::SWEEP_LIST_BYTES > 65536)
+    if (wb::state_lds_bytes(L, nmax) + 16 * 64 > wb::LDS_LIMIT)
         return fail(WB_ERR_UNSUPPORTED, "(links + 1) x spheres-per-link slots (%d x %d) exceed the 64 KB LDS tile",
                     L + 1, nmax);
     T.sph.resize(S);
@@ -257,6 +269,7 @@ int build_tables(const wb_robot_desc *d, Tables &T) {
     }
     T.n_blocks = (int)T.blocks.size();
     while (T.blocks.size() % 64) T.blocks.push_back((L << 16) | L);
+    T.list_cap = wb::sweep_list_cap(T.n_blocks);
     T.pair_off.resize(S);
     int64_t off = 0;
     for (int s = 0; s < S; ++s) {
@@ -321,10 +334,14 @@ wb_tune default_tune(int L) {
     return t;
 }
 
-int check_tune(const wb_tune &t, int L) {
+int check_tune(const wb_tune &t, const Tables &T) {
     const int g = t.lanes_per_state;
     if (g != 16 && g != 32 && g != 64) return fail(WB_ERR_INVALID_ARG, "lanes_per_state must be 16, 32 or 64");
-    if (g < L) return fail(WB_ERR_INVALID_ARG, "lanes_per_state %d is below the %d links", g, L);
+    if (g < T.L) return fail(WB_ERR_INVALID_ARG, "lanes_per_state %d is below the %d links", g, T.L);
+    const size_t need = wb::fused_lds_bytes(T.L, T.nmax, T.list_cap, g, (int)T.blocks.size());
+    if (need > wb::LDS_LIMIT)
+        return fail(WB_ERR_UNSUPPORTED, "lanes_per_state %d needs %zu bytes of LDS per workgroup (> %zu)", g, need,
+                    wb::LDS_LIMIT);
     if (t.states_per_item < 1 || t.states_per_item > 4096)
         return fail(WB_ERR_INVALID_ARG, "states_per_item must be in [1, 4096]");
     if (!(t.ns_per_state >= 0.0f) || !std::isfinite(t.ns_per_state))
@@ -426,6 +443,7 @@ int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
     D.max_depth = T.max_depth; D.simple_joints = T.simple;
     D.n_pairs = T.n_pairs;
     D.gx = T.g[0]; D.gy = T.g[1]; D.gz = T.g[2];
+    D.list_cap = T.list_cap;
     D.lf = reinterpret_cast<const wb::LinkF *>(base + o_lf);
     D.li = reinterpret_cast<const wb::LinkI *>(base + o_li);
     D.sph = reinterpret_cast<const float4 *>(base + o_sph);
@@ -649,7 +667,7 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, flo
 int wb_robot_set_tune(wb_robot *robot, const wb_tune *tune) {
     WB_TRY(check_robot(robot));
     if (!tune) return fail(WB_ERR_INVALID_ARG, "tune is null");
-    WB_TRY(check_tune(*tune, robot->T.L));
+    WB_TRY(check_tune(*tune, robot->T));
     robot->tune = *tune;
     return WB_OK;
 }
@@ -667,7 +685,7 @@ int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune) {
 
 struct wb_plan {
     int n_trees = 0, nmax = 1, n_wg = 0, n_items = 0, device = -1;
-    size_t lds = 0;
+    size_t lds = 0, wave_lds = 0;   // LDS per workgroup, and per wavefront region
     std::vector<int64_t> B;
     std::vector<int> n_dof;
     void *dmem = nullptr;
@@ -711,14 +729,18 @@ int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_tr
         device = robots[i]->device;
         nmax = std::max(nmax, robots[i]->T.nmax);
         tunes[i] = tune ? tune[i] : robots[i]->tune;
-        WB_TRY(check_tune(tunes[i], robots[i]->T.L));
+        WB_TRY(check_tune(tunes[i], robots[i]->T));
     }
-    size_t lds = 0;
+    size_t wave_lds = 0, tab_lds = 0;
     for (int i = 0; i < n_trees; ++i) {
-        const size_t per_wave = (size_t)(64 / tunes[i].lanes_per_state) * wb::group_lds_bytes(robots[i]->T.L, nmax);
-        lds = std::max(lds, 4 * per_wave);
+        const size_t per_wave = (size_t)(64 / tunes[i].lanes_per_state) *
+                                wb::group_lds_bytes(robots[i]->T.L, nmax, robots[i]->T.list_cap);
+        wave_lds = std::max(wave_lds, per_wave);
+        tab_lds = std::max(tab_lds, wb::tab_lds_bytes((int)robots[i]->T.blocks.size()));
     }
-    if (lds > 65536) return fail(WB_ERR_UNSUPPORTED, "plan needs %zu bytes of LDS per workgroup (> 64 KB)", lds);
+    const size_t lds = 4 * wave_lds + tab_lds;
+    if (lds > wb::LDS_LIMIT)
+        return fail(WB_ERR_UNSUPPORTED, "plan needs %zu bytes of LDS per workgroup (> %zu)", lds, wb::LDS_LIMIT);
 
     // Work items: contiguous state ranges of one tree, balanced over the
     // workgroups of one persistent wave of the launch (longest item first).
@@ -820,6 +842,7 @@ int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_tr
     p->n_items = (int)flat.size();
     p->device = device;
     p->lds = lds;
+    p->wave_lds = wave_lds;
     p->B.assign(B, B + n_trees);
     for (int i = 0; i < n_trees; ++i) p->n_dof.push_back(robots[i]->T.n);
     p->d_trees = reinterpret_cast<const wb::PlanTree *>(base + o_trees);
@@ -839,7 +862,7 @@ int wb_plan_run(const wb_plan *plan, const wb_tree_io *io, float torque_weight, 
     a.trees = plan->d_trees;
     a.items = plan->d_items;
     a.item_start = plan->d_item_start;
-    a.wave_stride = (int32_t)(plan->lds / 4 / 16);
+    a.wave_stride = (int32_t)(plan->wave_lds / 16);
     a.k = wb::StepScalars{torque_weight, margin, hinge_weight, lr};
     for (int i = 0; i < plan->n_trees; ++i) {
         const wb_tree_io &x = io[i];

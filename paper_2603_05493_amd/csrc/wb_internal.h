@@ -39,7 +39,8 @@ struct DevRobot {
     int32_t L, n, S, nmax;        // nmax: sphere slots per link (max spheres on a link)
     int32_t n_blocks, n_blocks_pad, max_depth, simple_joints;  // simple: one link per actuated joint, mult 1, offset 0
     int64_t n_pairs;
-    float gx, gy, gz, pad0;
+    float gx, gy, gz;
+    int32_t list_cap;             // ints of the per-group LDS list of the pair sweep (multiple of 64)
     const LinkF *__restrict__ lf;         // [L]
     const LinkI *__restrict__ li;         // [L]
     const float4 *__restrict__ sph;       // [S] local centre + radius
@@ -61,6 +62,8 @@ struct DevRobot {
 //   lf[f*64 + i]: f = 0..2 axis, 3..11 fixed R, 12..14 fixed p, 15 mass,
 //                 16..18 CoM, 19..24 inertia (xx yy zz xy xz yz)
 //   lsph[j*64 + i]: local centre and radius of the link's j-th sphere
+// Lanes past the last link hold an empty link: link -1, parent -1, subtree
+// end i, no joint, no spheres, identity fixed rotation, zero mass.
 struct DevFused {
     int32_t supported;   // L <= 64 and one link per actuated joint without mimic scaling
     int32_t jsteps;      // pointer-jumping steps, ceil(log2(max_depth + 1))
@@ -112,7 +115,8 @@ struct PlanArgs {
     const PlanTree *trees;
     const PlanItem *items;        // grouped by workgroup
     const int32_t *item_start;    // [n_wg + 1]
-    int32_t wave_stride;          // float4s of LDS per wave (the largest over the plan's trees)
+    int32_t wave_stride;          // float4s of LDS per wave (the largest over the plan's trees);
+                                  // the block table follows the four waves' regions
     StepScalars k;
     TreeIO io[WB_PLAN_MAX_TREES];
 };
@@ -145,15 +149,28 @@ hipError_t launch_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, 
                            const float *g_qdd, hipStream_t s);
 
 // LDS of one state's sweep: (L+1)*nmax sphere slots and L+1 link bounding
-// spheres (float4 each); plus, per sweeping group, a list of 256 block ids.
-constexpr int SWEEP_LIST_BYTES = 256 * 4;
-__host__ __device__ inline size_t state_lds_bytes(int L, int nmax) { return (size_t)(L + 1) * (nmax + 1) * 16; }
-__host__ __device__ inline size_t group_lds_bytes(int L, int nmax) {
-    return state_lds_bytes(L, nmax) + SWEEP_LIST_BYTES;
+// spheres (float4 each); plus, per sweeping group, a list of list_cap ints
+// (block bounds, then the surviving block ids).
+constexpr int SWEEP_LIST_MAX = 2048;
+inline int sweep_list_cap(int n_blocks) {
+    int c = (n_blocks + 63) / 64 * 64;
+    return c < 64 ? 64 : (c > SWEEP_LIST_MAX ? SWEEP_LIST_MAX : c);
 }
+__host__ __device__ inline size_t state_lds_bytes(int L, int nmax) { return (size_t)(L + 1) * (nmax + 1) * 16; }
+__host__ __device__ inline size_t group_lds_bytes(int L, int nmax, int list_cap) {
+    return state_lds_bytes(L, nmax) + (size_t)list_cap * 4;
+}
+// LDS copy of the block table (n_blocks_pad ints, a multiple of 64).
+__host__ __device__ inline size_t tab_lds_bytes(int n_blocks_pad) { return (size_t)n_blocks_pad * 4; }
+// LDS of a 256-lane workgroup of the fused kernels with G lanes per state:
+// four wavefronts' group regions, then the block table.
+inline size_t fused_lds_bytes(int L, int nmax, int list_cap, int G, int n_blocks_pad) {
+    return (size_t)4 * (64 / G) * group_lds_bytes(L, nmax, list_cap) + tab_lds_bytes(n_blocks_pad);
+}
+constexpr size_t LDS_LIMIT = 65536;
 
 // States per workgroup of the self-collision kernel (LDS tile).
-int self_collision_tile(int L, int nmax);
+int self_collision_tile(int L, int nmax, int list_cap);
 
 // Workspace floats per state needed by the backward kernels.
 inline int64_t workspace_floats_per_state(int L) { return (int64_t)L * 18 + 8; }

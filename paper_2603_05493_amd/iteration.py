@@ -104,3 +104,73 @@ class FusedIteration:
         wb.wb_wholebody_step(self.robot, q, qd, qdd, self.w, self.tw, self.margin, self.hw,
                              self.lr if step else 0.0, self.tau, self.cost, self.max_pen, self.argmax,
                              self.n_coll, self.g_q, self.g_qd, self.g_qdd)
+
+
+class OptimizerGraph:
+    """``iters`` fused iterations with the gradient step, captured in one HIP
+    graph (the paper captures the optimizer's inner loop as a CUDA graph,
+    Sec. 7.2).  At every ``every``-th iteration i, device-to-device copies
+    record the state x_i = (q, qd, qdd) before its step, the gradient of the
+    cost at x_i, the cost and the maximum penetration into ``hist``, so a run
+    can be checked afterwards without host round trips.  Snapshot iterations
+    run the kernel with its per-joint outputs enabled; the others write only
+    the state and the per-state scalars.
+
+    q, qd, qdd: [n][B] device tensors, updated in place by every iteration.
+    """
+
+    def __init__(self, robot: wb.Robot, q: torch.Tensor, qd: torch.Tensor, qdd: torch.Tensor,
+                 iters: int = 100, every: int = 10, w: Optional[torch.Tensor] = None,
+                 torque_weight: float = 1e-3, margin: float = 0.01, hinge_weight: float = 1.0,
+                 lr: float = 1e-3):
+        if iters < 1 or every < 1:
+            raise ValueError("iters and every must be >= 1")
+        B = q.shape[-1]
+        kw = dict(w=w, torque_weight=torque_weight, margin=margin, hinge_weight=hinge_weight, lr=lr)
+        self.q, self.qd, self.qdd = q, qd, qdd
+        self.lean = FusedIteration(robot, B, outputs=False, **kw)
+        self.full = FusedIteration(robot, B, outputs=True, **kw)
+        self.iters, self.every = iters, every
+        ns = (iters + every - 1) // every
+        n = robot.n_dof
+        e = lambda *shape: torch.empty(shape, dtype=torch.float32, device=q.device)
+        self.hist = {k: e(ns, n, B) for k in ("q", "qd", "qdd", "g_q", "g_qd", "g_qdd")}
+        self.hist["cost"], self.hist["max_pen"] = e(ns, B), e(ns, B)
+        self.graph = None
+
+    def _body(self) -> None:
+        h = self.hist
+        for i in range(self.iters):
+            k, r = divmod(i, self.every)
+            if r:
+                self.lean.run(self.q, self.qd, self.qdd, step=True)
+                continue
+            for name, x in (("q", self.q), ("qd", self.qd), ("qdd", self.qdd)):
+                h[name][k].copy_(x)
+            it = self.full
+            it.run(self.q, self.qd, self.qdd, step=True)
+            for name, x in (("g_q", it.g_q), ("g_qd", it.g_qd), ("g_qdd", it.g_qdd), ("cost", it.cost),
+                            ("max_pen", it.max_pen)):
+                h[name][k].copy_(x)
+
+    def run_eager(self) -> None:
+        """The same iterations and snapshots, issued launch by launch."""
+        self._body()
+
+    def capture(self) -> None:
+        # run each kernel once (no step) before capture, on a side stream
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.lean.run(self.q, self.qd, self.qdd, step=False)
+            self.full.run(self.q, self.qd, self.qdd, step=False)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._body()
+
+    def replay(self) -> None:
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
