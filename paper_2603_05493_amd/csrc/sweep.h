@@ -10,22 +10,22 @@
 //
 // Broad phase (exact): each link gets a bounding sphere (centroid C_a of its
 // sphere centres, reach R_a = max |c - C_a| + r), and no pair of block (a, b)
-// can penetrate more than bound = R_a + R_b - |C_a - C_b|.  A seed, the
-// exact maximum of the block with the largest bound, is a lower bound of the
-// state's maximum M.  Blocks with bound < min(seed, 0) - eps therefore hold
-// no pair that is the maximum, ties it, or collides; they are skipped.  eps
-// covers the FP32 rounding of both the bound and the pair penetrations (all
-// computed from the same FP32 centres), so the result is identical to the
-// full sweep.
-//
-// The bounds go to the group's LDS list once; the survivors' link pairs are
-// compacted in place into the same list (a survivor's list position never
-// exceeds its block index), and the pair loop runs over rows -- (block,
+// can penetrate more than bound = R_a + R_b - |C_a - C_b|.  eps covers the
+// FP32 rounding of both the bound and the pair penetrations (all computed
+// from the same FP32 centres), so a block whose computed bound is below t -
+// eps holds no pair whose computed penetration reaches t.
+//   Pass 1 sweeps the blocks with bound >= -eps.  If their maximum M0 is
+//   >= 0, every skipped pair penetrates less than 0 <= M0: none is the
+//   maximum, ties it, or collides, and the result is that of the full sweep.
+//   Otherwise (no collision) a lower bound of M -- M0, or the exact maximum
+//   of the block with the largest bound when pass 1 found nothing -- sets
+//   t1, and pass 2 sweeps the blocks with t1 - eps <= bound < -eps.
+// The surviving link pairs of each pass are compacted into the group's LDS
+// list (ballot + popcount), and the pair loop runs over rows -- (link pair,
 // sphere slot of the first link) against the NMAX slots of the second link
 // -- so that the lanes stay dense whatever the number of survivors.  Robots
-// with more blocks than the list holds are swept in chunks, recomputing the
-// bounds.  The block table itself is read from LDS where the caller has
-// staged it, so no step of the sweep waits on device memory.
+// with more blocks than the list holds are swept in chunks.  The block
+// table is read from LDS where the caller has staged it.
 //
 // Reduce: the pair count is a scalar ballot popcount per pair (one state per
 // wavefront) or a per-lane counter summed over the group; the maximum is a
@@ -113,24 +113,88 @@ __device__ __forceinline__ void link_bounds(const DevRobot &rb, const float4 *P,
     }
 }
 
+// Appends to list[0, nl) the link pairs of blocks [c0, cend) whose bound
+// lies in [lo, hi); returns nl.  TRACK: also keep the lane's largest bound
+// and its block.
+template <bool TRACK>
+__device__ __forceinline__ int compact_blocks(const int *tab, const float4 *Bd, int *list, int n, int c0,
+                                              int cend, float lo, float hi, int glane, int G, int gshift,
+                                              uint64_t gmask, float &bmax, int &bblk) {
+    const uint64_t below = (1ull << glane) - 1ull;
+    int nl = 0;
+    for (int base = c0; base < cend; base += 2 * G) {
+        const int k0 = base + glane, k1 = k0 + G;
+        const bool v0 = k0 < n, v1 = k1 < cend && k1 < n;
+        const int ab0 = v0 ? tab[k0] : 0, ab1 = v1 ? tab[k1] : 0;
+        const float d0 = v0 ? block_bound(Bd, ab0) : -INFINITY;
+        const float d1 = v1 ? block_bound(Bd, ab1) : -INFINITY;
+        if (TRACK) {
+            if (d0 > bmax) {
+                bmax = d0;
+                bblk = k0;
+            }
+            if (d1 > bmax) {
+                bmax = d1;
+                bblk = k1;
+            }
+        }
+        const bool s0 = d0 >= lo && d0 < hi, s1 = d1 >= lo && d1 < hi;
+        const uint64_t m0 = (__ballot(s0) >> gshift) & gmask;
+        const uint64_t m1 = (__ballot(s1) >> gshift) & gmask;
+        const int n0 = __popcll(m0);
+        if (s0) list[nl + __popcll(m0 & below)] = ab0;
+        if (s1) list[nl + n0 + __popcll(m1 & below)] = ab1;
+        nl += n0 + __popcll(m1);
+    }
+    return nl;
+}
+
+// Pair loop over the rows of list[0, nl): running maximum, the row where it
+// was set (link pair * NMAX + slot), whether it was met twice, and the count.
+template <int NMAX, bool FULL>
+__device__ __forceinline__ void sweep_rows(const DevRobot &rb, const float4 *P, const int *list, int nl, int glane,
+                                           int G, float &best, int &best_code, bool &tie, unsigned &cnt) {
+    const int items = nl * NMAX;
+    for (int j0 = 0; j0 < items; j0 += G) {
+        const int it = j0 + glane;
+        const bool ok = it < items;
+        const int e = it / NMAX, row = it - e * NMAX;
+        const int ab = ok ? list[e] : ((rb.L << 16) | rb.L);
+        const int a = ab >> 16, bb = ab & 0xffff;
+        const float4 A = P[a * NMAX + row];
+        float m = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) {
+            const float pen = pair_pen(A, P[bb * NMAX + k]);
+            m = fmaxf(m, pen);
+            if (FULL) cnt += (unsigned)__popcll(__ballot(pen > 0.0f));
+            else cnt += pen > 0.0f ? 1u : 0u;
+        }
+        if (m > best) {
+            best = m;
+            best_code = ok ? ab * NMAX + row : -1;
+            tie = false;
+        } else if (m == best) {
+            tie = true;
+        }
+    }
+}
+
 // Sweep one state.  tab: the robot's block table (rb.blocks or an LDS copy);
 // P: the state's (L+1)*NMAX sphere slots; Bd: its link bounding spheres
-// (link_bounds); list: rb.list_cap ints of LDS scratch for this group.  Every lane of the group returns the maximum penetration M,
-// the sphere key s*S + t of the lowest pair attaining it (INT_MAX if none)
-// and the number of pairs with positive penetration.  FULL: G == 64.
+// (link_bounds); list: rb.list_cap ints of LDS scratch for this group.
+// Every lane of the group returns the maximum penetration M, the sphere key
+// s*S + t of the lowest pair attaining it (INT_MAX if none) and the number
+// of pairs with positive penetration.  FULL: G == 64.
 template <int NMAX, bool FULL>
 __device__ __forceinline__ void sweep_state(const DevRobot &rb, const int *tab, const float4 *P, const float4 *Bd,
-                                            int *list,
-                                            int glane, int G, int grp, float &M_out, int &key_out,
+                                            int *list, int glane, int G, int grp, float &M_out, int &key_out,
                                             unsigned &cnt_out) {
     const int n = rb.n_blocks;
     const int nb = (n + G - 1) / G * G;
     const int cap = rb.list_cap;
-    const bool one_chunk = nb <= cap;
-    float *bnd = reinterpret_cast<float *>(list);
     const uint64_t gmask = FULL ? ~0ull : ((1ull << G) - 1ull);
     const int gshift = FULL ? 0 : grp * G;
-    const uint64_t below = (1ull << glane) - 1ull;
     // extent of the robot in this state, for the rounding margin
     float ext = 0.f;
     for (int a = glane; a < rb.L; a += G) {
@@ -139,103 +203,56 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const int *tab, 
             ext = fmaxf(ext, __builtin_amdgcn_sqrtf(__builtin_fmaf(c.x, c.x, __builtin_fmaf(c.y, c.y, c.z * c.z))) + c.w);
     }
     const float eps = 4e-6f * (1.f + group_reduce_max(ext, G));
-    // every block's bound (kept in the list when it fits) and the block with
-    // the largest bound, two blocks per lane per step
-    float bmax = -INFINITY;
-    int bblk = INT_MAX;
-    for (int base = 0; base < nb; base += 2 * G) {
-        const int k0 = base + glane, k1 = k0 + G;
-        const bool v0 = k0 < n, v1 = k1 < n;
-        const int ab0 = v0 ? tab[k0] : 0, ab1 = v1 ? tab[k1] : 0;
-        const float d0 = v0 ? block_bound(Bd, ab0) : -INFINITY;
-        const float d1 = v1 ? block_bound(Bd, ab1) : -INFINITY;
-        if (one_chunk) {
-            if (v0) bnd[k0] = d0;
-            if (v1) bnd[k1] = d1;
-        }
-        if (d0 > bmax) {
-            bmax = d0;
-            bblk = k0;
-        }
-        if (d1 > bmax) {
-            bmax = d1;
-            bblk = k1;
-        }
-    }
-    const float gbmax = group_reduce_max(bmax, G);
-    const int cand = group_reduce_min(bmax == gbmax ? bblk : INT_MAX, G);
-    // seed: exact maximum of that block
-    float seed = -INFINITY;
-    if (cand != INT_MAX) {
-        const int ab = tab[cand];
-        const int a = ab >> 16, bb = ab & 0xffff;
-        for (int j = glane; j < NMAX * NMAX; j += G) {
-            const int i = j / NMAX, k = j - i * NMAX;
-            seed = fmaxf(seed, pair_pen(P[a * NMAX + i], P[bb * NMAX + k]));
-        }
-    }
-    const float theta = fminf(group_reduce_max(seed, G), 0.f) - eps;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    const float theta0 = -eps;
 
     float best = -INFINITY;
-    int best_code = -1;   // link pair * NMAX + row of the running maximum
+    int best_code = -1;
     bool tie = false;
     unsigned cnt = 0;
+    float bmax = -INFINITY;
+    int bblk = INT_MAX;
+    // pass 1: blocks that may hold a collision
     for (int c0 = 0; c0 < nb; c0 += cap) {
-        const int cend = min(c0 + cap, nb);
-        // compaction of the chunk's surviving link pairs into list[0, nl)
-        int nl = 0;
-        for (int base = c0; base < cend; base += 2 * G) {
-            const int k0 = base + glane, k1 = k0 + G;
-            const bool v0 = k0 < n, v1 = k1 < cend && k1 < n;
-            const int ab0 = v0 ? tab[k0] : 0, ab1 = v1 ? tab[k1] : 0;
-            bool s0, s1;
-            if (one_chunk) {
-                s0 = v0 && bnd[k0] >= theta;
-                s1 = v1 && bnd[k1] >= theta;
-            } else {
-                s0 = v0 && block_bound(Bd, ab0) >= theta;
-                s1 = v1 && block_bound(Bd, ab1) >= theta;
-            }
-            const uint64_t m0 = (__ballot(s0) >> gshift) & gmask;
-            const uint64_t m1 = (__ballot(s1) >> gshift) & gmask;
-            const int n0 = __popcll(m0);
-            if (s0) list[nl + __popcll(m0 & below)] = ab0;
-            if (s1) list[nl + n0 + __popcll(m1 & below)] = ab1;
-            nl += n0 + __popcll(m1);
-        }
+        const int nl = compact_blocks<true>(tab, Bd, list, n, c0, min(c0 + cap, nb), theta0, INFINITY, glane, G,
+                                            gshift, gmask, bmax, bblk);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        // pair loop over rows (list entry j / NMAX, slot j % NMAX)
-        const int items = nl * NMAX;
-        for (int j0 = 0; j0 < items; j0 += G) {
-            const int it = j0 + glane;
-            const bool ok = it < items;
-            const int e = it / NMAX, row = it - e * NMAX;
-            const int ab = ok ? list[e] : ((rb.L << 16) | rb.L);
-            const int a = ab >> 16, bb = ab & 0xffff;
-            const float4 A = P[a * NMAX + row];
-            float m = -INFINITY;
-#pragma unroll
-            for (int k = 0; k < NMAX; ++k) {
-                const float pen = pair_pen(A, P[bb * NMAX + k]);
-                m = fmaxf(m, pen);
-                if (FULL) cnt += (unsigned)__popcll(__ballot(pen > 0.0f));
-                else cnt += pen > 0.0f ? 1u : 0u;
-            }
-            if (m > best) {
-                best = m;
-                best_code = ok ? ab * NMAX + row : -1;
-                tie = false;
-            } else if (m == best) {
-                tie = true;
-            }
-        }
+        sweep_rows<NMAX, FULL>(rb, P, list, nl, glane, G, best, best_code, tie, cnt);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
-    const float M = group_reduce_max(best, G);
+    float M = group_reduce_max(best, G);
+    if (!(M >= 0.f) && n > 0) {
+        // pass 2 (no collision): a lower bound of M, then the blocks below theta0 that can reach it
+        float lb = M;
+        if (lb == -INFINITY) {
+            const float gbmax = group_reduce_max(bmax, G);
+            const int cand = group_reduce_min(bmax == gbmax ? bblk : INT_MAX, G);
+            float seed = -INFINITY;
+            if (cand != INT_MAX) {   // no candidate only when every bound is NaN
+                const int ab = tab[cand];
+                const int a = ab >> 16, bb = ab & 0xffff;
+                for (int j = glane; j < NMAX * NMAX; j += G) {
+                    const int i = j / NMAX, k = j - i * NMAX;
+                    seed = fmaxf(seed, pair_pen(P[a * NMAX + i], P[bb * NMAX + k]));
+                }
+            }
+            lb = group_reduce_max(seed, G);
+        }
+        const float theta1 = lb - eps;
+        float unused_f = 0.f;
+        int unused_i = 0;
+        for (int c0 = 0; c0 < nb; c0 += cap) {
+            const int nl = compact_blocks<false>(tab, Bd, list, n, c0, min(c0 + cap, nb), theta1, theta0, glane,
+                                                 G, gshift, gmask, unused_f, unused_i);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            sweep_rows<NMAX, FULL>(rb, P, list, nl, glane, G, best, best_code, tie, cnt);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        M = group_reduce_max(best, G);
+    }
     int key = INT_MAX;
     const bool holder = best == M && M > -INFINITY && best_code >= 0;
     const bool rescan = group_reduce_min((holder && tie) ? 0 : 1, G) == 0;
