@@ -9,7 +9,8 @@
 // owns one state; lane i of the group holds link perm[i] in depth-first
 // pre-order, so the subtree of lane i is the lane range [i, sub_end_i].
 // Nothing intermediate leaves the chip: link poses and spatial quantities
-// live in registers, sphere centres in the group's LDS slots.
+// live in registers, sphere centres and link bounding spheres (transformed
+// from their link-frame tables) in the group's LDS.
 //
 // Forward kinematics: each lane forms its local transform (fixed (R, p) then
 // the joint rotation) and the world pose follows by pointer jumping over the
@@ -118,9 +119,9 @@ __device__ __forceinline__ void wave_sync() {
 // the lane tables at the point of use in every state (they stay in the L1
 // cache), so that no register holds them across the sweep.
 template <int NMAX, bool FULL>
-__device__ __forceinline__ void iterate_state(const DevRobot &rb, const int *tab, const DevFused &fz,
+__device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t *tab, const DevFused &fz,
                                               const TreeIO &io, const StepScalars &k, float4 *P, float4 *Bd,
-                                              int *list, int G, int grp, int glane, int64_t B, int64_t b,
+                                              uint16_t *list, int G, int grp, int glane, int64_t B, int64_t b,
                                               bool valid) {
     int gl = glane;
     asm volatile("" : "+v"(gl));   // keeps the table reads inside the state loop
@@ -163,7 +164,7 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const int *tab
             }
         }
     }
-    // ---- sphere centres into the group's LDS slots
+    // ---- sphere centres and the link's bounding sphere into the group's LDS
     const int link = li[0 * 64 + gl];
     {
         const int nsph = li[4 * 64 + gl];
@@ -175,11 +176,13 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const int *tab
                 const V3 c = mul(R, v3(loc.x, loc.y, loc.z)) + p;
                 P[link * NMAX + j] = make_float4(c.x, c.y, c.z, loc.w);
             }
+        if (nsph > 0) {
+            const V3 c = mul(R, v3(lf[25 * 64 + gl], lf[26 * 64 + gl], lf[27 * 64 + gl])) + p;
+            Bd[link] = make_float4(c.x, c.y, c.z, lf[28 * 64 + gl]);
+        }
         wave_sync();
     }
     // ---- self-collision
-    link_bounds<NMAX>(rb, P, Bd, glane, G);
-    wave_sync();
     float M;
     int key;
     unsigned cnt;
@@ -284,7 +287,7 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const int *tab
 // this workgroup, 64/G states per wavefront at a time; tab is the robot's
 // block table staged in LDS.
 template <int NMAX>
-__device__ __forceinline__ void run_states(const DevRobot &rb, const int *tab, const DevFused &fz, const TreeIO &io,
+__device__ __forceinline__ void run_states(const DevRobot &rb, const uint16_t *tab, const DevFused &fz, const TreeIO &io,
                                            const StepScalars &k, float4 *lds_wave, int G, int64_t B,
                                            int64_t b0, int count) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -292,9 +295,11 @@ __device__ __forceinline__ void run_states(const DevRobot &rb, const int *tab, c
     const int SL = (rb.L + 1) * NMAX;
     float4 *P = lds_wave + grp * (int)(group_lds_bytes(rb.L, NMAX, rb.list_cap) / 16);
     float4 *Bd = P + SL;
-    int *list = reinterpret_cast<int *>(Bd + rb.L + 1);
+    uint16_t *list = reinterpret_cast<uint16_t *>(Bd + rb.L + 1);
     wave_sync();
     for (int i = glane; i < SL; i += G) P[i] = make_float4(0.f, 0.f, 0.f, rb.slot_r[i]);
+    // links without spheres (and the padding link L) keep an empty bounding sphere
+    for (int i = glane; i <= rb.L; i += G) Bd[i] = make_float4(0.f, 0.f, 0.f, -1e30f);
     for (int base = wave * per_wave; base < count; base += 4 * per_wave) {
         const int s = base + grp;
         const bool valid = s < count;
@@ -304,8 +309,18 @@ __device__ __forceinline__ void run_states(const DevRobot &rb, const int *tab, c
     }
 }
 
+// The robot's block table into LDS as 16-bit link pairs (a << 8) | b (the
+// fused kernels take at most 64 links); padding entries become (L, L).
+__device__ __forceinline__ void stage_table(const DevRobot &rb, uint16_t *tab) {
+    for (int i = threadIdx.x; i < rb.n_blocks_pad; i += 256) {
+        const int ab = rb.blocks[i];
+        tab[i] = (uint16_t)PairCode<uint16_t>::make(ab >> 16, ab & 0xffff);
+    }
+}
+
+// Four wavefronts per SIMD: the register budget is 128 VGPRs.
 template <int NMAX>
-__global__ void __launch_bounds__(256) k_fused_step(FusedArgs A) {
+__global__ void __launch_bounds__(256, 4) k_fused_step(FusedArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
     const int G = A.lanes_per_state;
@@ -317,8 +332,8 @@ __global__ void __launch_bounds__(256) k_fused_step(FusedArgs A) {
     const int64_t b0 = (int64_t)chunk * A.chunk;
     const int64_t rem = A.B - b0;
     const int count = rem < A.chunk ? (int)rem : A.chunk;
-    int *tab = reinterpret_cast<int *>(lds + 4 * SLW);
-    for (int i = threadIdx.x; i < A.rb.n_blocks; i += 256) tab[i] = A.rb.blocks[i];
+    uint16_t *tab = reinterpret_cast<uint16_t *>(lds + 4 * SLW);
+    stage_table(A.rb, tab);
     __syncthreads();
     run_states<NMAX>(A.rb, tab, A.fz, A.io, A.k, lds + wave * SLW, G, A.B, b0, count);
 }
@@ -331,7 +346,7 @@ __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
     const int w = blockIdx.x;
-    int *tab = reinterpret_cast<int *>(lds + 4 * A.wave_stride);
+    uint16_t *tab = reinterpret_cast<uint16_t *>(lds + 4 * A.wave_stride);
     int staged = -1;   // tree whose block table is in LDS
     for (int it = A.item_start[w]; it < A.item_start[w + 1]; ++it) {
         const PlanItem item = A.items[it];
@@ -339,7 +354,7 @@ __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
         const int G = T.lanes_per_state;
         if (item.tree != staged) {
             __syncthreads();   // every wave is done with the previous table
-            for (int i = threadIdx.x; i < T.rb.n_blocks; i += 256) tab[i] = T.rb.blocks[i];
+            stage_table(T.rb, tab);
             __syncthreads();
             staged = item.tree;
         }

@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, 
     const int *tab = rb.blocks;
     if (TAB_LDS) {
         int *t = lists + 4 * rb.list_cap;
-        for (int i = tid; i < rb.n_blocks; i += 256) t[i] = rb.blocks[i];
+        for (int i = tid; i < rb.n_blocks_pad; i += 256) t[i] = rb.blocks[i];
         tab = t;
     }
     for (int i = tid; i < TS * SLB; i += 256) {
@@ -84,7 +84,7 @@ static hipError_t launch_sc(const DevRobot &rb0, int64_t B, const float *sph, fl
                             int32_t *nc, hipStream_t s) {
     DevRobot rb = rb0;
     const size_t per_state = state_lds_bytes(rb.L, NMAX);
-    const size_t tab = tab_lds_bytes(rb.n_blocks_pad);
+    const size_t tab = (size_t)rb.n_blocks_pad * 4;
     dim3 block(256);
     if (per_state + (size_t)16 * rb.list_cap + tab <= LDS_LIMIT) {
         const int TS = sc_tile(per_state, (size_t)16 * rb.list_cap + tab);
@@ -92,7 +92,7 @@ static hipError_t launch_sc(const DevRobot &rb0, int64_t B, const float *sph, fl
         dim3 grid((unsigned)((B + TS - 1) / TS));
         hipLaunchKernelGGL((k_self_collision<NMAX, true>), grid, block, lds, s, rb, B, TS, sph, mp, am, nc);
     } else {
-        const int room = (int)((LDS_LIMIT - per_state) / 16) / 64 * 64;
+        const int room = (int)((LDS_LIMIT - per_state) / 16) / 128 * 128;
         if (room < rb.list_cap) rb.list_cap = room;
         const int TS = self_collision_tile(rb.L, NMAX, rb.list_cap);
         const size_t lds = (size_t)TS * per_state + (size_t)16 * rb.list_cap;

@@ -14,18 +14,24 @@
 // FP32 rounding of both the bound and the pair penetrations (all computed
 // from the same FP32 centres), so a block whose computed bound is below t -
 // eps holds no pair whose computed penetration reaches t.
-//   Pass 1 sweeps the blocks with bound >= -eps.  If their maximum M0 is
+//   Pass 1 sweeps the blocks that may reach -eps, tested without a square
+//   root as |C_a - C_b|^2 <= (R_a + R_b + eps)^2.  If their maximum M0 is
 //   >= 0, every skipped pair penetrates less than 0 <= M0: none is the
 //   maximum, ties it, or collides, and the result is that of the full sweep.
 //   Otherwise (no collision) a lower bound of M -- M0, or the exact maximum
 //   of the block with the largest bound when pass 1 found nothing -- sets
-//   t1, and pass 2 sweeps the blocks with t1 - eps <= bound < -eps.
+//   t1, and pass 2 sweeps the blocks that pass 1 skipped and whose bound is
+//   >= t1 - eps (the two passes partition the blocks exactly).
 // The surviving link pairs of each pass are compacted into the group's LDS
 // list (ballot + popcount), and the pair loop runs over rows -- (link pair,
 // sphere slot of the first link) against the NMAX slots of the second link
 // -- so that the lanes stay dense whatever the number of survivors.  Robots
 // with more blocks than the list holds are swept in chunks.  The block
-// table is read from LDS where the caller has staged it.
+// table is read from LDS where the caller has staged it; it is padded to a
+// multiple of 128 entries with the empty pair (L, L), whose bounding sphere
+// Bd[L] has radius -1e30, so the pass-1 loop needs no range tests.  Table and
+// list entries are link pairs packed as (a << SH) | b in an entry type E:
+// 32-bit with SH = 16, or 16-bit with SH = 8 for robots of at most 255 links.
 //
 // Reduce: the pair count is a scalar ballot popcount per pair (one state per
 // wavefront) or a per-lane counter summed over the group; the maximum is a
@@ -51,17 +57,24 @@ __device__ __forceinline__ float pair_pen(float4 A, float4 Bv) {
     return (A.w + Bv.w) - __builtin_amdgcn_sqrtf(d2);
 }
 
-__device__ __forceinline__ float block_bound(const float4 *Bd, int ab) {
-    const float4 A = Bd[ab >> 16], Bv = Bd[ab & 0xffff];
+template <typename E>
+struct PairCode {
+    static constexpr int SH = sizeof(E) == 2 ? 8 : 16;
+    static __device__ __forceinline__ int a(int ab) { return ab >> SH; }
+    static __device__ __forceinline__ int b(int ab) { return ab & ((1 << SH) - 1); }
+    static __device__ __forceinline__ int make(int a, int b) { return (a << SH) | b; }
+};
+
+__device__ __forceinline__ float block_bound(const float4 *Bd, int a, int b) {
+    const float4 A = Bd[a], Bv = Bd[b];
     const float dx = A.x - Bv.x, dy = A.y - Bv.y, dz = A.z - Bv.z;
     return (A.w + Bv.w) - __builtin_amdgcn_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
 }
 
-// Lowest sphere key s*S + t in row i of link pair ab = (a << 16) | b whose
-// penetration equals M.
+// Lowest sphere key s*S + t in row i of link pair (a, bb) whose penetration
+// equals M.
 template <int NMAX>
-__device__ __forceinline__ int row_min_key(const DevRobot &rb, const float4 *P, int ab, int i, float M) {
-    const int a = ab >> 16, bb = ab & 0xffff;
+__device__ __forceinline__ int row_min_key(const DevRobot &rb, const float4 *P, int a, int bb, int i, float M) {
     if (a >= rb.L) return INT_MAX;
     const float4 A = P[a * NMAX + i];
     const int s = rb.li[a].sph_first + i, fb = rb.li[bb].sph_first;
@@ -72,10 +85,10 @@ __device__ __forceinline__ int row_min_key(const DevRobot &rb, const float4 *P, 
 }
 
 template <int NMAX>
-__device__ __forceinline__ int block_min_key(const DevRobot &rb, const float4 *P, int ab, float M) {
+__device__ __forceinline__ int block_min_key(const DevRobot &rb, const float4 *P, int a, int bb, float M) {
     int key = INT_MAX;
 #pragma unroll
-    for (int i = 0; i < NMAX; ++i) key = min(key, row_min_key<NMAX>(rb, P, ab, i, M));
+    for (int i = 0; i < NMAX; ++i) key = min(key, row_min_key<NMAX>(rb, P, a, bb, i, M));
     return key;
 }
 
@@ -113,37 +126,40 @@ __device__ __forceinline__ void link_bounds(const DevRobot &rb, const float4 *P,
     }
 }
 
-// Appends to list[0, nl) the link pairs of blocks [c0, cend) whose bound
-// lies in [lo, hi); returns nl.  TRACK: also keep the lane's largest bound
-// and its block.
-template <bool TRACK>
-__device__ __forceinline__ int compact_blocks(const int *tab, const float4 *Bd, int *list, int n, int c0,
-                                              int cend, float lo, float hi, int glane, int G, int gshift,
-                                              uint64_t gmask, float &bmax, int &bblk) {
+// Pass-1 test: block (a, b) may hold a pair whose penetration reaches -eps,
+// |C_a - C_b| <= R_a + R_b + eps, as one compare without a square root:
+// d2 <= s |s| is false for every s < 0 (d2 >= 0), so the empty pair (L, L)
+// never passes.
+__device__ __forceinline__ bool may_reach(const float4 *Bd, int a, int b, float eps) {
+    const float4 A = Bd[a], Bv = Bd[b];
+    const float dx = A.x - Bv.x, dy = A.y - Bv.y, dz = A.z - Bv.z;
+    const float s = (A.w + Bv.w) + eps;
+    const float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    return d2 <= s * fabsf(s);
+}
+
+// Appends to list[0, nl) the link pairs of blocks [c0, cend) that pass the
+// pass-1 test (PASS1) or, for pass 2, fail it with bound >= lo; returns nl.
+// cend - c0 is a multiple of 2G and every entry below cend is a table entry.
+template <bool PASS1, typename E>
+__device__ __forceinline__ int compact_blocks(const E *tab, const float4 *Bd, E *list, int c0, int cend, float eps,
+                                              float lo, int glane, int G, int gshift, uint64_t gmask) {
+    typedef PairCode<E> PC;
     const uint64_t below = (1ull << glane) - 1ull;
     int nl = 0;
     for (int base = c0; base < cend; base += 2 * G) {
         const int k0 = base + glane, k1 = k0 + G;
-        const bool v0 = k0 < n, v1 = k1 < cend && k1 < n;
-        const int ab0 = v0 ? tab[k0] : 0, ab1 = v1 ? tab[k1] : 0;
-        const float d0 = v0 ? block_bound(Bd, ab0) : -INFINITY;
-        const float d1 = v1 ? block_bound(Bd, ab1) : -INFINITY;
-        if (TRACK) {
-            if (d0 > bmax) {
-                bmax = d0;
-                bblk = k0;
-            }
-            if (d1 > bmax) {
-                bmax = d1;
-                bblk = k1;
-            }
+        const int ab0 = tab[k0], ab1 = tab[k1];
+        bool s0 = may_reach(Bd, PC::a(ab0), PC::b(ab0), eps), s1 = may_reach(Bd, PC::a(ab1), PC::b(ab1), eps);
+        if (!PASS1) {
+            s0 = !s0 && block_bound(Bd, PC::a(ab0), PC::b(ab0)) >= lo;
+            s1 = !s1 && block_bound(Bd, PC::a(ab1), PC::b(ab1)) >= lo;
         }
-        const bool s0 = d0 >= lo && d0 < hi, s1 = d1 >= lo && d1 < hi;
         const uint64_t m0 = (__ballot(s0) >> gshift) & gmask;
         const uint64_t m1 = (__ballot(s1) >> gshift) & gmask;
         const int n0 = __popcll(m0);
-        if (s0) list[nl + __popcll(m0 & below)] = ab0;
-        if (s1) list[nl + n0 + __popcll(m1 & below)] = ab1;
+        if (s0) list[nl + __popcll(m0 & below)] = (E)ab0;
+        if (s1) list[nl + n0 + __popcll(m1 & below)] = (E)ab1;
         nl += n0 + __popcll(m1);
     }
     return nl;
@@ -151,16 +167,17 @@ __device__ __forceinline__ int compact_blocks(const int *tab, const float4 *Bd, 
 
 // Pair loop over the rows of list[0, nl): running maximum, the row where it
 // was set (link pair * NMAX + slot), whether it was met twice, and the count.
-template <int NMAX, bool FULL>
-__device__ __forceinline__ void sweep_rows(const DevRobot &rb, const float4 *P, const int *list, int nl, int glane,
+template <int NMAX, bool FULL, typename E>
+__device__ __forceinline__ void sweep_rows(const DevRobot &rb, const float4 *P, const E *list, int nl, int glane,
                                            int G, float &best, int &best_code, bool &tie, unsigned &cnt) {
+    typedef PairCode<E> PC;
     const int items = nl * NMAX;
     for (int j0 = 0; j0 < items; j0 += G) {
         const int it = j0 + glane;
         const bool ok = it < items;
         const int e = it / NMAX, row = it - e * NMAX;
-        const int ab = ok ? list[e] : ((rb.L << 16) | rb.L);
-        const int a = ab >> 16, bb = ab & 0xffff;
+        const int ab = ok ? (int)list[e] : PC::make(rb.L, rb.L);
+        const int a = PC::a(ab), bb = PC::b(ab);
         const float4 A = P[a * NMAX + row];
         float m = -INFINITY;
 #pragma unroll
@@ -180,19 +197,20 @@ __device__ __forceinline__ void sweep_rows(const DevRobot &rb, const float4 *P, 
     }
 }
 
-// Sweep one state.  tab: the robot's block table (rb.blocks or an LDS copy);
-// P: the state's (L+1)*NMAX sphere slots; Bd: its link bounding spheres
-// (link_bounds); list: rb.list_cap ints of LDS scratch for this group.
+// Sweep one state.  tab: the robot's block table (rb.blocks, or an LDS copy
+// in the entry type E); P: the state's (L+1)*NMAX sphere slots; Bd: its link
+// bounding spheres; list: rb.list_cap entries of LDS scratch for this group.
 // Every lane of the group returns the maximum penetration M, the sphere key
 // s*S + t of the lowest pair attaining it (INT_MAX if none) and the number
 // of pairs with positive penetration.  FULL: G == 64.
-template <int NMAX, bool FULL>
-__device__ __forceinline__ void sweep_state(const DevRobot &rb, const int *tab, const float4 *P, const float4 *Bd,
-                                            int *list, int glane, int G, int grp, float &M_out, int &key_out,
+template <int NMAX, bool FULL, typename E>
+__device__ __forceinline__ void sweep_state(const DevRobot &rb, const E *tab, const float4 *P, const float4 *Bd,
+                                            E *list, int glane, int G, int grp, float &M_out, int &key_out,
                                             unsigned &cnt_out) {
+    typedef PairCode<E> PC;
     const int n = rb.n_blocks;
-    const int nb = (n + G - 1) / G * G;
-    const int cap = rb.list_cap;
+    const int nb = (n + 2 * G - 1) / (2 * G) * (2 * G);   // <= n_blocks_pad, a multiple of 128
+    const int cap = rb.list_cap;                          // a multiple of 128
     const uint64_t gmask = FULL ? ~0ull : ((1ull << G) - 1ull);
     const int gshift = FULL ? 0 : grp * G;
     // extent of the robot in this state, for the rounding margin
@@ -203,18 +221,14 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const int *tab, 
             ext = fmaxf(ext, __builtin_amdgcn_sqrtf(__builtin_fmaf(c.x, c.x, __builtin_fmaf(c.y, c.y, c.z * c.z))) + c.w);
     }
     const float eps = 4e-6f * (1.f + group_reduce_max(ext, G));
-    const float theta0 = -eps;
 
     float best = -INFINITY;
     int best_code = -1;
     bool tie = false;
     unsigned cnt = 0;
-    float bmax = -INFINITY;
-    int bblk = INT_MAX;
     // pass 1: blocks that may hold a collision
     for (int c0 = 0; c0 < nb; c0 += cap) {
-        const int nl = compact_blocks<true>(tab, Bd, list, n, c0, min(c0 + cap, nb), theta0, INFINITY, glane, G,
-                                            gshift, gmask, bmax, bblk);
+        const int nl = compact_blocks<true>(tab, Bd, list, c0, min(c0 + cap, nb), eps, 0.f, glane, G, gshift, gmask);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         sweep_rows<NMAX, FULL>(rb, P, list, nl, glane, G, best, best_code, tie, cnt);
@@ -223,15 +237,25 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const int *tab, 
     }
     float M = group_reduce_max(best, G);
     if (!(M >= 0.f) && n > 0) {
-        // pass 2 (no collision): a lower bound of M, then the blocks below theta0 that can reach it
+        // pass 2 (no collision): a lower bound of M, then the skipped blocks that can reach it
         float lb = M;
         if (lb == -INFINITY) {
+            float bmax = -INFINITY;
+            int bblk = INT_MAX;
+            for (int k = glane; k < n; k += G) {
+                const int ab = tab[k];
+                const float d = block_bound(Bd, PC::a(ab), PC::b(ab));
+                if (d > bmax) {
+                    bmax = d;
+                    bblk = k;
+                }
+            }
             const float gbmax = group_reduce_max(bmax, G);
             const int cand = group_reduce_min(bmax == gbmax ? bblk : INT_MAX, G);
             float seed = -INFINITY;
             if (cand != INT_MAX) {   // no candidate only when every bound is NaN
                 const int ab = tab[cand];
-                const int a = ab >> 16, bb = ab & 0xffff;
+                const int a = PC::a(ab), bb = PC::b(ab);
                 for (int j = glane; j < NMAX * NMAX; j += G) {
                     const int i = j / NMAX, k = j - i * NMAX;
                     seed = fmaxf(seed, pair_pen(P[a * NMAX + i], P[bb * NMAX + k]));
@@ -240,11 +264,9 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const int *tab, 
             lb = group_reduce_max(seed, G);
         }
         const float theta1 = lb - eps;
-        float unused_f = 0.f;
-        int unused_i = 0;
         for (int c0 = 0; c0 < nb; c0 += cap) {
-            const int nl = compact_blocks<false>(tab, Bd, list, n, c0, min(c0 + cap, nb), theta1, theta0, glane,
-                                                 G, gshift, gmask, unused_f, unused_i);
+            const int nl = compact_blocks<false>(tab, Bd, list, c0, min(c0 + cap, nb), eps, theta1, glane, G,
+                                                 gshift, gmask);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             sweep_rows<NMAX, FULL>(rb, P, list, nl, glane, G, best, best_code, tie, cnt);
@@ -257,10 +279,13 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const int *tab, 
     const bool holder = best == M && M > -INFINITY && best_code >= 0;
     const bool rescan = group_reduce_min((holder && tie) ? 0 : 1, G) == 0;
     if (rescan) {
-        for (int blk = glane; blk < n; blk += G) key = min(key, block_min_key<NMAX>(rb, P, tab[blk], M));
+        for (int blk = glane; blk < n; blk += G) {
+            const int ab = tab[blk];
+            key = min(key, block_min_key<NMAX>(rb, P, PC::a(ab), PC::b(ab), M));
+        }
     } else if (holder) {
         const int ab = best_code / NMAX;
-        key = row_min_key<NMAX>(rb, P, ab, best_code - ab * NMAX, M);
+        key = row_min_key<NMAX>(rb, P, PC::a(ab), PC::b(ab), best_code - ab * NMAX, M);
     }
     M_out = M;
     key_out = group_reduce_min(key, G);

@@ -77,7 +77,7 @@ void build_fused(Tables &T) {
     for (int i = 0; i < L; ++i) lane_of[perm[i]] = i;
     for (int k = L - 1; k >= 1; --k) size[T.li[k].parent] += size[k];
     T.f_li.assign(8 * 64, 0);
-    T.f_lf.assign(25 * 64, 0.0f);
+    T.f_lf.assign(29 * 64, 0.0f);
     T.f_sph.assign((size_t)WB_MAX_SPHERES_PER_LINK * 64, make_float4(0, 0, 0, 0));
     for (int i = 0; i < L; ++i) {
         const int k = perm[i];
@@ -97,6 +97,26 @@ void build_fused(Tables &T) {
         for (int c = 0; c < 3; ++c) T.f_lf[(16 + c) * 64 + i] = F.com[c];
         for (int c = 0; c < 6; ++c) T.f_lf[(19 + c) * 64 + i] = F.I[c];
         for (int j = 0; j < I.sph_count; ++j) T.f_sph[(size_t)j * 64 + i] = T.sph[I.sph_first + j];
+        // bounding sphere of the link's spheres in link coordinates: centroid,
+        // then the largest reach, rounded up so that it holds every sphere
+        double cen[3] = {0, 0, 0}, reach = -1e30;
+        if (I.sph_count > 0) {
+            for (int j = 0; j < I.sph_count; ++j) {
+                const float4 q = T.sph[I.sph_first + j];
+                cen[0] += q.x;
+                cen[1] += q.y;
+                cen[2] += q.z;
+            }
+            for (int c = 0; c < 3; ++c) cen[c] = (double)(float)(cen[c] / I.sph_count);
+            for (int j = 0; j < I.sph_count; ++j) {
+                const float4 q = T.sph[I.sph_first + j];
+                const double dx = q.x - cen[0], dy = q.y - cen[1], dz = q.z - cen[2];
+                reach = std::max(reach, std::sqrt(dx * dx + dy * dy + dz * dz) + q.w);
+            }
+            reach = reach * (1.0 + 1e-6) + 1e-7;
+        }
+        for (int c = 0; c < 3; ++c) T.f_lf[(25 + c) * 64 + i] = (float)cen[c];
+        T.f_lf[28 * 64 + i] = std::nextafter((float)reach, INFINITY);
     }
     // lanes past the robot: an empty massless link with no parent and no joint
     for (int i = L; i < 64; ++i) {
@@ -106,6 +126,7 @@ void build_fused(Tables &T) {
         T.f_li[3 * 64 + i] = -1;
         T.f_li[6 * 64 + i] = 1;
         for (int c = 0; c < 9; c += 4) T.f_lf[(3 + c) * 64 + i] = 1.0f;
+        T.f_lf[28 * 64 + i] = -1e30f;
     }
     int js = 0;
     while ((1 << js) < T.max_depth + 1) ++js;
@@ -226,7 +247,7 @@ int build_tables(const wb_robot_desc *d, Tables &T) {
     if (nmax > WB_MAX_SPHERES_PER_LINK)
         return fail(WB_ERR_UNSUPPORTED, "%d spheres on one link exceeds %d", nmax, WB_MAX_SPHERES_PER_LINK);
     T.nmax = nmax;
-    if (wb::state_lds_bytes(L, nmax) + 16 * 64 > wb::LDS_LIMIT)
+    if (wb::state_lds_bytes(L, nmax) + 16 * 128 > wb::LDS_LIMIT)
         return fail(WB_ERR_UNSUPPORTED, "(links + 1) x spheres-per-link slots (%d x %d) exceed the 64 KB LDS tile",
                     L + 1, nmax);
     T.sph.resize(S);
@@ -268,7 +289,7 @@ int build_tables(const wb_robot_desc *d, Tables &T) {
         partners[a] = run;
     }
     T.n_blocks = (int)T.blocks.size();
-    while (T.blocks.size() % 64) T.blocks.push_back((L << 16) | L);
+    while (T.blocks.size() % 128) T.blocks.push_back((L << 16) | L);
     T.list_cap = wb::sweep_list_cap(T.n_blocks);
     T.pair_off.resize(S);
     int64_t off = 0;

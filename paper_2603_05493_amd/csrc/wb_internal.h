@@ -40,14 +40,14 @@ struct DevRobot {
     int32_t n_blocks, n_blocks_pad, max_depth, simple_joints;  // simple: one link per actuated joint, mult 1, offset 0
     int64_t n_pairs;
     float gx, gy, gz;
-    int32_t list_cap;             // ints of the per-group LDS list of the pair sweep (multiple of 64)
+    int32_t list_cap;             // ints of the per-group LDS list of the pair sweep (multiple of 128)
     const LinkF *__restrict__ lf;         // [L]
     const LinkI *__restrict__ li;         // [L]
     const float4 *__restrict__ sph;       // [S] local centre + radius
     const int32_t *__restrict__ sph_link; // [S]
     const int32_t *__restrict__ sph_slot; // [S] padded slot a*nmax + (s - first sphere of a)
     const float *__restrict__ slot_r;     // [(L+1)*nmax] radius of slot (a,i), -1e30 for empty slots
-    const int32_t *__restrict__ blocks;   // [n_blocks_pad] packed (a<<16)|b, padding = (L<<16)|L
+    const int32_t *__restrict__ blocks;   // [n_blocks_pad] packed (a<<16)|b, padded to a multiple of 128 with (L<<16)|L
     const int32_t *__restrict__ pair_off; // [S] index of sphere s's first pair
     const int32_t *__restrict__ pair_cnt; // [L*L] pairs of a sphere on link a with links a<b'<b
     const int32_t *__restrict__ pair_s;   // [P]
@@ -60,7 +60,9 @@ struct DevRobot {
 //                 subtree, 3 joint index (-1 fixed), 4 sphere count,
 //                 5 revolute, 6 fixed rotation is the identity
 //   lf[f*64 + i]: f = 0..2 axis, 3..11 fixed R, 12..14 fixed p, 15 mass,
-//                 16..18 CoM, 19..24 inertia (xx yy zz xy xz yz)
+//                 16..18 CoM, 19..24 inertia (xx yy zz xy xz yz),
+//                 25..27 centre and 28 radius of the link's bounding sphere in
+//                 link coordinates (-1e30 without spheres)
 //   lsph[j*64 + i]: local centre and radius of the link's j-th sphere
 // Lanes past the last link hold an empty link: link -1, parent -1, subtree
 // end i, no joint, no spheres, identity fixed rotation, zero mass.
@@ -149,19 +151,21 @@ hipError_t launch_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, 
                            const float *g_qdd, hipStream_t s);
 
 // LDS of one state's sweep: (L+1)*nmax sphere slots and L+1 link bounding
-// spheres (float4 each); plus, per sweeping group, a list of list_cap ints
-// (block bounds, then the surviving block ids).
+// spheres (float4 each); plus, per sweeping group, a list of list_cap
+// surviving link pairs (16-bit entries in the fused kernels, 32-bit in the
+// standalone self-collision kernel).
 constexpr int SWEEP_LIST_MAX = 2048;
 inline int sweep_list_cap(int n_blocks) {
-    int c = (n_blocks + 63) / 64 * 64;
-    return c < 64 ? 64 : (c > SWEEP_LIST_MAX ? SWEEP_LIST_MAX : c);
+    int c = (n_blocks + 127) / 128 * 128;
+    return c < 128 ? 128 : (c > SWEEP_LIST_MAX ? SWEEP_LIST_MAX : c);
 }
 __host__ __device__ inline size_t state_lds_bytes(int L, int nmax) { return (size_t)(L + 1) * (nmax + 1) * 16; }
 __host__ __device__ inline size_t group_lds_bytes(int L, int nmax, int list_cap) {
-    return state_lds_bytes(L, nmax) + (size_t)list_cap * 4;
+    return state_lds_bytes(L, nmax) + (size_t)list_cap * 2;
 }
-// LDS copy of the block table (n_blocks_pad ints, a multiple of 64).
-__host__ __device__ inline size_t tab_lds_bytes(int n_blocks_pad) { return (size_t)n_blocks_pad * 4; }
+// LDS copy of the block table in the fused kernels (n_blocks_pad 16-bit
+// entries, a multiple of 128).
+__host__ __device__ inline size_t tab_lds_bytes(int n_blocks_pad) { return (size_t)n_blocks_pad * 2; }
 // LDS of a 256-lane workgroup of the fused kernels with G lanes per state:
 // four wavefronts' group regions, then the block table.
 inline size_t fused_lds_bytes(int L, int nmax, int list_cap, int G, int n_blocks_pad) {
