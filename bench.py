@@ -40,8 +40,8 @@ PEAK_FP32_PUBLISHED_TFLOPS = 157.3   # needs packed FP32, which this build disab
 # (profiles/k_fused_step_humanoid48_B24576_hbm_counters.md), scaled by a copy
 # calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
 # it was measured with; reported as null once they change.
-TRAFFIC_MEASURED = {"sources_sha1": "55235200a7b39c95ebaaac392d8c2e90d09464a5", "states": 24576,
-                    "bytes_per_launch": 28606.8 * 1024}
+TRAFFIC_MEASURED = {"sources_sha1": "2406790b4914ee0268818837bce2289d635bae8c", "states": 24576,
+                    "bytes_per_launch": 33099.4 * 1024}
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h")
 
 
@@ -66,7 +66,7 @@ def algorithmic_flop_per_state(L: int, S: int, P: int, n: int) -> float:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=24576)
     ap.add_argument("--cpu-sample", type=int, default=256)
