@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--forms", default="fused_graph,fused_graph1,plain_graph,plain")
     ap.add_argument("--no-uneven", dest="uneven", action="store_false",
                     help="skip the uneven multi-tree batch measurement")
+    ap.add_argument("--no-bspline", dest="bspline", action="store_false",
+                    help="skip the B-spline control-point iteration measurement")
     return ap.parse_args()
 
 
@@ -229,9 +231,51 @@ def main():
                            "hbm_gbps_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9}
     if args.uneven:
         out["uneven_batch"] = bench_uneven(args)
+    if args.bspline and B % 48 == 0:
+        out["bspline_front_end"] = bench_bspline(args, robot, B // 48)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(rb, st, args.cpu_sample)
     print(json.dumps(out))
+
+
+def bench_bspline(args, robot, T: int):
+    """The same optimizer load with B-spline control points as the variables:
+    T trajectories of 9 control points sampled 4 times per knot interval
+    (48 states each), splines -> fused iteration -> control-point gradient
+    and step, one iteration captured in a HIP graph and replayed.  The
+    control-point gradients are large (acceleration samples carry dt^-2), so
+    the step is small enough that the trajectories stay physical over the
+    whole run."""
+    import torch
+    from paper_2603_05493_amd.iteration import BsplineIteration
+    d, K, n_interp = robot.n_dof, 9, 4
+    g = torch.Generator(device="cpu").manual_seed(3)
+    U = (torch.rand((d, T, K), generator=g) * 3.0 - 1.5).cuda()
+    th0 = (torch.rand((d, T), generator=g) * 3.0 - 1.5).cuda()
+    it = BsplineIteration(robot, U, th0, torch.zeros_like(th0), torch.zeros_like(th0), dt=0.05, n_interp=n_interp,
+                          torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=1e-7)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        it.run(step=False)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        it.run(step=True)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    assert torch.isfinite(U).all()
+    states = T * it.H
+    return {"trajectories": T, "control_points": K, "n_interp": n_interp, "states": states,
+            "states_per_s": states / dt, "ms_per_step": dt * 1e3,
+            "form": "bspline_eval + fused iteration (per-joint outputs) + control-point gradient and step, graph"}
 
 
 def bench_uneven(args):

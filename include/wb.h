@@ -218,6 +218,45 @@ int wb_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float t
 int wb_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd, const float *g_q,
                 const float *g_q2, const float *g_qd, const float *g_qdd, hipStream_t stream);
 
+/* ---------------------------------------------- B-spline trajectory front end
+ * Uniform cubic B-spline joint trajectories (Sec. 4): the optimizer's
+ * variables are control points, and the hot path's states are samples of
+ * the splines (Eq. 10); the control-point gradient is the transpose of the
+ * sampling, summed over every sample of a control point's support
+ * (Eqs. 13-14).  T trajectories of d joints, K control points each
+ * (1 <= K <= WB_BSPLINE_MAX_K), n_interp samples per knot interval dt:
+ *   knots per trajectory and joint: three ghost knots from the initial
+ *   state, u_0 .. u_{K-1}, and three more copies of u_{K-1} (a static goal);
+ *   segment s = 0 .. K+2 uses knots s .. s+3 of that sequence and is sampled
+ *   at alpha = i / n_interp, i = 0 .. n_interp-1, so a trajectory has
+ *   H = (K + 3) n_interp samples and state b = traj * H + s * n_interp + i.
+ * reading selects the ghost knots: WB_GHOST_EXACT makes the first sample
+ * equal the initial state (theta, theta_dot, theta_ddot); WB_GHOST_PRINTED
+ * uses the paper's printed formulas, whose first sample is the initial state
+ * carried forward by dt at constant acceleration.
+ * Layouts: U [d][T][K] (a trajectory's control points contiguous); theta0,
+ * dtheta0, ddtheta0 [d][T]; states [d][T*H] (the hot path's [n][B] with
+ * B = T*H).
+ * T*H must stay below 2^31 (else WB_ERR_UNSUPPORTED). */
+#define WB_BSPLINE_MAX_K 65536
+#define WB_GHOST_EXACT 0
+#define WB_GHOST_PRINTED 1
+
+/* Samples of the splines: q, qd, qdd [d][T*H] (qd, qdd may be NULL).
+ * theta0 is required; dtheta0 and ddtheta0 may be NULL (zero). */
+int wb_bspline_eval(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, int32_t reading,
+                    const float *U, const float *theta0, const float *dtheta0, const float *ddtheta0,
+                    float *q, float *qd, float *qdd, hipStream_t stream);
+
+/* Control-point gradient g_U [d][T][K] (overwritten; may be NULL when lr != 0)
+ * from upstream gradients on the samples g_q, g_qd, g_qdd [d][T*H] (each
+ * may be NULL = zero).  The initial state is not a variable: ghost knots
+ * take no gradient; copies of u_{K-1} add into it.  When lr != 0, U is
+ * updated in place, U -= lr * g_U. */
+int wb_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, const float *g_q,
+                        const float *g_qd, const float *g_qdd, float *g_U, float lr, float *U,
+                        hipStream_t stream);
+
 /* ------------------------------------------------------ fused iteration
  * One trajectory-optimizer iteration of the whole-body terms (Sec. 3, the
  * six-step loop: kinematics and inverse dynamics, the self-collision cost,
@@ -261,6 +300,17 @@ typedef struct wb_tune {
     float ns_per_state;
 } wb_tune;
 int wb_robot_set_tune(wb_robot *robot, const wb_tune *tune);
+
+/* Replace the inertial parameters of one link of a live robot -- mass, CoM
+ * and rotational inertia about the CoM in link axes (xx yy zz xy xz yz),
+ * as in wb_robot_desc -- e.g. a payload picked up at run time (Sec. 6.3:
+ * runtime binding of the robot parameters), without re-creating the robot or
+ * its plans.  Every later launch (plain, fused or plan) uses the new values.
+ * Blocking: it copies to the device before returning and is not ordered with
+ * launches, so call it only when no launch that reads the robot is pending
+ * (synchronize its streams first).  WB_ERR_INVALID_ARG for an out-of-range
+ * link, null arrays, a negative or non-finite mass or non-finite values. */
+int wb_robot_set_link_inertia(wb_robot *robot, int32_t link, float mass, const float *com, const float *inertia);
 int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune);
 
 /* ------------------------------------------------ uneven multi-robot batches

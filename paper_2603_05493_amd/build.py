@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwb.so")
 
-SOURCES = ["wb_host.cpp", "fk.hip", "rnea.hip", "selfcoll.hip", "misc.hip", "fused.hip"]
+SOURCES = ["wb_host.cpp", "fk.hip", "rnea.hip", "selfcoll.hip", "misc.hip", "fused.hip", "bspline.hip"]
 ARCH = os.environ.get("WB_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,0 +1,275 @@
+// B-spline trajectory front end (cuRoboV2 Sec. 4): uniform cubic B-spline
+// evaluation of joint states from control points (Eq. 10) and its transpose,
+// the control-point gradient summed over every sample of a control point's
+// support (Eqs. 13-14), with ghost knots for the initial state and a
+// repeated final knot for a static goal.
+//
+// Knots of one trajectory and joint (extended index e):
+//   e = 0..2        ghost knots from (theta_0, theta_dot_0, theta_ddot_0)
+//   e = 3..K+2      control points u_0 .. u_{K-1}
+//   e = K+3..K+5    copies of u_{K-1}
+// Segment s (0 <= s < K+3) uses the window e = s..s+3 and is sampled at
+// alpha = i / n_interp; sample t = s * n_interp + i, H = (K+3) n_interp per
+// trajectory, state b = traj * H + t.
+//
+// Control points are stored [d][T][K] (a trajectory's knots contiguous).
+// Evaluation: one lane per (joint, state), so the three state arrays are
+// written coalesced; the lanes of one trajectory read its few knots from the
+// same cache lines.
+// Gradient: one lane per (joint, trajectory, control point), the control
+// point fastest, sums the samples of the (at most seven) segments containing
+// its knot, reading the trajectory's samples through the cache, and writes
+// its gradient (contiguous across the wavefront), optionally taking the
+// gradient step.  Both kernels are bound by HBM.
+#include "wb_internal.h"
+
+namespace wb {
+
+// Window gradient of one sample at alpha: B(alpha)^T [gp, gv, ga] added to
+// (r0, r1, r2, r3), with gv, ga already divided by dt, dt^2.
+__device__ __forceinline__ void window_grad(float alpha, float gp, float gv, float ga, float &r0, float &r1,
+                                            float &r2, float &r3) {
+    // gradient on the monomial coefficients (alpha^3, alpha^2, alpha, 1)
+    const float a2 = alpha * alpha;
+    const float d3 = gp * a2 * alpha + gv * 3.f * a2 + ga * 6.f * alpha;
+    const float d2 = gp * a2 + gv * 2.f * alpha + ga * 2.f;
+    const float d1 = gp * alpha + gv;
+    const float d0 = gp;
+    // C^T: onto the window
+    r0 += (-d3 + 3.f * d2 - 3.f * d1 + d0) * (1.f / 6.f);
+    r1 += (3.f * d3 - 6.f * d2 + 4.f * d0) * (1.f / 6.f);
+    r2 += (-3.f * d3 + 3.f * d2 + 3.f * d1 + d0) * (1.f / 6.f);
+    r3 += d3 * (1.f / 6.f);
+}
+
+// Knots of segment seg of one trajectory and joint, ghost knots blended in.
+// Every load is issued unconditionally (indices clamped, a missing initial
+// derivative read from theta0 with weight 0), so no load waits behind a
+// branch.
+__device__ __forceinline__ void segment_window(const float *__restrict__ Uj, int K, int seg, float th, float v,
+                                               float a, bool printed, float w[4]) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) w[m] = Uj[min(max(seg + m - 3, 0), K - 1)];
+    // ghost knots from the initial state: the paper's printed formulas, or
+    // the exact anchoring theta(0) = theta_0, theta_dot(0) = theta_dot_0,
+    // theta_ddot(0) = theta_ddot_0
+    const float g0 = printed ? th - a * (1.f / 6.f) : th - v + a * (1.f / 3.f);
+    const float g1 = printed ? th + v + a * (1.f / 3.f) : th - a * (1.f / 6.f);
+    const float g2 = printed ? th + 2.f * v + a * (11.f / 6.f) : th + v + a * (1.f / 3.f);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int e = seg + m;
+        const float f0 = e == 0 ? 1.f : 0.f, f1 = e == 1 ? 1.f : 0.f, f2 = e == 2 ? 1.f : 0.f;
+        w[m] = w[m] * (1.f - f0 - f1 - f2) + f0 * g0 + f1 * g1 + f2 * g2;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bspline_eval(int64_t T, int32_t K, int32_t n_interp, float dt,
+                                                      int32_t printed, const float *__restrict__ U,
+                                                      const float *__restrict__ th0,
+                                                      const float *__restrict__ dth0,
+                                                      const float *__restrict__ ddth0, float *__restrict__ q,
+                                                      float *__restrict__ qd, float *__restrict__ qdd) {
+    // 32-bit index arithmetic: the host keeps T * H below 2^31
+    const int H = (K + 3) * n_interp, NB = (int)T * H;
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (b >= NB) return;
+    const int traj = b / H;
+    const int t = b - traj * H;
+    const int seg = t / n_interp, i = t - seg * n_interp;
+    const float alpha = (float)i / (float)n_interp;
+    const int64_t o0 = (int64_t)j * T + traj;
+    const float *pv = dth0 ? dth0 : th0, *pa = ddth0 ? ddth0 : th0;
+    const float th = th0[o0];
+    const float v = pv[o0] * (dth0 ? dt : 0.f);
+    const float a = pa[o0] * (ddth0 ? dt * dt : 0.f);
+    float w[4];
+    segment_window(U + ((int64_t)j * T + traj) * K, K, seg, th, v, a, printed != 0, w);
+    // polynomial coefficients C w of alpha^3, alpha^2, alpha, 1
+    const float c3 = (-w[0] + 3.f * w[1] - 3.f * w[2] + w[3]) * (1.f / 6.f);
+    const float c2 = (3.f * w[0] - 6.f * w[1] + 3.f * w[2]) * (1.f / 6.f);
+    const float c1 = (-3.f * w[0] + 3.f * w[2]) * (1.f / 6.f);
+    const float c0 = (w[0] + 4.f * w[1] + w[2]) * (1.f / 6.f);
+    const float inv = 1.f / dt;
+    const int64_t o = (int64_t)j * NB + b;
+    q[o] = ((c3 * alpha + c2) * alpha + c1) * alpha + c0;
+    if (qd) qd[o] = ((3.f * c3 * alpha + 2.f * c2) * alpha + c1) * inv;
+    if (qdd) qdd[o] = (6.f * c3 * alpha + 2.f * c2) * (inv * inv);
+}
+
+// One lane per (joint, trajectory, control point), the control point
+// fastest: lane (j, traj, k) sums the window products of the segments that
+// contain its knot (extended index k + 3; for the final control point also
+// its three copies), reading the trajectory's samples from cache.  Every
+// sum runs in segment order, so the result is deterministic.
+__global__ void __launch_bounds__(256) k_bspline_backward(int64_t T, int32_t K, int32_t n_interp, float dt,
+                                                          const float *__restrict__ g_q,
+                                                          const float *__restrict__ g_qd,
+                                                          const float *__restrict__ g_qdd,
+                                                          float *__restrict__ g_U, float lr,
+                                                          float *__restrict__ U) {
+    // 32-bit index arithmetic: the host keeps T * H below 2^31
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (idx >= (int)T * K) return;
+    const int traj = idx / K;
+    const int k = idx - traj * K;
+    const int64_t H = (int64_t)(K + 3) * n_interp, NB = T * H;
+    const int64_t base = (int64_t)j * NB + traj * H;
+    const float inv = 1.f / dt, inv2 = inv * inv, rn = 1.f / (float)n_interp;
+    // segments touching the knot (and its copies): s from k to k + 3, or to K + 2
+    const int s_end = (k == K - 1) ? K + 2 : k + 3;
+    float g = 0.f;
+    for (int seg = k; seg <= s_end; ++seg) {
+        // window positions of this control point in segment seg: e - seg for
+        // e = k + 3 and, for the final control point, its copies K+3..K+5
+        float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;   // 1 where the window slot holds the knot
+        const int m = k + 3 - seg;
+        if (m == 0) w0 = 1.f; else if (m == 1) w1 = 1.f; else if (m == 2) w2 = 1.f; else if (m == 3) w3 = 1.f;
+        if (k == K - 1) {
+            for (int e = K + 3; e <= K + 5; ++e) {
+                const int mm = e - seg;
+                if (mm == 0) w0 = 1.f; else if (mm == 1) w1 = 1.f; else if (mm == 2) w2 = 1.f; else if (mm == 3) w3 = 1.f;
+            }
+        }
+        float r0 = 0.f, r1 = 0.f, r2 = 0.f, r3 = 0.f;
+        for (int i = 0; i < n_interp; ++i) {
+            const int64_t o = base + (int64_t)seg * n_interp + i;
+            const float gp = g_q ? g_q[o] : 0.f;
+            const float gv = g_qd ? g_qd[o] * inv : 0.f;
+            const float ga = g_qdd ? g_qdd[o] * inv2 : 0.f;
+            window_grad((float)i * rn, gp, gv, ga, r0, r1, r2, r3);
+        }
+        // the window slots holding the knot
+        g += w0 * r0 + w1 * r1 + w2 * r2 + w3 * r3;
+    }
+    const int64_t o = ((int64_t)j * T + traj) * K + k;
+    if (g_U) g_U[o] = g;
+    if (lr != 0.f) U[o] -= lr * g;
+}
+
+// Four samples per knot interval (alpha = 0, 1/4, 1/2, 3/4), the paper's
+// n_interp: one lane per (joint, trajectory, segment).  The evaluation forms
+// the segment's window and coefficients once and stores its four samples of
+// each output as one 16-byte vector.
+__global__ void __launch_bounds__(256) k_bspline_eval4(int32_t T, int32_t K, float dt, int32_t printed,
+                                                       const float *__restrict__ U, const float *__restrict__ th0,
+                                                       const float *__restrict__ dth0,
+                                                       const float *__restrict__ ddth0, float *__restrict__ q,
+                                                       float *__restrict__ qd, float *__restrict__ qdd) {
+    const int S = K + 3, NS = T * S;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (idx >= NS) return;
+    const int traj = idx / S, seg = idx - traj * S;
+    const int64_t o0 = (int64_t)j * T + traj;
+    const float *pv = dth0 ? dth0 : th0, *pa = ddth0 ? ddth0 : th0;
+    const float th = th0[o0];
+    const float v = pv[o0] * (dth0 ? dt : 0.f);
+    const float a = pa[o0] * (ddth0 ? dt * dt : 0.f);
+    float w[4];
+    segment_window(U + o0 * K, K, seg, th, v, a, printed != 0, w);
+    const float c3 = (-w[0] + 3.f * w[1] - 3.f * w[2] + w[3]) * (1.f / 6.f);
+    const float c2 = (3.f * w[0] - 6.f * w[1] + 3.f * w[2]) * (1.f / 6.f);
+    const float c1 = (-3.f * w[0] + 3.f * w[2]) * (1.f / 6.f);
+    const float c0 = (w[0] + 4.f * w[1] + w[2]) * (1.f / 6.f);
+    const float inv = 1.f / dt;
+    float p[4], pd[4], pdd[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float al = 0.25f * i;
+        p[i] = ((c3 * al + c2) * al + c1) * al + c0;
+        pd[i] = ((3.f * c3 * al + 2.f * c2) * al + c1) * inv;
+        pdd[i] = (6.f * c3 * al + 2.f * c2) * (inv * inv);
+    }
+    const int64_t o = (int64_t)j * NS * 4 + (int64_t)idx * 4;   // = j * T * H + traj * H + seg * 4
+    *reinterpret_cast<float4 *>(q + o) = make_float4(p[0], p[1], p[2], p[3]);
+    if (qd) *reinterpret_cast<float4 *>(qd + o) = make_float4(pd[0], pd[1], pd[2], pd[3]);
+    if (qdd) *reinterpret_cast<float4 *>(qdd + o) = make_float4(pdd[0], pdd[1], pdd[2], pdd[3]);
+}
+
+// Gradient for four samples per interval: lane (trajectory, segment) of a
+// workgroup holding whole trajectories forms its segment's window gradient
+// from three 16-byte loads, the workgroup stages them in LDS, and lane
+// (trajectory, s) for s >= 3 sums knot s over the (at most four) segments
+// that contain it -- the final control point also over its three copies --
+// in a fixed order.
+__global__ void __launch_bounds__(256) k_bspline_backward4(int32_t T, int32_t K, float dt,
+                                                           const float *__restrict__ g_q,
+                                                           const float *__restrict__ g_qd,
+                                                           const float *__restrict__ g_qdd,
+                                                           float *__restrict__ g_U, float lr,
+                                                           float *__restrict__ U) {
+    __shared__ float4 gw[256];
+    const int S = K + 3, tpb = 256 / S;
+    const int lt = threadIdx.x / S, seg = threadIdx.x - lt * S;
+    const int traj = blockIdx.x * tpb + lt;
+    const int j = blockIdx.y;
+    const bool act = lt < tpb && traj < T;
+    float r0 = 0.f, r1 = 0.f, r2 = 0.f, r3 = 0.f;
+    if (act) {
+        const int64_t o = (int64_t)j * T * S * 4 + ((int64_t)traj * S + seg) * 4;
+        const float inv = 1.f / dt, inv2 = inv * inv;
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 p = g_q ? *reinterpret_cast<const float4 *>(g_q + o) : z;
+        const float4 v = g_qd ? *reinterpret_cast<const float4 *>(g_qd + o) : z;
+        const float4 a = g_qdd ? *reinterpret_cast<const float4 *>(g_qdd + o) : z;
+        window_grad(0.00f, p.x, v.x * inv, a.x * inv2, r0, r1, r2, r3);
+        window_grad(0.25f, p.y, v.y * inv, a.y * inv2, r0, r1, r2, r3);
+        window_grad(0.50f, p.z, v.z * inv, a.z * inv2, r0, r1, r2, r3);
+        window_grad(0.75f, p.w, v.w * inv, a.w * inv2, r0, r1, r2, r3);
+    }
+    gw[threadIdx.x] = make_float4(r0, r1, r2, r3);
+    __syncthreads();
+    if (!act || seg < 3) return;   // ghost knots take no gradient
+    const float4 *row = gw + lt * S;
+    // knot e = seg is slot m of segment seg - m
+    float g = row[seg].x + row[seg - 1].y + row[seg - 2].z + row[seg - 3].w;
+    if (seg == S - 1) {
+        // copies e = S .. S+2 of the final control point: slot e - s of segment s
+        g += row[S - 1].y + row[S - 2].z + row[S - 3].w;   // e = S
+        g += row[S - 1].z + row[S - 2].w;                  // e = S + 1
+        g += row[S - 1].w;                                 // e = S + 2
+    }
+    const int64_t o = ((int64_t)j * T + traj) * K + (seg - 3);
+    if (g_U) g_U[o] = g;
+    if (lr != 0.f) U[o] -= lr * g;
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+hipError_t launch_bspline_eval(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, int32_t printed,
+                               const float *U, const float *th0, const float *dth0, const float *ddth0, float *q,
+                               float *qd, float *qdd, hipStream_t s) {
+    const int64_t NB = T * (int64_t)(K + 3) * n_interp;
+    if (NB == 0 || d == 0) return hipSuccess;
+    if (n_interp == 4 && aligned16(q) && aligned16(qd) && aligned16(qdd)) {
+        const int64_t NS = T * (int64_t)(K + 3);
+        dim3 grid((unsigned)((NS + 255) / 256), (unsigned)d);
+        hipLaunchKernelGGL(k_bspline_eval4, grid, dim3(256), 0, s, (int32_t)T, K, dt, printed, U, th0, dth0, ddth0, q,
+                           qd, qdd);
+        return hipGetLastError();
+    }
+    dim3 grid((unsigned)((NB + 255) / 256), (unsigned)d);
+    hipLaunchKernelGGL(k_bspline_eval, grid, dim3(256), 0, s, T, K, n_interp, dt, printed, U, th0, dth0, ddth0, q,
+                       qd, qdd);
+    return hipGetLastError();
+}
+
+hipError_t launch_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, const float *g_q,
+                                   const float *g_qd, const float *g_qdd, float *g_U, float lr, float *U,
+                                   hipStream_t s) {
+    if (T == 0 || d == 0) return hipSuccess;
+    if (n_interp == 4 && K + 3 <= 256 && aligned16(g_q) && aligned16(g_qd) && aligned16(g_qdd)) {
+        const int tpb = 256 / (K + 3);
+        dim3 grid((unsigned)((T + tpb - 1) / tpb), (unsigned)d);
+        hipLaunchKernelGGL(k_bspline_backward4, grid, dim3(256), 0, s, (int32_t)T, K, dt, g_q, g_qd, g_qdd, g_U, lr, U);
+        return hipGetLastError();
+    }
+    dim3 grid((unsigned)((T * K + 255) / 256), (unsigned)d);
+    hipLaunchKernelGGL(k_bspline_backward, grid, dim3(256), 0, s, T, K, n_interp, dt, g_q, g_qd, g_qdd, g_U, lr, U);
+    return hipGetLastError();
+}
+
+}  // namespace wb

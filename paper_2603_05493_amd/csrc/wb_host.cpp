@@ -45,6 +45,7 @@ struct Tables {
     float g[3] = {0, 0, 0};
     // fused-kernel lane tables (depth-first lane order)
     int fused = 0, jsteps = 0;
+    std::vector<int> lane_of;         // link -> lane of the fused tables
     std::vector<int32_t> f_li;
     std::vector<float> f_lf;
     std::vector<float4> f_sph;
@@ -73,7 +74,9 @@ void build_fused(Tables &T) {
         perm.push_back(k);
         for (auto it = kids[k].rbegin(); it != kids[k].rend(); ++it) stack.push_back(*it);
     }
-    std::vector<int> lane_of(L), size(L, 1);
+    std::vector<int> &lane_of = T.lane_of;
+    std::vector<int> size(L, 1);
+    lane_of.assign(L, 0);
     for (int i = 0; i < L; ++i) lane_of[perm[i]] = i;
     for (int k = L - 1; k >= 1; --k) size[T.li[k].parent] += size[k];
     T.f_li.assign(8 * 64, 0);
@@ -340,6 +343,7 @@ struct wb_robot {
     wb::DevFused fz{};
     wb_tune tune{};
     void *dmem = nullptr;
+    size_t o_lf = 0, o_ff = 0;   // offsets of the link records and the fused float lane table
     int device = -1;
 };
 
@@ -458,6 +462,8 @@ int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
         return hip_fail(e, "uploading the robot tables");
     }
     char *base = static_cast<char *>(r->dmem);
+    r->o_lf = o_lf;
+    r->o_ff = o_ff;
     wb::DevRobot &D = r->dev;
     D.L = T.L; D.n = T.n; D.S = T.S; D.nmax = T.nmax;
     D.n_blocks = T.n_blocks; D.n_blocks_pad = (int)T.blocks.size();
@@ -650,6 +656,55 @@ int wb_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd,
     return finish(wb::launch_sgd_step(B, n, lr, q, qd, qdd, g_q, g_q2, g_qd, g_qdd, stream), "wb_sgd_step launch");
 }
 
+namespace {
+int check_bspline(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt) {
+    WB_TRY(check_B(T));
+    if (d < 0) return fail(WB_ERR_INVALID_ARG, "d must be >= 0");
+    if (K < 1 || K > WB_BSPLINE_MAX_K) return fail(WB_ERR_INVALID_ARG, "K must be in [1, %d]", WB_BSPLINE_MAX_K);
+    if (n_interp < 1 || n_interp > 1024) return fail(WB_ERR_INVALID_ARG, "n_interp must be in [1, 1024]");
+    if (!(dt > 0.0f) || !std::isfinite(dt)) return fail(WB_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (d > 65535) return fail(WB_ERR_UNSUPPORTED, "d must be <= 65535");
+    const int64_t H = (int64_t)(K + 3) * n_interp;
+    if (T > 0 && H > (INT64_C(1) << 31) / T - 1)
+        return fail(WB_ERR_UNSUPPORTED, "T * (K + 3) * n_interp samples must stay below 2^31");
+    return WB_OK;
+}
+}  // namespace
+
+int wb_bspline_eval(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, int32_t reading,
+                    const float *U, const float *theta0, const float *dtheta0, const float *ddtheta0,
+                    float *q, float *qd, float *qdd, hipStream_t stream) {
+    WB_TRY(check_bspline(T, d, K, n_interp, dt));
+    if (reading != WB_GHOST_EXACT && reading != WB_GHOST_PRINTED)
+        return fail(WB_ERR_INVALID_ARG, "reading must be WB_GHOST_EXACT or WB_GHOST_PRINTED");
+    if (T == 0 || d == 0) return WB_OK;
+    WB_TRY(check_ptr(U, "U", true));
+    WB_TRY(check_ptr(theta0, "theta0", true));
+    WB_TRY(check_ptr(dtheta0, "dtheta0", false));
+    WB_TRY(check_ptr(ddtheta0, "ddtheta0", false));
+    WB_TRY(check_ptr(q, "q", true));
+    WB_TRY(check_ptr(qd, "qd", false));
+    WB_TRY(check_ptr(qdd, "qdd", false));
+    return finish(wb::launch_bspline_eval(T, d, K, n_interp, dt, reading, U, theta0, dtheta0, ddtheta0, q, qd, qdd,
+                                          stream),
+                  "wb_bspline_eval launch");
+}
+
+int wb_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, const float *g_q,
+                        const float *g_qd, const float *g_qdd, float *g_U, float lr, float *U,
+                        hipStream_t stream) {
+    WB_TRY(check_bspline(T, d, K, n_interp, dt));
+    if (!std::isfinite(lr)) return fail(WB_ERR_INVALID_ARG, "lr must be finite");
+    if (T == 0 || d == 0) return WB_OK;
+    WB_TRY(check_ptr(g_q, "g_q", false));
+    WB_TRY(check_ptr(g_qd, "g_qd", false));
+    WB_TRY(check_ptr(g_qdd, "g_qdd", false));
+    WB_TRY(check_ptr(g_U, "g_U", lr == 0.0f));
+    WB_TRY(check_ptr(U, "U", lr != 0.0f));
+    return finish(wb::launch_bspline_backward(T, d, K, n_interp, dt, g_q, g_qd, g_qdd, g_U, lr, U, stream),
+                  "wb_bspline_backward launch");
+}
+
 int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, float *qdd, const float *w,
                       float torque_weight, float margin, float hinge_weight, float lr, float *tau, float *cost,
                       float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q, float *g_qd, float *g_qdd,
@@ -690,6 +745,37 @@ int wb_robot_set_tune(wb_robot *robot, const wb_tune *tune) {
     if (!tune) return fail(WB_ERR_INVALID_ARG, "tune is null");
     WB_TRY(check_tune(*tune, robot->T));
     robot->tune = *tune;
+    return WB_OK;
+}
+
+int wb_robot_set_link_inertia(wb_robot *robot, int32_t link, float mass, const float *com, const float *inertia) {
+    WB_TRY(check_robot(robot));
+    Tables &T = robot->T;
+    if (link < 0 || link >= T.L) return fail(WB_ERR_INVALID_ARG, "link %d out of range [0, %d)", link, T.L);
+    if (!com || !inertia) return fail(WB_ERR_INVALID_ARG, "com and inertia must not be null");
+    if (!std::isfinite(mass) || mass < 0.0f || !finite_all(com, 3) || !finite_all(inertia, 6))
+        return fail(WB_ERR_INVALID_ARG, "mass must be finite and >= 0, com and inertia finite");
+    wb::LinkF &F = T.lf[link];
+    F.mass = mass;
+    for (int c = 0; c < 3; ++c) F.com[c] = com[c];
+    for (int c = 0; c < 6; ++c) F.I[c] = inertia[c];
+    if (T.fused) {
+        const int i = T.lane_of[link];
+        T.f_lf[15 * 64 + i] = mass;
+        for (int c = 0; c < 3; ++c) T.f_lf[(16 + c) * 64 + i] = com[c];
+        for (int c = 0; c < 6; ++c) T.f_lf[(19 + c) * 64 + i] = inertia[c];
+    }
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != robot->device) e = hipSetDevice(robot->device);
+    char *base = static_cast<char *>(robot->dmem);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + robot->o_lf + (size_t)link * sizeof(wb::LinkF), &F, sizeof(wb::LinkF),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && T.fused)
+        e = hipMemcpy(base + robot->o_ff, T.f_lf.data(), T.f_lf.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (prev >= 0 && prev != robot->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "updating the link inertia");
     return WB_OK;
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include "wb.h"
 
 namespace wb {
 
@@ -149,6 +150,13 @@ hipError_t launch_cost_head(int64_t B, int32_t n, const float *tau, const float 
 hipError_t launch_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd,
                            const float *g_q, const float *g_q2, const float *g_qd,
                            const float *g_qdd, hipStream_t s);
+
+hipError_t launch_bspline_eval(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, int32_t printed,
+                               const float *U, const float *th0, const float *dth0, const float *ddth0, float *q,
+                               float *qd, float *qdd, hipStream_t s);
+hipError_t launch_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, const float *g_q,
+                                   const float *g_qd, const float *g_qdd, float *g_U, float lr, float *U,
+                                   hipStream_t s);
 
 // LDS of one state's sweep: (L+1)*nmax sphere slots and L+1 link bounding
 // spheres (float4 each); plus, per sweeping group, a list of list_cap

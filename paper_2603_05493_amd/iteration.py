@@ -174,3 +174,43 @@ class OptimizerGraph:
         if self.graph is None:
             raise RuntimeError("capture() first")
         self.graph.replay()
+
+
+class BsplineIteration:
+    """The optimizer iteration over B-spline control points (Sec. 3 step 1
+    and Sec. 4 in front of the whole-body terms): sample the splines into
+    states (wb_bspline_eval), run the fused whole-body iteration on those
+    states without its own step, then pull the state gradients back onto the
+    control points and step them (wb_bspline_backward).
+
+    U [d][T][K] control points (updated in place when stepping); theta0,
+    dtheta0, ddtheta0 [d][T] the initial state of each trajectory; the
+    samples are the states b = traj * H + t of the fused iteration.
+    """
+
+    def __init__(self, robot: wb.Robot, U: torch.Tensor, theta0: torch.Tensor,
+                 dtheta0: Optional[torch.Tensor] = None, ddtheta0: Optional[torch.Tensor] = None,
+                 dt: float = 0.05, n_interp: int = 4, reading: int = wb.GHOST_EXACT,
+                 w: Optional[torch.Tensor] = None, torque_weight: float = 1e-3, margin: float = 0.01,
+                 hinge_weight: float = 1.0, lr: float = 0.0):
+        d, T, K = U.shape
+        if d != robot.n_dof:
+            raise ValueError(f"U has {d} joints, the robot {robot.n_dof}")
+        self.U, self.theta0, self.dtheta0, self.ddtheta0 = U, theta0, dtheta0, ddtheta0
+        self.dt, self.n_interp, self.reading, self.lr = dt, n_interp, reading, lr
+        self.K, self.T = K, T
+        self.H = wb.bspline_horizon(K, n_interp)
+        B = T * self.H
+        e = lambda *shape: torch.empty(shape, dtype=torch.float32, device=U.device)
+        self.q, self.qd, self.qdd = e(d, B), e(d, B), e(d, B)
+        self.fused = FusedIteration(robot, B, w=w, torque_weight=torque_weight, margin=margin,
+                                    hinge_weight=hinge_weight, lr=0.0, outputs=True)
+        self.g_U = e(d, T, K)
+
+    def run(self, step: bool = True) -> None:
+        wb.wb_bspline_eval(self.U, self.theta0, self.dt, self.n_interp, self.dtheta0, self.ddtheta0,
+                           q=self.q, qd=self.qd, qdd=self.qdd, reading=self.reading)
+        self.fused.run(self.q, self.qd, self.qdd, step=False)
+        f = self.fused
+        wb.wb_bspline_backward(self.K, self.T, self.dt, self.n_interp, g_q=f.g_q, g_qd=f.g_qd, g_qdd=f.g_qdd,
+                               g_U=self.g_U, lr=self.lr if step else 0.0, U=self.U)

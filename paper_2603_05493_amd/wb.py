@@ -115,6 +115,14 @@ class Robot:
         t = _abi.WbTune(int(lanes_per_state), int(states_per_item), float(ns_per_state))
         check(lib().wb_robot_set_tune(self.handle, C.byref(t)))
 
+    def set_link_inertia(self, link: int, mass: float, com, inertia) -> None:
+        """Replace one link's mass, CoM and inertia about the CoM (xx yy zz xy
+        xz yz, link axes) on the device, e.g. for a payload; blocking, call
+        between launches."""
+        c = (C.c_float * 3)(*[float(x) for x in com])
+        i6 = (C.c_float * 6)(*[float(x) for x in inertia])
+        check(lib().wb_robot_set_link_inertia(self.handle, int(link), float(mass), c, i6))
+
     def get_tune(self) -> dict:
         t = _abi.WbTune()
         check(lib().wb_robot_get_tune(self.handle, C.byref(t)))
@@ -260,6 +268,56 @@ def wb_sgd_step(lr: float, q, qd, qdd, g_q, g_qd, g_qdd, g_q2=None):
         _chk(t, nm, (n, B), device=q.device)
     check(lib().wb_sgd_step(B, n, float(lr), _p(q), _p(qd), _p(qdd), _p(g_q), _p(g_q2), _p(g_qd),
                             _p(g_qdd), _stream()))
+
+
+GHOST_EXACT, GHOST_PRINTED = 0, 1
+BSPLINE_MAX_K = 65536
+
+
+def bspline_horizon(K: int, n_interp: int) -> int:
+    """Samples per trajectory: K + 3 segments of n_interp samples."""
+    return (K + 3) * n_interp
+
+
+def wb_bspline_eval(U, theta0, dt: float, n_interp: int = 4, dtheta0=None, ddtheta0=None, q=None, qd=None,
+                    qdd=None, reading: int = GHOST_EXACT):
+    """Sample the control points U [d][T][K] into q, qd, qdd [d][T*H]
+    (allocated when None; qd and qdd are skipped when passed as False)."""
+    d, T, K = U.shape
+    H = bspline_horizon(K, n_interp)
+    _chk(U, "U", (d, T, K), device=U.device)
+    for t, nm in ((theta0, "theta0"), (dtheta0, "dtheta0"), (ddtheta0, "ddtheta0")):
+        _chk(t, nm, (d, T), device=U.device)
+    outs = []
+    for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd")):
+        if t is False:
+            outs.append(None)
+            continue
+        if t is None:
+            t = torch.empty((d, T * H), dtype=torch.float32, device=U.device)
+        _chk(t, nm, (d, T * H), device=U.device)
+        outs.append(t)
+    check(lib().wb_bspline_eval(T, d, K, n_interp, float(dt), int(reading), _p(U), _p(theta0), _p(dtheta0),
+                                _p(ddtheta0), _p(outs[0]), _p(outs[1]), _p(outs[2]), _stream()))
+    return tuple(outs)
+
+
+def wb_bspline_backward(K: int, T: int, dt: float, n_interp: int = 4, g_q=None, g_qd=None, g_qdd=None, g_U=None,
+                        lr: float = 0.0, U=None):
+    """Control-point gradient [d][T][K] of upstream sample gradients
+    [d][T*H]; with lr != 0 also U -= lr * g_U in place."""
+    ref = next(t for t in (g_q, g_qd, g_qdd) if t is not None)
+    d = ref.shape[0]
+    H = bspline_horizon(K, n_interp)
+    for t, nm in ((g_q, "g_q"), (g_qd, "g_qd"), (g_qdd, "g_qdd")):
+        _chk(t, nm, (d, T * H), device=ref.device)
+    if g_U is None and lr == 0.0:
+        g_U = torch.empty((d, T, K), dtype=torch.float32, device=ref.device)
+    _chk(g_U, "g_U", (d, T, K), device=ref.device)
+    _chk(U, "U", (d, T, K), device=ref.device)
+    check(lib().wb_bspline_backward(T, d, K, n_interp, float(dt), _p(g_q), _p(g_qd), _p(g_qdd), _p(g_U),
+                                    float(lr), _p(U), _stream()))
+    return g_U
 
 
 def wb_wholebody_step(robot: Robot, q, qd, qdd, w=None, torque_weight=0.0, margin=0.0, hinge_weight=0.0,

@@ -140,3 +140,26 @@ def test_launch_calls_reject_null_robot(abi):
         abi.WB_ERR_INVALID_ARG
     # B = 0 with no pointers is a valid no-op for the robot-free kernels
     assert lib.wb_sgd_step(0, 3, 0.1, None, None, None, None, None, None, None, None) == abi.WB_OK
+
+
+def test_bspline_calls_validate_arguments(abi):
+    lib = abi.lib()
+    E = abi.WB_ERR_INVALID_ARG
+    ev = lambda T, d, K, n, dt, rd, U=None, th=None, q=None: lib.wb_bspline_eval(T, d, K, n, dt, rd, U, th, None,
+                                                                                  None, q, None, None, None)
+    # empty batches are valid no-ops
+    assert ev(0, 4, 9, 4, 0.05, 0) == abi.WB_OK
+    assert lib.wb_bspline_backward(0, 4, 9, 4, 0.05, None, None, None, None, 0.0, None, None) == abi.WB_OK
+    # shape and parameter checks come before any launch
+    assert ev(1, 4, 0, 4, 0.05, 0) == E                      # no control points
+    assert ev(1, 4, 9, 0, 0.05, 0) == E                      # no samples per interval
+    assert ev(1, 4, 9, 4, 0.0, 0) == E                       # dt must be > 0
+    assert ev(1, 4, 9, 4, float("nan"), 0) == E
+    assert ev(1, 4, 9, 4, 0.05, 2) == E                      # unknown ghost-knot reading
+    assert ev(-1, 4, 9, 4, 0.05, 0) == E
+    assert ev(1, 4, 9, 4, 0.05, 0) == E                      # U, theta0 and q are required
+    assert "U" in lib.wb_last_error().decode()
+    # the gradient needs somewhere to go: g_U, or U with a step
+    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, 0.0, None, None) == E
+    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, 0.1, None, None) == E
+    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, float("inf"), None, None) == E
