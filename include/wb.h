@@ -157,9 +157,11 @@ int wb_fk(const wb_robot *robot, int64_t B, const float *q, float *link_pose, fl
           hipStream_t stream);
 
 /* Inverse dynamics by RNEA (Alg. 4).  q, qd, qdd [n][B] -> tau[n][B].
- * f_ext must be NULL in this build (external link forces are not supported:
- * WB_ERR_UNSUPPORTED).  cache[L][18][B] (required) receives v, a and the
- * accumulated link forces for wb_rnea_backward. */
+ * f_ext[L][6][B] (NULL = none): external spatial force on each link in link
+ * coordinates, moment then force about the link origin; it enters Alg. 4's
+ * force line as f_k = I_k a_k + v_k x* I_k v_k - f_ext_k.  cache[L][18][B]
+ * (required) receives v, a and the accumulated link forces (including
+ * f_ext) for wb_rnea_backward. */
 int wb_rnea(const wb_robot *robot, int64_t B, const float *q, const float *qd, const float *qdd,
             const float *f_ext, float *tau, float *cache, hipStream_t stream);
 
@@ -193,12 +195,15 @@ int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float
                    hipStream_t stream);
 
 /* Vector-Jacobian product of RNEA (the role of Alg. 5): g_tau[n][B] ->
- * g_q, g_qd, g_qdd [n][B] (overwritten).  cache is the one written by
- * wb_rnea for the same q, qd, qdd.  Transforms are recomputed from q.
+ * g_q, g_qd, g_qdd [n][B] (overwritten) and, when g_fext is not NULL, the
+ * gradient on the external forces g_fext[L][6][B] (overwritten; link
+ * coordinates like f_ext; it is minus the adjoint of each link's accumulated
+ * force, Alg. 5's f-bar_ext).  cache is the one written by wb_rnea for the
+ * same q, qd, qdd and f_ext.  Transforms are recomputed from q.
  * workspace: wb_workspace_bytes(robot, B). */
 int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const float *qd,
                      const float *qdd, const float *cache, const float *g_tau, float *g_q,
-                     float *g_qd, float *g_qdd, void *workspace, hipStream_t stream);
+                     float *g_qd, float *g_qdd, float *g_fext, void *workspace, hipStream_t stream);
 
 /* ------------------------------------------------ cost head and update step
  * The per-state scalar costs of the trajectory-optimization iteration
@@ -271,6 +276,10 @@ int wb_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float
  *   g_q, g_qd, g_qdd [n][B]   optional outputs (NULL to skip); the gradients
  *                      are those of cost[b] (FK through the hinge plus RNEA),
  *                      evaluated before the step.
+ *   f_ext [L][6][B] or NULL    external link forces, as in wb_rnea;
+ *   g_fext [L][6][B] or NULL   their gradient (as wb_rnea_backward's g_fext,
+ *                      for the torque cost).  Either one selects the kernel
+ *                      variant that carries external forces.
  * Results agree with the separate calls (same definitions, same tolerance;
  * floating-point sums are ordered differently).  Needs n_links <= 64, no
  * mimic joints, and the per-state sweep tables of a 256-lane workgroup
@@ -279,7 +288,7 @@ int wb_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float
 int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, float *qdd, const float *w,
                       float torque_weight, float margin, float hinge_weight, float lr, float *tau,
                       float *cost, float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q,
-                      float *g_qd, float *g_qdd, hipStream_t stream);
+                      float *g_qd, float *g_qdd, const float *f_ext, float *g_fext, hipStream_t stream);
 
 /* Launch shape of the fused iteration for one robot (the paper dispatches
  * FK differently by robot size, Sec. 6.1 "adaptive kernel dispatch"; here the

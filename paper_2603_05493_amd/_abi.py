@@ -68,7 +68,7 @@ _SIGS = {
     "wb_self_collision": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp],
     "wb_self_collision_backward": [_vp, C.c_int64, _vp, _vp, _vp, C.c_float, _vp, _vp, _vp],
     "wb_fk_backward": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
-    "wb_rnea_backward": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "wb_rnea_backward": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "wb_cost_head": [C.c_int64, C.c_int32, _vp, _vp, C.c_float, _vp, C.c_float, C.c_float, _vp, _vp,
                      _vp, _vp],
     "wb_sgd_step": [C.c_int64, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
@@ -78,7 +78,7 @@ _SIGS = {
     "wb_bspline_backward": [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, C.c_float,
                             _vp, _vp],
     "wb_wholebody_step": [_vp, C.c_int64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float,
-                          _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+                          _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "wb_robot_set_tune": [_vp, C.POINTER(WbTune)],
     "wb_robot_get_tune": [_vp, C.POINTER(WbTune)],
     "wb_plan_create": [C.POINTER(_vp), C.POINTER(C.c_int64), C.c_int32, C.POINTER(WbTune), C.POINTER(_vp)],

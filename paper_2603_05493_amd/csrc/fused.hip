@@ -38,6 +38,11 @@
 //   q-bar = S . subsum(W)
 // since rotating joint i moves every world axis and inertia in its subtree
 // (dS = dq S_i x S, dI = dq (S_i x* I - I S_i x)).
+//
+// External link forces (the FEXT variant): f_ext is given in link
+// coordinates and turns with its link, f_w = X* f_ext; it enters the force
+// line as f = I a + v x* I v - f_w, adds fb x* f_w to W (the rotation of f_w
+// with the joints above it), and its gradient is f_ext-bar = -X*^T fb.
 #include "sweep.h"
 
 namespace wb {
@@ -118,7 +123,7 @@ __device__ __forceinline__ void wave_sync() {
 // a valid state and store nothing.  The lane's link constants are read from
 // the lane tables at the point of use in every state (they stay in the L1
 // cache), so that no register holds them across the sweep.
-template <int NMAX, bool FULL>
+template <int NMAX, bool FULL, bool FEXT>
 __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t *tab, const DevFused &fz,
                                               const TreeIO &io, const StepScalars &k, float4 *P, float4 *Bd,
                                               uint16_t *list, int G, int grp, int glane, int64_t B, int64_t b,
@@ -217,6 +222,13 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
         rotate_inertia(R, Ic, J.I);
     }
     const int sub_end = li[2 * 64 + gl];
+    // ---- external force in world coordinates, f_w = X* f_ext (moment about the world origin)
+    SV fe = zsv();
+    if (FEXT && io.f_ext && act) {
+        const float *fx = io.f_ext + (int64_t)(link * 6) * B + b;
+        const V3 Rf = mul(R, v3(fx[3 * B], fx[4 * B], fx[5 * B]));
+        fe = sv(mul(R, v3(fx[0], fx[B], fx[2 * B])) + cross(p, Rf), Rf);
+    }
     // ---- RNEA forward
     const SV Sqd = thd * S;
     const SV v = path_sum(Sqd, parent_lane, glane, fz.jsteps, G);
@@ -224,6 +236,7 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     if (act) a += sv(v3(0.f, 0.f, 0.f), v3(-rb.gx, -rb.gy, -rb.gz));
     const SV Ia = iw_apply(J, a), Iv = iw_apply(J, v);
     SV F = Ia + crf(v, Iv);
+    if (FEXT) F = F - fe;
     if (!act) F = zsv();
     F = subtree_sum(F, glane, sub_end, G);
     const float tau = revolute ? dot(S, F) : 0.f;
@@ -245,6 +258,7 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     const SV fb = path_sum(taub * S, parent_lane, glane, fz.jsteps, G);
     SV ab = iw_apply(J, fb);
     W = W - (crf(fb, Ia) + crf(a, ab));
+    if (FEXT) W += crf(fb, fe);
     const SV vxfb = crm(v, fb);
     const SV Ivxfb = iw_apply(J, vxfb);
     SV vb = zsv() - (crf(fb, Iv) + Ivxfb);
@@ -264,6 +278,13 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     const float th_b = dot(S, Ws);
     // ---- outputs and the gradient step
     if (!valid) return;
+    if (FEXT && io.g_fext && act) {
+        // -X*^T fb: moment part -R^T fb_w, force part -R^T (fb_l + fb_w x p)
+        const V3 gn = mulT(R, fb.w), gf = mulT(R, fb.l + cross(fb.w, p));
+        float *gx = io.g_fext + (int64_t)(link * 6) * B + b;
+        gx[0] = -gn.x; gx[B] = -gn.y; gx[2 * B] = -gn.z;
+        gx[3 * B] = -gf.x; gx[4 * B] = -gf.y; gx[5 * B] = -gf.z;
+    }
     if (revolute) {
         if (io.tau) io.tau[jo] = tau;
         if (io.g_q) io.g_q[jo] = th_b;
@@ -286,7 +307,7 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
 // Process `count` states starting at b0 of one robot with the 4 waves of
 // this workgroup, 64/G states per wavefront at a time; tab is the robot's
 // block table staged in LDS.
-template <int NMAX>
+template <int NMAX, bool FEXT>
 __device__ __forceinline__ void run_states(const DevRobot &rb, const uint16_t *tab, const DevFused &fz, const TreeIO &io,
                                            const StepScalars &k, float4 *lds_wave, int G, int64_t B,
                                            int64_t b0, int count) {
@@ -304,8 +325,8 @@ __device__ __forceinline__ void run_states(const DevRobot &rb, const uint16_t *t
         const int s = base + grp;
         const bool valid = s < count;
         const int64_t b = b0 + (valid ? s : base);
-        if (G == 64) iterate_state<NMAX, true>(rb, tab, fz, io, k, P, Bd, list, 64, 0, glane, B, b, valid);
-        else iterate_state<NMAX, false>(rb, tab, fz, io, k, P, Bd, list, G, grp, glane, B, b, valid);
+        if (G == 64) iterate_state<NMAX, true, FEXT>(rb, tab, fz, io, k, P, Bd, list, 64, 0, glane, B, b, valid);
+        else iterate_state<NMAX, false, FEXT>(rb, tab, fz, io, k, P, Bd, list, G, grp, glane, B, b, valid);
     }
 }
 
@@ -318,8 +339,9 @@ __device__ __forceinline__ void stage_table(const DevRobot &rb, uint16_t *tab) {
     }
 }
 
-// Four wavefronts per SIMD: the register budget is 128 VGPRs.
-template <int NMAX>
+// Four wavefronts per SIMD: the register budget is 128 VGPRs.  FEXT: the
+// variant with external link forces (and their gradient).
+template <int NMAX, bool FEXT>
 __global__ void __launch_bounds__(256, 4) k_fused_step(FusedArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
@@ -335,7 +357,7 @@ __global__ void __launch_bounds__(256, 4) k_fused_step(FusedArgs A) {
     uint16_t *tab = reinterpret_cast<uint16_t *>(lds + 4 * SLW);
     stage_table(A.rb, tab);
     __syncthreads();
-    run_states<NMAX>(A.rb, tab, A.fz, A.io, A.k, lds + wave * SLW, G, A.B, b0, count);
+    run_states<NMAX, FEXT>(A.rb, tab, A.fz, A.io, A.k, lds + wave * SLW, G, A.B, b0, count);
 }
 
 // Persistent launch over an uneven batch of robots: workgroup w processes
@@ -359,8 +381,8 @@ __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
             staged = item.tree;
         }
         // a fixed region per wave, sized for the plan's largest tree
-        run_states<NMAX>(T.rb, tab, T.fz, A.io[item.tree], A.k, lds + wave * A.wave_stride, G, T.B, item.b0,
-                         item.count);
+        run_states<NMAX, false>(T.rb, tab, T.fz, A.io[item.tree], A.k, lds + wave * A.wave_stride, G, T.B,
+                                item.b0, item.count);
     }
 }
 
@@ -368,7 +390,8 @@ template <int NMAX>
 static hipError_t launch_fused_t(const FusedArgs &a, hipStream_t s) {
     const size_t lds = fused_lds_bytes(a.rb.L, NMAX, a.rb.list_cap, a.lanes_per_state, a.rb.n_blocks_pad);
     const unsigned nwg = (unsigned)((a.B + a.chunk - 1) / a.chunk);
-    hipLaunchKernelGGL(k_fused_step<NMAX>, dim3(nwg), dim3(256), lds, s, a);
+    if (a.io.f_ext || a.io.g_fext) hipLaunchKernelGGL((k_fused_step<NMAX, true>), dim3(nwg), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_fused_step<NMAX, false>), dim3(nwg), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 

@@ -9,7 +9,10 @@
 // (a "carry"), touching the cache only at branch points.
 //
 // Cache layout [L][18][B]: v (6), a (6), accumulated force F (6) per link;
-// link 0 (the fixed base, v = 0, a = -g) is not stored.
+// link 0 (the fixed base, v = 0, a = -g) is not stored.  External link
+// forces f_ext [L][6][B] (link coordinates, moment then force about the link
+// origin) enter Alg. 4 as f_k = I a + v x* I v - f_ext_k, so the cached F
+// includes them and the backward needs only their adjoint, -F-bar_k.
 //
 // The backward is the exact reverse mode of the forward sweep (with
 // dX/dtheta = -crm(S) X):
@@ -56,7 +59,8 @@ __device__ __forceinline__ JointIn joint_in(const LinkF &f, const LinkI &i, cons
 
 __global__ void __launch_bounds__(256) k_rnea(DevRobot rb, int64_t B, const float *__restrict__ q,
                                               const float *__restrict__ qd, const float *__restrict__ qdd,
-                                              float *__restrict__ tau, float *__restrict__ cache) {
+                                              const float *__restrict__ f_ext, float *__restrict__ tau,
+                                              float *__restrict__ cache) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     const int L = rb.L;
@@ -86,7 +90,8 @@ __global__ void __launch_bounds__(256) k_rnea(DevRobot rb, int64_t B, const floa
         const SV Sqd = sv(J.thd * s, v3(0.f, 0.f, 0.f));
         v = X_apply(R, r, vp) + Sqd;
         a = X_apply(R, r, ap) + sv(J.thdd * s, v3(0.f, 0.f, 0.f)) + crm(v, Sqd);
-        const SV f = I_apply(lf, a) + crf(v, I_apply(lf, v));
+        SV f = I_apply(lf, a) + crf(v, I_apply(lf, v));
+        if (f_ext) f = f - ld_sv(f_ext + (int64_t)(k * 6) * B + b, B);
         float *ck = cb + (int64_t)(k * 18) * B;
         st_sv(ck, B, v);
         st_sv(ck + 6 * B, B, a);
@@ -133,7 +138,8 @@ __global__ void __launch_bounds__(256) k_rnea_backward(DevRobot rb, int64_t B, c
                                                        const float *__restrict__ cache,
                                                        const float *__restrict__ g_tau,
                                                        float *__restrict__ g_q, float *__restrict__ g_qd,
-                                                       float *__restrict__ g_qdd, float *__restrict__ ws) {
+                                                       float *__restrict__ g_qdd, float *__restrict__ g_fext,
+                                                       float *__restrict__ ws) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     const int L = rb.L;
@@ -149,6 +155,7 @@ __global__ void __launch_bounds__(256) k_rnea_backward(DevRobot rb, int64_t B, c
         }
     // Sweep A (base -> tips): adjoint of the force accumulation.
     SV Fb = zero;
+    if (g_fext) st_sv(g_fext + b, B, zero);   // the base's force reaches no joint
     for (int k = 1; k < L; ++k) {
         const LinkI li = ldu(rb.li + k);
         const LinkF lf = ldu(rb.lf + k);
@@ -164,6 +171,7 @@ __global__ void __launch_bounds__(256) k_rnea_backward(DevRobot rb, int64_t B, c
         Fb = sv(tb * s, v3(0.f, 0.f, 0.f)) + XFp;
         float *wk = wb_ + (int64_t)(k * 18) * B;
         st_sv(wk, B, Fb);
+        if (g_fext) st_sv(g_fext + (int64_t)(k * 6) * B + b, B, zero - Fb);
         if (li.far_child) {
             st_sv(wk + 6 * B, B, zero);
             st_sv(wk + 12 * B, B, zero);
@@ -241,20 +249,20 @@ __global__ void __launch_bounds__(256) k_rnea_backward(DevRobot rb, int64_t B, c
 }
 
 hipError_t launch_rnea(const DevRobot &rb, int64_t B, const float *q, const float *qd,
-                       const float *qdd, float *tau, float *cache, hipStream_t s) {
+                       const float *qdd, const float *f_ext, float *tau, float *cache, hipStream_t s) {
     if (B == 0) return hipSuccess;
     dim3 grid((unsigned)((B + 255) / 256));
-    hipLaunchKernelGGL(k_rnea, grid, dim3(256), 0, s, rb, B, q, qd, qdd, tau, cache);
+    hipLaunchKernelGGL(k_rnea, grid, dim3(256), 0, s, rb, B, q, qd, qdd, f_ext, tau, cache);
     return hipGetLastError();
 }
 
 hipError_t launch_rnea_backward(const DevRobot &rb, int64_t B, const float *q, const float *qd,
                                 const float *qdd, const float *cache, const float *g_tau,
-                                float *g_q, float *g_qd, float *g_qdd, float *ws, hipStream_t s) {
+                                float *g_q, float *g_qd, float *g_qdd, float *g_fext, float *ws, hipStream_t s) {
     if (B == 0) return hipSuccess;
     dim3 grid((unsigned)((B + 255) / 256));
     hipLaunchKernelGGL(k_rnea_backward, grid, dim3(256), 0, s, rb, B, q, qd, qdd, cache, g_tau, g_q,
-                       g_qd, g_qdd, ws);
+                       g_qd, g_qdd, g_fext, ws);
     return hipGetLastError();
 }
 

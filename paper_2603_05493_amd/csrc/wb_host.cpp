@@ -540,15 +540,15 @@ int wb_rnea(const wb_robot *robot, int64_t B, const float *q, const float *qd, c
             const float *f_ext, float *tau, float *cache, hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
-    if (f_ext) return fail(WB_ERR_UNSUPPORTED, "external link forces are not supported in this build");
     if (B == 0) return WB_OK;
     const bool need = robot->T.n > 0;
     WB_TRY(check_ptr(q, "q", need));
     WB_TRY(check_ptr(qd, "qd", need));
     WB_TRY(check_ptr(qdd, "qdd", need));
+    WB_TRY(check_ptr(f_ext, "f_ext", false));
     WB_TRY(check_ptr(tau, "tau", need));
     WB_TRY(check_ptr(cache, "cache", true));
-    return finish(wb::launch_rnea(robot->dev, B, q, qd, qdd, tau, cache, stream), "wb_rnea launch");
+    return finish(wb::launch_rnea(robot->dev, B, q, qd, qdd, f_ext, tau, cache, stream), "wb_rnea launch");
 }
 
 int wb_self_collision(const wb_robot *robot, int64_t B, const float *spheres, float *max_pen,
@@ -602,7 +602,7 @@ int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float
 
 int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const float *qd,
                      const float *qdd, const float *cache, const float *g_tau, float *g_q,
-                     float *g_qd, float *g_qdd, void *workspace, hipStream_t stream) {
+                     float *g_qd, float *g_qdd, float *g_fext, void *workspace, hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
     if (B == 0) return WB_OK;
@@ -615,8 +615,9 @@ int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const flo
     WB_TRY(check_ptr(g_q, "g_q", need));
     WB_TRY(check_ptr(g_qd, "g_qd", need));
     WB_TRY(check_ptr(g_qdd, "g_qdd", need));
+    WB_TRY(check_ptr(g_fext, "g_fext", false));
     WB_TRY(check_ptr(workspace, "workspace", true));
-    return finish(wb::launch_rnea_backward(robot->dev, B, q, qd, qdd, cache, g_tau, g_q, g_qd, g_qdd,
+    return finish(wb::launch_rnea_backward(robot->dev, B, q, qd, qdd, cache, g_tau, g_q, g_qd, g_qdd, g_fext,
                                            static_cast<float *>(workspace), stream),
                   "wb_rnea_backward launch");
 }
@@ -708,7 +709,7 @@ int wb_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float
 int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, float *qdd, const float *w,
                       float torque_weight, float margin, float hinge_weight, float lr, float *tau, float *cost,
                       float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q, float *g_qd, float *g_qdd,
-                      hipStream_t stream) {
+                      const float *f_ext, float *g_fext, hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
     if (!robot->fz.supported)
@@ -729,13 +730,15 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, flo
     WB_TRY(check_ptr(g_q, "g_q", false));
     WB_TRY(check_ptr(g_qd, "g_qd", false));
     WB_TRY(check_ptr(g_qdd, "g_qdd", false));
+    WB_TRY(check_ptr(f_ext, "f_ext", false));
+    WB_TRY(check_ptr(g_fext, "g_fext", false));
     wb::FusedArgs a{};
     a.rb = robot->dev;
     a.fz = robot->fz;
     a.B = B;
     a.chunk = robot->tune.states_per_item;
     a.lanes_per_state = robot->tune.lanes_per_state;
-    a.io = wb::TreeIO{q, qd, qdd, w, tau, cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd};
+    a.io = wb::TreeIO{q, qd, qdd, w, tau, cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd, f_ext, g_fext};
     a.k = wb::StepScalars{torque_weight, margin, hinge_weight, lr};
     return finish(wb::launch_fused(a, stream), "wb_wholebody_step launch");
 }

@@ -82,6 +82,8 @@ struct TreeIO {
     float *tau, *cost, *max_pen;  // optional outputs
     int32_t *argmax, *n_coll;
     float *g_q, *g_qd, *g_qdd;
+    const float *f_ext;           // [L][6][B] external link forces (link coordinates) or null
+    float *g_fext;                // [L][6][B] their gradient or null
 };
 
 // Scalars of the cost head and the step.
@@ -134,10 +136,10 @@ hipError_t launch_fk_backward(const DevRobot &rb, int64_t B, const float *q, con
                               const float *g_pose, const float *g_sph, float *g_q, float *ws,
                               hipStream_t s);
 hipError_t launch_rnea(const DevRobot &rb, int64_t B, const float *q, const float *qd,
-                       const float *qdd, float *tau, float *cache, hipStream_t s);
+                       const float *qdd, const float *f_ext, float *tau, float *cache, hipStream_t s);
 hipError_t launch_rnea_backward(const DevRobot &rb, int64_t B, const float *q, const float *qd,
                                 const float *qdd, const float *cache, const float *g_tau,
-                                float *g_q, float *g_qd, float *g_qdd, float *ws, hipStream_t s);
+                                float *g_q, float *g_qd, float *g_qdd, float *g_fext, float *ws, hipStream_t s);
 hipError_t launch_self_collision(const DevRobot &rb, int64_t B, const float *spheres,
                                  float *max_pen, int32_t *argmax, int32_t *n_coll, hipStream_t s);
 hipError_t launch_self_collision_backward(const DevRobot &rb, int64_t B, const float *spheres,

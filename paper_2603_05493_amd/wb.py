@@ -171,14 +171,17 @@ def wb_fk(robot: Robot, q: torch.Tensor, link_pose=None, spheres=None, want_sphe
     return link_pose, spheres
 
 
-def wb_rnea(robot: Robot, q, qd, qdd, tau=None, cache=None):
+def wb_rnea(robot: Robot, q, qd, qdd, tau=None, cache=None, f_ext=None):
+    """tau [n,B] (and the cache for the backward); f_ext [L,6,B] external
+    link forces in link coordinates (moment, force), or None."""
     n, B, L = robot.n_dof, q.shape[-1], robot.n_links
     tau = _empty((n, B), robot) if tau is None else tau
     cache = _empty((L, 18, B), robot) if cache is None else cache
     for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (tau, "tau")):
         _chk(t, nm, (n, B), device=robot.device)
     _chk(cache, "cache", (L, 18, B), device=robot.device)
-    check(lib().wb_rnea(robot.handle, B, _p(q), _p(qd), _p(qdd), None, _p(tau), _p(cache), _stream()))
+    _chk(f_ext, "f_ext", (L, 6, B), device=robot.device)
+    check(lib().wb_rnea(robot.handle, B, _p(q), _p(qd), _p(qdd), _p(f_ext), _p(tau), _p(cache), _stream()))
     return tau, cache
 
 
@@ -228,7 +231,9 @@ def wb_fk_backward(robot: Robot, q, g_spheres=None, g_link_pose=None, link_pose=
 
 
 def wb_rnea_backward(robot: Robot, q, qd, qdd, cache, g_tau, g_q=None, g_qd=None, g_qdd=None,
-                     workspace=None):
+                     workspace=None, g_fext=None):
+    """g_q, g_qd, g_qdd [n,B]; with g_fext [L,6,B] also the gradient on the
+    external forces of the forward call that wrote the cache."""
     n, B, L = robot.n_dof, q.shape[-1], robot.n_links
     g_q = _empty((n, B), robot) if g_q is None else g_q
     g_qd = _empty((n, B), robot) if g_qd is None else g_qd
@@ -238,10 +243,11 @@ def wb_rnea_backward(robot: Robot, q, qd, qdd, cache, g_tau, g_q=None, g_qd=None
                   (g_qdd, "g_qdd")):
         _chk(t, nm, (n, B), device=robot.device)
     _chk(cache, "cache", (L, 18, B), device=robot.device)
+    _chk(g_fext, "g_fext", (L, 6, B), device=robot.device)
     if workspace.numel() * workspace.element_size() < robot.workspace_bytes(B):
         raise ValueError("workspace too small")
     check(lib().wb_rnea_backward(robot.handle, B, _p(q), _p(qd), _p(qdd), _p(cache), _p(g_tau), _p(g_q),
-                                 _p(g_qd), _p(g_qdd), _p(workspace), _stream()))
+                                 _p(g_qd), _p(g_qdd), _p(g_fext), _p(workspace), _stream()))
     return g_q, g_qd, g_qdd
 
 
@@ -322,10 +328,14 @@ def wb_bspline_backward(K: int, T: int, dt: float, n_interp: int = 4, g_q=None, 
 
 def wb_wholebody_step(robot: Robot, q, qd, qdd, w=None, torque_weight=0.0, margin=0.0, hinge_weight=0.0,
                       lr=0.0, tau=None, cost=None, max_pen=None, argmax=None, n_coll=None, g_q=None,
-                      g_qd=None, g_qdd=None):
+                      g_qd=None, g_qdd=None, f_ext=None, g_fext=None):
     """One fused iteration (FK, self-collision, RNEA, cost head, adjoints,
-    optional in-place step on q, qd, qdd).  Outputs left as None are skipped."""
-    n, B = robot.n_dof, q.shape[-1]
+    optional in-place step on q, qd, qdd).  Outputs left as None are skipped.
+    f_ext [L,6,B]: external link forces (link coordinates, moment then force);
+    g_fext [L,6,B]: their gradient."""
+    n, B, L = robot.n_dof, q.shape[-1], robot.n_links
+    _chk(f_ext, "f_ext", (L, 6, B), device=robot.device)
+    _chk(g_fext, "g_fext", (L, 6, B), device=robot.device)
     for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (w, "w"), (tau, "tau"), (g_q, "g_q"), (g_qd, "g_qd"),
                   (g_qdd, "g_qdd")):
         _chk(t, nm, (n, B), device=robot.device)
@@ -336,7 +346,7 @@ def wb_wholebody_step(robot: Robot, q, qd, qdd, w=None, torque_weight=0.0, margi
     check(lib().wb_wholebody_step(robot.handle, B, _p(q), _p(qd), _p(qdd), _p(w), float(torque_weight),
                                   float(margin), float(hinge_weight), float(lr), _p(tau), _p(cost),
                                   _p(max_pen), _p(argmax), _p(n_coll), _p(g_q), _p(g_qd), _p(g_qdd),
-                                  _stream()))
+                                  _p(f_ext), _p(g_fext), _stream()))
 
 
 class Plan:

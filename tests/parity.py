@@ -93,18 +93,19 @@ def hinge_conditioning(ref, rb):
     return cond
 
 
-def oracle_iteration(O, rb, q, qd, qdd, w=None, torque_weight=1e-3, margin=0.01, hinge_weight=1.0):
+def oracle_iteration(O, rb, q, qd, qdd, w=None, torque_weight=1e-3, margin=0.01, hinge_weight=1.0, fext=None):
     """FP64 reference of one iteration: costs and the gradient of
-    sum_b cost_b with respect to q, qd, qdd (state-major arrays)."""
+    sum_b cost_b with respect to q, qd, qdd (state-major arrays); with
+    external link forces fext [B, L, 6] also the gradient on them."""
     R, p, c = O.fk(rb, q)
     mp, am, nc = O.self_collision(rb, c)
-    tau = O.rnea(rb, q, qd, qdd)
+    tau = O.rnea(rb, q, qd, qdd, fext)
     g_tau = w if w is not None else 2.0 * torque_weight * tau
     tcost = np.sum(w * tau, 1) if w is not None else torque_weight * np.sum(tau * tau, 1)
     h = np.maximum(0.0, mp + margin)
     cost = tcost + hinge_weight * h
     g_c = O.self_collision_backward(rb, c, am, mp, margin, np.full(q.shape[0], hinge_weight))
     gq_fk = O.fk_backward(rb, q, g_spheres=g_c)
-    gq, gqd, gqdd = O.rnea_vjp(rb, q, qd, qdd, g_tau)
+    gq, gqd, gqdd, gfe = O.rnea_vjp(rb, q, qd, qdd, g_tau, fext=fext, want_fext=True)
     return dict(R=R, p=p, c=c, max_pen=mp, argmax=am, n_coll=nc, tau=tau, cost=cost,
-                g_q=gq + gq_fk, g_q_fk=gq_fk, g_q_rnea=gq, g_qd=gqd, g_qdd=gqdd, g_spheres=g_c)
+                g_q=gq + gq_fk, g_q_fk=gq_fk, g_q_rnea=gq, g_qd=gqd, g_qdd=gqdd, g_spheres=g_c, g_fext=gfe)
