@@ -112,6 +112,7 @@ typedef struct wb_robot_info {
     int32_t n_blocks;         /* checked link pairs (a < b) carrying spheres */
     int32_t max_spheres_per_link;
     int32_t fused_supported;  /* 1 if wb_wholebody_step accepts this robot */
+    int32_t kinematics_supported;  /* 1 if wb_kinematics accepts this robot (L <= 64, n <= 64) */
 } wb_robot_info;
 
 typedef struct wb_robot wb_robot;   /* opaque; owns a device copy of the tables */
@@ -155,6 +156,55 @@ int wb_rnea_cache_bytes(const wb_robot *robot, int64_t B, size_t *bytes);
  *   spheres[S][3][B] world sphere centres (NULL to skip). */
 int wb_fk(const wb_robot *robot, int64_t B, const float *q, float *link_pose, float *spheres,
           hipStream_t stream);
+
+/* ------------------------------------------------------ kinematics outputs
+ * The other outputs of a forward-kinematics call (Sec. 6.1: tool poses,
+ * centres of mass and Jacobians besides frame transforms and sphere centres),
+ * the tool-frame Jacobian of Alg. 2 (for least-squares solvers such as the
+ * Levenberg-Marquardt step of Alg. 3), and the gradient of losses on tool
+ * poses and the centre of mass.  One wavefront group per state computes them
+ * all in one launch; needs n_links <= 64 and n_dof <= 64
+ * (wb_robot_info.kinematics_supported), else WB_ERR_UNSUPPORTED.  Mimic
+ * joints are supported. */
+#define WB_MAX_TOOLS 32
+
+/* Set the robot's tool frames (Sec. 6.1 "tool poses"; several per robot,
+ * e.g. hands and feet of a humanoid).  link[n_tools] (host): the link each
+ * tool is fixed to; offset[n_tools][12] (host): the tool frame in that link's
+ * frame, rotation row-major then translation.  n_tools = 0 clears them.
+ * Builds Alg. 2's coarse filter affects[joint, tool] on the host.  Blocking
+ * and not ordered with launches, like wb_robot_set_link_inertia.
+ * WB_ERR_INVALID_ARG for n_tools outside [0, WB_MAX_TOOLS], an out-of-range
+ * link, a non-finite offset or a rotation that is not orthonormal (1e-4). */
+int wb_robot_set_tool_frames(wb_robot *robot, int32_t n_tools, const int32_t *link, const float *offset);
+int wb_robot_get_tool_count(const wb_robot *robot, int32_t *n_tools);
+
+/* q[n][B] -> any of (each NULL to skip; with all NULL the call does nothing):
+ *   link_pose[L][12][B]   world link poses, as wb_fk;
+ *   spheres[S][3][B]      world sphere centres, as wb_fk;
+ *   tool_pose[T][12][B]   world tool poses R_link R_off (row-major), then
+ *                         p_link + R_link p_off;
+ *   com[3][B]             centre of mass: sum_k m_k (R_k c_k + p_k) / sum_k m_k
+ *                         over every link, the fixed base included;
+ *   jacobian[T][6][n][B]  Alg. 2's Jacobian of each tool frame: rows are the
+ *                         tool point's linear velocity then the angular
+ *                         velocity (world axes) per unit joint rate; column j
+ *                         sums mult_l [s_l x (x - o_l); s_l] over the links l
+ *                         that joint j drives on the chain of the tool's link
+ *                         (s_l world axis, o_l world origin of the joint);
+ *   com_jacobian[3][n][B] d com / d q.
+ * T is the count set by wb_robot_set_tool_frames.  WB_ERR_INVALID_ARG when
+ * com or com_jacobian is requested for a robot of zero total mass. */
+int wb_kinematics(const wb_robot *robot, int64_t B, const float *q, float *link_pose, float *spheres,
+                  float *tool_pose, float *com, float *jacobian, float *com_jacobian, hipStream_t stream);
+
+/* Gradient of L = sum_t <g_tool_pose[t], tool_pose[t]> + <g_com, com> with
+ * respect to q: g_q[n][B] (overwritten) = sum_t J_t^T [g_x; w_t] +
+ * J_com^T g_com, with w_t = sum_c r_c x G_c over the columns r_c of the tool
+ * rotation and G_c of its gradient.  g_tool_pose[T][12][B] and g_com[3][B]
+ * may each be NULL (no such term). */
+int wb_kinematics_backward(const wb_robot *robot, int64_t B, const float *q, const float *g_tool_pose,
+                           const float *g_com, float *g_q, hipStream_t stream);
 
 /* Inverse dynamics by RNEA (Alg. 4).  q, qd, qdd [n][B] -> tau[n][B].
  * f_ext[L][6][B] (NULL = none): external spatial force on each link in link

@@ -36,6 +36,7 @@ class WbRobotInfo(C.Structure):
         ("n_links", C.c_int32), ("n_dof", C.c_int32), ("n_spheres", C.c_int32),
         ("max_depth", C.c_int32), ("n_pairs", C.c_int64), ("n_blocks", C.c_int32),
         ("max_spheres_per_link", C.c_int32), ("fused_supported", C.c_int32),
+        ("kinematics_supported", C.c_int32),
     ]
 
 
@@ -73,6 +74,10 @@ _SIGS = {
                      _vp, _vp],
     "wb_sgd_step": [C.c_int64, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "wb_robot_set_link_inertia": [_vp, C.c_int32, C.c_float, _vp, _vp],
+    "wb_robot_set_tool_frames": [_vp, C.c_int32, _vp, _vp],
+    "wb_robot_get_tool_count": [_vp, _i32p],
+    "wb_kinematics": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "wb_kinematics_backward": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp],
     "wb_bspline_eval": [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_int32, _vp, _vp, _vp, _vp,
                         _vp, _vp, _vp, _vp],
     "wb_bspline_backward": [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, C.c_float,

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwb.so")
 
-SOURCES = ["wb_host.cpp", "fk.hip", "rnea.hip", "selfcoll.hip", "misc.hip", "fused.hip", "bspline.hip"]
+SOURCES = ["wb_host.cpp", "fk.hip", "rnea.hip", "selfcoll.hip", "misc.hip", "fused.hip", "bspline.hip",
+           "kinematics.hip"]
 ARCH = os.environ.get("WB_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,0 +1,265 @@
+// Kinematics outputs for optimizers and solvers in one launch (cuRoboV2
+// Sec. 6.1: a forward-kinematics call yields frame transforms, tool poses,
+// sphere centres, centres of mass and Jacobians), and the gradient of
+// tool-pose and centre-of-mass losses.
+//
+// Mapping: a group of G lanes (16, 32 or 64) owns one state; lane i holds
+// link perm[i] in depth-first pre-order and lane j also owns Jacobian
+// column j.  World poses follow by pointer jumping over the parent lanes
+// as in the fused iteration; nothing but the requested outputs reaches
+// memory.
+//
+// Jacobian of tool t (Alg. 2).  Column lane j walks connectedLinks[j] (the
+// links whose angle joint j sets, several for a mimic joint) and fetches
+// each one's world axis s and origin o from that link's lane.  The coarse
+// filter is affects[j, e] (a bit mask per tool, built on the host); the
+// fine filter keeps a link l only when it lies on the chain of the tool's
+// link e, which in depth-first lane order is lane(l) <= lane(e) <=
+// sub_end(l).  Each kept link adds mult_l [s x (x - o); s] with x the tool
+// point.
+//
+// Centre of mass: sum_l m_l c_l / M by a group reduction.  Its Jacobian:
+// link lane l forms mult_l s_l x (C_l - M_l o_l) / M from its subtree's
+// mass M_l and first moment C_l (subtree sums by the group's prefix scan),
+// and column lane j gathers its connected links as above.
+//
+// Gradient: dL/dq_j = sum_t J_t[:, j] . [g_x; w_t] + J_com[:, j] . g_com,
+// where w_t = sum_c r_c x G_c over the columns of the tool rotation and of
+// its gradient (a rotation turns by [s]x R about a joint axis s).
+#include "kin.h"
+#include "lanes.h"
+#include "spatial.h"
+
+namespace wb {
+namespace {
+
+constexpr int KIN_WG = 256;
+
+__device__ __forceinline__ V3 shfl3(V3 v, int src, int G) {
+    return v3(__shfl(v.x, src, G), __shfl(v.y, src, G), __shfl(v.z, src, G));
+}
+
+__device__ __forceinline__ V3 scan3(V3 v, int G) {
+    return v3(group_scan(v.x, G), group_scan(v.y, G), group_scan(v.z, G));
+}
+
+// Element c (0..11) of a pose held as R (row-major) then p.
+__device__ __forceinline__ float pose_elem(const M3 &R, V3 p, int c) {
+    float r = p.z;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r = c == i ? R.m[i] : r;
+    r = c == 9 ? p.x : r;
+    r = c == 10 ? p.y : r;
+    return r;
+}
+
+template <bool BWD>
+__device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b, bool valid, int gl,
+                                          const float *__restrict__ q, const KinOut &o, const KinGrad &g) {
+    const int G = k.G;
+    const int *li = k.li;
+    const float *lf = k.lf;
+    const bool act = gl < k.L;
+    const int parent_lane = li[1 * 64 + gl];
+    const int sub_end = li[2 * 64 + gl];
+    const bool rev = li[4 * 64 + gl] != 0;
+    const float mult = lf[15 * 64 + gl];
+    const V3 ax = v3(lf[0 * 64 + gl], lf[1 * 64 + gl], lf[2 * 64 + gl]);
+    // ---- forward kinematics: local transform, then pointer jumping
+    M3 R;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) R.m[t] = lf[(3 + t) * 64 + gl];
+    V3 p = v3(lf[12 * 64 + gl], lf[13 * 64 + gl], lf[14 * 64 + gl]);
+    if (rev) {
+        const float th = mult * q[(int64_t)li[3 * 64 + gl] * B + b] + lf[16 * 64 + gl];
+        float sn, cs;
+        sincosf(th, &sn, &cs);
+        const M3 Jr = axis_angle(ax, sn, cs);
+        R = li[5 * 64 + gl] ? Jr : matmul(R, Jr);
+    }
+    {
+        int anc = parent_lane;
+        for (int st = 0; st < k.jsteps; ++st) {
+            const int src = anc < 0 ? gl : anc;
+            M3 Ra;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) Ra.m[t] = __shfl(R.m[t], src, G);
+            const V3 pa = shfl3(p, src, G);
+            const int aa = __shfl(anc, src, G);
+            if (anc >= 0) {
+                p = mul(Ra, p) + pa;
+                R = matmul(Ra, R);
+                anc = aa;
+            }
+        }
+    }
+    if (!BWD && valid && act) {
+        const int link = li[0 * 64 + gl];
+        if (o.link_pose) {
+            float *d = o.link_pose + (int64_t)link * 12 * B + b;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) d[t * B] = R.m[t];
+            d[9 * B] = p.x;
+            d[10 * B] = p.y;
+            d[11 * B] = p.z;
+        }
+        if (o.spheres) {
+            const int first = li[6 * 64 + gl], cnt = li[7 * 64 + gl];
+            for (int j = 0; j < cnt; ++j) {
+                const float4 c4 = k.sph[first + j];
+                const V3 c = mul(R, v3(c4.x, c4.y, c4.z)) + p;
+                float *d = o.spheres + (int64_t)(first + j) * 3 * B + b;
+                d[0] = c.x;
+                d[B] = c.y;
+                d[2 * B] = c.z;
+            }
+        }
+    }
+    const V3 s_w = mul(R, ax);   // world joint axis; the joint's world origin is p
+    const int n = k.n;
+    const bool col_lane = gl < n;
+    float gq = 0.f;
+    // ---- centre of mass and its Jacobian
+    const bool want_com = BWD ? g.g_com != nullptr : (o.com != nullptr || o.com_jac != nullptr);
+    if (want_com) {
+        const float m = lf[17 * 64 + gl];
+        const V3 mc = m * (mul(R, v3(lf[18 * 64 + gl], lf[19 * 64 + gl], lf[20 * 64 + gl])) + p);
+        if (!BWD && o.com) {
+            const V3 tot = v3(group_reduce_sum(mc.x, G), group_reduce_sum(mc.y, G), group_reduce_sum(mc.z, G));
+            if (valid && gl < 3) o.com[(int64_t)gl * B + b] = (gl == 0 ? tot.x : gl == 1 ? tot.y : tot.z) * k.inv_mass;
+        }
+        if (BWD || o.com_jac) {
+            const V3 sc = scan3(mc, G);
+            const float sm = group_scan(m, G);
+            const V3 hc = shfl3(sc, sub_end, G);
+            const float hm = __shfl(sm, sub_end, G);
+            const V3 lc = v3(lane_prev(sc.x), lane_prev(sc.y), lane_prev(sc.z));
+            const float lm = lane_prev(sm);
+            const V3 Csub = gl > 0 ? hc - lc : hc;
+            const float Msub = gl > 0 ? hm - lm : hm;
+            const V3 cj = rev ? (mult * k.inv_mass) * cross(s_w, Csub - Msub * p) : v3(0.f, 0.f, 0.f);
+            V3 col = v3(0.f, 0.f, 0.f);
+            for (int kk = 0; kk < k.mc; ++kk) {
+                const int lk = k.conn[kk * 64 + gl];
+                const V3 y = shfl3(cj, lk >= 0 ? lk : gl, G);
+                if (lk >= 0) col += y;
+            }
+            if (!BWD) {
+                if (valid && col_lane) {
+                    float *d = o.com_jac + (int64_t)gl * B + b;
+                    const int64_t rs = (int64_t)n * B;
+                    d[0] = col.x;
+                    d[rs] = col.y;
+                    d[2 * rs] = col.z;
+                }
+            } else {
+                const V3 gc = v3(g.g_com[b], g.g_com[B + b], g.g_com[2 * B + b]);
+                gq += dot(col, gc);
+            }
+        }
+    }
+    // ---- tool frames: poses and Jacobians (Alg. 2)
+    const bool want_j = BWD ? g.g_tool != nullptr : o.jac != nullptr;
+    if (BWD ? want_j : (o.tool_pose != nullptr || want_j)) {
+        for (int t = 0; t < k.n_tools; ++t) {
+            const int e = k.tool_lane[t];
+            const float *off = k.tool_off + 12 * t;
+            M3 Re, Ro;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                Re.m[i] = __shfl(R.m[i], e, G);
+                Ro.m[i] = off[i];
+            }
+            const V3 pe = shfl3(p, e, G);
+            const M3 Rt = matmul(Re, Ro);
+            const V3 x = mul(Re, v3(off[9], off[10], off[11])) + pe;
+            if (!BWD && o.tool_pose && valid && gl < 12)
+                o.tool_pose[((int64_t)t * 12 + gl) * B + b] = pose_elem(Rt, x, gl);
+            if (!want_j) continue;
+            const bool aff = col_lane && ((k.tool_aff[t] >> gl) & 1ull);
+            V3 jl = v3(0.f, 0.f, 0.f), ja = v3(0.f, 0.f, 0.f);
+            for (int kk = 0; kk < k.mc; ++kk) {
+                const int lk = k.conn[kk * 64 + gl];
+                const int src = lk >= 0 ? lk : gl;
+                const V3 sk = shfl3(s_w, src, G), ok = shfl3(p, src, G);
+                const float mk = __shfl(mult, src, G);
+                const int lend = __shfl(sub_end, src, G);
+                if (aff && lk >= 0 && lk <= e && e <= lend) {
+                    jl += mk * cross(sk, x - ok);
+                    ja += mk * sk;
+                }
+            }
+            if (!BWD) {
+                if (valid && col_lane) {
+                    float *d = o.jac + ((int64_t)t * 6 * n + gl) * B + b;
+                    const int64_t rs = (int64_t)n * B;
+                    d[0] = jl.x;
+                    d[rs] = jl.y;
+                    d[2 * rs] = jl.z;
+                    d[3 * rs] = ja.x;
+                    d[4 * rs] = ja.y;
+                    d[5 * rs] = ja.z;
+                }
+            } else {
+                const float *gt = g.g_tool + (int64_t)t * 12 * B + b;
+                M3 GR;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) GR.m[i] = gt[i * B];
+                const V3 gx = v3(gt[9 * B], gt[10 * B], gt[11 * B]);
+                V3 w = v3(0.f, 0.f, 0.f);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) w += cross(col(Rt, c), col(GR, c));
+                gq += dot(jl, gx) + dot(ja, w);
+            }
+        }
+    }
+    if (BWD && valid && col_lane) g.g_q[(int64_t)gl * B + b] = gq;
+}
+
+// Each workgroup takes `spb` consecutive states (a multiple of its 256 / G
+// groups), so the rows of every [..][B] output are written in whole runs
+// of consecutive states by one workgroup.
+template <bool BWD>
+__global__ void __launch_bounds__(KIN_WG) k_kinematics(DevKin k, int64_t B, const float *__restrict__ q, KinOut o,
+                                                       KinGrad g, int32_t spb) {
+    const int G = k.G;
+    const int gl = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
+    const int gpw = KIN_WG / G;
+    const int64_t base = (int64_t)blockIdx.x * spb;
+    for (int it = 0; it < spb / gpw; ++it) {
+        const int64_t b0 = base + (int64_t)it * gpw;
+        if (b0 >= B) break;   // uniform over the workgroup
+        const int64_t br = b0 + grp;
+        const bool valid = br < B;
+        kin_state<BWD>(k, B, valid ? br : B - 1, valid, gl, q, o, g);
+    }
+}
+
+int32_t states_per_block(const DevKin &k, int64_t B) {
+    const int gpw = KIN_WG / k.G;
+    int32_t spb = gpw > 32 ? gpw : 32;          // at least 32 consecutive states: 128-byte rows
+    while (spb > gpw && (B + spb - 1) / spb < 512) spb /= 2;
+    return spb;
+}
+
+}  // namespace
+
+hipError_t launch_kinematics(const DevKin &k, int64_t B, const float *q, const KinOut &o, hipStream_t s) {
+    if (B == 0) return hipSuccess;
+    const int32_t spb = states_per_block(k, B);
+    const dim3 grid((unsigned)((B + spb - 1) / spb));
+    hipLaunchKernelGGL(k_kinematics<false>, grid, dim3(KIN_WG), 0, s, k, B, q, o, KinGrad{}, spb);
+    return hipGetLastError();
+}
+
+hipError_t launch_kinematics_backward(const DevKin &k, int64_t B, const float *q, const KinGrad &g,
+                                      hipStream_t s) {
+    if (B == 0) return hipSuccess;
+    const int32_t spb = states_per_block(k, B);
+    const dim3 grid((unsigned)((B + spb - 1) / spb));
+    hipLaunchKernelGGL(k_kinematics<true>, grid, dim3(KIN_WG), 0, s, k, B, q, KinOut{}, g, spb);
+    return hipGetLastError();
+}
+
+}  // namespace wb

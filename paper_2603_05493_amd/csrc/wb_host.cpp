@@ -1,6 +1,7 @@
 // Host side of libwb: descriptor validation, derived kernel tables, device
 // upload and the extern "C" entry points declared in include/wb.h.
 #include "wb.h"
+#include "kin.h"
 #include "wb_internal.h"
 
 #include <algorithm>
@@ -49,6 +50,12 @@ struct Tables {
     std::vector<int32_t> f_li;
     std::vector<float> f_lf;
     std::vector<float4> f_sph;
+    // lane tables of the kinematics-outputs kernel (same depth-first order)
+    int kin = 0, kin_G = 0, kin_jsteps = 0, kin_mc = 0;
+    std::vector<int> kin_lane, kin_sub_end;   // link -> lane, lane -> last lane of its subtree
+    std::vector<int32_t> k_li, k_conn;
+    std::vector<float> k_lf;
+    double total_mass = 0.0;
 };
 
 bool finite_all(const float *p, size_t n) {
@@ -59,26 +66,100 @@ bool finite_all(const float *p, size_t n) {
 
 // Lane tables of the fused kernel: links in depth-first pre-order so every
 // subtree is a contiguous lane range.
-void build_fused(Tables &T) {
+// Depth-first pre-order of the links (children in index order): perm[i] is
+// the link of lane i, lane_of its inverse, size[k] the size of k's subtree.
+void dfs_lanes(const Tables &T, std::vector<int> &perm, std::vector<int> &lane_of, std::vector<int> &size) {
     const int L = T.L;
-    T.fused = 0;
-    if (L > 64 || !T.simple) return;
-    const int g_default = L <= 16 ? 16 : (L <= 32 ? 32 : 64);
-    if (wb::fused_lds_bytes(L, T.nmax, T.list_cap, g_default, (int)T.blocks.size()) > wb::LDS_LIMIT) return;
     std::vector<std::vector<int>> kids(L);
     for (int k = 1; k < L; ++k) kids[T.li[k].parent].push_back(k);
-    std::vector<int> perm, stack{0};
+    perm.clear();
+    std::vector<int> stack{0};
     while (!stack.empty()) {
         const int k = stack.back();
         stack.pop_back();
         perm.push_back(k);
         for (auto it = kids[k].rbegin(); it != kids[k].rend(); ++it) stack.push_back(*it);
     }
-    std::vector<int> &lane_of = T.lane_of;
-    std::vector<int> size(L, 1);
     lane_of.assign(L, 0);
     for (int i = 0; i < L; ++i) lane_of[perm[i]] = i;
+    size.assign(L, 1);
     for (int k = L - 1; k >= 1; --k) size[T.li[k].parent] += size[k];
+}
+
+int pointer_jump_steps(int max_depth) {
+    int js = 0;
+    while ((1 << js) < max_depth + 1) ++js;
+    return js;
+}
+
+// Lane tables of the kinematics-outputs kernel (layout in kin.h): any robot
+// with at most 64 links and 64 joints, mimic joints included.
+void build_kin(Tables &T) {
+    const int L = T.L, n = T.n;
+    T.kin = 0;
+    T.total_mass = 0.0;
+    for (int k = 0; k < L; ++k) T.total_mass += T.lf[k].mass;
+    if (L > 64 || n > 64) return;
+    std::vector<int> perm, size;
+    dfs_lanes(T, perm, T.kin_lane, size);
+    T.kin_sub_end.assign(64, 0);
+    std::vector<std::vector<int>> conn(n);
+    T.k_li.assign(8 * 64, 0);
+    T.k_lf.assign(21 * 64, 0.0f);
+    for (int i = 0; i < 64; ++i) {
+        T.kin_sub_end[i] = i;
+        T.k_li[0 * 64 + i] = -1;
+        T.k_li[1 * 64 + i] = -1;
+        T.k_li[2 * 64 + i] = i;
+        T.k_li[3 * 64 + i] = -1;
+        T.k_li[5 * 64 + i] = 1;
+        for (int c = 0; c < 9; c += 4) T.k_lf[(3 + c) * 64 + i] = 1.0f;
+        T.k_lf[15 * 64 + i] = 1.0f;
+    }
+    for (int i = 0; i < L; ++i) {
+        const int k = perm[i];
+        const wb::LinkI &I = T.li[k];
+        const wb::LinkF &F = T.lf[k];
+        const bool rev = k > 0 && I.revolute && I.jidx >= 0;
+        T.kin_sub_end[i] = i + size[k] - 1;
+        T.k_li[0 * 64 + i] = k;
+        T.k_li[1 * 64 + i] = k == 0 ? -1 : T.kin_lane[I.parent];
+        T.k_li[2 * 64 + i] = i + size[k] - 1;
+        T.k_li[3 * 64 + i] = rev ? I.jidx : -1;
+        T.k_li[4 * 64 + i] = rev ? 1 : 0;
+        T.k_li[5 * 64 + i] = k == 0 ? 1 : I.fR_identity;
+        T.k_li[6 * 64 + i] = I.sph_first;
+        T.k_li[7 * 64 + i] = I.sph_count;
+        for (int c = 0; c < 3; ++c) T.k_lf[(0 + c) * 64 + i] = F.axis[c];
+        for (int c = 0; c < 9; ++c) T.k_lf[(3 + c) * 64 + i] = k == 0 ? (c % 4 == 0 ? 1.0f : 0.0f) : F.fR[c];
+        for (int c = 0; c < 3; ++c) T.k_lf[(12 + c) * 64 + i] = k == 0 ? 0.0f : F.fp[c];
+        T.k_lf[15 * 64 + i] = F.mult;
+        T.k_lf[16 * 64 + i] = F.offset;
+        T.k_lf[17 * 64 + i] = F.mass;
+        for (int c = 0; c < 3; ++c) T.k_lf[(18 + c) * 64 + i] = F.com[c];
+        if (rev) conn[I.jidx].push_back(i);
+    }
+    int mc = 1;
+    for (int j = 0; j < n; ++j) mc = std::max(mc, (int)conn[j].size());
+    T.kin_mc = mc;
+    T.k_conn.assign((size_t)mc * 64, -1);
+    for (int j = 0; j < n; ++j)
+        for (size_t c = 0; c < conn[j].size(); ++c) T.k_conn[c * 64 + j] = conn[j][c];
+    const int need = std::max(std::max(L, n), 12);
+    T.kin_G = need <= 16 ? 16 : (need <= 32 ? 32 : 64);
+    T.kin_jsteps = pointer_jump_steps(T.max_depth);
+    T.kin = 1;
+}
+
+void build_fused(Tables &T) {
+    const int L = T.L;
+    T.fused = 0;
+    if (L > 64 || !T.simple) return;
+    const int g_default = L <= 16 ? 16 : (L <= 32 ? 32 : 64);
+    if (wb::fused_lds_bytes(L, T.nmax, T.list_cap, g_default, (int)T.blocks.size()) > wb::LDS_LIMIT) return;
+    std::vector<int> perm, size;
+    std::vector<int> &lane_of = T.lane_of;
+    dfs_lanes(T, perm, lane_of, size);
     T.f_li.assign(8 * 64, 0);
     T.f_lf.assign(29 * 64, 0.0f);
     T.f_sph.assign((size_t)WB_MAX_SPHERES_PER_LINK * 64, make_float4(0, 0, 0, 0));
@@ -131,9 +212,7 @@ void build_fused(Tables &T) {
         for (int c = 0; c < 9; c += 4) T.f_lf[(3 + c) * 64 + i] = 1.0f;
         T.f_lf[28 * 64 + i] = -1e30f;
     }
-    int js = 0;
-    while ((1 << js) < T.max_depth + 1) ++js;
-    T.jsteps = js;
+    T.jsteps = pointer_jump_steps(T.max_depth);
     T.fused = 1;
 }
 
@@ -319,6 +398,7 @@ int build_tables(const wb_robot_desc *d, Tables &T) {
     }
     for (int c = 0; c < 3; ++c) T.g[c] = d->gravity[c];
     build_fused(T);
+    build_kin(T);
     return WB_OK;
 }
 
@@ -331,6 +411,7 @@ void fill_info(const Tables &T, wb_robot_info *info) {
     info->n_blocks = T.n_blocks;
     info->max_spheres_per_link = T.nmax;
     info->fused_supported = T.fused;
+    info->kinematics_supported = T.kin;
 }
 
 bool aligned4(const void *p) { return ((uintptr_t)p & 3) == 0; }
@@ -341,9 +422,12 @@ struct wb_robot {
     Tables T;
     wb::DevRobot dev{};
     wb::DevFused fz{};
+    wb::DevKin kin{};
     wb_tune tune{};
     void *dmem = nullptr;
     size_t o_lf = 0, o_ff = 0;   // offsets of the link records and the fused float lane table
+    size_t o_kf = 0;             // offset of the kinematics float lane table
+    size_t o_tl = 0, o_to = 0, o_ta = 0;   // tool lanes, offsets and affects masks (WB_MAX_TOOLS each)
     int device = -1;
 };
 
@@ -452,6 +536,10 @@ int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
     const size_t o_po = append(blob, T.pair_off), o_pc = append(blob, T.pair_cnt);
     const size_t o_ps = append(blob, T.pair_s), o_pt = append(blob, T.pair_t);
     const size_t o_fi = append(blob, T.f_li), o_ff = append(blob, T.f_lf), o_fs = append(blob, T.f_sph);
+    const size_t o_ki = append(blob, T.k_li), o_kf = append(blob, T.k_lf), o_kc = append(blob, T.k_conn);
+    const size_t o_tl = append(blob, std::vector<int32_t>(WB_MAX_TOOLS, 0));
+    const size_t o_to = append(blob, std::vector<float>(12 * WB_MAX_TOOLS, 0.0f));
+    const size_t o_ta = append(blob, std::vector<uint64_t>(WB_MAX_TOOLS, 0));
     blob.resize(blob.size() + 256);
     hipError_t e = hipGetDevice(&r->device);
     if (e == hipSuccess) e = hipMalloc(&r->dmem, blob.size());
@@ -488,6 +576,21 @@ int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
     Fz.li = reinterpret_cast<const int32_t *>(base + o_fi);
     Fz.lf = reinterpret_cast<const float *>(base + o_ff);
     Fz.lsph = reinterpret_cast<const float4 *>(base + o_fs);
+    wb::DevKin &Kn = r->kin;
+    Kn.L = T.L; Kn.n = T.n; Kn.G = T.kin_G; Kn.jsteps = T.kin_jsteps; Kn.mc = T.kin_mc;
+    Kn.inv_mass = T.total_mass > 0.0 ? (float)(1.0 / T.total_mass) : 0.0f;
+    Kn.li = reinterpret_cast<const int32_t *>(base + o_ki);
+    Kn.lf = reinterpret_cast<const float *>(base + o_kf);
+    Kn.conn = reinterpret_cast<const int32_t *>(base + o_kc);
+    Kn.sph = D.sph;
+    Kn.n_tools = 0;
+    Kn.tool_lane = reinterpret_cast<const int32_t *>(base + o_tl);
+    Kn.tool_off = reinterpret_cast<const float *>(base + o_to);
+    Kn.tool_aff = reinterpret_cast<const uint64_t *>(base + o_ta);
+    r->o_kf = o_kf;
+    r->o_tl = o_tl;
+    r->o_to = o_to;
+    r->o_ta = o_ta;
     r->tune = default_tune(T.L);
     *out = r;
     return WB_OK;
@@ -768,6 +871,14 @@ int wb_robot_set_link_inertia(wb_robot *robot, int32_t link, float mass, const f
         for (int c = 0; c < 3; ++c) T.f_lf[(16 + c) * 64 + i] = com[c];
         for (int c = 0; c < 6; ++c) T.f_lf[(19 + c) * 64 + i] = inertia[c];
     }
+    T.total_mass = 0.0;
+    for (int k = 0; k < T.L; ++k) T.total_mass += T.lf[k].mass;
+    robot->kin.inv_mass = T.total_mass > 0.0 ? (float)(1.0 / T.total_mass) : 0.0f;
+    if (T.kin) {
+        const int i = T.kin_lane[link];
+        T.k_lf[17 * 64 + i] = mass;
+        for (int c = 0; c < 3; ++c) T.k_lf[(18 + c) * 64 + i] = com[c];
+    }
     int prev = -1;
     hipError_t e = hipGetDevice(&prev);
     if (e == hipSuccess && prev != robot->device) e = hipSetDevice(robot->device);
@@ -777,9 +888,105 @@ int wb_robot_set_link_inertia(wb_robot *robot, int32_t link, float mass, const f
                       hipMemcpyHostToDevice);
     if (e == hipSuccess && T.fused)
         e = hipMemcpy(base + robot->o_ff, T.f_lf.data(), T.f_lf.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess && T.kin)
+        e = hipMemcpy(base + robot->o_kf, T.k_lf.data(), T.k_lf.size() * sizeof(float), hipMemcpyHostToDevice);
     if (prev >= 0 && prev != robot->device) (void)hipSetDevice(prev);
     if (e != hipSuccess) return hip_fail(e, "updating the link inertia");
     return WB_OK;
+}
+
+int wb_robot_set_tool_frames(wb_robot *robot, int32_t n_tools, const int32_t *link, const float *offset) {
+    WB_TRY(check_robot(robot));
+    const Tables &T = robot->T;
+    if (!T.kin)
+        return fail(WB_ERR_UNSUPPORTED, "tool frames need n_links <= 64 and n_dof <= 64 (got %d, %d)", T.L, T.n);
+    if (n_tools < 0 || n_tools > WB_MAX_TOOLS)
+        return fail(WB_ERR_INVALID_ARG, "n_tools %d outside [0, %d]", n_tools, WB_MAX_TOOLS);
+    if (n_tools > 0 && (!link || !offset)) return fail(WB_ERR_INVALID_ARG, "link and offset must not be null");
+    std::vector<int32_t> lane(WB_MAX_TOOLS, 0);
+    std::vector<float> off(12 * WB_MAX_TOOLS, 0.0f);
+    std::vector<uint64_t> aff(WB_MAX_TOOLS, 0);
+    for (int t = 0; t < n_tools; ++t) {
+        if (link[t] < 0 || link[t] >= T.L)
+            return fail(WB_ERR_INVALID_ARG, "tool %d: link %d out of range [0, %d)", t, link[t], T.L);
+        const float *R = offset + 12 * t;
+        if (!finite_all(R, 12)) return fail(WB_ERR_INVALID_ARG, "tool %d: offset is not finite", t);
+        double orth = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double d = 0.0;
+                for (int c = 0; c < 3; ++c) d += (double)R[3 * c + i] * R[3 * c + j];
+                orth = std::fmax(orth, std::fabs(d - (i == j ? 1.0 : 0.0)));
+            }
+        if (orth > 1e-4) return fail(WB_ERR_INVALID_ARG, "tool %d: offset rotation is not orthonormal", t);
+        const int e = T.kin_lane[link[t]];
+        lane[t] = e;
+        memcpy(off.data() + 12 * t, R, 12 * sizeof(float));
+        // affects[j, e]: some link driven by joint j is on e's chain
+        for (int j = 0; j < T.n; ++j)
+            for (int c = 0; c < T.kin_mc; ++c) {
+                const int l = T.k_conn[(size_t)c * 64 + j];
+                if (l >= 0 && l <= e && e <= T.kin_sub_end[l]) aff[t] |= 1ull << j;
+            }
+    }
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != robot->device) e = hipSetDevice(robot->device);
+    char *base = static_cast<char *>(robot->dmem);
+    if (e == hipSuccess) e = hipMemcpy(base + robot->o_tl, lane.data(), lane.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + robot->o_to, off.data(), off.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + robot->o_ta, aff.data(), aff.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (prev >= 0 && prev != robot->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "uploading the tool frames");
+    robot->kin.n_tools = n_tools;
+    return WB_OK;
+}
+
+int wb_robot_get_tool_count(const wb_robot *robot, int32_t *n_tools) {
+    WB_TRY(check_robot(robot));
+    if (!n_tools) return fail(WB_ERR_INVALID_ARG, "n_tools is null");
+    *n_tools = robot->kin.n_tools;
+    return WB_OK;
+}
+
+int wb_kinematics(const wb_robot *robot, int64_t B, const float *q, float *link_pose, float *spheres,
+                  float *tool_pose, float *com, float *jacobian, float *com_jacobian, hipStream_t stream) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    const Tables &T = robot->T;
+    if (!T.kin)
+        return fail(WB_ERR_UNSUPPORTED, "wb_kinematics needs n_links <= 64 and n_dof <= 64 (got %d, %d)", T.L, T.n);
+    if ((com || com_jacobian) && !(T.total_mass > 0.0))
+        return fail(WB_ERR_INVALID_ARG, "the robot has no mass: its centre of mass is undefined");
+    if (B == 0) return WB_OK;
+    WB_TRY(check_ptr(q, "q", T.n > 0));
+    WB_TRY(check_ptr(link_pose, "link_pose", false));
+    WB_TRY(check_ptr(spheres, "spheres", false));
+    WB_TRY(check_ptr(tool_pose, "tool_pose", false));
+    WB_TRY(check_ptr(com, "com", false));
+    WB_TRY(check_ptr(jacobian, "jacobian", false));
+    WB_TRY(check_ptr(com_jacobian, "com_jacobian", false));
+    wb::KinOut o{link_pose, spheres, tool_pose, com, jacobian, com_jacobian};
+    return finish(wb::launch_kinematics(robot->kin, B, q, o, stream), "wb_kinematics launch");
+}
+
+int wb_kinematics_backward(const wb_robot *robot, int64_t B, const float *q, const float *g_tool_pose,
+                           const float *g_com, float *g_q, hipStream_t stream) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_B(B));
+    const Tables &T = robot->T;
+    if (!T.kin)
+        return fail(WB_ERR_UNSUPPORTED, "wb_kinematics_backward needs n_links <= 64 and n_dof <= 64 (got %d, %d)",
+                    T.L, T.n);
+    if (g_com && !(T.total_mass > 0.0))
+        return fail(WB_ERR_INVALID_ARG, "the robot has no mass: its centre of mass is undefined");
+    if (B == 0 || T.n == 0) return WB_OK;
+    WB_TRY(check_ptr(q, "q", true));
+    WB_TRY(check_ptr(g_tool_pose, "g_tool_pose", false));
+    WB_TRY(check_ptr(g_com, "g_com", false));
+    WB_TRY(check_ptr(g_q, "g_q", true));
+    wb::KinGrad g{g_tool_pose, g_com, g_q};
+    return finish(wb::launch_kinematics_backward(robot->kin, B, q, g, stream), "wb_kinematics_backward launch");
 }
 
 int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune) {

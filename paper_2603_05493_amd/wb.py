@@ -82,6 +82,8 @@ class Robot:
         self.max_depth, self.n_pairs, self.n_blocks = inf.max_depth, inf.n_pairs, inf.n_blocks
         self.max_spheres_per_link = inf.max_spheres_per_link
         self.fused_supported = bool(inf.fused_supported)
+        self.kinematics_supported = bool(inf.kinematics_supported)
+        self.n_tools = 0
         self.handle = None
         self.device = None
 
@@ -122,6 +124,19 @@ class Robot:
         c = (C.c_float * 3)(*[float(x) for x in com])
         i6 = (C.c_float * 6)(*[float(x) for x in inertia])
         check(lib().wb_robot_set_link_inertia(self.handle, int(link), float(mass), c, i6))
+
+    def set_tool_frames(self, links, R=None, p=None) -> None:
+        """Tool frames fixed to `links` [T] with offsets R [T,3,3] (identity by
+        default) and p [T,3] (zero by default) in the link frames; blocking,
+        call between launches.  An empty list clears them."""
+        links = np.ascontiguousarray(np.asarray(links, dtype=np.int32).reshape(-1))
+        T = links.shape[0]
+        R = np.tile(np.eye(3), (T, 1, 1)) if R is None else np.asarray(R, dtype=np.float64).reshape(T, 3, 3)
+        p = np.zeros((T, 3)) if p is None else np.asarray(p, dtype=np.float64).reshape(T, 3)
+        off = np.ascontiguousarray(np.concatenate([R.reshape(T, 9), p], 1), dtype=np.float32)
+        check(lib().wb_robot_set_tool_frames(self.handle, T, links.ctypes.data_as(C.c_void_p),
+                                             off.ctypes.data_as(C.c_void_p)))
+        self.n_tools = T
 
     def get_tune(self) -> dict:
         t = _abi.WbTune()
@@ -169,6 +184,41 @@ def wb_fk(robot: Robot, q: torch.Tensor, link_pose=None, spheres=None, want_sphe
     _chk(spheres, "spheres", (S, 3, B), device=robot.device)
     check(lib().wb_fk(robot.handle, B, _p(q), _p(link_pose), _p(spheres), _stream()))
     return link_pose, spheres
+
+
+def wb_kinematics(robot: Robot, q, link_pose=False, spheres=False, tool_pose=True, com=True, jacobian=True,
+                  com_jacobian=False):
+    """One launch of the kinematics outputs.  Each argument is False (skip),
+    True (allocate) or a tensor to fill; returns a dict of the requested
+    outputs: link_pose [L,12,B], spheres [S,3,B], tool_pose [T,12,B],
+    com [3,B], jacobian [T,6,n,B], com_jacobian [3,n,B]."""
+    n, B, L, S, T = robot.n_dof, q.shape[-1], robot.n_links, robot.n_spheres, robot.n_tools
+    shapes = dict(link_pose=(L, 12, B), spheres=(S, 3, B), tool_pose=(T, 12, B), com=(3, B),
+                  jacobian=(T, 6, n, B), com_jacobian=(3, n, B))
+    want = dict(link_pose=link_pose, spheres=spheres, tool_pose=tool_pose, com=com, jacobian=jacobian,
+                com_jacobian=com_jacobian)
+    out = {}
+    for k, v in want.items():
+        if v is True:
+            out[k] = _empty(shapes[k], robot)
+        elif v is not False and v is not None:
+            _chk(v, k, shapes[k], device=robot.device)
+            out[k] = v
+    _chk(q, "q", (n, B), device=robot.device)
+    check(lib().wb_kinematics(robot.handle, B, _p(q), *[_p(out.get(k)) for k in shapes], _stream()))
+    return out
+
+
+def wb_kinematics_backward(robot: Robot, q, g_tool_pose=None, g_com=None, g_q=None):
+    """dL/dq [n,B] for L = <g_tool_pose, tool_pose> + <g_com, com>."""
+    n, B, T = robot.n_dof, q.shape[-1], robot.n_tools
+    g_q = _empty((n, B), robot) if g_q is None else g_q
+    _chk(q, "q", (n, B), device=robot.device)
+    _chk(g_tool_pose, "g_tool_pose", (T, 12, B), device=robot.device)
+    _chk(g_com, "g_com", (3, B), device=robot.device)
+    _chk(g_q, "g_q", (n, B), device=robot.device)
+    check(lib().wb_kinematics_backward(robot.handle, B, _p(q), _p(g_tool_pose), _p(g_com), _p(g_q), _stream()))
+    return g_q
 
 
 def wb_rnea(robot: Robot, q, qd, qdd, tau=None, cache=None, f_ext=None):
