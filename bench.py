@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 # 256 CU x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz, without packed FP32
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3   # needs packed FP32, which this build disables
+PEAK_HBM_GBPS = 8000.0
 
 
 # HBM traffic of the fused kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
@@ -45,10 +46,17 @@ TRAFFIC_MEASURED = {"sources_sha1": "47d429bc016feaa55be288b4731e28e32787b5c2", 
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h")
 
 
-def fused_sources_sha1() -> str:
+# HBM traffic of the kinematics-outputs kernel, measured the same way
+# (profiles/k_kinematics_humanoid48_B24576.md; 4 tool frames), per launch.
+KIN_TRAFFIC_MEASURED = {"sources_sha1": "3547258eb4d75b287ae012f0d59d48fd04d8f48b", "states": 24576, "tools": 4,
+                        "forward_bytes": (5636.2 + 133209.9) * 1024, "backward_bytes": (9664.0 + 4608.0) * 1024}
+KIN_SOURCES = ("kinematics.hip", "kin.h", "lanes.h", "spatial.h", "wb_internal.h")
+
+
+def fused_sources_sha1(sources=FUSED_SOURCES) -> str:
     import hashlib
     h = hashlib.sha1()
-    for f in FUSED_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2603_05493_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -74,6 +82,8 @@ def parse():
     ap.add_argument("--forms", default="fused_graph,fused_graph1,plain_graph,plain")
     ap.add_argument("--no-uneven", dest="uneven", action="store_false",
                     help="skip the uneven multi-tree batch measurement")
+    ap.add_argument("--no-kinematics", dest="kinematics", action="store_false",
+                    help="skip the kinematics-outputs line (tool poses, CoM, Jacobians)")
     ap.add_argument("--no-bspline", dest="bspline", action="store_false",
                     help="skip the B-spline control-point iteration measurement")
     return ap.parse_args()
@@ -231,6 +241,8 @@ def main():
                            "hbm_gbps_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9}
     if args.uneven:
         out["uneven_batch"] = bench_uneven(args)
+    if args.kinematics and robot.kinematics_supported:
+        out["kinematics"] = bench_kinematics(args, robot, q0)
     if args.bspline and B % 48 == 0:
         out["bspline_front_end"] = bench_bspline(args, robot, B // 48)
     if not args.no_cpu:
@@ -276,6 +288,54 @@ def bench_bspline(args, robot, T: int):
     return {"trajectories": T, "control_points": K, "n_interp": n_interp, "states": states,
             "states_per_s": states / dt, "ms_per_step": dt * 1e3,
             "form": "bspline_eval + fused iteration (per-joint outputs) + control-point gradient and step, graph"}
+
+
+def bench_kinematics(args, robot, q, reps: int = 50):
+    """The kinematics outputs a least-squares solver needs at the optimizer
+    batch: four tool frames (feet and wrists), the centre of mass, the four
+    tool Jacobians and the CoM Jacobian in one launch, and the gradient of a
+    tool-pose and CoM loss in another; each timed with HIP events on the
+    stream it is launched on."""
+    import torch
+    from paper_2603_05493_amd import synth, wb
+    names = ("left_foot", "right_foot", "left_wrist", "right_wrist")
+    tl = synth.humanoid48_tool_links()
+    links = [tl[k] for k in names]
+    robot.set_tool_frames(links, None, np.tile([[0.0, 0.0, -0.05]], (len(links), 1)))
+    n, B, T = robot.n_dof, q.shape[-1], len(links)
+    out = wb.wb_kinematics(robot, q, tool_pose=True, com=True, jacobian=True, com_jacobian=True)
+    g_tool = torch.randn((T, 12, B), device="cuda")
+    g_com = torch.randn((3, B), device="cuda")
+    g_q = torch.empty((n, B), device="cuda")
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    fwd = timed(lambda: wb.wb_kinematics(robot, q, tool_pose=out["tool_pose"], com=out["com"],
+                                         jacobian=out["jacobian"], com_jacobian=out["com_jacobian"]))
+    bwd = timed(lambda: wb.wb_kinematics_backward(robot, q, g_tool_pose=g_tool, g_com=g_com, g_q=g_q))
+    robot.set_tool_frames([])
+    fwd_bytes = B * 4 * (n + 12 * T + 3 + 6 * n * T + 3 * n)
+    bwd_bytes = B * 4 * (n + 12 * T + 3 + n)
+    m = KIN_TRAFFIC_MEASURED
+    same = (fused_sources_sha1(KIN_SOURCES) == m["sources_sha1"] and B == m["states"] and T == m["tools"])
+    line = lambda t, nb, tr: {"kernel_us": t * 1e6, "states_per_s": B / t, "algorithmic_bytes_per_launch": nb,
+                              "roofline": {"bound": "hbm", "achieved": nb / t / 1e9, "peak": PEAK_HBM_GBPS,
+                                           "unit": "GB/s", "frac": nb / t / 1e9 / PEAK_HBM_GBPS,
+                                           "traffic": tr if same else None}}
+    return {"states": B, "tools": T, "kernel": "k_kinematics",
+            "forward": dict(line(fwd, fwd_bytes, m["forward_bytes"]),
+                            outputs="tool poses, com, tool Jacobians, com Jacobian"),
+            "backward": dict(line(bwd, bwd_bytes, m["backward_bytes"]), outputs="d(tool-pose and com loss)/dq")}
 
 
 def bench_uneven(args):

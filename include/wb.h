@@ -186,13 +186,15 @@ int wb_robot_get_tool_count(const wb_robot *robot, int32_t *n_tools);
  *                         p_link + R_link p_off;
  *   com[3][B]             centre of mass: sum_k m_k (R_k c_k + p_k) / sum_k m_k
  *                         over every link, the fixed base included;
- *   jacobian[T][6][n][B]  Alg. 2's Jacobian of each tool frame: rows are the
- *                         tool point's linear velocity then the angular
- *                         velocity (world axes) per unit joint rate; column j
- *                         sums mult_l [s_l x (x - o_l); s_l] over the links l
- *                         that joint j drives on the chain of the tool's link
- *                         (s_l world axis, o_l world origin of the joint);
- *   com_jacobian[3][n][B] d com / d q.
+ *   jacobian[B][T][6][n]  Alg. 2's Jacobian of each tool frame, state-major
+ *                         (each state's 6T x n block contiguous, row-major, as
+ *                         batched solvers consume it): rows are the tool
+ *                         point's linear velocity then the angular velocity
+ *                         (world axes) per unit joint rate; column j sums
+ *                         mult_l [s_l x (x - o_l); s_l] over the links l that
+ *                         joint j drives on the chain of the tool's link (s_l
+ *                         world axis, o_l world origin of the joint);
+ *   com_jacobian[B][3][n] d com / d q, state-major likewise.
  * T is the count set by wb_robot_set_tool_frames.  WB_ERR_INVALID_ARG when
  * com or com_jacobian is requested for a robot of zero total mass. */
 int wb_kinematics(const wb_robot *robot, int64_t B, const float *q, float *link_pose, float *spheres,

@@ -40,8 +40,8 @@ struct KinOut {
     float *spheres;     // [S][3][B]
     float *tool_pose;   // [T][12][B]
     float *com;         // [3][B]
-    float *jac;         // [T][6][n][B]
-    float *com_jac;     // [3][n][B]
+    float *jac;         // [B][T][6][n] (state-major)
+    float *com_jac;     // [B][3][n] (state-major)
 };
 
 // Inputs and output of the backward call.

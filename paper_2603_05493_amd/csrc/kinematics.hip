@@ -9,6 +9,11 @@
 // as in the fused iteration; nothing but the requested outputs reaches
 // memory.
 //
+// The Jacobians are stored state-major ([B][T][6][n] and [B][3][n]): one
+// state's block is contiguous, as batched linear algebra on them (J^T J per
+// state) wants, and a group writes each row as n consecutive floats, so
+// cache lines are written whole.  The other outputs keep the [k][B] layout.
+//
 // Jacobian of tool t (Alg. 2).  Column lane j walks connectedLinks[j] (the
 // links whose angle joint j sets, several for a mimic joint) and fetches
 // each one's world axis s and origin o from that link's lane.  The coarse
@@ -145,12 +150,11 @@ __device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b,
                 if (lk >= 0) col += y;
             }
             if (!BWD) {
-                if (valid && col_lane) {
-                    float *d = o.com_jac + (int64_t)gl * B + b;
-                    const int64_t rs = (int64_t)n * B;
+                if (valid && col_lane) {   // state-major: the state's 3 x n block is contiguous
+                    float *d = o.com_jac + (int64_t)b * 3 * n + gl;
                     d[0] = col.x;
-                    d[rs] = col.y;
-                    d[2 * rs] = col.z;
+                    d[n] = col.y;
+                    d[2 * n] = col.z;
                 }
             } else {
                 const V3 gc = v3(g.g_com[b], g.g_com[B + b], g.g_com[2 * B + b]);
@@ -190,15 +194,14 @@ __device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b,
                 }
             }
             if (!BWD) {
-                if (valid && col_lane) {
-                    float *d = o.jac + ((int64_t)t * 6 * n + gl) * B + b;
-                    const int64_t rs = (int64_t)n * B;
+                if (valid && col_lane) {   // state-major: each row is n consecutive floats
+                    float *d = o.jac + ((int64_t)b * k.n_tools + t) * 6 * n + gl;
                     d[0] = jl.x;
-                    d[rs] = jl.y;
-                    d[2 * rs] = jl.z;
-                    d[3 * rs] = ja.x;
-                    d[4 * rs] = ja.y;
-                    d[5 * rs] = ja.z;
+                    d[n] = jl.y;
+                    d[2 * n] = jl.z;
+                    d[3 * n] = ja.x;
+                    d[4 * n] = ja.y;
+                    d[5 * n] = ja.z;
                 }
             } else {
                 const float *gt = g.g_tool + (int64_t)t * 12 * B + b;
@@ -217,8 +220,8 @@ __device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b,
 }
 
 // Each workgroup takes `spb` consecutive states (a multiple of its 256 / G
-// groups), so the rows of every [..][B] output are written in whole runs
-// of consecutive states by one workgroup.
+// groups), so the rows of every [k][B] output are written in runs of
+// consecutive states by one workgroup.
 template <bool BWD>
 __global__ void __launch_bounds__(KIN_WG) k_kinematics(DevKin k, int64_t B, const float *__restrict__ q, KinOut o,
                                                        KinGrad g, int32_t spb) {
@@ -226,7 +229,12 @@ __global__ void __launch_bounds__(KIN_WG) k_kinematics(DevKin k, int64_t B, cons
     const int gl = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int gpw = KIN_WG / G;
-    const int64_t base = (int64_t)blockIdx.x * spb;
+    // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2:
+    // renumber them so that every XCD takes one contiguous range of runs
+    // and the cache lines its runs share are fetched and written once.
+    const unsigned nb = gridDim.x;
+    const unsigned bid = (nb & 7u) == 0 ? (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    const int64_t base = (int64_t)bid * spb;
     for (int it = 0; it < spb / gpw; ++it) {
         const int64_t b0 = base + (int64_t)it * gpw;
         if (b0 >= B) break;   // uniform over the workgroup
@@ -236,10 +244,14 @@ __global__ void __launch_bounds__(KIN_WG) k_kinematics(DevKin k, int64_t B, cons
     }
 }
 
+// Runs of up to 32 consecutive states (128-byte rows of the [k][B]
+// outputs), shortened until the grid has 2048 workgroups: each state is a
+// chain of dependent cross-lane steps, so latency hiding wants many
+// resident wavefronts.
 int32_t states_per_block(const DevKin &k, int64_t B) {
     const int gpw = KIN_WG / k.G;
-    int32_t spb = gpw > 32 ? gpw : 32;          // at least 32 consecutive states: 128-byte rows
-    while (spb > gpw && (B + spb - 1) / spb < 512) spb /= 2;
+    int32_t spb = gpw > 32 ? gpw : 32;
+    while (spb > gpw && (B + spb - 1) / spb < 2048) spb /= 2;
     return spb;
 }
 

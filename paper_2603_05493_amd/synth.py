@@ -337,6 +337,13 @@ def humanoid48(seed: int = 0, n_spheres: int = 240) -> Robot:
                    sl, np.concatenate(sp), np.concatenate(sr))
 
 
+def humanoid48_tool_links() -> dict:
+    """Links of humanoid48 that carry its natural tool frames, by the
+    generator's depth-first numbering: the last link of each leg (feet), of
+    each arm (wrists) and of the neck (head)."""
+    return {"left_foot": 6, "right_foot": 12, "head": 18, "left_wrist": 25, "right_wrist": 40}
+
+
 def with_fixed_links(rb: Robot, links) -> Robot:
     """Turn the given links' joints into fixed joints (actuated indices renumbered)."""
     fixed = set(int(k) for k in links)

@@ -191,10 +191,11 @@ def wb_kinematics(robot: Robot, q, link_pose=False, spheres=False, tool_pose=Tru
     """One launch of the kinematics outputs.  Each argument is False (skip),
     True (allocate) or a tensor to fill; returns a dict of the requested
     outputs: link_pose [L,12,B], spheres [S,3,B], tool_pose [T,12,B],
-    com [3,B], jacobian [T,6,n,B], com_jacobian [3,n,B]."""
+    com [3,B], and the state-major jacobian [B,T,6,n] and com_jacobian
+    [B,3,n]."""
     n, B, L, S, T = robot.n_dof, q.shape[-1], robot.n_links, robot.n_spheres, robot.n_tools
     shapes = dict(link_pose=(L, 12, B), spheres=(S, 3, B), tool_pose=(T, 12, B), com=(3, B),
-                  jacobian=(T, 6, n, B), com_jacobian=(3, n, B))
+                  jacobian=(B, T, 6, n), com_jacobian=(B, 3, n))
     want = dict(link_pose=link_pose, spheres=spheres, tool_pose=tool_pose, com=com, jacobian=jacobian,
                 com_jacobian=com_jacobian)
     out = {}

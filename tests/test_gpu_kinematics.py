@@ -3,6 +3,8 @@ wb_kinematics_backward): link poses, sphere centres, tool poses, centre of
 mass, Alg. 2's tool Jacobians, the CoM Jacobian and the tool/CoM gradient,
 against the FP64 oracle on the same FP32 robot tables.
 
+The Jacobians are state-major on the device ([B, T, 6, n], [B, 3, n]).
+
 Tolerances (FP32 against FP64), per state: positions and the centre of
 mass scaled by the robot extent (1e-4); rotations, Jacobians and gradients
 1e-4 normwise (floors 1e-3 and 1e-6).  Columns that Alg. 2's filters drop
@@ -32,6 +34,18 @@ def _mimic_tree():
     return rb
 
 
+def _mimic3_tree():
+    """One joint drives three links (a longer connectedLinks list)."""
+    rb = _mimic_tree()
+    rb.joint_index = rb.joint_index.copy()
+    rb.joint_mult = rb.joint_mult.copy()
+    rb.joint_index[8], rb.joint_mult[8] = rb.joint_index[2], np.float32(0.5)
+    used = sorted(set(int(j) for j in rb.joint_index if j >= 0))
+    remap = {j: i for i, j in enumerate(used)}
+    rb.joint_index = np.array([remap[int(j)] if j >= 0 else -1 for j in rb.joint_index], dtype=np.int32)
+    return rb
+
+
 def _tools(rb, links, seed):
     rng = np.random.default_rng(seed)
     Rs = []
@@ -49,6 +63,7 @@ ROBOTS = [("chain7", lambda: synth.serial_chain(7, 5, seed=0), 1000),
           ("tree23", lambda: synth.random_tree(23, 6, seed=2), 513),
           ("humanoid48", lambda: synth.humanoid48(seed=0), 1500),
           ("mimic_tree", _mimic_tree, 300),
+          ("mimic3_tree", _mimic3_tree, 300),
           ("planar2r", lambda: synth.planar_2r(), 33)]
 
 
@@ -61,6 +76,10 @@ def _setup(rb, B, seed):
     r.set_tool_frames(links, tR, tp)
     st = synth.states(rb, B, seed=seed + 1)
     return r, st, links, tR, tp
+
+
+def _host_sm(t):              # state-major device array -> float64 numpy, same axes
+    return t.detach().cpu().numpy().astype(np.float64)
 
 
 def _pose_host(t):            # [T, 12, B] -> R [B, T, 3, 3], p [B, T, 3]
@@ -84,7 +103,7 @@ def test_kinematics_outputs_match_oracle(oracle, label, factory, B):
     com_ref = K.center_of_mass(rb, st.q)
     lp = P.host(out["link_pose"])                                 # [B, L, 12]
     Rt, xt = _pose_host(out["tool_pose"])
-    J = P.host(out["jacobian"])                                   # [B, T, 6, n]
+    J = _host_sm(out["jacobian"])                                 # [B, T, 6, n]
     errs = dict(
         link_R=P.normwise(lp[:, :, :9], R_ref.reshape(B, -1, 9), floor=1.0).max(),
         link_p=P.scaled(lp[:, :, 9:], p_ref, ext).max(),
@@ -93,7 +112,7 @@ def test_kinematics_outputs_match_oracle(oracle, label, factory, B):
         tool_x=P.scaled(xt, xt_ref, ext).max(),
         com=P.scaled(P.host(out["com"]), com_ref, ext).max(),
         jac=max(P.normwise(J[:, t], J_ref[:, t], floor=1e-3).max() for t in range(len(links))),
-        com_jac=P.normwise(P.host(out["com_jacobian"]), Jc_ref, floor=1e-3).max())
+        com_jac=P.normwise(_host_sm(out["com_jacobian"]), Jc_ref, floor=1e-3).max())
     print(label, " ".join(f"{k}={v:.3g}" for k, v in errs.items()), flush=True)
     assert all(v < P.TOL for v in errs.values())
     # Alg. 2's filters: columns of joints off the chain are exactly zero
@@ -140,7 +159,7 @@ def test_kinematics_ragged_batches(oracle, B):
     out = wb.wb_kinematics(r, P.dev(st.q), tool_pose=True, com=True, jacobian=True)
     torch.cuda.synchronize()
     J_ref = K.jacobian(rb, st.q, links, tR, tp)
-    J = P.host(out["jacobian"])
+    J = _host_sm(out["jacobian"])
     assert max(P.normwise(J[:, t], J_ref[:, t], floor=1e-3).max() for t in range(len(links))) < P.TOL
     _, xt = _pose_host(out["tool_pose"])
     _, xt_ref = K.tool_poses(rb, st.q, links, tR, tp)
@@ -155,7 +174,7 @@ def test_kinematics_empty_batch_and_no_tools():
     assert out["com"].shape == (3, 0)
     q = P.dev(synth.states(rb, 50, seed=1).q)
     out = wb.wb_kinematics(r, q, tool_pose=True, jacobian=True, com=False)   # no tools: nothing to write
-    assert out["jacobian"].shape == (0, 6, 7, 50)
+    assert out["jacobian"].shape == (50, 0, 6, 7)
     g = wb.wb_kinematics_backward(r, q)                                      # no loss terms: zero gradient
     torch.cuda.synchronize()
     assert torch.equal(g, torch.zeros_like(g))
@@ -181,8 +200,8 @@ def test_kinematics_sees_payload_and_new_tools(oracle):
     ext = P.extent(oracle.fk(rb, st.q)[2])
     assert P.scaled(P.host(out["com"]), K.center_of_mass(heavy, st.q), ext).max() < P.TOL
     assert P.scaled(P.host(out["com"]), K.center_of_mass(rb, st.q), ext).max() > 100 * P.TOL
-    assert P.normwise(P.host(out["com_jacobian"]), K.com_jacobian(heavy, st.q), floor=1e-3).max() < P.TOL
-    J = P.host(out["jacobian"])
+    assert P.normwise(_host_sm(out["com_jacobian"]), K.com_jacobian(heavy, st.q), floor=1e-3).max() < P.TOL
+    J = _host_sm(out["jacobian"])
     J_ref = K.jacobian(rb, st.q, links2, tR2, tp2)
     assert J.shape[1] == 2
     assert max(P.normwise(J[:, t], J_ref[:, t], floor=1e-3).max() for t in range(2)) < P.TOL
@@ -199,10 +218,10 @@ def test_kinematics_optimizer_size_sampled(oracle):
     torch.cuda.synchronize()
     idx = np.random.default_rng(61).choice(B, 300, replace=False)
     q = st.q[idx]
-    J = P.host(out["jacobian"])[idx]
+    J = _host_sm(out["jacobian"])[idx]
     J_ref = K.jacobian(rb, q, links, tR, tp)
     assert max(P.normwise(J[:, t], J_ref[:, t], floor=1e-3).max() for t in range(len(links))) < P.TOL
-    assert P.normwise(P.host(out["com_jacobian"])[idx], K.com_jacobian(rb, q), floor=1e-3).max() < P.TOL
+    assert P.normwise(_host_sm(out["com_jacobian"])[idx], K.com_jacobian(rb, q), floor=1e-3).max() < P.TOL
 
 
 def test_kinematics_rejects_bad_arguments():
