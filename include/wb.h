@@ -330,13 +330,14 @@ int wb_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float
  *                      evaluated before the step.
  *   f_ext [L][6][B] or NULL    external link forces, as in wb_rnea;
  *   g_fext [L][6][B] or NULL   their gradient (as wb_rnea_backward's g_fext,
- *                      for the torque cost).  Either one selects the kernel
- *                      variant that carries external forces.
- * Results agree with the separate calls (same definitions, same tolerance;
- * floating-point sums are ordered differently).  Needs n_links <= 64, no
- * mimic joints, and the per-state sweep tables of a 256-lane workgroup
- * within 64 KB of LDS (wb_robot_info.fused_supported), else
- * WB_ERR_UNSUPPORTED. */
+ *                      for the torque cost).
+ * External forces and mimic joints (several links per actuated joint, or a
+ * multiplier other than 1 or offset other than 0) select the kernel variant
+ * that carries them; other robots run the lean variant.  Results agree with
+ * the separate calls (same definitions, same tolerance; floating-point sums
+ * are ordered differently).  Needs n_links <= 64 and the per-state sweep
+ * tables of a 256-lane workgroup within 64 KB of LDS
+ * (wb_robot_info.fused_supported), else WB_ERR_UNSUPPORTED. */
 int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, float *qdd, const float *w,
                       float torque_weight, float margin, float hinge_weight, float lr, float *tau,
                       float *cost, float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q,
@@ -387,14 +388,18 @@ int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune);
  *     outlive it.  WB_ERR_UNSUPPORTED if the LDS of a workgroup would exceed
  *     64 KB.
  *   wb_plan_run: io[n_trees] holds each robot's device buffers with the
- *     meaning and layout of wb_wholebody_step; the scalars are shared.
- *     Never allocates or synchronizes. */
+ *     meaning and layout of wb_wholebody_step (external forces included);
+ *     the scalars are shared.  A plan with a mimic robot, or a run with
+ *     external forces, uses the kernel variant that carries them for every
+ *     tree.  Never allocates or synchronizes. */
 typedef struct wb_tree_io {
     float *q, *qd, *qdd;
     const float *w;
     float *tau, *cost, *max_pen;
     int32_t *argmax, *n_coll;
     float *g_q, *g_qd, *g_qdd;
+    const float *f_ext;   /* [L][6][B] or NULL, as in wb_wholebody_step */
+    float *g_fext;        /* [L][6][B] or NULL */
 } wb_tree_io;
 typedef struct wb_plan wb_plan;
 int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_trees, const wb_tune *tune,

@@ -46,7 +46,7 @@ class WbTune(C.Structure):
 
 class WbTreeIO(C.Structure):
     _fields_ = [(nm, _vp) for nm in ("q", "qd", "qdd", "w", "tau", "cost", "max_pen", "argmax", "n_coll",
-                                     "g_q", "g_qd", "g_qdd")]
+                                     "g_q", "g_qd", "g_qdd", "f_ext", "g_fext")]
 
 
 class WbError(RuntimeError):

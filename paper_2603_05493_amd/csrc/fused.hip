@@ -39,10 +39,18 @@
 // since rotating joint i moves every world axis and inertia in its subtree
 // (dS = dq S_i x S, dI = dq (S_i x* I - I S_i x)).
 //
-// External link forces (the FEXT variant): f_ext is given in link
-// coordinates and turns with its link, f_w = X* f_ext; it enters the force
-// line as f = I a + v x* I v - f_w, adds fb x* f_w to W (the rotation of f_w
-// with the joints above it), and its gradient is f_ext-bar = -X*^T fb.
+// The EXT variant adds two features, each switched on at run time:
+// * external link forces: f_ext is given in link coordinates and turns with
+//   its link, f_w = X* f_ext; it enters the force line as
+//   f = I a + v x* I v - f_w, adds fb x* f_w to W (the rotation of f_w with
+//   the joints above it), and its gradient is f_ext-bar = -X*^T fb;
+// * mimic joints (Alg. 4's m_k and joint map): link l turns by
+//   theta_l = m_l q_j + o_l, so its rates are m_l qd_j and m_l qdd_j; joint j's
+//   torque is sum over its links of m_l S_l . F_l.  Lane j of the group owns
+//   joint j: it gathers the torque from the links' lanes (connectedLinks),
+//   runs the cost head, and its tau-bar returns to each link as m_l tau-bar_j;
+//   the per-link adjoints (q-bar, qd-bar, qdd-bar) come back the same way,
+//   each scaled by m_l, and lane j writes joint j's outputs and step.
 #include "sweep.h"
 
 namespace wb {
@@ -117,13 +125,25 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Sum over the links joint `glane` drives (connectedLinks, lanes of the
+// group) of their x; 0 in lanes past the last joint.
+__device__ __forceinline__ float gather_joint(float x, const DevFused &fz, int glane, int G) {
+    float acc = 0.f;
+    for (int kk = 0; kk < fz.mc; ++kk) {
+        const int l = fz.conn[kk * 64 + glane];
+        const float y = __shfl(x, l >= 0 ? l : glane, G);
+        if (l >= 0) acc += y;
+    }
+    return acc;
+}
+
 // The whole iteration for one state per group of G lanes.  Every lane of
 // the wavefront calls this (group-local shuffles need all lanes); `valid`
 // is false for groups past the end of the batch, which compute on a copy of
 // a valid state and store nothing.  The lane's link constants are read from
 // the lane tables at the point of use in every state (they stay in the L1
 // cache), so that no register holds them across the sweep.
-template <int NMAX, bool FULL, bool FEXT>
+template <int NMAX, bool FULL, bool EXT>
 __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t *tab, const DevFused &fz,
                                               const TreeIO &io, const StepScalars &k, float4 *P, float4 *Bd,
                                               uint16_t *list, int G, int grp, int glane, int64_t B, int64_t b,
@@ -136,11 +156,18 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     const int parent_lane = li[1 * 64 + gl];
     const bool revolute = li[5 * 64 + gl] != 0;
     const int64_t jo = (int64_t)li[3 * 64 + gl] * B + b;
-    float th = 0.f, thd = 0.f, thdd = 0.f;
+    const bool mim = EXT && fz.mimic;
+    float th = 0.f, thd = 0.f, thdd = 0.f, mult = 1.f;
     if (revolute) {
         th = io.q[jo];
         thd = io.qd[jo];
         thdd = io.qdd[jo];
+        if (mim) {
+            mult = lf[29 * 64 + gl];
+            th = mult * th + lf[30 * 64 + gl];
+            thd *= mult;
+            thdd *= mult;
+        }
     }
     // ---- forward kinematics
     M3 R;
@@ -224,7 +251,7 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     const int sub_end = li[2 * 64 + gl];
     // ---- external force in world coordinates, f_w = X* f_ext (moment about the world origin)
     SV fe = zsv();
-    if (FEXT && io.f_ext && act) {
+    if (EXT && io.f_ext && act) {
         const float *fx = io.f_ext + (int64_t)(link * 6) * B + b;
         const V3 Rf = mul(R, v3(fx[3 * B], fx[4 * B], fx[5 * B]));
         fe = sv(mul(R, v3(fx[0], fx[B], fx[2 * B])) + cross(p, Rf), Rf);
@@ -236,15 +263,19 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     if (act) a += sv(v3(0.f, 0.f, 0.f), v3(-rb.gx, -rb.gy, -rb.gz));
     const SV Ia = iw_apply(J, a), Iv = iw_apply(J, v);
     SV F = Ia + crf(v, Iv);
-    if (FEXT) F = F - fe;
+    if (EXT) F = F - fe;
     if (!act) F = zsv();
     F = subtree_sum(F, glane, sub_end, G);
-    const float tau = revolute ? dot(S, F) : 0.f;
+    float tau = revolute ? dot(S, F) : 0.f;
+    // with mimic joints, joint lane j (j < n) holds joint j from here to the cost head
+    const bool jlane = mim ? gl < rb.n : revolute;
+    const int64_t jrow = mim ? (int64_t)gl * B + b : jo;
+    if (mim) tau = gather_joint(mult * tau, fz, gl, G);
     // ---- cost head
     float tcost = 0.f, taub = 0.f;
-    if (revolute) {
+    if (jlane) {
         if (io.w) {
-            const float wj = io.w[jo];
+            const float wj = io.w[jrow];
             tcost = wj * tau;
             taub = wj;
         } else {
@@ -253,12 +284,16 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
         }
     }
     tcost = group_reduce_sum(tcost, G);
+    if (mim) {   // tau-bar back to the links: m_l tau-bar_j
+        const float tj = __shfl(taub, revolute ? li[3 * 64 + gl] : gl, G);
+        taub = revolute ? mult * tj : 0.f;
+    }
     // ---- VJP, with the terms of W added as soon as their factors exist
     W += taub * crf(S, F);
     const SV fb = path_sum(taub * S, parent_lane, glane, fz.jsteps, G);
     SV ab = iw_apply(J, fb);
     W = W - (crf(fb, Ia) + crf(a, ab));
-    if (FEXT) W += crf(fb, fe);
+    if (EXT) W += crf(fb, fe);
     const SV vxfb = crm(v, fb);
     const SV Ivxfb = iw_apply(J, vxfb);
     SV vb = zsv() - (crf(fb, Iv) + Ivxfb);
@@ -275,25 +310,37 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     W += thd * crf(S, V);
     if (!act) W = zsv();
     const SV Ws = subtree_sum(W, glane, sub_end, G);
-    const float th_b = dot(S, Ws);
+    float th_b = dot(S, Ws);
+    float thd_o = thd_b, thdd_o = thdd_b;
+    if (mim) {   // per-link adjoints to joints: sum of m_l x (link adjoint)
+        th_b = gather_joint(mult * th_b, fz, gl, G);
+        thd_o = gather_joint(mult * thd_b, fz, gl, G);
+        thdd_o = gather_joint(mult * thdd_b, fz, gl, G);
+    }
     // ---- outputs and the gradient step
     if (!valid) return;
-    if (FEXT && io.g_fext && act) {
+    if (EXT && io.g_fext && act) {
         // -X*^T fb: moment part -R^T fb_w, force part -R^T (fb_l + fb_w x p)
         const V3 gn = mulT(R, fb.w), gf = mulT(R, fb.l + cross(fb.w, p));
         float *gx = io.g_fext + (int64_t)(link * 6) * B + b;
         gx[0] = -gn.x; gx[B] = -gn.y; gx[2 * B] = -gn.z;
         gx[3 * B] = -gf.x; gx[4 * B] = -gf.y; gx[5 * B] = -gf.z;
     }
-    if (revolute) {
-        if (io.tau) io.tau[jo] = tau;
-        if (io.g_q) io.g_q[jo] = th_b;
-        if (io.g_qd) io.g_qd[jo] = thd_b;
-        if (io.g_qdd) io.g_qdd[jo] = thdd_b;
+    if (jlane) {
+        if (io.tau) io.tau[jrow] = tau;
+        if (io.g_q) io.g_q[jrow] = th_b;
+        if (io.g_qd) io.g_qd[jrow] = thd_o;
+        if (io.g_qdd) io.g_qdd[jrow] = thdd_o;
         if (k.lr != 0.f) {
-            io.q[jo] = th - k.lr * th_b;
-            io.qd[jo] = thd - k.lr * thd_b;
-            io.qdd[jo] = thdd - k.lr * thdd_b;
+            if (mim) {   // the joint's own values (a link lane holds m_l q + o_l)
+                io.q[jrow] -= k.lr * th_b;
+                io.qd[jrow] -= k.lr * thd_o;
+                io.qdd[jrow] -= k.lr * thdd_o;
+            } else {
+                io.q[jo] = th - k.lr * th_b;
+                io.qd[jo] = thd - k.lr * thd_b;
+                io.qdd[jo] = thdd - k.lr * thdd_b;
+            }
         }
     }
     if (glane == 0) {
@@ -307,7 +354,7 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
 // Process `count` states starting at b0 of one robot with the 4 waves of
 // this workgroup, 64/G states per wavefront at a time; tab is the robot's
 // block table staged in LDS.
-template <int NMAX, bool FEXT>
+template <int NMAX, bool EXT>
 __device__ __forceinline__ void run_states(const DevRobot &rb, const uint16_t *tab, const DevFused &fz, const TreeIO &io,
                                            const StepScalars &k, float4 *lds_wave, int G, int64_t B,
                                            int64_t b0, int count) {
@@ -325,8 +372,8 @@ __device__ __forceinline__ void run_states(const DevRobot &rb, const uint16_t *t
         const int s = base + grp;
         const bool valid = s < count;
         const int64_t b = b0 + (valid ? s : base);
-        if (G == 64) iterate_state<NMAX, true, FEXT>(rb, tab, fz, io, k, P, Bd, list, 64, 0, glane, B, b, valid);
-        else iterate_state<NMAX, false, FEXT>(rb, tab, fz, io, k, P, Bd, list, G, grp, glane, B, b, valid);
+        if (G == 64) iterate_state<NMAX, true, EXT>(rb, tab, fz, io, k, P, Bd, list, 64, 0, glane, B, b, valid);
+        else iterate_state<NMAX, false, EXT>(rb, tab, fz, io, k, P, Bd, list, G, grp, glane, B, b, valid);
     }
 }
 
@@ -339,9 +386,9 @@ __device__ __forceinline__ void stage_table(const DevRobot &rb, uint16_t *tab) {
     }
 }
 
-// Four wavefronts per SIMD: the register budget is 128 VGPRs.  FEXT: the
-// variant with external link forces (and their gradient).
-template <int NMAX, bool FEXT>
+// Four wavefronts per SIMD: the register budget is 128 VGPRs.  EXT: the
+// variant with external link forces and mimic joints.
+template <int NMAX, bool EXT>
 __global__ void __launch_bounds__(256, 4) k_fused_step(FusedArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
@@ -357,13 +404,14 @@ __global__ void __launch_bounds__(256, 4) k_fused_step(FusedArgs A) {
     uint16_t *tab = reinterpret_cast<uint16_t *>(lds + 4 * SLW);
     stage_table(A.rb, tab);
     __syncthreads();
-    run_states<NMAX, FEXT>(A.rb, tab, A.fz, A.io, A.k, lds + wave * SLW, G, A.B, b0, count);
+    run_states<NMAX, EXT>(A.rb, tab, A.fz, A.io, A.k, lds + wave * SLW, G, A.B, b0, count);
 }
 
 // Persistent launch over an uneven batch of robots: workgroup w processes
 // the items [item_start[w], item_start[w+1]) of the plan's work list, each a
-// contiguous range of states of one robot.
-template <int NMAX>
+// contiguous range of states of one robot.  EXT as for k_fused_step, chosen
+// when any tree has mimic joints or external forces.
+template <int NMAX, bool EXT>
 __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
@@ -381,8 +429,8 @@ __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
             staged = item.tree;
         }
         // a fixed region per wave, sized for the plan's largest tree
-        run_states<NMAX, false>(T.rb, tab, T.fz, A.io[item.tree], A.k, lds + wave * A.wave_stride, G, T.B,
-                                item.b0, item.count);
+        run_states<NMAX, EXT>(T.rb, tab, T.fz, A.io[item.tree], A.k, lds + wave * A.wave_stride, G, T.B,
+                              item.b0, item.count);
     }
 }
 
@@ -390,7 +438,8 @@ template <int NMAX>
 static hipError_t launch_fused_t(const FusedArgs &a, hipStream_t s) {
     const size_t lds = fused_lds_bytes(a.rb.L, NMAX, a.rb.list_cap, a.lanes_per_state, a.rb.n_blocks_pad);
     const unsigned nwg = (unsigned)((a.B + a.chunk - 1) / a.chunk);
-    if (a.io.f_ext || a.io.g_fext) hipLaunchKernelGGL((k_fused_step<NMAX, true>), dim3(nwg), dim3(256), lds, s, a);
+    if (a.io.f_ext || a.io.g_fext || a.fz.mimic)
+        hipLaunchKernelGGL((k_fused_step<NMAX, true>), dim3(nwg), dim3(256), lds, s, a);
     else hipLaunchKernelGGL((k_fused_step<NMAX, false>), dim3(nwg), dim3(256), lds, s, a);
     return hipGetLastError();
 }
@@ -411,22 +460,23 @@ hipError_t launch_fused(const FusedArgs &a, hipStream_t s) {
 }
 
 template <int NMAX>
-static hipError_t launch_plan_t(const PlanArgs &a, int n_wg, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_plan_step<NMAX>, dim3(n_wg), dim3(256), lds, s, a);
+static hipError_t launch_plan_t(const PlanArgs &a, int n_wg, size_t lds, bool ext, hipStream_t s) {
+    if (ext) hipLaunchKernelGGL((k_plan_step<NMAX, true>), dim3(n_wg), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_plan_step<NMAX, false>), dim3(n_wg), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_plan(const PlanArgs &a, int nmax, int n_wg, size_t lds, hipStream_t s) {
+hipError_t launch_plan(const PlanArgs &a, int nmax, int n_wg, size_t lds, bool ext, hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
     switch (nmax) {
-        case 1: return launch_plan_t<1>(a, n_wg, lds, s);
-        case 2: return launch_plan_t<2>(a, n_wg, lds, s);
-        case 3: return launch_plan_t<3>(a, n_wg, lds, s);
-        case 4: return launch_plan_t<4>(a, n_wg, lds, s);
-        case 5: return launch_plan_t<5>(a, n_wg, lds, s);
-        case 6: return launch_plan_t<6>(a, n_wg, lds, s);
-        case 7: return launch_plan_t<7>(a, n_wg, lds, s);
-        case 8: return launch_plan_t<8>(a, n_wg, lds, s);
+        case 1: return launch_plan_t<1>(a, n_wg, lds, ext, s);
+        case 2: return launch_plan_t<2>(a, n_wg, lds, ext, s);
+        case 3: return launch_plan_t<3>(a, n_wg, lds, ext, s);
+        case 4: return launch_plan_t<4>(a, n_wg, lds, ext, s);
+        case 5: return launch_plan_t<5>(a, n_wg, lds, ext, s);
+        case 6: return launch_plan_t<6>(a, n_wg, lds, ext, s);
+        case 7: return launch_plan_t<7>(a, n_wg, lds, ext, s);
+        case 8: return launch_plan_t<8>(a, n_wg, lds, ext, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -50,6 +50,8 @@ struct Tables {
     std::vector<int32_t> f_li;
     std::vector<float> f_lf;
     std::vector<float4> f_sph;
+    int f_mimic = 0, f_mc = 1;        // mimic joints present; longest connectedLinks list
+    std::vector<int32_t> f_conn;      // [f_mc][64] lanes of each joint's links
     // lane tables of the kinematics-outputs kernel (same depth-first order)
     int kin = 0, kin_G = 0, kin_jsteps = 0, kin_mc = 0;
     std::vector<int> kin_lane, kin_sub_end;   // link -> lane, lane -> last lane of its subtree
@@ -154,14 +156,15 @@ void build_kin(Tables &T) {
 void build_fused(Tables &T) {
     const int L = T.L;
     T.fused = 0;
-    if (L > 64 || !T.simple) return;
+    if (L > 64) return;
     const int g_default = L <= 16 ? 16 : (L <= 32 ? 32 : 64);
     if (wb::fused_lds_bytes(L, T.nmax, T.list_cap, g_default, (int)T.blocks.size()) > wb::LDS_LIMIT) return;
     std::vector<int> perm, size;
     std::vector<int> &lane_of = T.lane_of;
     dfs_lanes(T, perm, lane_of, size);
     T.f_li.assign(8 * 64, 0);
-    T.f_lf.assign(29 * 64, 0.0f);
+    T.f_lf.assign(31 * 64, 0.0f);
+    std::vector<std::vector<int>> conn(T.n);
     T.f_sph.assign((size_t)WB_MAX_SPHERES_PER_LINK * 64, make_float4(0, 0, 0, 0));
     for (int i = 0; i < L; ++i) {
         const int k = perm[i];
@@ -180,6 +183,9 @@ void build_fused(Tables &T) {
         T.f_lf[15 * 64 + i] = F.mass;
         for (int c = 0; c < 3; ++c) T.f_lf[(16 + c) * 64 + i] = F.com[c];
         for (int c = 0; c < 6; ++c) T.f_lf[(19 + c) * 64 + i] = F.I[c];
+        T.f_lf[29 * 64 + i] = F.mult;
+        T.f_lf[30 * 64 + i] = F.offset;
+        if (I.revolute && I.jidx >= 0) conn[I.jidx].push_back(i);
         for (int j = 0; j < I.sph_count; ++j) T.f_sph[(size_t)j * 64 + i] = T.sph[I.sph_first + j];
         // bounding sphere of the link's spheres in link coordinates: centroid,
         // then the largest reach, rounded up so that it holds every sphere
@@ -211,7 +217,14 @@ void build_fused(Tables &T) {
         T.f_li[6 * 64 + i] = 1;
         for (int c = 0; c < 9; c += 4) T.f_lf[(3 + c) * 64 + i] = 1.0f;
         T.f_lf[28 * 64 + i] = -1e30f;
+        T.f_lf[29 * 64 + i] = 1.0f;
     }
+    T.f_mimic = T.simple ? 0 : 1;
+    T.f_mc = 1;
+    for (int j = 0; j < T.n; ++j) T.f_mc = std::max(T.f_mc, (int)conn[j].size());
+    T.f_conn.assign((size_t)T.f_mc * 64, -1);
+    for (int j = 0; j < T.n; ++j)
+        for (size_t c = 0; c < conn[j].size(); ++c) T.f_conn[c * 64 + j] = conn[j][c];
     T.jsteps = pointer_jump_steps(T.max_depth);
     T.fused = 1;
 }
@@ -536,6 +549,7 @@ int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
     const size_t o_po = append(blob, T.pair_off), o_pc = append(blob, T.pair_cnt);
     const size_t o_ps = append(blob, T.pair_s), o_pt = append(blob, T.pair_t);
     const size_t o_fi = append(blob, T.f_li), o_ff = append(blob, T.f_lf), o_fs = append(blob, T.f_sph);
+    const size_t o_fc = append(blob, T.f_conn);
     const size_t o_ki = append(blob, T.k_li), o_kf = append(blob, T.k_lf), o_kc = append(blob, T.k_conn);
     const size_t o_tl = append(blob, std::vector<int32_t>(WB_MAX_TOOLS, 0));
     const size_t o_to = append(blob, std::vector<float>(12 * WB_MAX_TOOLS, 0.0f));
@@ -576,6 +590,9 @@ int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
     Fz.li = reinterpret_cast<const int32_t *>(base + o_fi);
     Fz.lf = reinterpret_cast<const float *>(base + o_ff);
     Fz.lsph = reinterpret_cast<const float4 *>(base + o_fs);
+    Fz.mimic = T.f_mimic;
+    Fz.mc = T.f_mc;
+    Fz.conn = reinterpret_cast<const int32_t *>(base + o_fc);
     wb::DevKin &Kn = r->kin;
     Kn.L = T.L; Kn.n = T.n; Kn.G = T.kin_G; Kn.jsteps = T.kin_jsteps; Kn.mc = T.kin_mc;
     Kn.inv_mass = T.total_mass > 0.0 ? (float)(1.0 / T.total_mass) : 0.0f;
@@ -816,7 +833,8 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, flo
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
     if (!robot->fz.supported)
-        return fail(WB_ERR_UNSUPPORTED, "the fused iteration needs <= 64 links and no mimic joints");
+        return fail(WB_ERR_UNSUPPORTED, "the fused iteration needs <= 64 links and sweep tables within %zu bytes of LDS",
+                    wb::LDS_LIMIT);
     if (!std::isfinite(torque_weight) || !std::isfinite(margin) || !std::isfinite(hinge_weight) || !std::isfinite(lr))
         return fail(WB_ERR_INVALID_ARG, "weights, margin and lr must be finite");
     if (B == 0) return WB_OK;
@@ -1002,6 +1020,7 @@ int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune) {
 
 struct wb_plan {
     int n_trees = 0, nmax = 1, n_wg = 0, n_items = 0, device = -1;
+    int mimic = 0;                  // some tree has mimic joints: the EXT kernel variant
     size_t lds = 0, wave_lds = 0;   // LDS per workgroup, and per wavefront region
     std::vector<int64_t> B;
     std::vector<int> n_dof;
@@ -1040,7 +1059,9 @@ int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_tr
         WB_TRY(check_robot(robots[i]));
         WB_TRY(check_B(B[i]));
         if (!robots[i]->fz.supported)
-            return fail(WB_ERR_UNSUPPORTED, "tree %d: the fused iteration needs <= 64 links and no mimic joints", i);
+            return fail(WB_ERR_UNSUPPORTED,
+                        "tree %d: the fused iteration needs <= 64 links and sweep tables within %zu bytes of LDS", i,
+                        wb::LDS_LIMIT);
         if (device >= 0 && robots[i]->device != device)
             return fail(WB_ERR_INVALID_ARG, "all robots of a plan must live on one device");
         device = robots[i]->device;
@@ -1155,6 +1176,7 @@ int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_tr
     }
     p->n_trees = n_trees;
     p->nmax = nmax;
+    for (int i = 0; i < n_trees; ++i) p->mimic |= robots[i]->fz.mimic;
     p->n_wg = n_wg;
     p->n_items = (int)flat.size();
     p->device = device;
@@ -1181,6 +1203,7 @@ int wb_plan_run(const wb_plan *plan, const wb_tree_io *io, float torque_weight, 
     a.item_start = plan->d_item_start;
     a.wave_stride = (int32_t)(plan->wave_lds / 16);
     a.k = wb::StepScalars{torque_weight, margin, hinge_weight, lr};
+    bool ext = plan->mimic != 0;
     for (int i = 0; i < plan->n_trees; ++i) {
         const wb_tree_io &x = io[i];
         const bool need = plan->B[i] > 0 && plan->n_dof[i] > 0;
@@ -1196,9 +1219,13 @@ int wb_plan_run(const wb_plan *plan, const wb_tree_io *io, float torque_weight, 
         WB_TRY(check_ptr(x.g_q, "io.g_q", false));
         WB_TRY(check_ptr(x.g_qd, "io.g_qd", false));
         WB_TRY(check_ptr(x.g_qdd, "io.g_qdd", false));
-        a.io[i] = wb::TreeIO{x.q, x.qd, x.qdd, x.w, x.tau, x.cost, x.max_pen, x.argmax, x.n_coll, x.g_q, x.g_qd, x.g_qdd};
+        WB_TRY(check_ptr(x.f_ext, "io.f_ext", false));
+        WB_TRY(check_ptr(x.g_fext, "io.g_fext", false));
+        a.io[i] = wb::TreeIO{x.q,     x.qd,     x.qdd, x.w,    x.tau,   x.cost,   x.max_pen, x.argmax,
+                             x.n_coll, x.g_q, x.g_qd, x.g_qdd, x.f_ext, x.g_fext};
+        ext = ext || x.f_ext || x.g_fext;
     }
-    return finish(wb::launch_plan(a, plan->nmax, plan->n_wg, plan->lds, stream), "wb_plan_run launch");
+    return finish(wb::launch_plan(a, plan->nmax, plan->n_wg, plan->lds, ext, stream), "wb_plan_run launch");
 }
 
 int wb_plan_get_info(const wb_plan *plan, int32_t *n_items, int32_t *n_workgroups) {

@@ -63,16 +63,22 @@ struct DevRobot {
 //   lf[f*64 + i]: f = 0..2 axis, 3..11 fixed R, 12..14 fixed p, 15 mass,
 //                 16..18 CoM, 19..24 inertia (xx yy zz xy xz yz),
 //                 25..27 centre and 28 radius of the link's bounding sphere in
-//                 link coordinates (-1e30 without spheres)
+//                 link coordinates (-1e30 without spheres), 29 joint
+//                 multiplier, 30 joint offset
 //   lsph[j*64 + i]: local centre and radius of the link's j-th sphere
+//   conn[k*64 + j]: lane of the k-th link that joint j drives, -1 past the
+//                 end of the list (read only when mimic is set)
 // Lanes past the last link hold an empty link: link -1, parent -1, subtree
 // end i, no joint, no spheres, identity fixed rotation, zero mass.
 struct DevFused {
-    int32_t supported;   // L <= 64 and one link per actuated joint without mimic scaling
+    int32_t supported;   // L <= 64 and the sweep tables fit the LDS budget
     int32_t jsteps;      // pointer-jumping steps, ceil(log2(max_depth + 1))
+    int32_t mimic;       // some joint drives several links, or a multiplier != 1 or offset != 0
+    int32_t mc;          // longest connectedLinks list
     const int32_t *__restrict__ li;
     const float *__restrict__ lf;
     const float4 *__restrict__ lsph;
+    const int32_t *__restrict__ conn;
 };
 
 // Device pointers of one robot's batch in a fused iteration.
@@ -127,7 +133,7 @@ struct PlanArgs {
 };
 
 hipError_t launch_fused(const FusedArgs &a, hipStream_t s);
-hipError_t launch_plan(const PlanArgs &a, int nmax, int n_wg, size_t lds, hipStream_t s);
+hipError_t launch_plan(const PlanArgs &a, int nmax, int n_wg, size_t lds, bool ext, hipStream_t s);
 
 // Kernel launchers (each defined next to its kernels).
 hipError_t launch_fk(const DevRobot &rb, int64_t B, const float *q, float *pose, float *spheres,

@@ -421,13 +421,16 @@ class Plan:
 
     def run(self, ios, torque_weight=0.0, margin=0.0, hinge_weight=0.0, lr=0.0):
         """ios: one dict per robot with keys q, qd, qdd and optional w, tau,
-        cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd (device tensors)."""
+        cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd, f_ext, g_fext
+        (device tensors)."""
         n = len(self.robots)
         arr = (_abi.WbTreeIO * n)()
         for i, (r, b, io) in enumerate(zip(self.robots, self.B, ios)):
             nd = r.n_dof
             for key in ("q", "qd", "qdd", "w", "tau", "g_q", "g_qd", "g_qdd"):
                 _chk(io.get(key), key, (nd, b), device=r.device)
+            for key in ("f_ext", "g_fext"):
+                _chk(io.get(key), key, (r.n_links, 6, b), device=r.device)
             for key in ("cost", "max_pen"):
                 _chk(io.get(key), key, (b,), device=r.device)
             for key in ("argmax", "n_coll"):

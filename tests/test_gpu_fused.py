@@ -133,16 +133,60 @@ def test_fused_matches_plain_and_steps():
     assert ((qa - qb).abs().amax(0)[same] < 1e-6).all()
 
 
-def test_fused_rejects_mimic():
-    from paper_2603_05493_amd import _abi, wb
-    rb = synth.random_tree(5, 2, seed=3)
-    rb.joint_index = np.array([-1, 0, 1, 1, 2, 3], dtype=np.int32)
+def _mimic_tree():
+    rb = synth.random_tree(9, 3, seed=31, random_fixed_rotation=True)
+    rb.joint_index = np.array([-1, 0, 1, 1, 2, 3, 4, 5, 5, 6], dtype=np.int32)
+    rb.joint_mult = synth._f32([1.0, 1.0, 1.0, -0.5, 1.0, 2.0, 1.0, 1.0, 0.75, 1.0])
+    rb.joint_offset = synth._f32([0.0, 0.0, 0.1, 0.25, 0.0, 0.0, -0.2, 0.0, 0.0, 0.0])
+    return rb
+
+
+def _humanoid_coupled_fingers():
+    """The humanoid with each finger's distal joint following its proximal
+    joint (ratio 0.8): 40 actuated joints drive 48 links."""
+    rb = synth.humanoid48(seed=0)
+    ji, jm = rb.joint_index.copy(), rb.joint_mult.copy()
+    for wrist in (25, 40):
+        for f in range(4):
+            prox = wrist + 1 + 2 * f
+            ji[prox + 1], jm[prox + 1] = ji[prox], 0.8
+    used = sorted(set(int(j) for j in ji if j >= 0))
+    remap = {j: i for i, j in enumerate(used)}
+    rb.joint_index = np.array([remap[int(j)] if j >= 0 else -1 for j in ji], dtype=np.int32)
+    rb.joint_mult = synth._f32(jm)
+    return rb
+
+
+@pytest.mark.parametrize("label,factory,B,qr,weighted", [
+    ("mimic_tree9_B3000", _mimic_tree, 3000, np.pi, True),
+    ("humanoid_coupled_fingers_B2048", _humanoid_coupled_fingers, 2048, 1.5, False),
+])
+def test_fused_mimic_joints(oracle, label, factory, B, qr, weighted):
+    """Mimic joints (one actuator driving several links with a gain and an
+    offset) in the fused iteration, against the oracle."""
+    rb = factory()
+    assert _robot(rb).fused_supported
+    st = synth.states(rb, B, seed=17, q_range=qr)
+    w = synth.weights((B, rb.n_dof), seed=18) if weighted else None
+    check_fused(oracle, rb, st, label, w=w)
+
+
+def test_fused_mimic_step_updates_each_joint_once():
+    from paper_2603_05493_amd.iteration import FusedIteration
+    rb = _humanoid_coupled_fingers()
+    B = 1024
+    st = synth.states(rb, B, seed=19, q_range=1.5)
     r = _robot(rb)
-    assert not r.fused_supported
-    q = torch.zeros((4, 8), device="cuda")
-    with pytest.raises(_abi.WbError) as e:
-        wb.wb_wholebody_step(r, q, q.clone(), q.clone())
-    assert e.value.code == _abi.WB_ERR_UNSUPPORTED
+    fu = FusedIteration(r, B, torque_weight=1e-3, margin=0.01, hinge_weight=1.0)
+    q, qd, qdd = P.dev(st.q), P.dev(st.qd), P.dev(st.qdd)
+    fu.run(q, qd, qdd, step=False)
+    g_q, g_qd, g_qdd = fu.g_q.clone(), fu.g_qd.clone(), fu.g_qdd.clone()
+    lr = 1e-3
+    fu.lr = lr
+    fu.run(q, qd, qdd, step=True)
+    torch.cuda.synchronize()
+    for x, x0, g in ((q, st.q, g_q), (qd, st.qd, g_qd), (qdd, st.qdd, g_qdd)):
+        assert torch.allclose(x, P.dev(x0) - lr * g, rtol=0, atol=1e-6)
 
 
 def test_fused_deterministic():

@@ -17,8 +17,13 @@ def _robot(rb):
     return wb.Robot(rb).to_device("cuda:0")
 
 
-def _oracle_check(O, rb, st, out, label, margin=0.01, torque_weight=1e-3):
-    ref = P.oracle_iteration(O, rb, st.q, st.qd, st.qdd, None, torque_weight, margin, 1.0)
+def _oracle_check(O, rb, st, out, label, margin=0.01, torque_weight=1e-3, fext=None):
+    ref = P.oracle_iteration(O, rb, st.q, st.qd, st.qdd, None, torque_weight, margin, 1.0, fext=fext)
+    if "g_fext" in out:
+        g = np.transpose(out["g_fext"].cpu().numpy().astype(np.float64), (2, 0, 1))
+        e = P.normwise(g, ref["g_fext"], floor=1e-6).max()
+        print(label, f"e_gfext={e:.2e}", flush=True)
+        assert e < P.TOL
     pens = O.self_collision_pens(rb, ref["c"])
     ok = P.unambiguous(pens) & (np.abs(ref["max_pen"] + margin) >= P.DELTA)
     cond = P.hinge_conditioning(ref, rb)
@@ -146,3 +151,37 @@ def test_autotuner_picks_a_valid_shape():
     assert len(res["candidates"]) == 4 and res["ns_per_state"] > 0
     assert r.get_tune()["lanes_per_state"] == res["lanes_per_state"]
     assert tune.apply(r, {r.topology_key(): res})
+
+
+def test_plan_mimic_tree_and_external_forces(oracle):
+    """A plan holding a mimic robot, with external forces on two of its
+    trees, runs the variant that carries both; every tree agrees with the
+    oracle (torques, gradients and the gradient on the forces)."""
+    from paper_2603_05493_amd import wb
+    from tests.test_gpu_fused import _mimic_tree
+    jobs = [(_mimic_tree(), 900), (synth.serial_chain(7, 5, seed=0), 1500), (synth.random_tree(12, 6, seed=1), 700)]
+    robots = [_robot(rb) for rb, _ in jobs]
+    plan = wb.Plan(robots, [B for _, B in jobs])
+    rng = np.random.default_rng(90)
+    ios, sts, fexts = [], [], []
+    for i, (rb, B) in enumerate(jobs):
+        st = synth.states(rb, B, seed=91 + i)
+        n = rb.n_dof
+        io = dict(q=P.dev(st.q), qd=P.dev(st.qd), qdd=P.dev(st.qdd))
+        for key in ("tau", "g_q", "g_qd", "g_qdd"):
+            io[key] = torch.empty((n, B), device="cuda")
+        io["cost"] = torch.empty(B, device="cuda")
+        io["argmax"] = torch.empty(B, dtype=torch.int32, device="cuda")
+        io["n_coll"] = torch.empty(B, dtype=torch.int32, device="cuda")
+        fe = None
+        if i < 2:
+            fe = synth._f32(rng.normal(scale=2.0, size=(B, rb.n_links, 6)))
+            io["f_ext"] = torch.from_numpy(np.ascontiguousarray(np.transpose(fe, (1, 2, 0)), dtype=np.float32)).cuda()
+            io["g_fext"] = torch.empty((rb.n_links, 6, B), device="cuda")
+        ios.append(io)
+        sts.append(st)
+        fexts.append(fe)
+    plan.run(ios, 1e-3, 0.01, 1.0, 0.0)
+    torch.cuda.synchronize()
+    for (rb, B), st, io, fe in zip(jobs, sts, ios, fexts):
+        _oracle_check(oracle, rb, st, io, f"plan-ext {rb.name} B={B}", fext=fe)
