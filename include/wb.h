@@ -375,6 +375,28 @@ int wb_robot_set_tune(wb_robot *robot, const wb_tune *tune);
 int wb_robot_set_link_inertia(wb_robot *robot, int32_t link, float mass, const float *com, const float *inertia);
 int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune);
 
+/* -------------------------------------------------- distance transform
+ * Exact Euclidean distance transform of a site grid (Sec. 5, "Stage 2:
+ * Distance Propagation": the dense ESDF's nearest-site assignment, computed
+ * by the separable three-pass PBA+ decomposition with Maurer's dominance
+ * test, in integer arithmetic).  Grids are [nz][ny][nx], x fastest, each
+ * extent in [1, WB_EDT_MAX_DIM].
+ *   sites[nz][ny][nx] (device, uint8): nonzero voxels are sites;
+ *   nearest[nz][ny][nx] (int32, NULL to skip): a nearest site, packed
+ *     x | y << 10 | z << 20, or -1 when the grid has no site (any one of
+ *     several equidistant sites);
+ *   dist[nz][ny][nx] (float, NULL to skip): voxel_size * its Euclidean
+ *     distance, +inf when there is no site;
+ *   workspace: wb_edt_workspace_bytes bytes of device memory, 256-byte
+ *     aligned, reused across calls on one stream.
+ * Five launches whose shapes depend only on the grid size; never allocates
+ * or synchronizes.  WB_ERR_INVALID_ARG for extents outside the range, a
+ * non-finite or negative voxel_size, or missing pointers. */
+#define WB_EDT_MAX_DIM 1024
+int wb_edt_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, size_t *bytes);
+int wb_edt(int32_t nx, int32_t ny, int32_t nz, const uint8_t *sites, float voxel_size, int32_t *nearest,
+           float *dist, void *workspace, hipStream_t stream);
+
 /* ------------------------------------------------ uneven multi-robot batches
  * A plan runs the fused iteration for several robots, each with its own
  * batch size, in one persistent launch (suitable for HIP graph capture; the

@@ -1007,6 +1007,39 @@ int wb_kinematics_backward(const wb_robot *robot, int64_t B, const float *q, con
     return finish(wb::launch_kinematics_backward(robot->kin, B, q, g, stream), "wb_kinematics_backward launch");
 }
 
+int wb_edt_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, size_t *bytes) {
+    if (!bytes) return fail(WB_ERR_INVALID_ARG, "bytes is null");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > WB_EDT_MAX_DIM || ny > WB_EDT_MAX_DIM || nz > WB_EDT_MAX_DIM)
+        return fail(WB_ERR_INVALID_ARG, "grid %d x %d x %d: extents must be in [1, %d]", nx, ny, nz, WB_EDT_MAX_DIM);
+    const size_t N = (size_t)nx * ny * nz;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    *bytes = 2 * up(N * 4) + up((size_t)nx * nz * 4) + up((size_t)ny * nz * 4);
+    return WB_OK;
+}
+
+int wb_edt(int32_t nx, int32_t ny, int32_t nz, const uint8_t *sites, float voxel_size, int32_t *nearest, float *dist,
+           void *workspace, hipStream_t stream) {
+    size_t need = 0;
+    WB_TRY(wb_edt_workspace_bytes(nx, ny, nz, &need));
+    if (!std::isfinite(voxel_size) || voxel_size < 0.0f)
+        return fail(WB_ERR_INVALID_ARG, "voxel_size must be finite and >= 0");
+    if (!sites) return fail(WB_ERR_INVALID_ARG, "sites is null");
+    if (!workspace) return fail(WB_ERR_INVALID_ARG, "workspace is null");
+    if (((uintptr_t)workspace & 255) != 0) return fail(WB_ERR_INVALID_ARG, "workspace is not 256-byte aligned");
+    WB_TRY(check_ptr(nearest, "nearest", false));
+    WB_TRY(check_ptr(dist, "dist", false));
+    const size_t N = (size_t)nx * ny * nz;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char *w = static_cast<char *>(workspace);
+    int32_t *A = reinterpret_cast<int32_t *>(w);
+    int32_t *Bt = reinterpret_cast<int32_t *>(w + up(N * 4));
+    int32_t *kY = reinterpret_cast<int32_t *>(w + 2 * up(N * 4));
+    int32_t *kX = reinterpret_cast<int32_t *>(w + 2 * up(N * 4) + up((size_t)nx * nz * 4));
+    // without a nearest-site output the last pass writes into A, free by then
+    return finish(wb::launch_edt(nx, ny, nz, sites, voxel_size, nearest ? nearest : A, dist, A, Bt, kY, kX, stream),
+                  "wb_edt launch");
+}
+
 int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune) {
     WB_TRY(check_robot(robot));
     if (!tune) return fail(WB_ERR_INVALID_ARG, "tune is null");

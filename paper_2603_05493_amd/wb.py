@@ -222,6 +222,42 @@ def wb_kinematics_backward(robot: Robot, q, g_tool_pose=None, g_com=None, g_q=No
     return g_q
 
 
+EDT_NONE = -1
+
+
+def edt_workspace_bytes(nx: int, ny: int, nz: int) -> int:
+    n = C.c_size_t()
+    check(lib().wb_edt_workspace_bytes(int(nx), int(ny), int(nz), C.byref(n)))
+    return n.value
+
+
+def wb_edt(sites: torch.Tensor, voxel_size: float = 1.0, nearest=True, dist=True, workspace=None):
+    """Exact Euclidean distance transform of a uint8 site grid [nz, ny, nx]:
+    returns (nearest [nz, ny, nx] int32 packed x | y << 10 | z << 20 or -1,
+    dist [nz, ny, nx] float32, voxel_size * distance or +inf); either may be
+    False to skip or a tensor to fill."""
+    if sites.dim() != 3:
+        raise ValueError("sites must be [nz, ny, nx]")
+    nz, ny, nx = sites.shape
+    _chk(sites, "sites", (nz, ny, nx), torch.uint8)
+    dev = sites.device
+    if nearest is True:
+        nearest = torch.empty((nz, ny, nx), dtype=torch.int32, device=dev)
+    if dist is True:
+        dist = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
+    nearest = None if nearest is False else nearest
+    dist = None if dist is False else dist
+    _chk(nearest, "nearest", (nz, ny, nx), torch.int32)
+    _chk(dist, "dist", (nz, ny, nx))
+    need = edt_workspace_bytes(nx, ny, nz)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    if workspace.numel() * workspace.element_size() < need:
+        raise ValueError("workspace too small")
+    check(lib().wb_edt(nx, ny, nz, _p(sites), float(voxel_size), _p(nearest), _p(dist), _p(workspace), _stream()))
+    return nearest, dist
+
+
 def wb_rnea(robot: Robot, q, qd, qdd, tau=None, cache=None, f_ext=None):
     """tau [n,B] (and the cache for the backward); f_ext [L,6,B] external
     link forces in link coordinates (moment, force), or None."""

@@ -1,0 +1,146 @@
+"""GPU parity of the exact distance transform (wb_edt) against the oracle's
+definition (brute force over sites).
+
+The squared distance to the nearest site is unique and an integer, so it is
+compared exactly; the nearest site may not be unique, so the reported one
+is checked to be a site at that squared distance.  Distances are
+voxel_size * sqrt(d2) in FP32: compared to 2 ulp."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import edt as O
+from paper_2603_05493_amd import sitegrid
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(m, voxel_size=0.02, **kw):
+    from paper_2603_05493_amd import wb
+    near, dist = wb.wb_edt(torch.from_numpy(np.ascontiguousarray(m)).cuda(), voxel_size, **kw)
+    torch.cuda.synchronize()
+    return (None if near is None else near.cpu().numpy()), (None if dist is None else dist.cpu().numpy())
+
+
+def _check(m, near, dist, d2, voxel_size, pts=None):
+    """near/dist/d2 at the points pts [P, 3] (z, y, x), or on the whole grid."""
+    if pts is None:
+        pts = np.argwhere(np.ones(m.shape, bool))
+    z, y, x = pts[:, 0], pts[:, 1], pts[:, 2]
+    if not m.any():
+        assert np.all(near[z, y, x] == -1) and np.all(np.isinf(dist[z, y, x]))
+        return
+    c = near[z, y, x].astype(np.int64)
+    assert np.all(c >= 0)
+    sx, sy, sz = c & 1023, (c >> 10) & 1023, c >> 20
+    assert np.all(m[sz, sy, sx] != 0), "reported nearest voxel is not a site"
+    g2 = (x - sx) ** 2 + (y - sy) ** 2 + (z - sz) ** 2
+    np.testing.assert_array_equal(g2, d2)
+    ref = (voxel_size * np.sqrt(d2.astype(np.float64))).astype(np.float32)
+    got = dist[z, y, x]
+    ulp = np.spacing(np.maximum(ref, np.float32(1e-30)))
+    assert np.all(np.abs(got.astype(np.float64) - ref) <= 2 * ulp + (ref == 0) * 0.0)
+
+
+@pytest.mark.parametrize("shape,p,seed", [((7, 9, 11), 0.05, 0), ((16, 5, 23), 0.01, 1), ((12, 12, 12), 0.3, 2),
+                                          ((1, 1, 40), 0.1, 3), ((3, 30, 1), 0.1, 4), ((5, 6, 70), 0.002, 5),
+                                          ((9, 33, 35), 0.02, 8), ((33, 65, 31), 0.001, 9)])
+def test_edt_random_grids(shape, p, seed):
+    m = sitegrid.random_sites(*shape, p=p, seed=seed)
+    if not m.any():
+        m[shape[0] // 2, 0, shape[2] - 1] = 1
+    near, dist = _run(m)
+    _check(m, near, dist, O.d2_grid(m).reshape(-1), 0.02)
+
+
+def test_edt_room_grid_whole():
+    m = sitegrid.room(48, 40, 24, seed=2)
+    near, dist = _run(m, voxel_size=0.02)
+    _check(m, near, dist, O.d2_grid(m).reshape(-1), 0.02)
+
+
+def test_edt_room_full_size_sampled():
+    """The 256 x 256 x 128 room (a 5.12 m room at 20 mm), sampled voxels
+    against the definition."""
+    m = sitegrid.room(256, 256, 128, seed=0)
+    near, dist = _run(m, voxel_size=0.02)
+    rng = np.random.default_rng(1)
+    pts = np.stack([rng.integers(0, n, 400) for n in m.shape], 1)
+    # and the far corners, where the distance is largest
+    pts = np.concatenate([pts, np.array([[127, 255, 255], [127, 0, 255], [60, 255, 0], [127, 128, 128]])])
+    _check(m, near, dist, O.d2_at(m, pts), 0.02, pts)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1024), (1, 1024, 1), (1024, 1, 1), (2, 3, 1024), (1, 1, 1)])
+def test_edt_extreme_extents(shape):
+    rng = np.random.default_rng(sum(shape))
+    m = (rng.random(shape) < 0.003).astype(np.uint8)
+    m.reshape(-1)[rng.integers(0, m.size)] = 1
+    near, dist = _run(m, voxel_size=1.0)
+    _check(m, near, dist, O.d2_grid(m).reshape(-1), 1.0)
+
+
+def test_edt_empty_and_full_grids():
+    e = np.zeros((5, 6, 7), np.uint8)
+    near, dist = _run(e)
+    assert np.all(near == -1) and np.all(np.isinf(dist))
+    f = np.ones((5, 6, 7), np.uint8)
+    near, dist = _run(f)
+    assert np.all(dist == 0)
+    z, y, x = np.meshgrid(np.arange(5), np.arange(6), np.arange(7), indexing="ij")
+    np.testing.assert_array_equal(near, x | (y << 10) | (z << 20))
+
+
+def test_edt_optional_outputs_and_workspace_reuse():
+    from paper_2603_05493_amd import wb
+    big = sitegrid.room(64, 48, 32, seed=4)
+    small = sitegrid.random_sites(6, 7, 9, p=0.05, seed=5)
+    small[0, 0, 0] = 1
+    ws = torch.empty(wb.edt_workspace_bytes(64, 48, 32), dtype=torch.uint8, device="cuda")
+    n_only, none_d = wb.wb_edt(torch.from_numpy(big).cuda(), 0.02, dist=False, workspace=ws)
+    none_n, d_only = wb.wb_edt(torch.from_numpy(big).cuda(), 0.02, nearest=False, workspace=ws)
+    near_s, dist_s = wb.wb_edt(torch.from_numpy(small).cuda(), 0.5, workspace=ws)   # smaller grid, same workspace
+    torch.cuda.synchronize()
+    assert none_d is None and none_n is None
+    near_b, dist_b = _run(big)
+    np.testing.assert_array_equal(n_only.cpu().numpy(), near_b)
+    np.testing.assert_array_equal(d_only.cpu().numpy(), dist_b)
+    _check(small, near_s.cpu().numpy(), dist_s.cpu().numpy(), O.d2_grid(small).reshape(-1), 0.5)
+
+
+def test_edt_graph_replays_match_eager():
+    from paper_2603_05493_amd import wb
+    m = torch.from_numpy(sitegrid.room(64, 64, 32, seed=6)).cuda()
+    ws = torch.empty(wb.edt_workspace_bytes(64, 64, 32), dtype=torch.uint8, device="cuda")
+    near = torch.empty((32, 64, 64), dtype=torch.int32, device="cuda")
+    dist = torch.empty((32, 64, 64), device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        wb.wb_edt(m, 0.02, nearest=near, dist=dist, workspace=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ref_n, ref_d = near.clone(), dist.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        wb.wb_edt(m, 0.02, nearest=near, dist=dist, workspace=ws)
+    for _ in range(3):
+        near.fill_(7)
+        dist.fill_(-1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(near, ref_n) and torch.equal(dist, ref_d)
+
+
+def test_edt_rejects_bad_arguments():
+    from paper_2603_05493_amd import _abi, wb
+    for dims in ((0, 4, 4), (4, 1025, 4), (-1, 2, 2)):
+        with pytest.raises(_abi.WbError):
+            wb.edt_workspace_bytes(*dims)
+    m = torch.zeros((4, 4, 4), dtype=torch.uint8, device="cuda")
+    with pytest.raises(_abi.WbError):
+        wb.wb_edt(m, float("nan"))
+    with pytest.raises(_abi.WbError):
+        wb.wb_edt(m, -1.0)
+    with pytest.raises(ValueError):
+        wb.wb_edt(m.float(), 1.0)
