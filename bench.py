@@ -84,6 +84,8 @@ def parse():
                     help="skip the uneven multi-tree batch measurement")
     ap.add_argument("--no-kinematics", dest="kinematics", action="store_false",
                     help="skip the kinematics-outputs line (tool poses, CoM, Jacobians)")
+    ap.add_argument("--no-edt", dest="edt", action="store_false",
+                    help="skip the distance-transform line")
     ap.add_argument("--no-bspline", dest="bspline", action="store_false",
                     help="skip the B-spline control-point iteration measurement")
     return ap.parse_args()
@@ -243,6 +245,8 @@ def main():
         out["uneven_batch"] = bench_uneven(args)
     if args.kinematics and robot.kinematics_supported:
         out["kinematics"] = bench_kinematics(args, robot, q0)
+    if args.edt:
+        out["edt"] = bench_edt(args)
     if args.bspline and B % 48 == 0:
         out["bspline_front_end"] = bench_bspline(args, robot, B // 48)
     if not args.no_cpu:
@@ -336,6 +340,39 @@ def bench_kinematics(args, robot, q, reps: int = 50):
             "forward": dict(line(fwd, fwd_bytes, m["forward_bytes"]),
                             outputs="tool poses, com, tool Jacobians, com Jacobian"),
             "backward": dict(line(bwd, bwd_bytes, m["backward_bytes"]), outputs="d(tool-pose and com loss)/dq")}
+
+
+def bench_edt(args, reps: int = 20):
+    """The exact distance transform of a room-scan site grid: 256 x 256 x 128
+    voxels (a 5.12 m x 5.12 m x 2.56 m room at the paper's 20 mm ESDF voxel),
+    nearest site and distance for every voxel, five launches timed together
+    with HIP events on the launching stream."""
+    import torch
+    from paper_2603_05493_amd import sitegrid, wb
+    nx, ny, nz = 256, 256, 128
+    m = torch.from_numpy(sitegrid.room(nx, ny, nz, seed=0)).cuda()
+    ws = torch.empty(wb.edt_workspace_bytes(nx, ny, nz), dtype=torch.uint8, device="cuda")
+    near = torch.empty((nz, ny, nx), dtype=torch.int32, device="cuda")
+    dist = torch.empty((nz, ny, nx), device="cuda")
+    run = lambda: wb.wb_edt(m, 0.02, nearest=near, dist=dist, workspace=ws)
+    for _ in range(3):
+        run()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        run()
+    e1.record(s)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    N = nx * ny * nz
+    # site grid read, A written; A read, Bt written; Bt read, nearest and dist written
+    nbytes = N * (1 + 4 + 4 + 4 + 4 + 4 + 4)
+    return {"grid": [nx, ny, nz], "voxels": N, "sites": int(m.sum().item()), "voxel_size_m": 0.02,
+            "ms": t * 1e3, "voxels_per_s": N / t, "algorithmic_bytes": nbytes,
+            "roofline": {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                         "frac": nbytes / t / 1e9 / PEAK_HBM_GBPS, "traffic": None},
+            "form": "five launches: z flood, y envelope, y assign, x envelope, x assign"}
 
 
 def bench_uneven(args):

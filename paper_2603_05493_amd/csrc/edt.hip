@@ -7,23 +7,22 @@
 //
 // Grid [nz][ny][nx], x fastest.  A site is stored packed as
 // x | y << 10 | z << 20 (coordinates below 1024), NONE (-1) when there is
-// none.  Five launches, fixed for a grid size (graph-capturable, no atomics):
-//   1. along z, thread per (x, y): a forward flood keeps the last site seen,
-//      a backward flood the next one; the closer wins -> A [nz][ny][nx];
-//   2. along y, thread per (x, z): the lower envelope of the parabolas
-//      (y - y')^2 + (z - z*)^2 of the column sites, built as a stack in place
-//      in the line of A (entry k lands at position k <= the position being
-//      read), with its size in kY;
-//   3. along y, thread per (x, z, segment of SEG voxels): a binary search
-//      finds the envelope entry that owns the segment's first voxel, then a
-//      walk assigns the segment -> Bt [nz][nx][ny] (transposed, so the x pass
-//      reads along its lines' contiguous axis);
-//   4. along x, thread per (y, z): the envelope of (x - x')^2 + h, h the
-//      squared y, z offsets of the plane's nearest site, in place in Bt, kX;
-//   5. along x, thread per (y, z, segment): as 3 -> nearest site and
-//      voxel_size * sqrt(d2) in [nz][ny][nx].
-// Lanes run along a contiguous axis for every line read: x in passes 1-3,
-// y in passes 4-5.
+// none.  The axes are taken in the order x, y, z so that every pass keeps
+// its lanes along x, the contiguous axis: loads and stores are coalesced
+// and no transpose is needed.  Three launches, fixed for a grid size
+// (graph-capturable, no atomics):
+//   1. along x, one wavefront per row (y, z): the nearest site of the row,
+//      from a forward and a backward flood, each an inclusive max-scan over
+//      the wavefront (DPP; the backward one toward lower lanes) carried
+//      across 64-voxel chunks -> A;
+//   2. along y, a workgroup per tile of lines (x0 .. x0+TL-1, z) held in
+//      LDS: the lower envelope of the parabolas (y - y')^2 + (x - x*)^2 of
+//      the row sites, built band by band and merged at the band junctions
+//      as in PBA+, then every voxel assigned its envelope entry -> B;
+//   3. along z, the same on tiles (x0 .. x0+TL-1, y) with the parabolas
+//      (z - z')^2 + (x - x*)^2 + (y - y*)^2 -> the nearest site and
+//      voxel_size * sqrt(d2).
+// Each pass reads its input grid once and writes its output once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -33,171 +32,235 @@ namespace wb {
 namespace {
 
 constexpr int32_t EDT_NONE = -1;
-constexpr int EDT_SEG = 32;      // voxels per thread in the assignment passes
-constexpr int EDT_CHUNK = 8;     // loads issued ahead in the sequential passes
+constexpr int EDT_BIG = 1 << 20; // above any coordinate
 
 __device__ __forceinline__ int32_t pack(int x, int y, int z) { return x | (y << 10) | (z << 20); }
 __device__ __forceinline__ int cx(int32_t c) { return c & 1023; }
 __device__ __forceinline__ int cy(int32_t c) { return (c >> 10) & 1023; }
 __device__ __forceinline__ int cz(int32_t c) { return c >> 20; }
 
-// Position along the line and the squared offset across it, for a line of
-// the y pass (fixed x, z) or of the x pass (fixed y, z).
-template <int AX>
-__device__ __forceinline__ int pos(int32_t c) { return AX == 1 ? cy(c) : cx(c); }
-template <int AX>
-__device__ __forceinline__ int height(int32_t c, int qy, int qz) {
-    const int dz = qz - cz(c);
-    if (AX == 1) return dz * dz;
-    const int dy = qy - cy(c);
-    return dy * dy + dz * dz;
+// Inclusive max-scan over the 64 lanes of a wavefront, for values >= 0 (0 is
+// the identity): row_shr 1, 2, 4, 8 inside each row of 16, then row_bcast15
+// and row_bcast31 carry the row maxima upward.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_up(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ int wave_max_scan(int v) {
+    v = max(v, dpp_up<0x111>(v));
+    v = max(v, dpp_up<0x112>(v));
+    v = max(v, dpp_up<0x114>(v));
+    v = max(v, dpp_up<0x118>(v));
+    v = max(v, dpp_up<0x142, 0xa>(v));
+    v = max(v, dpp_up<0x143, 0xc>(v));
+    return v;
+}
+// Inclusive max-scan toward lower lanes (lane i: max over lanes >= i):
+// row_shl 1, 2, 4, 8 inside each row, then the maxima of the rows above,
+// read from the first lane of each row.
+__device__ __forceinline__ int wave_max_suffix_scan(int v, int lane) {
+    v = max(v, dpp_up<0x101>(v));
+    v = max(v, dpp_up<0x102>(v));
+    v = max(v, dpp_up<0x104>(v));
+    v = max(v, dpp_up<0x108>(v));
+    const int r1 = __builtin_amdgcn_readlane(v, 16), r2 = __builtin_amdgcn_readlane(v, 32),
+              r3 = __builtin_amdgcn_readlane(v, 48);
+    const int row = lane >> 4;
+    if (row < 3) v = max(v, r3);
+    if (row < 2) v = max(v, r2);
+    if (row < 1) v = max(v, r1);
+    return v;
 }
 
-// Maurer's test: with positions ua < ub < uc, b never attains the minimum of
-// the three parabolas (t - u)^2 + h when the a/b crossing is not left of
-// the b/c crossing.
-__device__ __forceinline__ bool dominated(int ua, int ha, int ub, int hb, int uc, int hc) {
-    const int64_t ab = (int64_t)(ub * ub + hb - ua * ua - ha) * (uc - ub);
-    const int64_t bc = (int64_t)(uc * uc + hc - ub * ub - hb) * (ub - ua);
-    return ab >= bc;
-}
-
-struct LineGeom {
-    int64_t base, stride;   // element i of the line is at base + i * stride
-    int n;                  // line length
-    int qy, qz;             // fixed coordinates of the line (qy unused in the y pass)
-};
-
-template <int AX>
-__device__ __forceinline__ LineGeom line_of(int64_t t, int nx, int ny, int nz) {
-    LineGeom g;
-    if (AX == 1) {   // line (x, z) of A, along y
-        const int x = (int)(t % nx), z = (int)(t / nx);
-        g.base = (int64_t)z * ny * nx + x;
-        g.stride = nx;
-        g.n = ny;
-        g.qy = 0;
-        g.qz = z;
-    } else {         // line (y, z) of Bt, along x
-        const int y = (int)(t % ny), z = (int)(t / ny);
-        g.base = (int64_t)z * nx * ny + y;
-        g.stride = ny;
-        g.n = nx;
-        g.qy = y;
-        g.qz = z;
-    }
-    return g;
-}
-
-// ---- pass 1: nearest site along z
-__global__ void __launch_bounds__(256) k_edt_z(const uint8_t *__restrict__ sites, int32_t *__restrict__ A, int nx,
+// ---- pass 1: nearest site along x, one wavefront per row (y, z)
+__global__ void __launch_bounds__(256) k_edt_x(const uint8_t *__restrict__ sites, int32_t *__restrict__ A, int nx,
                                                int ny, int nz) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (int64_t)nx * ny) return;
-    const int x = (int)(t % nx), y = (int)(t / nx);
-    const int64_t plane = (int64_t)nx * ny;
-    int last = EDT_NONE;
-    for (int z0 = 0; z0 < nz; z0 += EDT_CHUNK) {
-        uint8_t m[EDT_CHUNK];
-#pragma unroll
-        for (int j = 0; j < EDT_CHUNK; ++j) m[j] = z0 + j < nz ? sites[(z0 + j) * plane + t] : 0;
-#pragma unroll
-        for (int j = 0; j < EDT_CHUNK; ++j)
-            if (z0 + j < nz) {
-                if (m[j]) last = z0 + j;
-                A[(z0 + j) * plane + t] = last;
-            }
+    const int64_t w = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= (int64_t)ny * nz) return;   // uniform over the wavefront
+    const int y = (int)(w % ny), z = (int)(w / ny);
+    const int64_t base = w * nx;
+    // forward: 1 + the last site at or before x (0: none)
+    int carry = 0;
+    for (int x0 = 0; x0 < nx; x0 += 64) {
+        const int x = x0 + lane;
+        const int s = x < nx && sites[base + x] ? x + 1 : 0;
+        const int v = max(wave_max_scan(s), carry);
+        carry = __builtin_amdgcn_readlane(v, 63);
+        if (x < nx) A[base + x] = v - 1;
     }
-    int next = EDT_NONE;
-    for (int z1 = nz; z1 > 0; z1 -= EDT_CHUNK) {
-        int32_t f[EDT_CHUNK];
-#pragma unroll
-        for (int j = 0; j < EDT_CHUNK; ++j) f[j] = z1 - 1 - j >= 0 ? A[(z1 - 1 - j) * plane + t] : EDT_NONE;
-#pragma unroll
-        for (int j = 0; j < EDT_CHUNK; ++j) {
-            const int z = z1 - 1 - j;
-            if (z < 0) continue;
-            if (f[j] == z) next = z;
-            const int prev = f[j];
-            const int best = prev < 0 ? next : (next < 0 ? prev : (z - prev <= next - z ? prev : next));
-            A[z * plane + t] = best < 0 ? EDT_NONE : pack(x, y, best);
+    // backward: BIG - the next site at or after x (0: none); each lane reads
+    // back only what it stored itself
+    carry = 0;
+    for (int x0 = ((nx - 1) >> 6) << 6; x0 >= 0; x0 -= 64) {
+        const int x = x0 + lane;
+        const int s = x < nx && sites[base + x] ? EDT_BIG - x : 0;
+        const int v = max(wave_max_suffix_scan(s, lane), carry);
+        carry = __builtin_amdgcn_readlane(v, 0);
+        if (x < nx) {
+            const int prev = A[base + x], next = v > 0 ? EDT_BIG - v : EDT_NONE;
+            const int best = prev < 0 ? next : (next < 0 ? prev : (x - prev <= next - x ? prev : next));
+            A[base + x] = best < 0 ? EDT_NONE : pack(best, y, z);
         }
     }
 }
 
-// ---- passes 2 and 4: the lower envelope of a line, in place
+// Positions along the line and squared cross offsets: AX == 1 runs along y
+// (a line (x, z); the candidate is the row's nearest site (x*, y', z)),
+// AX == 2 along z (a line (x, y); the candidate is the plane's nearest site
+// (x*, y*, z')).
 template <int AX>
-__global__ void __launch_bounds__(256) k_edt_envelope(int32_t *__restrict__ buf, int32_t *__restrict__ kcount,
-                                                      int nx, int ny, int nz) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t lines = AX == 1 ? (int64_t)nx * nz : (int64_t)ny * nz;
-    if (t >= lines) return;
-    const LineGeom g = line_of<AX>(t, nx, ny, nz);
-    int k = 0;
-    // the two top entries of the stack: position and height
-    int u1 = 0, h1 = 0, u2 = 0, h2 = 0;
-    for (int i0 = 0; i0 < g.n; i0 += EDT_CHUNK) {
-        int32_t c[EDT_CHUNK];
+__device__ __forceinline__ int pos(int32_t c) { return AX == 1 ? cy(c) : cz(c); }
+template <int AX>
+__device__ __forceinline__ int height(int32_t c, int qx, int qy) {
+    const int dx = qx - cx(c);
+    if (AX == 1) return dx * dx;
+    const int dy = qy - cy(c);
+    return dx * dx + dy * dy;
+}
+
+// A candidate at line position u with squared cross offset h is kept as
+// (u, g = u^2 + h).  Maurer's test: with positions ua < ub < uc, b never
+// attains the minimum of the three parabolas (t - u)^2 + h when the a/b
+// crossing is not left of the b/c crossing.
+__device__ __forceinline__ bool dominated(int ua, int ga, int ub, int gb, int uc, int gc) {
+    return (int64_t)(gb - ga) * (uc - ub) >= (int64_t)(gc - gb) * (ub - ua);
+}
+
+// ---- passes 2 and 3: one workgroup per tile of TL lines (consecutive x)
+// at a fixed z (AX == 1) or y (AX == 2), the tile resident in LDS as
+// ent[p * TL + l] (position p, line l).  Three phases, PBA+'s banding:
+//   bands:  thread (l, b) stacks the envelope of band b of line l in place
+//           from the band's first position (256 / TL bands per line);
+//   merge:  thread l merges its line's band envelopes left to right; only
+//           the junctions can change (entries of the envelope so far that a
+//           band's first entries dominate, and first entries of the band
+//           the junction dominates), the rest moves down, so the line's
+//           envelope ends up packed at positions [0, K);
+//   assign: thread (l, s) takes segment s of line l: a binary search finds
+//           the envelope entry owning the segment's first voxel, a walk the
+//           rest, and the segment is written to the next pass's grid (and
+//           the distances after the last pass).
+template <int AX, int TL>
+__global__ void __launch_bounds__(256) k_edt_tile(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                  float *__restrict__ dist, float voxel_size, int nx, int ny,
+                                                  int nz) {
+    extern __shared__ int32_t ent[];
+    constexpr int NB = 256 / TL;   // bands (and assignment segments) per line
+    __shared__ int32_t bcnt[256], ksz[TL];
+    const int n = AX == 1 ? ny : nz;
+    const int ntx = (nx + TL - 1) / TL;
+    const int x0 = (int)(blockIdx.x % ntx) * TL;
+    const int o = (int)(blockIdx.x / ntx);   // z for AX == 1, y for AX == 2
+    // element p of line x: AX == 1 (x, p, o), AX == 2 (x, o, p)
+    auto gidx = [&](int p, int x) -> uint32_t {
+        return AX == 1 ? ((uint32_t)o * ny + p) * nx + x : ((uint32_t)p * ny + o) * nx + x;
+    };
+    // the tile into LDS, eight loads in flight per thread
+    for (int i0 = threadIdx.x; i0 < n * TL; i0 += 256 * 8) {
+        int32_t v[8];
 #pragma unroll
-        for (int j = 0; j < EDT_CHUNK; ++j) c[j] = i0 + j < g.n ? buf[g.base + (i0 + j) * g.stride] : EDT_NONE;
+        for (int j = 0; j < 8; ++j) {
+            const int i = i0 + 256 * j;
+            const int p = i / TL, x = x0 + (i - p * TL);
+            v[j] = i < n * TL && x < nx ? in[gidx(p, x)] : EDT_NONE;
+        }
 #pragma unroll
-        for (int j = 0; j < EDT_CHUNK; ++j) {
-            if (c[j] < 0) continue;
-            const int uc = pos<AX>(c[j]), hc = height<AX>(c[j], g.qy, g.qz);
-            while (k >= 2 && dominated(u1, h1, u2, h2, uc, hc)) {
+        for (int j = 0; j < 8; ++j)
+            if (i0 + 256 * j < n * TL) ent[i0 + 256 * j] = v[j];
+    }
+    __syncthreads();
+    const int l = threadIdx.x % TL, sidx = threadIdx.x / TL;
+    const int qx = x0 + l, qy = o;
+    const int bw = (n + NB - 1) / NB;
+    // ---- bands
+    {
+        const int p0 = sidx * bw, p1 = min(p0 + bw, n);
+        int k = 0, u1 = 0, g1 = 0, u2 = 0, g2 = 0;
+        for (int p = p0; p < p1; ++p) {
+            const int32_t c = ent[p * TL + l];
+            if (c < 0) continue;
+            const int gc = p * p + height<AX>(c, qx, qy);   // a candidate sits at its own position
+            while (k >= 2 && dominated(u2, g2, u1, g1, p, gc)) {
                 --k;
-                u2 = u1;
-                h2 = h1;
+                u1 = u2;
+                g1 = g2;
                 if (k >= 2) {
-                    const int32_t e = buf[g.base + (int64_t)(k - 2) * g.stride];
-                    u1 = pos<AX>(e);
-                    h1 = height<AX>(e, g.qy, g.qz);
+                    const int32_t e = ent[(p0 + k - 2) * TL + l];
+                    u2 = pos<AX>(e);
+                    g2 = u2 * u2 + height<AX>(e, qx, qy);
                 }
             }
-            buf[g.base + (int64_t)k * g.stride] = c[j];   // k <= i0 + j: that input is consumed
+            ent[(p0 + k) * TL + l] = c;   // p0 + k <= p: that input is consumed
             ++k;
-            u1 = u2;
-            h1 = h2;
-            u2 = uc;
-            h2 = hc;
+            u2 = u1;
+            g2 = g1;
+            u1 = p;
+            g1 = gc;
         }
+        bcnt[sidx * TL + l] = k;
     }
-    kcount[t] = k;
-}
-
-// ---- passes 3 and 5: assign every voxel of a segment its envelope entry
-template <int AX>
-__global__ void __launch_bounds__(256) k_edt_assign(const int32_t *__restrict__ buf, const int32_t *__restrict__ kcount,
-                                                    int32_t *__restrict__ out, float *__restrict__ dist,
-                                                    float voxel_size, int nx, int ny, int nz) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int n = AX == 1 ? ny : nx;            // line length
-    const int m = AX == 1 ? nx : ny;            // lines per z slice, consecutive in t
-    const int nseg = (n + EDT_SEG - 1) / EDT_SEG;
-    if (t >= (int64_t)m * nseg * nz) return;
-    const int a = (int)(t % m);
-    const int64_t r = t / m;
-    const int seg = (int)(r % nseg), z = (int)(r / nseg);
-    const int64_t line = (int64_t)z * m + a;
-    const LineGeom g = line_of<AX>(line, nx, ny, nz);
-    const int k = kcount[line];
-    const int t0 = seg * EDT_SEG, t1 = min(t0 + EDT_SEG, n);
-    // outputs: Bt [z][x][y] for the y pass, [z][y][x] for the x pass; both contiguous along t
-    const int64_t obase = AX == 1 ? ((int64_t)z * nx + a) * ny : ((int64_t)z * ny + a) * nx;
-    if (k == 0) {
+    __syncthreads();
+    // ---- merge
+    if (threadIdx.x < TL) {
+        auto ug = [&](int32_t c, int &u, int &gg) {
+            u = pos<AX>(c);
+            gg = u * u + height<AX>(c, qx, qy);
+        };
+        int K = 0, u1 = 0, g1 = 0, u2 = 0, g2 = 0;
+        for (int b = 0; b < NB; ++b) {
+            const int cb = bcnt[b * TL + l], p0 = b * bw;
+            int lo = 0;
+            while (lo < cb) {
+                int uc, gc;
+                ug(ent[(p0 + lo) * TL + l], uc, gc);
+                while (K >= 2 && dominated(u2, g2, u1, g1, uc, gc)) {
+                    --K;
+                    u1 = u2;
+                    g1 = g2;
+                    if (K >= 2) ug(ent[(K - 2) * TL + l], u2, g2);
+                }
+                if (K >= 1 && lo + 1 < cb) {
+                    int un, gn;
+                    ug(ent[(p0 + lo + 1) * TL + l], un, gn);
+                    if (dominated(u1, g1, uc, gc, un, gn)) {
+                        ++lo;
+                        continue;
+                    }
+                }
+                break;
+            }
+            for (int j = lo; j < cb; ++j) {   // destinations never pass their sources
+                const int32_t e = ent[(p0 + j) * TL + l];
+                ent[K * TL + l] = e;
+                ++K;
+                u2 = u1;
+                g2 = g1;
+                ug(e, u1, g1);
+            }
+        }
+        ksz[l] = K;
+    }
+    __syncthreads();
+    // ---- assign
+    const int x = x0 + l;
+    if (x >= nx) return;
+    const int K = ksz[l];
+    const int t0 = sidx * bw, t1 = min(t0 + bw, n);
+    if (t0 >= t1) return;
+    if (K == 0) {
         for (int s = t0; s < t1; ++s) {
-            out[obase + s] = EDT_NONE;
-            if (AX == 0 && dist) dist[obase + s] = INFINITY;
+            out[gidx(s, x)] = EDT_NONE;
+            if (dist) dist[gidx(s, x)] = INFINITY;
         }
         return;
     }
-    auto entry = [&](int i) { return buf[g.base + (int64_t)i * g.stride]; };
+    auto entry = [&](int i) { return ent[i * TL + l]; };
     auto f = [&](int32_t c, int s) {
         const int d = s - pos<AX>(c);
-        return d * d + height<AX>(c, g.qy, g.qz);
+        return d * d + height<AX>(c, qx, qy);
     };
-    // first entry i with f(i + 1, t0) > f(i, t0): the owner of t0
-    int lo = 0, hi = k - 1;
+    int lo = 0, hi = K - 1;   // the first entry i with f(i + 1, t0) > f(i, t0) owns t0
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (f(entry(mid + 1), t0) <= f(entry(mid), t0)) lo = mid + 1;
@@ -205,31 +268,43 @@ __global__ void __launch_bounds__(256) k_edt_assign(const int32_t *__restrict__ 
     }
     int ptr = lo;
     int32_t cur = entry(ptr);
-    int32_t nxt = ptr + 1 < k ? entry(ptr + 1) : cur;
+    int32_t nxt = ptr + 1 < K ? entry(ptr + 1) : cur;
     for (int s = t0; s < t1; ++s) {
-        while (ptr + 1 < k && f(nxt, s) <= f(cur, s)) {
+        while (ptr + 1 < K && f(nxt, s) <= f(cur, s)) {
             ++ptr;
             cur = nxt;
-            nxt = ptr + 1 < k ? entry(ptr + 1) : cur;
+            nxt = ptr + 1 < K ? entry(ptr + 1) : cur;
         }
-        out[obase + s] = cur;
-        if (AX == 0 && dist) dist[obase + s] = voxel_size * sqrtf((float)f(cur, s));
+        out[gidx(s, x)] = cur;
+        if (dist) dist[gidx(s, x)] = voxel_size * sqrtf((float)f(cur, s));
     }
+}
+
+// Tiles of TL lines with TL * n * 4 bytes of LDS at most 32 KB: 32 lines
+// up to n = 256, 16 up to 512, 8 up to 1024.
+template <int AX>
+bool tile_pass(const int32_t *in, int32_t *out, float *dist, float voxel_size, int nx, int ny, int nz, hipStream_t s) {
+    const int n = AX == 1 ? ny : nz, o_n = AX == 1 ? nz : ny;
+    const int tl = n <= 256 ? 32 : (n <= 512 ? 16 : 8);
+    const dim3 grid((unsigned)(((nx + tl - 1) / tl) * (int64_t)o_n));
+    const size_t lds = (size_t)n * tl * 4;
+    switch (tl) {
+        case 32: hipLaunchKernelGGL((k_edt_tile<AX, 32>), grid, dim3(256), lds, s, in, out, dist, voxel_size, nx, ny, nz); break;
+        case 16: hipLaunchKernelGGL((k_edt_tile<AX, 16>), grid, dim3(256), lds, s, in, out, dist, voxel_size, nx, ny, nz); break;
+        case 8: hipLaunchKernelGGL((k_edt_tile<AX, 8>), grid, dim3(256), lds, s, in, out, dist, voxel_size, nx, ny, nz); break;
+        default: return false;
+    }
+    return true;
 }
 
 }  // namespace
 
 hipError_t launch_edt(int nx, int ny, int nz, const uint8_t *sites, float voxel_size, int32_t *nearest, float *dist,
-                      int32_t *A, int32_t *Bt, int32_t *kY, int32_t *kX, hipStream_t s) {
-    const int64_t cols = (int64_t)nx * ny, ly = (int64_t)nx * nz, lx = (int64_t)ny * nz;
-    const int64_t ay = ly * ((ny + EDT_SEG - 1) / EDT_SEG), ax = lx * ((nx + EDT_SEG - 1) / EDT_SEG);
-    auto blocks = [](int64_t n) { return dim3((unsigned)((n + 255) / 256)); };
-    hipLaunchKernelGGL(k_edt_z, blocks(cols), dim3(256), 0, s, sites, A, nx, ny, nz);
-    hipLaunchKernelGGL(k_edt_envelope<1>, blocks(ly), dim3(256), 0, s, A, kY, nx, ny, nz);
-    hipLaunchKernelGGL(k_edt_assign<1>, blocks(ay), dim3(256), 0, s, A, kY, Bt, (float *)nullptr, voxel_size, nx, ny,
-                       nz);
-    hipLaunchKernelGGL(k_edt_envelope<0>, blocks(lx), dim3(256), 0, s, Bt, kX, nx, ny, nz);
-    hipLaunchKernelGGL(k_edt_assign<0>, blocks(ax), dim3(256), 0, s, Bt, kX, nearest, dist, voxel_size, nx, ny, nz);
+                      int32_t *A, int32_t *B, hipStream_t s) {
+    const int64_t rows = (int64_t)ny * nz;
+    hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((rows * 64 + 255) / 256)), dim3(256), 0, s, sites, A, nx, ny, nz);
+    if (!tile_pass<1>(A, B, nullptr, voxel_size, nx, ny, nz, s)) return hipErrorInvalidValue;
+    if (!tile_pass<2>(B, nearest, dist, voxel_size, nx, ny, nz, s)) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

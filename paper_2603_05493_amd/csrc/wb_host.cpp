@@ -1013,7 +1013,7 @@ int wb_edt_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, size_t *bytes) {
         return fail(WB_ERR_INVALID_ARG, "grid %d x %d x %d: extents must be in [1, %d]", nx, ny, nz, WB_EDT_MAX_DIM);
     const size_t N = (size_t)nx * ny * nz;
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    *bytes = 2 * up(N * 4) + up((size_t)nx * nz * 4) + up((size_t)ny * nz * 4);
+    *bytes = 2 * up(N * 4);
     return WB_OK;
 }
 
@@ -1032,11 +1032,9 @@ int wb_edt(int32_t nx, int32_t ny, int32_t nz, const uint8_t *sites, float voxel
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
     char *w = static_cast<char *>(workspace);
     int32_t *A = reinterpret_cast<int32_t *>(w);
-    int32_t *Bt = reinterpret_cast<int32_t *>(w + up(N * 4));
-    int32_t *kY = reinterpret_cast<int32_t *>(w + 2 * up(N * 4));
-    int32_t *kX = reinterpret_cast<int32_t *>(w + 2 * up(N * 4) + up((size_t)nx * nz * 4));
+    int32_t *Bg = reinterpret_cast<int32_t *>(w + up(N * 4));
     // without a nearest-site output the last pass writes into A, free by then
-    return finish(wb::launch_edt(nx, ny, nz, sites, voxel_size, nearest ? nearest : A, dist, A, Bt, kY, kX, stream),
+    return finish(wb::launch_edt(nx, ny, nz, sites, voxel_size, nearest ? nearest : A, dist, A, Bg, stream),
                   "wb_edt launch");
 }
 

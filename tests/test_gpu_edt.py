@@ -44,7 +44,8 @@ def _check(m, near, dist, d2, voxel_size, pts=None):
 
 @pytest.mark.parametrize("shape,p,seed", [((7, 9, 11), 0.05, 0), ((16, 5, 23), 0.01, 1), ((12, 12, 12), 0.3, 2),
                                           ((1, 1, 40), 0.1, 3), ((3, 30, 1), 0.1, 4), ((5, 6, 70), 0.002, 5),
-                                          ((9, 33, 35), 0.02, 8), ((33, 65, 31), 0.001, 9)])
+                                          ((9, 33, 35), 0.02, 8), ((33, 65, 31), 0.001, 9),
+                                          ((300, 3, 5), 0.01, 10), ((4, 400, 6), 0.005, 11)])
 def test_edt_random_grids(shape, p, seed):
     m = sitegrid.random_sites(*shape, p=p, seed=seed)
     if not m.any():
