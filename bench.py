@@ -48,9 +48,14 @@ FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h"
 
 # HBM traffic of the kinematics-outputs kernel, measured the same way
 # (profiles/k_kinematics_humanoid48_B24576.md; 4 tool frames), per launch.
-KIN_TRAFFIC_MEASURED = {"sources_sha1": "3547258eb4d75b287ae012f0d59d48fd04d8f48b", "states": 24576, "tools": 4,
-                        "forward_bytes": (5636.2 + 133209.9) * 1024, "backward_bytes": (9664.0 + 4608.0) * 1024}
+KIN_TRAFFIC_MEASURED = {"sources_sha1": "7a68d7553e40d4f68379fb8b6c3863b096b052d9", "states": 24576, "tools": 4,
+                        "forward_bytes": (5628.8 + 133206.8) * 1024, "backward_bytes": (9664.0 + 4608.0) * 1024}
 KIN_SOURCES = ("kinematics.hip", "kin.h", "lanes.h", "spatial.h", "wb_internal.h")
+# ... and of the three distance-transform launches on the 256 x 256 x 128 room
+# (profiles/edt_room256_kernel_trace.md), summed per transform.
+EDT_TRAFFIC_MEASURED = {"sources_sha1": "f45d8d48b2c7b95662d5d90ee9a5396cdacb0c55", "grid": [256, 256, 128],
+                        "bytes": (27508.2 + 32844.0 + 32849.2 + 32768.0 + 32768.0 + 65536.0) * 1024}
+EDT_SOURCES = ("edt.hip", "edt.h")
 
 
 def fused_sources_sha1(sources=FUSED_SOURCES) -> str:
@@ -371,7 +376,9 @@ def bench_edt(args, reps: int = 20):
     return {"grid": [nx, ny, nz], "voxels": N, "sites": int(m.sum().item()), "voxel_size_m": 0.02,
             "ms": t * 1e3, "voxels_per_s": N / t, "algorithmic_bytes": nbytes,
             "roofline": {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                         "frac": nbytes / t / 1e9 / PEAK_HBM_GBPS, "traffic": None},
+                         "frac": nbytes / t / 1e9 / PEAK_HBM_GBPS,
+                         "traffic": EDT_TRAFFIC_MEASURED["bytes"]
+                         if fused_sources_sha1(EDT_SOURCES) == EDT_TRAFFIC_MEASURED["sources_sha1"] else None},
             "form": "five launches: z flood, y envelope, y assign, x envelope, x assign"}
 
 

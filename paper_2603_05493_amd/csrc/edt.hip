@@ -26,7 +26,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "wb_internal.h"
+#include "edt.h"
 
 namespace wb {
 namespace {

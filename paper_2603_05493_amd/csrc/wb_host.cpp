@@ -1,6 +1,7 @@
 // Host side of libwb: descriptor validation, derived kernel tables, device
 // upload and the extern "C" entry points declared in include/wb.h.
 #include "wb.h"
+#include "edt.h"
 #include "kin.h"
 #include "wb_internal.h"
 

@@ -135,11 +135,6 @@ struct PlanArgs {
 hipError_t launch_fused(const FusedArgs &a, hipStream_t s);
 hipError_t launch_plan(const PlanArgs &a, int nmax, int n_wg, size_t lds, bool ext, hipStream_t s);
 
-// Exact distance transform of a site grid (edt.hip); A and B hold nx*ny*nz
-// ints each.
-hipError_t launch_edt(int nx, int ny, int nz, const uint8_t *sites, float voxel_size, int32_t *nearest, float *dist,
-                      int32_t *A, int32_t *B, hipStream_t s);
-
 // Kernel launchers (each defined next to its kernels).
 hipError_t launch_fk(const DevRobot &rb, int64_t B, const float *q, float *pose, float *spheres,
                      hipStream_t s);
