@@ -88,7 +88,8 @@ class FusedIteration:
                  torque_weight: float = 1e-3, margin: float = 0.01, hinge_weight: float = 1.0,
                  lr: float = 0.0, outputs: bool = True):
         if not robot.fused_supported:
-            raise ValueError("robot not supported by the fused iteration (needs <= 64 links, no mimic joints)")
+            raise ValueError("robot not supported by the fused iteration (needs <= 64 links and its sweep "
+                             "tables within the LDS budget)")
         self.robot, self.B = robot, B
         self.w, self.tw, self.margin, self.hw, self.lr = w, torque_weight, margin, hinge_weight, lr
         n = robot.n_dof
@@ -109,12 +110,13 @@ class FusedIteration:
 class OptimizerGraph:
     """``iters`` fused iterations with the gradient step, captured in one HIP
     graph (the paper captures the optimizer's inner loop as a CUDA graph,
-    Sec. 7.2).  At every ``every``-th iteration i, device-to-device copies
-    record the state x_i = (q, qd, qdd) before its step, the gradient of the
-    cost at x_i, the cost and the maximum penetration into ``hist``, so a run
-    can be checked afterwards without host round trips.  Snapshot iterations
-    run the kernel with its per-joint outputs enabled; the others write only
-    the state and the per-state scalars.
+    Sec. 7.2).  At every ``every``-th iteration i, ``hist`` records the state
+    x_i = (q, qd, qdd) before its step (device-to-device copies), and the
+    kernel writes the gradient of the cost at x_i, the cost and the maximum
+    penetration straight into its slot, so a run can be checked afterwards
+    without host round trips.  Snapshot iterations run the kernel with its
+    per-joint outputs enabled; the others write only the state and the
+    per-state scalars.
 
     q, qd, qdd: [n][B] device tensors, updated in place by every iteration.
     """
@@ -148,10 +150,9 @@ class OptimizerGraph:
             for name, x in (("q", self.q), ("qd", self.qd), ("qdd", self.qdd)):
                 h[name][k].copy_(x)
             it = self.full
-            it.run(self.q, self.qd, self.qdd, step=True)
-            for name, x in (("g_q", it.g_q), ("g_qd", it.g_qd), ("g_qdd", it.g_qdd), ("cost", it.cost),
-                            ("max_pen", it.max_pen)):
-                h[name][k].copy_(x)
+            wb.wb_wholebody_step(it.robot, self.q, self.qd, self.qdd, it.w, it.tw, it.margin, it.hw, it.lr, it.tau,
+                                 h["cost"][k], h["max_pen"][k], it.argmax, it.n_coll, h["g_q"][k], h["g_qd"][k],
+                                 h["g_qdd"][k])
 
     def run_eager(self) -> None:
         """The same iterations and snapshots, issued launch by launch."""
