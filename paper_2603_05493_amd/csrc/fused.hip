@@ -280,7 +280,7 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
             taub = wj;
         } else {
             tcost = k.torque_weight * tau * tau;
-            taub = 2.f * k.torque_weight * tau;
+            taub = k.torque_weight * (2.f * tau);   // the same product as 2 tw tau (x2 is exact), nothing loop-invariant to keep
         }
     }
     tcost = group_reduce_sum(tcost, G);
