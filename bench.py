@@ -41,8 +41,8 @@ PEAK_HBM_GBPS = 8000.0
 # (profiles/k_fused_step_humanoid48_B24576_hbm_counters.md), scaled by a copy
 # calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
 # it was measured with; reported as null once they change.
-TRAFFIC_MEASURED = {"sources_sha1": "1758938e3cbbfc00468169b7222255921ae8cf57", "states": 24576,
-                    "bytes_per_launch": 33169.2 * 1024}
+TRAFFIC_MEASURED = {"sources_sha1": "1f20b2317dfe58dacee6b804bf8637a3bf258f06", "states": 24576,
+                    "bytes_per_launch": 31617.0 * 1024}
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h")
 
 
@@ -90,6 +90,8 @@ def parse():
                     help="skip the uneven multi-tree batch measurement")
     ap.add_argument("--no-kinematics", dest="kinematics", action="store_false",
                     help="skip the kinematics-outputs line (tool poses, CoM, Jacobians)")
+    ap.add_argument("--no-ext", dest="ext", action="store_false",
+                    help="skip the line of the fused variant with mimic joints and external forces")
     ap.add_argument("--no-edt", dest="edt", action="store_false",
                     help="skip the distance-transform line")
     ap.add_argument("--no-bspline", dest="bspline", action="store_false",
@@ -258,6 +260,8 @@ def main():
                            "hbm_gbps_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9}
     if args.uneven:
         out["uneven_batch"] = bench_uneven(args)
+    if args.ext:
+        out["ext_variant"] = bench_ext_variant(args, st)
     if args.kinematics and robot.kinematics_supported:
         out["kinematics"] = bench_kinematics(args, robot, q0)
     if args.edt:
@@ -307,6 +311,49 @@ def bench_bspline(args, robot, T: int):
     return {"trajectories": T, "control_points": K, "n_interp": n_interp, "states": states,
             "states_per_s": states / dt, "ms_per_step": dt * 1e3,
             "form": "bspline_eval + fused iteration (per-joint outputs) + control-point gradient and step, graph"}
+
+
+def bench_ext_variant(args, st, reps: int = 50):
+    """The fused iteration's variant with mimic joints and external link
+    forces on the optimizer batch: the humanoid with each finger's distal
+    joint following its proximal one (40 actuated joints for 48 links),
+    forces on every link and their gradient, the step on; timed with HIP
+    events, next to the lean kernel on the plain humanoid."""
+    import torch
+    from paper_2603_05493_amd import synth, wb
+    rb = synth.humanoid48(seed=0)
+    ji, jm = rb.joint_index.copy(), rb.joint_mult.copy()
+    for wrist in (synth.humanoid48_tool_links()["left_wrist"], synth.humanoid48_tool_links()["right_wrist"]):
+        for f in range(4):
+            prox = wrist + 1 + 2 * f
+            ji[prox + 1], jm[prox + 1] = ji[prox], 0.8
+    remap = {j: i for i, j in enumerate(sorted(set(int(j) for j in ji if j >= 0)))}
+    rb.joint_index = np.array([remap[int(j)] if j >= 0 else -1 for j in ji], dtype=np.int32)
+    rb.joint_mult = synth._f32(jm)
+    r = wb.Robot(rb).to_device("cuda:0")
+    B, n, L = st.B, rb.n_dof, rb.n_links
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a.T.astype(np.float32))).cuda()
+    q, qd, qdd = d(st.q[:, :n]), d(st.qd[:, :n]), d(st.qdd[:, :n])
+    g = torch.Generator(device="cpu").manual_seed(5)
+    f_ext = (torch.randn((L, 6, B), generator=g) * 2.0).cuda()
+    g_fext = torch.empty((L, 6, B), device="cuda")
+    out = dict(cost=torch.empty(B, device="cuda"), max_pen=torch.empty(B, device="cuda"),
+               argmax=torch.empty(B, dtype=torch.int32, device="cuda"),
+               n_coll=torch.empty(B, dtype=torch.int32, device="cuda"))
+    run = lambda: wb.wb_wholebody_step(r, q, qd, qdd, torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=1e-7,
+                                       f_ext=f_ext, g_fext=g_fext, **out)
+    for _ in range(5):
+        run()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        run()
+    e1.record(s)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    return {"robot": "humanoid48 with coupled fingers (40 joints, 48 links)", "states": B, "kernel_us": t * 1e6,
+            "states_per_s": B / t, "features": "mimic joints, external link forces and their gradient, step"}
 
 
 def bench_kinematics(args, robot, q, reps: int = 50):
@@ -389,7 +436,7 @@ def bench_edt(args, reps: int = 20):
                          "frac": nbytes / t / 1e9 / PEAK_HBM_GBPS,
                          "traffic": EDT_TRAFFIC_MEASURED["bytes"]
                          if fused_sources_sha1(EDT_SOURCES) == EDT_TRAFFIC_MEASURED["sources_sha1"] else None},
-            "form": "five launches: z flood, y envelope, y assign, x envelope, x assign"}
+            "form": "three launches: x flood (wave per row), y and z envelope+assign passes over LDS tiles"}
 
 
 def bench_uneven(args):
