@@ -41,8 +41,8 @@ PEAK_HBM_GBPS = 8000.0
 # (profiles/k_fused_step_humanoid48_B24576_hbm_counters.md), scaled by a copy
 # calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
 # it was measured with; reported as null once they change.
-TRAFFIC_MEASURED = {"sources_sha1": "1f20b2317dfe58dacee6b804bf8637a3bf258f06", "states": 24576,
-                    "bytes_per_launch": 31617.0 * 1024}
+TRAFFIC_MEASURED = {"sources_sha1": "149ec8cf73463d7833c5aee8ed3423f9bb6ca6d1", "states": 24576,
+                    "bytes_per_launch": 30644.0 * 1024}
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h")
 
 

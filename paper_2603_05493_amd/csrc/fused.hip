@@ -386,10 +386,12 @@ __device__ __forceinline__ void stage_table(const DevRobot &rb, uint16_t *tab) {
     }
 }
 
-// Four wavefronts per SIMD: the register budget is 128 VGPRs.  EXT: the
-// variant with external link forces and mimic joints.
+// Four wavefronts per SIMD: the register budget is 128 VGPRs.  EXT, the
+// variant with external link forces and mimic joints, holds the forces, the
+// joint-to-link map and their adjoints as well: at 128 VGPRs it spilled ~48
+// registers, so it runs three wavefronts per SIMD (168 VGPRs) without spills.
 template <int NMAX, bool EXT>
-__global__ void __launch_bounds__(256, 4) k_fused_step(FusedArgs A) {
+__global__ void __launch_bounds__(256, EXT ? 3 : 4) k_fused_step(FusedArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
     const int G = A.lanes_per_state;
