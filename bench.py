@@ -13,8 +13,10 @@ timed on the same inputs:
   plain_graph   one launch per operation, captured in a HIP graph;
   plain         one launch per operation, issued eagerly (the "plain launch").
 The roofline object covers the fused kernel, timed with HIP events on its
-stream over an eager timed loop; the CPU baseline is the FP64 oracle on a
-bounded sample of the same workload.
+stream over an eager timed loop, with an issue-slot model beside the FLOP
+model; shard_share_B3072 times the fused graph on the 3072 states one GPU
+holds when the batch is split over eight; the CPU baseline is the FP64
+oracle on a bounded sample of the same workload (all threads, then one).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -76,6 +78,22 @@ def algorithmic_flop_per_state(L: int, S: int, P: int, n: int) -> float:
     return 135 * links + 18 * S + 11 * P + 290 * links + 860 * links + 30 + 38 * links + 10 * n
 
 
+# One VALU issue slot = one lane of one VALU instruction; the chip issues
+# 256 CU x 64 lanes x 2.4 GHz of them per second (one wave64 instruction per
+# SIMD every 4 cycles, 4 SIMDs per CU).
+PEAK_ISSUE_TSLOTS = 256 * 64 * 2.4e9 / 1e12
+
+
+def issue_slots_per_state(L: int, S: int, P: int, n: int) -> float:
+    """VALU issue-slot model of one iteration per state, fixed in advance and
+    crediting every pair of the pair set (no pruning): a pair costs 16 slots
+    (difference 3, squared norm 3, sqrt 4 at quarter rate, radius sum and
+    penetration 2, max / argmax / count selects 4); everything else is the
+    FLOP model's non-pair work with every FMA paired (FLOP / 2)."""
+    other = algorithmic_flop_per_state(L, S, P, n) - 11 * P
+    return 16 * P + other / 2
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,9 +138,43 @@ def cpu_baseline(rb, st, seconds: float, chunk: int = 2048):
         dt = time.perf_counter() - t0
         if dt >= min(seconds, 30.0):
             break
-    return {"value": done / dt, "unit": "states/s", "cores": O.num_threads(), "kind": "oracle",
+    cores = O.num_threads()
+    # the same work on one thread, over a shorter sample
+    O.set_num_threads(1)
+    done1, t1 = 0, time.perf_counter()
+    try:
+        while True:
+            idx = (np.arange(256) + done1) % st.B
+            q, qd, qdd = st.q[idx], st.qd[idx], st.qdd[idx]
+            R, p, c = O.fk(rb, q)
+            mp, am, nc = O.self_collision(rb, c)
+            tau = O.rnea(rb, q, qd, qdd)
+            gc = O.self_collision_backward(rb, c, am, mp, 0.01, np.ones(len(idx)))
+            O.fk_backward(rb, q, g_spheres=gc)
+            O.rnea_vjp(rb, q, qd, qdd, 2e-3 * tau)
+            done1 += len(idx)
+            dt1 = time.perf_counter() - t1
+            if dt1 >= min(seconds / 3, 5.0):
+                break
+    finally:
+        O.set_num_threads(cores)
+    return {"value": done / dt, "unit": "states/s", "cores": cores, "kind": "oracle",
             "sample": f"{done} state evaluations ({chunk}-state chunks cycling through the {st.B}-state batch) "
-                      f"in {dt:.1f} s, FP64 oracle forward + analytic backward"}
+                      f"in {dt:.1f} s, FP64 oracle forward + analytic backward",
+            "single_thread": {"value": done1 / dt1, "unit": "states/s",
+                              "sample": f"{done1} state evaluations in {dt1:.1f} s on one thread"},
+            "host_cpu": host_cpu_model()}
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -153,8 +205,9 @@ def main():
         return FusedIteration(robot, B, outputs=False, **kw) if form.startswith("fused") else \
             PlainIteration(robot, B, **kw)
 
-    def timed_optimizer_graph():
-        q, qd, qdd = q0.clone(), qd0.clone(), qdd0.clone()
+    def timed_optimizer_graph(nb=None):
+        sl = slice(0, nb if nb is not None else B)
+        q, qd, qdd = (x[:, sl].contiguous() for x in (q0, qd0, qdd0))
         og = OptimizerGraph(robot, q, qd, qdd, iters=args.steps, every=10, **kw)
         for _ in range(args.warmup):
             og.lean.run(q, qd, qdd)
@@ -208,7 +261,7 @@ def main():
                 ev[k][1].record(stream)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
-        kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev])) if events else None
+        kernel_ms = [a.elapsed_time(b) for a, b in ev] if events else None
         return dt, kernel_ms
 
     for form in forms:
@@ -220,7 +273,8 @@ def main():
             res[form] = timed_eager(form)[0]
     fused_ms = None
     if robot.fused_supported and any(f.startswith("fused") for f in forms):
-        _, fused_ms = timed_eager("fused", events=True)
+        _, fused_all = timed_eager("fused", events=True)
+        fused_ms = float(np.mean(fused_all))
 
     head = "fused_graph" if "fused_graph" in res else forms[0]
     L, S, P, n = robot.n_links, robot.n_spheres, robot.n_pairs, robot.n_dof
@@ -255,9 +309,22 @@ def main():
                            "peak": PEAK_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / PEAK_FP32_NONPACKED_TFLOPS,
                            "frac_of_published_packed_peak": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
-                           "kernel_ms": fused_ms, "flop_per_launch": flop, "traffic": traffic,
+                           "kernel_ms": fused_ms, "kernel_ms_median": float(np.median(fused_all)),
+                           "kernel_ms_min": float(np.min(fused_all)), "flop_per_launch": flop, "traffic": traffic,
                            "algorithmic_bytes_per_launch": alg_bytes,
                            "hbm_gbps_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9}
+        slots = issue_slots_per_state(L, S, P, n) * B
+        ach_slots = slots / (fused_ms * 1e-3) / 1e12
+        out["roofline"]["issue_slot_model"] = {
+            "slots_per_state": slots / B, "achieved": ach_slots, "peak": PEAK_ISSUE_TSLOTS,
+            "unit": "T lane-slots/s", "frac": ach_slots / PEAK_ISSUE_TSLOTS,
+            "note": "credits every pair; above 1 where the exact broad phase skips pairs the model counts"}
+        if "fused_graph" in res and B > 3072:
+            t_share = timed_optimizer_graph(3072)
+            out["shard_share_B3072"] = {
+                "states": 3072, "states_per_s": 3072 / t_share, "ms_per_step": t_share * 1e3,
+                "per_state_rate_vs_full_batch": (3072 / t_share) / (B / res["fused_graph"]),
+                "form": "fused_graph (one GPU's share of the batch over 8 GPUs)"}
     if args.uneven:
         out["uneven_batch"] = bench_uneven(args)
     if args.ext:

@@ -349,7 +349,11 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, flo
  *   lanes_per_state  16, 32 or 64 lanes of a 64-wide wavefront per state
  *                    (>= the robot's links); 64 / lanes_per_state states run
  *                    side by side in one wavefront.
- *   states_per_item  states per workgroup work item (1..4096).
+ *   states_per_item  states per workgroup work item (1..4096).  For a
+ *                    wb_wholebody_step batch too small to give every
+ *                    compute unit four workgroups it is halved, down to the
+ *                    4 * 64 / lanes_per_state states a workgroup holds at
+ *                    once (results do not depend on it).
  *   ns_per_state     measured cost of one state, used to balance uneven
  *                    batches (0 = use the built-in cost model).
  * wb_robot_create sets a default; wb_robot_set_tune validates and replaces it

@@ -202,6 +202,11 @@ def num_threads() -> int:
     return int(lib().orc_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's loops over states (used for timing only)."""
+    lib().orc_set_num_threads(C.c_int(int(n)))
+
+
 # ------------------------------------------------------------- cost heads
 # Upstream adjoints of the scalar costs the optimizer-shaped workload uses:
 # L = sum(w * tau) -> tau-bar = w;  L = c ||tau||^2 -> tau-bar = 2 c tau;

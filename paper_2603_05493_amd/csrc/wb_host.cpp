@@ -443,6 +443,7 @@ struct wb_robot {
     size_t o_kf = 0;             // offset of the kinematics float lane table
     size_t o_tl = 0, o_to = 0, o_ta = 0;   // tool lanes, offsets and affects masks (WB_MAX_TOOLS each)
     int device = -1;
+    int cus = 256;   // compute units of that device
 };
 
 namespace {
@@ -455,6 +456,18 @@ wb_tune default_tune(int L) {
     t.states_per_item = 16;
     t.ns_per_state = 0.0f;
     return t;
+}
+
+// States per workgroup of the fused launch.  The tuned value holds for
+// large batches; a batch too small to give every compute unit four
+// workgroups (its occupancy at 4 wavefronts per SIMD) gets a smaller chunk,
+// halved down to the states one workgroup has in flight at once, so that
+// the work spreads over the whole chip instead of a few deep workgroups.
+int small_batch_chunk(const wb_tune &t, int64_t B, int cus) {
+    const int in_flight = 4 * (64 / t.lanes_per_state);
+    int c = t.states_per_item;
+    while (c > in_flight && (B + c - 1) / c < (int64_t)cus * 4) c = std::max(in_flight, c / 2);
+    return c;
 }
 
 int check_tune(const wb_tune &t, const Tables &T) {
@@ -557,6 +570,11 @@ int wb_robot_create(const wb_robot_desc *desc, wb_robot **out) {
     const size_t o_ta = append(blob, std::vector<uint64_t>(WB_MAX_TOOLS, 0));
     blob.resize(blob.size() + 256);
     hipError_t e = hipGetDevice(&r->device);
+    if (e == hipSuccess) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, r->device) == hipSuccess && cus > 0)
+            r->cus = cus;
+    }
     if (e == hipSuccess) e = hipMalloc(&r->dmem, blob.size());
     if (e == hipSuccess) e = hipMemcpy(r->dmem, blob.data(), blob.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -858,7 +876,7 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, flo
     a.rb = robot->dev;
     a.fz = robot->fz;
     a.B = B;
-    a.chunk = robot->tune.states_per_item;
+    a.chunk = small_batch_chunk(robot->tune, B, robot->cus);
     a.lanes_per_state = robot->tune.lanes_per_state;
     a.io = wb::TreeIO{q, qd, qdd, w, tau, cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd, f_ext, g_fext};
     a.k = wb::StepScalars{torque_weight, margin, hinge_weight, lr};
