@@ -50,8 +50,8 @@ FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h"
 
 # HBM traffic of the kinematics-outputs kernel, measured the same way
 # (profiles/k_kinematics_humanoid48_B24576.md; 4 tool frames), per launch.
-KIN_TRAFFIC_MEASURED = {"sources_sha1": "7a68d7553e40d4f68379fb8b6c3863b096b052d9", "states": 24576, "tools": 4,
-                        "forward_bytes": (5628.8 + 133206.8) * 1024, "backward_bytes": (9664.0 + 4608.0) * 1024}
+KIN_TRAFFIC_MEASURED = {"sources_sha1": "0f6cc4a3df15b9cfa666ce9d20f5c930b30cb888", "states": 24576, "tools": 4,
+                        "forward_bytes": (5436.5 + 133147.3) * 1024, "backward_bytes": (9676.0 + 4608.1) * 1024}
 KIN_SOURCES = ("kinematics.hip", "kin.h", "lanes.h", "spatial.h", "wb_internal.h")
 # ... and of the three distance-transform launches on the 256 x 256 x 128 room
 # (profiles/edt_room256_kernel_trace.md), summed per transform.

@@ -48,14 +48,94 @@ __device__ __forceinline__ V3 scan3(V3 v, int G) {
     return v3(group_scan(v.x, G), group_scan(v.y, G), group_scan(v.z, G));
 }
 
-// Element c (0..11) of a pose held as R (row-major) then p.
-__device__ __forceinline__ float pose_elem(const M3 &R, V3 p, int c) {
-    float r = p.z;
+// Tool frames of one state (Alg. 2).  Poses lane-parallel: lane (t, c) of
+// a pass, t = gl / 12 and c = gl % 12, forms element c of tool t's pose
+// (R_e R_o row-major, then R_e p_o + p_e) with one 3-term dot product, so
+// a 64-lane group covers five tools per pass.  Jacobian columns: every
+// column lane fetches its first connected link's axis, origin, multiplier
+// and subtree end once for all tools, then takes each tool point (and, for
+// the gradient, the tool rotation) from the lanes that formed it.
+// Forward: writes the poses and Jacobians.  BWD: returns this column's
+// dL/dq_j = sum_t J_t[:, j] . [g_x; w_t].
+template <bool BWD>
+__device__ __forceinline__ float tool_frames(const DevKin &k, int64_t B, int64_t b, bool valid, int gl, const M3 &R,
+                                             V3 p, V3 s_w, float mult, int sub_end, const KinOut &o,
+                                             const float *__restrict__ g_tool) {
+    const int G = k.G, n = k.n;
+    const bool col_lane = gl < n;
+    const int lk0 = k.conn[gl];
+    const int src0 = lk0 >= 0 ? lk0 : gl;
+    const V3 s0 = shfl3(s_w, src0, G), o0 = shfl3(p, src0, G);
+    const float m0 = __shfl(mult, src0, G);
+    const int lend0 = __shfl(sub_end, src0, G);
+    const int per = G / 12;   // tools per pass (G >= 16)
+    const int c = gl % 12, row = c < 9 ? c / 3 : c - 9, cj = c % 3;
+    float gq = 0.f;
+    for (int t0 = 0; t0 < k.n_tools; t0 += per) {
+        const int tt = t0 + gl / 12;
+        const bool tl = gl < per * 12 && tt < k.n_tools;
+        const int tq = tl ? tt : t0;
+        const int e = k.tool_lane[tq];
+        const float *off = k.tool_off + 12 * tq;
+        const V3 re = v3(__shfl(R.m[3 * 0 + 0], e, G), __shfl(R.m[3 * 0 + 1], e, G), __shfl(R.m[3 * 0 + 2], e, G));
+        const V3 r1 = v3(__shfl(R.m[3 * 1 + 0], e, G), __shfl(R.m[3 * 1 + 1], e, G), __shfl(R.m[3 * 1 + 2], e, G));
+        const V3 r2 = v3(__shfl(R.m[3 * 2 + 0], e, G), __shfl(R.m[3 * 2 + 1], e, G), __shfl(R.m[3 * 2 + 2], e, G));
+        const V3 pe = shfl3(p, e, G);
+        const V3 rr = row == 0 ? re : (row == 1 ? r1 : r2);
+        const V3 oc = c < 9 ? v3(off[cj], off[3 + cj], off[6 + cj]) : v3(off[9], off[10], off[11]);
+        const float val = dot(rr, oc) + (c < 9 ? 0.f : (row == 0 ? pe.x : (row == 1 ? pe.y : pe.z)));
+        if (!BWD && o.tool_pose && valid && tl) o.tool_pose[((int64_t)tt * 12 + c) * B + b] = val;
+        if (!BWD && !o.jac) continue;
+        const int t1 = min(t0 + per, k.n_tools);
+        for (int t = t0; t < t1; ++t) {
+            const int xb = (t - t0) * 12;
+            const V3 x = v3(__shfl(val, xb + 9, G), __shfl(val, xb + 10, G), __shfl(val, xb + 11, G));
+            const int et = k.tool_lane[t];
+            const bool aff = col_lane && ((k.tool_aff[t] >> gl) & 1ull);
+            V3 jl = v3(0.f, 0.f, 0.f), ja = v3(0.f, 0.f, 0.f);
+            if (aff && lk0 >= 0 && lk0 <= et && et <= lend0) {
+                jl = m0 * cross(s0, x - o0);
+                ja = m0 * s0;
+            }
+            for (int kk = 1; kk < k.mc; ++kk) {   // further links of a mimic joint
+                const int lk = k.conn[kk * 64 + gl];
+                const int src = lk >= 0 ? lk : gl;
+                const V3 sk = shfl3(s_w, src, G), ok = shfl3(p, src, G);
+                const float mk = __shfl(mult, src, G);
+                const int lend = __shfl(sub_end, src, G);
+                if (aff && lk >= 0 && lk <= et && et <= lend) {
+                    jl += mk * cross(sk, x - ok);
+                    ja += mk * sk;
+                }
+            }
+            if (!BWD) {
+                if (valid && col_lane) {   // state-major: each row is n consecutive floats
+                    float *d = o.jac + ((int64_t)b * k.n_tools + t) * 6 * n + gl;
+                    d[0] = jl.x;
+                    d[n] = jl.y;
+                    d[2 * n] = jl.z;
+                    d[3 * n] = ja.x;
+                    d[4 * n] = ja.y;
+                    d[5 * n] = ja.z;
+                }
+            } else {
+                // a rotation turns by [s]x R about a joint axis s: w = sum_c r_c x G_c
+                M3 Rt;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r = c == i ? R.m[i] : r;
-    r = c == 9 ? p.x : r;
-    r = c == 10 ? p.y : r;
-    return r;
+                for (int i = 0; i < 9; ++i) Rt.m[i] = __shfl(val, xb + i, G);
+                const float *gt = g_tool + (int64_t)t * 12 * B + b;
+                M3 GR;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) GR.m[i] = gt[i * B];
+                const V3 gx = v3(gt[9 * B], gt[10 * B], gt[11 * B]);
+                V3 w = v3(0.f, 0.f, 0.f);
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) w += cross(col(Rt, cc), col(GR, cc));
+                gq += dot(jl, gx) + dot(ja, w);
+            }
+        }
+    }
+    return gq;
 }
 
 template <bool BWD>
@@ -162,60 +242,9 @@ __device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b,
             }
         }
     }
-    // ---- tool frames: poses and Jacobians (Alg. 2)
-    const bool want_j = BWD ? g.g_tool != nullptr : o.jac != nullptr;
-    if (BWD ? want_j : (o.tool_pose != nullptr || want_j)) {
-        for (int t = 0; t < k.n_tools; ++t) {
-            const int e = k.tool_lane[t];
-            const float *off = k.tool_off + 12 * t;
-            M3 Re, Ro;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                Re.m[i] = __shfl(R.m[i], e, G);
-                Ro.m[i] = off[i];
-            }
-            const V3 pe = shfl3(p, e, G);
-            const M3 Rt = matmul(Re, Ro);
-            const V3 x = mul(Re, v3(off[9], off[10], off[11])) + pe;
-            if (!BWD && o.tool_pose && valid && gl < 12)
-                o.tool_pose[((int64_t)t * 12 + gl) * B + b] = pose_elem(Rt, x, gl);
-            if (!want_j) continue;
-            const bool aff = col_lane && ((k.tool_aff[t] >> gl) & 1ull);
-            V3 jl = v3(0.f, 0.f, 0.f), ja = v3(0.f, 0.f, 0.f);
-            for (int kk = 0; kk < k.mc; ++kk) {
-                const int lk = k.conn[kk * 64 + gl];
-                const int src = lk >= 0 ? lk : gl;
-                const V3 sk = shfl3(s_w, src, G), ok = shfl3(p, src, G);
-                const float mk = __shfl(mult, src, G);
-                const int lend = __shfl(sub_end, src, G);
-                if (aff && lk >= 0 && lk <= e && e <= lend) {
-                    jl += mk * cross(sk, x - ok);
-                    ja += mk * sk;
-                }
-            }
-            if (!BWD) {
-                if (valid && col_lane) {   // state-major: each row is n consecutive floats
-                    float *d = o.jac + ((int64_t)b * k.n_tools + t) * 6 * n + gl;
-                    d[0] = jl.x;
-                    d[n] = jl.y;
-                    d[2 * n] = jl.z;
-                    d[3 * n] = ja.x;
-                    d[4 * n] = ja.y;
-                    d[5 * n] = ja.z;
-                }
-            } else {
-                const float *gt = g.g_tool + (int64_t)t * 12 * B + b;
-                M3 GR;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) GR.m[i] = gt[i * B];
-                const V3 gx = v3(gt[9 * B], gt[10 * B], gt[11 * B]);
-                V3 w = v3(0.f, 0.f, 0.f);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) w += cross(col(Rt, c), col(GR, c));
-                gq += dot(jl, gx) + dot(ja, w);
-            }
-        }
-    }
+    // ---- tool frames: poses and Jacobians, or their gradient
+    if (BWD ? g.g_tool != nullptr : (o.tool_pose != nullptr || o.jac != nullptr))
+        gq += tool_frames<BWD>(k, B, b, valid, gl, R, p, s_w, mult, sub_end, o, g.g_tool);
     if (BWD && valid && col_lane) g.g_q[(int64_t)gl * B + b] = gq;
 }
 
@@ -223,7 +252,7 @@ __device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b,
 // groups), so the rows of every [k][B] output are written in runs of
 // consecutive states by one workgroup.
 template <bool BWD>
-__global__ void __launch_bounds__(KIN_WG) k_kinematics(DevKin k, int64_t B, const float *__restrict__ q, KinOut o,
+__global__ void __launch_bounds__(KIN_WG, 5) k_kinematics(DevKin k, int64_t B, const float *__restrict__ q, KinOut o,
                                                        KinGrad g, int32_t spb) {
     const int G = k.G;
     const int gl = threadIdx.x & (G - 1);
