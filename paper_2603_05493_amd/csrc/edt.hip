@@ -129,14 +129,20 @@ __device__ __forceinline__ bool dominated(int ua, int ga, int ub, int gb, int uc
 
 // ---- passes 2 and 3: one workgroup per tile of TL lines (consecutive x)
 // at a fixed z (AX == 1) or y (AX == 2), the tile resident in LDS as
-// ent[p * TL + l] (position p, line l).  Three phases, PBA+'s banding:
+// ent[p * TL + l] (position p, line l).  Phases, after PBA+'s banding:
 //   bands:  thread (l, b) stacks the envelope of band b of line l in place
 //           from the band's first position (256 / TL bands per line);
-//   merge:  thread l merges its line's band envelopes left to right; only
-//           the junctions can change (entries of the envelope so far that a
-//           band's first entries dominate, and first entries of the band
-//           the junction dominates), the rest moves down, so the line's
-//           envelope ends up packed at positions [0, K);
+//   trim:   thread (l, b) merges the envelopes of bands b - 1 and b alone,
+//           then of what is left of bands b - 2 and b.  An entry off such a
+//           pair's envelope is off the line's envelope too, so the trimmed
+//           prefix of band b and suffix of the other band go; every
+//           junction of a round is trimmed at once;
+//   merge:  thread l merges the trimmed bands left to right.  Only the
+//           junctions change, so each band keeps a range [lo, hi) of its
+//           stack: popping the envelope's last entry shortens its band's
+//           range, dropping a band's first entry raises lo; nothing moves;
+//   pack:   thread (l, b) moves band b's surviving range down, so the
+//           line's envelope ends up packed at positions [0, K);
 //   assign: thread (l, s) takes segment s of line l: a binary search finds
 //           the envelope entry owning the segment's first voxel, a walk the
 //           rest, and the segment is written to the next pass's grid (and
@@ -147,7 +153,7 @@ __global__ void __launch_bounds__(256) k_edt_tile(const int32_t *__restrict__ in
                                                   int nz) {
     extern __shared__ int32_t ent[];
     constexpr int NB = 256 / TL;   // bands (and assignment segments) per line
-    __shared__ int32_t bcnt[256], ksz[TL];
+    __shared__ int32_t bcnt[256], blo[256], bhi[256], boff[256], ksz[TL];
     const int n = AX == 1 ? ny : nz;
     const int ntx = (nx + TL - 1) / TL;
     const int x0 = (int)(blockIdx.x % ntx) * TL;
@@ -201,28 +207,32 @@ __global__ void __launch_bounds__(256) k_edt_tile(const int32_t *__restrict__ in
         bcnt[sidx * TL + l] = k;
     }
     __syncthreads();
-    // ---- merge
-    if (threadIdx.x < TL) {
-        auto ug = [&](int32_t c, int &u, int &gg) {
-            u = pos<AX>(c);
-            gg = u * u + height<AX>(c, qx, qy);
-        };
-        int K = 0, u1 = 0, g1 = 0, u2 = 0, g2 = 0;
-        for (int b = 0; b < NB; ++b) {
-            const int cb = bcnt[b * TL + l], p0 = b * bw;
-            int lo = 0;
-            while (lo < cb) {
+    auto ug = [&](int b, int i, int &u, int &gg) {   // entry i of band b's stack
+        const int32_t c = ent[(b * bw + i) * TL + l];
+        u = pos<AX>(c);
+        gg = u * u + height<AX>(c, qx, qy);
+    };
+    // Trim the junction of band ba's range [la, ha) and band bb's range
+    // [lb, hb) (ba < bb) from those two ranges alone: the new end of ba's
+    // range and the new start of bb's.
+    auto trim = [&](int ba, int la, int ha, int bb, int lb, int hb, int &nha, int &nlb) {
+        int lo = lb, hi = ha;
+        if (ha > la && hb > lb) {
+            int u1, g1, u2 = 0, g2 = 0;   // last and second-to-last kept entries of band ba
+            ug(ba, hi - 1, u1, g1);
+            if (hi - la >= 2) ug(ba, hi - 2, u2, g2);
+            while (lo < hb) {
                 int uc, gc;
-                ug(ent[(p0 + lo) * TL + l], uc, gc);
-                while (K >= 2 && dominated(u2, g2, u1, g1, uc, gc)) {
-                    --K;
+                ug(bb, lo, uc, gc);
+                while (hi - la >= 2 && dominated(u2, g2, u1, g1, uc, gc)) {
+                    --hi;
                     u1 = u2;
                     g1 = g2;
-                    if (K >= 2) ug(ent[(K - 2) * TL + l], u2, g2);
+                    if (hi - la >= 2) ug(ba, hi - 2, u2, g2);
                 }
-                if (K >= 1 && lo + 1 < cb) {
+                if (lo + 1 < hb) {
                     int un, gn;
-                    ug(ent[(p0 + lo + 1) * TL + l], un, gn);
+                    ug(bb, lo + 1, un, gn);
                     if (dominated(u1, g1, uc, gc, un, gn)) {
                         ++lo;
                         continue;
@@ -230,16 +240,124 @@ __global__ void __launch_bounds__(256) k_edt_tile(const int32_t *__restrict__ in
                 }
                 break;
             }
-            for (int j = lo; j < cb; ++j) {   // destinations never pass their sources
-                const int32_t e = ent[(p0 + j) * TL + l];
-                ent[K * TL + l] = e;
-                ++K;
+        }
+        nha = hi;
+        nlb = lo;
+    };
+    // ---- trim, round 1: bands b - 1 and b, from the two stacks alone
+    {
+        const int b = sidx;
+        int hi = b > 0 ? bcnt[(b - 1) * TL + l] : 0, lo = 0;
+        const int cb = bcnt[b * TL + l];
+        if (b > 0) trim(b - 1, 0, hi, b, 0, cb, hi, lo);
+        blo[b * TL + l] = lo;
+        if (b > 0) bhi[(b - 1) * TL + l] = hi;
+        if (b == NB - 1) bhi[b * TL + l] = cb;
+    }
+    __syncthreads();
+    // ---- trim, round 2: bands b - 2 and b, from their trimmed ranges (each
+    // range end has one writer; every thread reads its ranges first)
+    {
+        const int b = sidx;
+        int la = 0, ha = 0, lb = 0, hb = 0;
+        if (b >= 2) {
+            la = blo[(b - 2) * TL + l];
+            ha = bhi[(b - 2) * TL + l];
+            lb = blo[b * TL + l];
+            hb = bhi[b * TL + l];
+        }
+        __syncthreads();
+        if (b >= 2) {
+            int nha, nlb;
+            trim(b - 2, la, ha, b, lb, hb, nha, nlb);
+            bhi[(b - 2) * TL + l] = nha;
+            blo[b * TL + l] = nlb;
+        }
+    }
+    __syncthreads();
+    // ---- merge: the junctions of the trimmed ranges only
+    if (threadIdx.x < TL) {
+        // the envelope's last (b1, i1) and second-to-last (b2, i2) entries
+        int K = 0, b1 = 0, i1 = 0, u1 = 0, g1 = 0, b2 = 0, i2 = 0, u2 = 0, g2 = 0;
+        for (int b = 0; b < NB; ++b) {
+            int lo = blo[b * TL + l];
+            const int cb = max(bhi[b * TL + l], lo);
+            while (lo < cb) {
+                int uc, gc;
+                ug(b, lo, uc, gc);
+                while (K >= 2 && dominated(u2, g2, u1, g1, uc, gc)) {
+                    bhi[b1 * TL + l] = i1;   // the last entry of band b1's range goes
+                    --K;
+                    b1 = b2;
+                    i1 = i2;
+                    u1 = u2;
+                    g1 = g2;
+                    if (K >= 2) {   // the entry before (b1, i1), in b1 or the last non-empty band before it
+                        if (i1 > blo[b1 * TL + l]) {
+                            b2 = b1;
+                            i2 = i1 - 1;
+                        } else {
+                            int bb = b1 - 1;
+                            while (blo[bb * TL + l] >= bhi[bb * TL + l]) --bb;
+                            b2 = bb;
+                            i2 = bhi[bb * TL + l] - 1;
+                        }
+                        ug(b2, i2, u2, g2);
+                    }
+                }
+                if (K >= 1 && lo + 1 < cb) {
+                    int un, gn;
+                    ug(b, lo + 1, un, gn);
+                    if (dominated(u1, g1, uc, gc, un, gn)) {
+                        ++lo;
+                        continue;
+                    }
+                }
+                break;
+            }
+            blo[b * TL + l] = lo;
+            bhi[b * TL + l] = cb;
+            const int m = cb - lo;
+            if (m >= 2) {
+                b2 = b;
+                i2 = cb - 2;
+                ug(b, i2, u2, g2);
+                b1 = b;
+                i1 = cb - 1;
+                ug(b, i1, u1, g1);
+            } else if (m == 1) {
+                b2 = b1;
+                i2 = i1;
                 u2 = u1;
                 g2 = g1;
-                ug(e, u1, g1);
+                b1 = b;
+                i1 = lo;
+                ug(b, lo, u1, g1);
             }
+            K += m;
         }
-        ksz[l] = K;
+        int off = 0;
+        for (int b = 0; b < NB; ++b) {
+            boff[b * TL + l] = off;
+            off += max(bhi[b * TL + l] - blo[b * TL + l], 0);
+        }
+        ksz[l] = off;
+    }
+    __syncthreads();
+    // ---- pack: thread (l, b) moves band b's range to its place in the
+    // packed envelope [0, K) through registers (a range holds at most
+    // bw <= 32 entries), so no thread overwrites a range still being read.
+    {
+        const int lo = blo[sidx * TL + l], cnt = bhi[sidx * TL + l] - lo, dst = boff[sidx * TL + l];
+        const int src = sidx * bw + lo;
+        int32_t v[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j)
+            if (j < cnt) v[j] = ent[(src + j) * TL + l];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 32; ++j)
+            if (j < cnt) ent[(dst + j) * TL + l] = v[j];
     }
     __syncthreads();
     // ---- assign

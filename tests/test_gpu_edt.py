@@ -72,6 +72,35 @@ def test_edt_room_full_size_sampled():
     _check(m, near, dist, O.d2_at(m, pts), 0.02, pts)
 
 
+@pytest.mark.parametrize("axis", [1, 0])
+def test_edt_diagonal_wall_full_band_envelopes(axis):
+    """A diagonal wall (x = y, or x = z) gives every line along that axis a
+    candidate at every position with a convex height profile, so every band
+    of the envelope passes starts full and most of its entries must go at the
+    junctions; a few scattered sites dominate long runs of them.  Whole
+    lines plus random voxels against the definition."""
+    n = 256
+    shape = (4, n, n) if axis == 1 else (n, 4, n)
+    m = np.zeros(shape, np.uint8)
+    i = np.arange(n)
+    if axis == 1:
+        m[:, i, i] = 1
+    else:
+        m[i, :, i] = 1
+    rng = np.random.default_rng(7 + axis)
+    m |= (rng.random(shape) < 0.0004).astype(np.uint8)
+    near, dist = _run(m, voxel_size=0.02)
+    lines = []
+    for x in (3, 100, 200, 255):
+        t = np.arange(n)
+        if axis == 1:
+            lines.append(np.stack([np.full(n, 2), t, np.full(n, x)], 1))
+        else:
+            lines.append(np.stack([t, np.full(n, 1), np.full(n, x)], 1))
+    pts = np.concatenate(lines + [np.stack([rng.integers(0, k, 600) for k in shape], 1)])
+    _check(m, near, dist, O.d2_at(m, pts), 0.02, pts)
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 1024), (1, 1024, 1), (1024, 1, 1), (2, 3, 1024), (1, 1, 1)])
 def test_edt_extreme_extents(shape):
     rng = np.random.default_rng(sum(shape))
