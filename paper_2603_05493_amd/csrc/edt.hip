@@ -14,7 +14,8 @@
 //   1. along x, one wavefront per row (y, z): the nearest site of the row,
 //      from a forward and a backward flood, each an inclusive max-scan over
 //      the wavefront (DPP; the backward one toward lower lanes) carried
-//      across 64-voxel chunks -> A;
+//      across chunks -> A (rows of a multiple of 4 voxels: 4 voxels per
+//      lane, in registers, one read and one write of the row);
 //   2. along y, a workgroup per tile of lines (x0 .. x0+TL-1, z) held in
 //      LDS: the lower envelope of the parabolas (y - y')^2 + (x - x*)^2 of
 //      the row sites, built band by band and merged at the band junctions
@@ -102,6 +103,78 @@ __global__ void __launch_bounds__(256) k_edt_x(const uint8_t *__restrict__ sites
             const int best = prev < 0 ? next : (next < 0 ? prev : (x - prev <= next - x ? prev : next));
             A[base + x] = best < 0 ? EDT_NONE : pack(best, y, z);
         }
+    }
+}
+
+// Pass 1 for rows whose length is a multiple of 4 (up to 1024): lane i of
+// the row's wavefront holds voxels 4i .. 4i + 3 of each 256-voxel chunk in
+// registers, read as one 4-byte word per chunk.  Both floods run on those
+// registers (a 4-voxel scan inside the lane, a wavefront scan of the lane
+// totals, a carry across chunks), and each chunk's result leaves as one
+// 16-byte store per lane: the site row is read once and A written once.
+template <int NC>
+__global__ void __launch_bounds__(256) k_edt_x4(const uint8_t *__restrict__ sites, int32_t *__restrict__ A, int nx,
+                                                int ny, int nz) {
+    const int64_t w = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= (int64_t)ny * nz) return;   // uniform over the wavefront
+    const int y = (int)(w % ny), z = (int)(w / ny);
+    const int n4 = nx >> 2;
+    const uint32_t *row = reinterpret_cast<const uint32_t *>(sites + w * nx);
+    int4 *out = reinterpret_cast<int4 *>(A + w * nx);
+    uint32_t sb[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int i = c * 64 + lane;
+        sb[c] = i < n4 ? row[i] : 0u;
+    }
+    // forward: 1 + the last site at or before x (0: none)
+    int prev[NC][4];
+    int carry = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int x0 = (c * 64 + lane) * 4;
+        int v = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v = (sb[c] >> (8 * j)) & 0xffu ? x0 + j + 1 : v;
+            prev[c][j] = v;
+        }
+        const int incl = wave_max_scan(v);
+        const int up = __shfl_up(incl, 1, 64);
+        const int excl = max(lane > 0 ? up : 0, carry);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) prev[c][j] = max(prev[c][j], excl);
+        carry = max(carry, __builtin_amdgcn_readlane(incl, 63));
+    }
+    // backward: BIG - the next site at or after x (0: none), then the nearer
+    carry = 0;
+#pragma unroll
+    for (int c = NC - 1; c >= 0; --c) {
+        const int x0 = (c * 64 + lane) * 4;
+        int nxt[4];
+        int v = 0;
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            v = (sb[c] >> (8 * j)) & 0xffu ? EDT_BIG - (x0 + j) : v;
+            nxt[j] = v;
+        }
+        const int incl = wave_max_suffix_scan(v, lane);
+        const int down = __shfl_down(incl, 1, 64);
+        const int excl = max(lane < 63 ? down : 0, carry);
+        carry = max(carry, __builtin_amdgcn_readlane(incl, 0));
+        int r[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = x0 + j;
+            const int pv = prev[c][j] - 1;
+            const int nv = max(nxt[j], excl);
+            const int nx_ = nv > 0 ? EDT_BIG - nv : EDT_NONE;
+            const int best = pv < 0 ? nx_ : (nx_ < 0 ? pv : (x - pv <= nx_ - x ? pv : nx_));
+            r[j] = best < 0 ? EDT_NONE : pack(best, y, z);
+        }
+        const int i = c * 64 + lane;
+        if (i < n4) out[i] = make_int4(r[0], r[1], r[2], r[3]);
     }
 }
 
@@ -420,7 +493,18 @@ bool tile_pass(const int32_t *in, int32_t *out, float *dist, float voxel_size, i
 hipError_t launch_edt(int nx, int ny, int nz, const uint8_t *sites, float voxel_size, int32_t *nearest, float *dist,
                       int32_t *A, int32_t *B, hipStream_t s) {
     const int64_t rows = (int64_t)ny * nz;
-    hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((rows * 64 + 255) / 256)), dim3(256), 0, s, sites, A, nx, ny, nz);
+    const dim3 xgrid((unsigned)((rows * 64 + 255) / 256));
+    // the 4-voxel form needs rows of whole 4-byte words and 16-byte aligned rows of A
+    if (nx % 4 != 0 || reinterpret_cast<uintptr_t>(sites) % 4 != 0 || reinterpret_cast<uintptr_t>(A) % 16 != 0)
+        hipLaunchKernelGGL(k_edt_x, xgrid, dim3(256), 0, s, sites, A, nx, ny, nz);
+    else if (nx <= 256)
+        hipLaunchKernelGGL(k_edt_x4<1>, xgrid, dim3(256), 0, s, sites, A, nx, ny, nz);
+    else if (nx <= 512)
+        hipLaunchKernelGGL(k_edt_x4<2>, xgrid, dim3(256), 0, s, sites, A, nx, ny, nz);
+    else if (nx <= 768)
+        hipLaunchKernelGGL(k_edt_x4<3>, xgrid, dim3(256), 0, s, sites, A, nx, ny, nz);
+    else
+        hipLaunchKernelGGL(k_edt_x4<4>, xgrid, dim3(256), 0, s, sites, A, nx, ny, nz);
     if (!tile_pass<1>(A, B, nullptr, voxel_size, nx, ny, nz, s)) return hipErrorInvalidValue;
     if (!tile_pass<2>(B, nearest, dist, voxel_size, nx, ny, nz, s)) return hipErrorInvalidValue;
     return hipGetLastError();
