@@ -43,15 +43,15 @@ PEAK_HBM_GBPS = 8000.0
 # (profiles/k_fused_step_humanoid48_B24576_hbm_counters.md), scaled by a copy
 # calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
 # it was measured with; reported as null once they change.
-TRAFFIC_MEASURED = {"sources_sha1": "149ec8cf73463d7833c5aee8ed3423f9bb6ca6d1", "states": 24576,
-                    "bytes_per_launch": 30644.0 * 1024}
+TRAFFIC_MEASURED = {"sources_sha1": "fe69a9ff7449180b0470726eae05dde7a5727755", "states": 24576,
+                    "bytes_per_launch": 30467.4 * 1024}
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h")
 
 
 # HBM traffic of the kinematics-outputs kernel, measured the same way
 # (profiles/k_kinematics_humanoid48_B24576.md; 4 tool frames), per launch.
-KIN_TRAFFIC_MEASURED = {"sources_sha1": "0f6cc4a3df15b9cfa666ce9d20f5c930b30cb888", "states": 24576, "tools": 4,
-                        "forward_bytes": (5436.5 + 133147.3) * 1024, "backward_bytes": (9676.0 + 4608.1) * 1024}
+KIN_TRAFFIC_MEASURED = {"sources_sha1": "97e1f5eb1642b2717a5eeb01cb82719756e8fecb", "states": 24576, "tools": 4,
+                        "forward_bytes": (5476.7 + 133171.7) * 1024, "backward_bytes": (9685.0 + 4608.0) * 1024}
 KIN_SOURCES = ("kinematics.hip", "kin.h", "lanes.h", "spatial.h", "wb_internal.h")
 # ... and of the three distance-transform launches on the 256 x 256 x 128 room
 # (profiles/edt_room256_kernel_trace.md), summed per transform.

@@ -62,17 +62,17 @@ __device__ __forceinline__ SV shfl_sv(SV x, int src, int G) {
 }
 __device__ __forceinline__ SV zsv() { return sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f)); }
 
-// Sum of x over the path from the root to this lane's link.
+// Sum of x over the path from the root to this lane's link.  Lane 0 (the
+// fixed root) and the lanes past the robot must hold zero: a chain that has
+// reached the root keeps jumping to lane 0 and adds that zero, exactly, so
+// no lane needs a guard (and no masked copy of x) per step.
 __device__ __forceinline__ SV path_sum(SV x, int parent_lane, int glane, int steps, int G) {
-    int anc = parent_lane;
+    (void)glane;
+    int anc = max(parent_lane, 0);
     for (int s = 0; s < steps; ++s) {
-        const int src = anc < 0 ? glane : anc;
-        const SV y = shfl_sv(x, src, G);
-        const int aa = __shfl(anc, src, G);
-        if (anc >= 0) {
-            x += y;
-            anc = aa;
-        }
+        const SV y = shfl_sv(x, anc, G);
+        anc = __shfl(anc, anc, G);
+        x += y;
     }
     return x;
 }
@@ -181,20 +181,28 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
         R = li[6 * 64 + gl] ? Jr : matmul(R, Jr);
     }
     {
-        int anc = parent_lane;
-        for (int st = 0; st < fz.jsteps; ++st) {
-            const int src = anc < 0 ? glane : anc;
+        // Lane 0 is the fixed root, whose pose is the world frame (identity),
+        // as is every lane past the robot: a chain that has reached the root
+        // keeps composing with that identity, which changes nothing exactly,
+        // so every lane takes every step without a guard.
+        int anc = max(parent_lane, 0);
+        auto jump = [&]() {
             M3 Ra;
 #pragma unroll
-            for (int t = 0; t < 9; ++t) Ra.m[t] = __shfl(R.m[t], src, G);
-            const V3 pa = v3(__shfl(p.x, src, G), __shfl(p.y, src, G), __shfl(p.z, src, G));
-            const int aa = __shfl(anc, src, G);
-            if (anc >= 0) {
-                p = mul(Ra, p) + pa;
-                R = matmul(Ra, R);
-                anc = aa;
-            }
+            for (int t = 0; t < 9; ++t) Ra.m[t] = __shfl(R.m[t], anc, G);
+            const V3 pa = v3(__shfl(p.x, anc, G), __shfl(p.y, anc, G), __shfl(p.z, anc, G));
+            anc = __shfl(anc, anc, G);
+            p = mul(Ra, p) + pa;
+            R = matmul(Ra, R);
+        };
+        // two steps per trip: the pose alternates between two register sets
+        // instead of being copied back after every step
+        int st = 0;
+        for (; st + 1 < fz.jsteps; st += 2) {
+            jump();
+            jump();
         }
+        if (st < fz.jsteps) jump();
     }
     // ---- sphere centres and the link's bounding sphere into the group's LDS
     const int link = li[0 * 64 + gl];

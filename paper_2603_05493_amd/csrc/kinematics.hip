@@ -163,20 +163,27 @@ __device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b,
         R = li[5 * 64 + gl] ? Jr : matmul(R, Jr);
     }
     {
-        int anc = parent_lane;
-        for (int st = 0; st < k.jsteps; ++st) {
-            const int src = anc < 0 ? gl : anc;
+        // Lane 0 is the fixed root at the world frame (identity pose), as is
+        // every lane past the robot: a finished chain keeps composing with
+        // that identity, which changes nothing exactly, so no step needs a
+        // guard; two steps per trip let the pose alternate between register
+        // sets instead of being copied back.
+        int anc = max(parent_lane, 0);
+        auto jump = [&]() {
             M3 Ra;
 #pragma unroll
-            for (int t = 0; t < 9; ++t) Ra.m[t] = __shfl(R.m[t], src, G);
-            const V3 pa = shfl3(p, src, G);
-            const int aa = __shfl(anc, src, G);
-            if (anc >= 0) {
-                p = mul(Ra, p) + pa;
-                R = matmul(Ra, R);
-                anc = aa;
-            }
+            for (int t = 0; t < 9; ++t) Ra.m[t] = __shfl(R.m[t], anc, G);
+            const V3 pa = shfl3(p, anc, G);
+            anc = __shfl(anc, anc, G);
+            p = mul(Ra, p) + pa;
+            R = matmul(Ra, R);
+        };
+        int st = 0;
+        for (; st + 1 < k.jsteps; st += 2) {
+            jump();
+            jump();
         }
+        if (st < k.jsteps) jump();
     }
     if (!BWD && valid && act) {
         const int link = li[0 * 64 + gl];
