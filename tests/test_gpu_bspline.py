@@ -141,7 +141,9 @@ def test_empty_batch():
 
 
 @pytest.mark.parametrize("label,factory,T,K", [("chain7", lambda: synth.serial_chain(7, 5, seed=0), 24, 9),
-                                               ("humanoid48", lambda: synth.humanoid48(seed=0), 8, 9)])
+                                               ("humanoid48", lambda: synth.humanoid48(seed=0), 8, 9),
+                                               # the benchmarked size: 512 trajectories x 48 samples
+                                               ("humanoid48_T512", lambda: synth.humanoid48(seed=0), 512, 9)])
 def test_control_point_iteration_matches_oracle(oracle, label, factory, T, K):
     """Splines -> fused iteration -> control-point gradient, against the
     oracle's composition evaluated at the oracle's own samples.  The
