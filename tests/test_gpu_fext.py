@@ -67,12 +67,22 @@ def test_plain_rnea_with_external_forces(oracle, label, factory, B, qr):
     np.testing.assert_array_equal(_host_fext(g_fext)[:, 0], 0.0)
 
 
-@pytest.mark.parametrize("label,factory,B,qr", CASES)
-def test_fused_iteration_with_external_forces(oracle, label, factory, B, qr):
+def _humanoid_coupled_fingers():
+    from tests.test_gpu_fused import _humanoid_coupled_fingers as h
+    return h()
+
+
+@pytest.mark.parametrize("label,factory,B,qr,n_sample", [c + (None,) for c in CASES] + [
+    # the EXT variant at the optimizer batch: mimic finger joints and forces
+    # on every link, 512 sampled states against the oracle
+    ("humanoid_coupled_fingers_B24576_sampled", _humanoid_coupled_fingers, 24576, 1.5, 512)])
+def test_fused_iteration_with_external_forces(oracle, label, factory, B, qr, n_sample):
     from paper_2603_05493_amd import wb
     rb = factory()
     st = synth.states(rb, B, seed=41, q_range=qr)
     fe = _fext(rb, B, seed=42)
+    sample = (np.sort(np.random.default_rng(43).choice(B, n_sample, replace=False)) if n_sample
+              else np.arange(B))
     r = wb.Robot(rb).to_device("cuda:0")
     n, L = rb.n_dof, rb.n_links
     tw, margin, hw = 1e-3, 0.01, 1.0
@@ -86,21 +96,23 @@ def test_fused_iteration_with_external_forces(oracle, label, factory, B, qr):
     wb.wb_wholebody_step(r, q, qd, qdd, torque_weight=tw, margin=margin, hinge_weight=hw,
                          f_ext=_dev_fext(fe), g_fext=g_fext, **out)
     torch.cuda.synchronize()
-    ref = P.oracle_iteration(oracle, rb, st.q, st.qd, st.qdd, None, tw, margin, hw, fext=fe)
+    ref = P.oracle_iteration(oracle, rb, st.q[sample], st.qd[sample], st.qdd[sample], None, tw, margin, hw,
+                             fext=fe[sample])
     pens = oracle.self_collision_pens(rb, ref["c"])
     ok = P.unambiguous(pens) & (np.abs(ref["max_pen"] + margin) >= P.DELTA)
     cond = P.hinge_conditioning(ref, rb)
-    e_gq_all = P.normwise(P.host(out["g_q"]), ref["g_q"], floor=1e-6)
-    errs = dict(tau=P.normwise(P.host(out["tau"]), ref["tau"], floor=1e-3).max(),
-                cost=(np.abs(P.host(out["cost"]) - ref["cost"]) / P.cost_scale(ref, None, tw, margin))[ok].max(),
+    h = lambda x: P.host(x)[sample]
+    e_gq_all = P.normwise(h(out["g_q"]), ref["g_q"], floor=1e-6)
+    errs = dict(tau=P.normwise(h(out["tau"]), ref["tau"], floor=1e-3).max(),
+                cost=(np.abs(h(out["cost"]) - ref["cost"]) / P.cost_scale(ref, None, tw, margin))[ok].max(),
                 g_q=e_gq_all[ok & (cond <= 1.0)].max(),
-                g_qd=P.normwise(P.host(out["g_qd"]), ref["g_qd"], floor=1e-6).max(),
-                g_qdd=P.normwise(P.host(out["g_qdd"]), ref["g_qdd"], floor=1e-6).max(),
-                g_fext=P.normwise(_host_fext(g_fext), ref["g_fext"], floor=1e-6).max())
+                g_qd=P.normwise(h(out["g_qd"]), ref["g_qd"], floor=1e-6).max(),
+                g_qdd=P.normwise(h(out["g_qdd"]), ref["g_qdd"], floor=1e-6).max(),
+                g_fext=P.normwise(_host_fext(g_fext)[sample], ref["g_fext"], floor=1e-6).max())
     print(label, "fused", " ".join(f"{k}={v:.3g}" for k, v in errs.items()), "checked", int(ok.sum()), flush=True)
     assert all(v < P.TOL for v in errs.values())
     assert np.all(e_gq_all[ok] <= P.TOL * np.maximum(cond[ok], 1.0))
-    assert ok.sum() > 0.8 * B
+    assert ok.sum() > 0.8 * len(sample)
 
 
 def test_fused_external_force_outputs_are_independent():
