@@ -42,9 +42,10 @@ PEAK_HBM_GBPS = 8000.0
 # HBM traffic of the fused kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (profiles/k_fused_step_humanoid48_B24576_hbm_counters.md), scaled by a copy
 # calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
-# it was measured with; reported as null once they change.
+# and the launch shape (states per workgroup) it was measured with; reported
+# as null once either changes.
 TRAFFIC_MEASURED = {"sources_sha1": "fe69a9ff7449180b0470726eae05dde7a5727755", "states": 24576,
-                    "bytes_per_launch": 30467.4 * 1024}
+                    "states_per_item": 8, "bytes_per_launch": 29711.0 * 1024}
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h")
 
 
@@ -302,7 +303,8 @@ def main():
     if fused_ms is not None:
         achieved = flop / (fused_ms * 1e-3) / 1e12
         traffic = None
-        if fused_sources_sha1() == TRAFFIC_MEASURED["sources_sha1"] and B == TRAFFIC_MEASURED["states"]:
+        if (fused_sources_sha1() == TRAFFIC_MEASURED["sources_sha1"] and B == TRAFFIC_MEASURED["states"]
+                and robot.get_tune()["states_per_item"] == TRAFFIC_MEASURED["states_per_item"]):
             traffic = TRAFFIC_MEASURED["bytes_per_launch"]
         alg_bytes = B * (6 * 4 * n + 16)
         out["roofline"] = {"bound": "alu", "kernel": "k_fused_step", "achieved": achieved,
@@ -508,8 +510,9 @@ def bench_edt(args, reps: int = 20):
 
 def bench_uneven(args):
     """Random trees of 7/12/23/48 DoF with 8192/4096/2048/1024 states: one
-    persistent plan launch (tuned shapes) replayed from a HIP graph, against
-    one plain launch sequence per tree."""
+    persistent plan launch (plan shapes: narrowest lanes, two rounds per
+    work item, costs from the tuned table) replayed from a HIP graph,
+    against one plain launch sequence per tree."""
     import torch
     from paper_2603_05493_amd import synth, tune, wb
     from paper_2603_05493_amd.iteration import PlainIteration, PlanIteration
@@ -528,7 +531,8 @@ def bench_uneven(args):
     total = sum(Bs)
     kw = dict(torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=0.0)
 
-    plan = PlanIteration(robots, Bs, outputs=False, **kw)
+    shapes = [tune.plan_tune(r, table) for r in robots]
+    plan = PlanIteration(robots, Bs, tunes=shapes, outputs=False, **kw)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -563,7 +567,7 @@ def bench_uneven(args):
                            "items": plan.plan.n_items, "workgroups": plan.plan.n_workgroups},
             "plain_per_tree": {"states_per_s": total / t_plain, "ms_per_step": t_plain * 1e3},
             "speedup": t_plain / t_plan,
-            "shapes": [r.get_tune() for r in robots]}
+            "shapes": shapes}
 
 
 if __name__ == "__main__":

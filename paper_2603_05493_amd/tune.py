@@ -28,7 +28,10 @@ from . import synth, wb
 from .iteration import FusedIteration
 
 LANES = (16, 32, 64)
-ITEMS = (4, 8, 16, 32, 64)
+# states per work item: powers of two and the sizes between them, so that a
+# batch can fill whole rounds of the chip's resident workgroups (a partial
+# last round leaves compute units idle)
+ITEMS = (4, 6, 8, 12, 16, 24, 32, 48, 64)
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned", "mi355x.json")
 
 
@@ -55,15 +58,20 @@ def measure(robot: wb.Robot, qs, shape: Dict, reps: int = 10, warmup: int = 3) -
 
 
 def tune_robot(robot: wb.Robot, desc, B: int, lanes: Iterable[int] = LANES, items: Iterable[int] = ITEMS,
-               reps: int = 10) -> Dict:
+               reps: int = 20, rounds: int = 5) -> Dict:
+    """Time every candidate shape `rounds` times, the candidates interleaved
+    within each round so that clock and thermal drift reach all of them
+    alike, and keep the one with the lowest median."""
     qs = _states(robot, desc, B)
-    cands = []
-    for g in lanes:
-        if g < robot.n_links:
-            continue
-        for c in items:
-            t = measure(robot, qs, {"lanes_per_state": g, "states_per_item": c}, reps=reps)
-            cands.append([g, c, t / B * 1e9])
+    # a work item smaller than one round of the workgroup's 4 wavefronts
+    # (4 * 64 / G states) leaves wavefronts idle, in the fused launch and in
+    # a plan's work list alike: only whole rounds are candidates
+    shapes = [(g, c) for g in lanes if g >= robot.n_links for c in items if c % (4 * (64 // g)) == 0]
+    times = {s: [] for s in shapes}
+    for _ in range(rounds):
+        for g, c in shapes:
+            times[(g, c)].append(measure(robot, qs, {"lanes_per_state": g, "states_per_item": c}, reps=reps))
+    cands = [[g, c, float(np.median(times[(g, c)])) / B * 1e9] for g, c in shapes]
     best = min(cands, key=lambda x: x[2])
     robot.set_tune(best[0], best[1], best[2])
     return {"lanes_per_state": best[0], "states_per_item": best[1], "ns_per_state": best[2], "B": B,
@@ -79,6 +87,24 @@ def apply(robot: wb.Robot, table: Dict) -> bool:
     return True
 
 
+def plan_tune(robot: wb.Robot, table: Optional[Dict] = None, rounds: int = 2) -> Dict:
+    """Launch shape of one tree inside a multi-robot plan.  A plan is a
+    different launch from a single robot's: its few hundred workgroups take
+    work items from a balanced list, so fine items balance best, and the
+    narrowest group of lanes per state keeps a workgroup's wavefronts on
+    more states at once.  Measured on the four-tree uneven batch (trees of
+    7/12/23/48 joints, 8192/4096/2048/1024 states): the narrowest lanes
+    with two rounds of the workgroup per item (4 * 64 / G states a round)
+    ran at 276-280 M states/s, against 247-250 M with one round, 226 M with
+    three and 183 M with four, and 223 M with the single-robot tune's
+    32 lanes for the 13-link tree.  The per-state cost that balances the
+    list comes from the single-robot table when it has the topology."""
+    g = 16 if robot.n_links <= 16 else (32 if robot.n_links <= 32 else 64)
+    e = (table or {}).get(robot.topology_key(), {})
+    return {"lanes_per_state": g, "states_per_item": rounds * 4 * (64 // g),
+            "ns_per_state": float(e.get("ns_per_state", 0.0))}
+
+
 def load(path: Optional[str] = None) -> Dict:
     path = path or DEFAULT_TABLE
     if not os.path.exists(path):
@@ -90,7 +116,7 @@ def load(path: Optional[str] = None) -> Dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_TABLE)
-    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
     torch.cuda.set_device(0)
     table = {}

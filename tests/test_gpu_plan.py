@@ -88,6 +88,28 @@ def test_plan_uneven_trees_against_oracle(oracle):
         _oracle_check(oracle, rb, st, buf, f"plan {rb.name} B={B}")
 
 
+def test_plan_tune_shapes_against_oracle(oracle):
+    """The plan shapes the benchmark uses (narrowest lanes, two rounds of the
+    workgroup per work item, costs from the tuned table) on the uneven
+    trees, against the oracle."""
+    from paper_2603_05493_amd import tune
+    from paper_2603_05493_amd.iteration import PlanIteration
+    jobs = _uneven()
+    robots = [_robot(rb) for rb, _ in jobs]
+    table = tune.load()
+    tunes = [tune.plan_tune(r, table) for r in robots]
+    for r, t in zip(robots, tunes):
+        g = t["lanes_per_state"]
+        assert g >= r.n_links and (g == 16 or g // 2 < r.n_links)
+        assert t["states_per_item"] == 2 * 4 * (64 // g)
+    sts = [synth.states(rb, B, seed=90 + i) for i, (rb, B) in enumerate(jobs)]
+    it = PlanIteration(robots, [B for _, B in jobs], tunes=tunes)
+    it.run([(P.dev(s.q), P.dev(s.qd), P.dev(s.qdd)) for s in sts], step=False)
+    torch.cuda.synchronize()
+    for (rb, B), st, buf in zip(jobs, sts, it.bufs):
+        _oracle_check(oracle, rb, st, buf, f"plan (plan shapes) {rb.name} B={B}")
+
+
 def test_plan_matches_single_robot_launch_bitwise():
     from paper_2603_05493_amd.iteration import FusedIteration, PlanIteration
     jobs = _uneven()
@@ -146,9 +168,11 @@ def test_autotuner_picks_a_valid_shape():
     from paper_2603_05493_amd import tune
     rb = synth.random_tree(7, 6, seed=0)
     r = _robot(rb)
-    res = tune.tune_robot(r, rb, 2048, lanes=(16, 64), items=(8, 16), reps=2)
+    res = tune.tune_robot(r, rb, 2048, lanes=(16, 64), items=(8, 16), reps=2, rounds=2)
     assert res["lanes_per_state"] in (16, 64) and res["states_per_item"] in (8, 16)
-    assert len(res["candidates"]) == 4 and res["ns_per_state"] > 0
+    # (16 lanes, 8 states) is less than one round of the workgroup (16 states) and is not offered
+    assert sorted((g, c) for g, c, _ in res["candidates"]) == [(16, 16), (64, 8), (64, 16)]
+    assert res["ns_per_state"] > 0
     assert r.get_tune()["lanes_per_state"] == res["lanes_per_state"]
     assert tune.apply(r, {r.topology_key(): res})
 
