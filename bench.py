@@ -400,6 +400,8 @@ def bench_ext_variant(args, st, reps: int = 50):
     rb.joint_index = np.array([remap[int(j)] if j >= 0 else -1 for j in ji], dtype=np.int32)
     rb.joint_mult = synth._f32(jm)
     r = wb.Robot(rb).to_device("cuda:0")
+    from paper_2603_05493_amd import tune
+    tune.apply(r, tune.load())   # the same topology as the humanoid: its tuned shape
     B, n, L = st.B, rb.n_dof, rb.n_links
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a.T.astype(np.float32))).cuda()
     q, qd, qdd = d(st.q[:, :n]), d(st.qd[:, :n]), d(st.qdd[:, :n])
@@ -422,7 +424,8 @@ def bench_ext_variant(args, st, reps: int = 50):
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / reps * 1e-3
     return {"robot": "humanoid48 with coupled fingers (40 joints, 48 links)", "states": B, "kernel_us": t * 1e6,
-            "states_per_s": B / t, "features": "mimic joints, external link forces and their gradient, step"}
+            "states_per_s": B / t, "features": "mimic joints, external link forces and their gradient, step",
+            "states_per_workgroup": r.get_tune()["states_per_item"]}
 
 
 def bench_kinematics(args, robot, q, reps: int = 50):
