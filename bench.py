@@ -44,8 +44,8 @@ PEAK_HBM_GBPS = 8000.0
 # calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
 # and the launch shape (states per workgroup) it was measured with; reported
 # as null once either changes.
-TRAFFIC_MEASURED = {"sources_sha1": "fe69a9ff7449180b0470726eae05dde7a5727755", "states": 24576,
-                    "states_per_item": 8, "bytes_per_launch": 29711.0 * 1024}
+TRAFFIC_MEASURED = {"sources_sha1": "525888b65b98bd1b0279e5cdd2334260a750b910", "states": 24576,
+                    "states_per_item": 8, "bytes_per_launch": 29710.6 * 1024}
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h")
 
 
@@ -513,7 +513,7 @@ def bench_edt(args, reps: int = 20):
 
 def bench_uneven(args):
     """Random trees of 7/12/23/48 DoF with 8192/4096/2048/1024 states: one
-    persistent plan launch (plan shapes: narrowest lanes, two rounds per
+    persistent plan launch (plan shapes: narrowest lanes, one round per
     work item, costs from the tuned table) replayed from a HIP graph,
     against one plain launch sequence per tree."""
     import torch

@@ -476,6 +476,28 @@ static hipError_t launch_plan_t(const PlanArgs &a, int n_wg, size_t lds, bool ex
     return hipGetLastError();
 }
 
+template <int NMAX>
+static int plan_workgroups_per_cu_t(bool ext, size_t lds) {
+    int n = 0;
+    const hipError_t e = ext ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plan_step<NMAX, true>, 256, lds)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_plan_step<NMAX, false>, 256, lds);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+int plan_workgroups_per_cu(int nmax, bool ext, size_t lds) {
+    switch (nmax) {
+        case 1: return plan_workgroups_per_cu_t<1>(ext, lds);
+        case 2: return plan_workgroups_per_cu_t<2>(ext, lds);
+        case 3: return plan_workgroups_per_cu_t<3>(ext, lds);
+        case 4: return plan_workgroups_per_cu_t<4>(ext, lds);
+        case 5: return plan_workgroups_per_cu_t<5>(ext, lds);
+        case 6: return plan_workgroups_per_cu_t<6>(ext, lds);
+        case 7: return plan_workgroups_per_cu_t<7>(ext, lds);
+        case 8: return plan_workgroups_per_cu_t<8>(ext, lds);
+        default: return 1;
+    }
+}
+
 hipError_t launch_plan(const PlanArgs &a, int nmax, int n_wg, size_t lds, bool ext, hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
     switch (nmax) {

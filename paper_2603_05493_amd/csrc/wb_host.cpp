@@ -1153,7 +1153,14 @@ int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_tr
             dev_cus > 0)
             cus = dev_cus;
     }
-    const int n_wg = (int)std::min<size_t>(items.size(), (size_t)cus * 2);
+    // one persistent round: as many workgroups as the compute units keep
+    // resident for the kernel variant the plan runs (the mimic variant when
+    // a tree has mimic joints; a plan that turns to it for external forces
+    // alone runs the same list in more than one round)
+    bool any_mimic = false;
+    for (int i = 0; i < n_trees; ++i) any_mimic |= robots[i]->fz.mimic != 0;
+    const int per_cu = std::min(8, wb::plan_workgroups_per_cu(nmax, any_mimic, lds));
+    const int n_wg = (int)std::min<size_t>(items.size(), (size_t)cus * per_cu);
     std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
     std::vector<double> load(n_wg, 0.0);
     std::vector<std::vector<wb::PlanItem>> per_wg(n_wg);

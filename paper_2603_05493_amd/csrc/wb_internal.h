@@ -134,6 +134,9 @@ struct PlanArgs {
 
 hipError_t launch_fused(const FusedArgs &a, hipStream_t s);
 hipError_t launch_plan(const PlanArgs &a, int nmax, int n_wg, size_t lds, bool ext, hipStream_t s);
+// Workgroups of the plan kernel (variant nmax, ext, `lds` bytes of dynamic
+// LDS) that one compute unit keeps resident; at least 1.
+int plan_workgroups_per_cu(int nmax, bool ext, size_t lds);
 
 // Kernel launchers (each defined next to its kernels).
 hipError_t launch_fk(const DevRobot &rb, int64_t B, const float *q, float *pose, float *spheres,

@@ -87,18 +87,19 @@ def apply(robot: wb.Robot, table: Dict) -> bool:
     return True
 
 
-def plan_tune(robot: wb.Robot, table: Optional[Dict] = None, rounds: int = 2) -> Dict:
+def plan_tune(robot: wb.Robot, table: Optional[Dict] = None, rounds: int = 1) -> Dict:
     """Launch shape of one tree inside a multi-robot plan.  A plan is a
-    different launch from a single robot's: its few hundred workgroups take
-    work items from a balanced list, so fine items balance best, and the
-    narrowest group of lanes per state keeps a workgroup's wavefronts on
-    more states at once.  Measured on the four-tree uneven batch (trees of
-    7/12/23/48 joints, 8192/4096/2048/1024 states): the narrowest lanes
-    with two rounds of the workgroup per item (4 * 64 / G states a round)
-    ran at 276-280 M states/s, against 247-250 M with one round, 226 M with
-    three and 183 M with four, and 223 M with the single-robot tune's
-    32 lanes for the 13-link tree.  The per-state cost that balances the
-    list comes from the single-robot table when it has the topology."""
+    different launch from a single robot's: its workgroups (as many as the
+    compute units keep resident) take work items from a balanced list, so
+    fine items balance best, and the narrowest group of lanes per state
+    keeps a workgroup's wavefronts on more states at once.  Measured on the
+    four-tree uneven batch (trees of 7/12/23/48 joints, 8192/4096/2048/1024
+    states) at three workgroups per CU: the narrowest lanes (16/16/32/64)
+    with one round of the workgroup per item (4 * 64 / G states) ran at
+    369-373 M states/s, with two rounds 301-312 M, and 288-289 M with the
+    single-robot tune's 32 lanes for the 13-link tree.  The per-state cost
+    that balances the list comes from the single-robot table when it has
+    the topology."""
     g = 16 if robot.n_links <= 16 else (32 if robot.n_links <= 32 else 64)
     e = (table or {}).get(robot.topology_key(), {})
     return {"lanes_per_state": g, "states_per_item": rounds * 4 * (64 // g),
