@@ -406,7 +406,11 @@ int wb_edt(int32_t nx, int32_t ny, int32_t nz, const uint8_t *sites, float voxel
  * batch size, in one persistent launch (suitable for HIP graph capture; the
  * paper captures its whole iteration in CUDA graphs, Sec. 7.2).  The plan
  * owns a static work list of (robot, state range) items balanced over the
- * workgroups by cost (longest first), using each robot's tune record.
+ * workgroups by cost (longest first), using each robot's tune record.  The
+ * launch has as many workgroups as the device's compute units keep
+ * resident for the plan kernel (its occupancy at the plan's LDS size), so
+ * that every workgroup runs from the start; with an item count below that,
+ * one workgroup per item.
  *   wb_plan_create: robots[n_trees] (created on one device, each
  *     fused_supported), B[n_trees] states per robot, tune[n_trees] or NULL
  *     (each robot's current record); 1 <= n_trees <= 16.  Allocates the
