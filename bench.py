@@ -51,8 +51,9 @@ FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h"
 
 # HBM traffic of the kinematics-outputs kernel, measured the same way
 # (profiles/k_kinematics_humanoid48_B24576.md; 4 tool frames), per launch.
-KIN_TRAFFIC_MEASURED = {"sources_sha1": "97e1f5eb1642b2717a5eeb01cb82719756e8fecb", "states": 24576, "tools": 4,
-                        "forward_bytes": (5476.7 + 133171.7) * 1024, "backward_bytes": (9685.0 + 4608.0) * 1024}
+KIN_TRAFFIC_MEASURED = {"sources_sha1": "3ab2f81f4a04f9d1a92a4e4dc8a96f08b93d823f", "states": 24576, "tools": 4,
+                        "forward_bytes": (5473.2 + 133170.7) * 1024,
+                        "backward_bytes": (9685.0 + 4608.0) * 1024}
 KIN_SOURCES = ("kinematics.hip", "kin.h", "lanes.h", "spatial.h", "wb_internal.h")
 # ... and of the three distance-transform launches on the 256 x 256 x 128 room
 # (profiles/edt_room256_kernel_trace.md), summed per transform.
