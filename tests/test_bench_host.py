@@ -39,3 +39,20 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_tuned_shapes_are_whole_workgroup_rounds():
+    """Every shape in the shipped tuning table keeps all four wavefronts of
+    a workgroup busy (a multiple of 4 * 64 / G states) and is valid."""
+    import json
+    path = os.path.join(ROOT, "paper_2603_05493_amd", "tuned", "mi355x.json")
+    with open(path) as f:
+        table = json.load(f)
+    assert table
+    for key, e in table.items():
+        g, c = e["lanes_per_state"], e["states_per_item"]
+        assert g in (16, 32, 64), key
+        assert c % (4 * (64 // g)) == 0, key
+        assert e["ns_per_state"] > 0, key
+        best = min(e["candidates"], key=lambda x: x[2])
+        assert [g, c] == best[:2], key
