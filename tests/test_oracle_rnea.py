@@ -197,6 +197,65 @@ def test_external_force_gradient(oracle):
         np.testing.assert_allclose(gfe[:, k, i], fd, rtol=1e-6, atol=1e-9)
 
 
+def _link_jacobians(oracle, rb, q, h=1e-6):
+    """World Jacobians of every link frame from forward kinematics alone:
+    Jw[k, :, j] is link k's angular velocity per unit rate of joint j (the vee
+    of dR_k/dq_j R_k^T) and Jv[k, :, j] the velocity of its origin, both by
+    central differences of the oracle's link poses."""
+    n, L = q.shape[0], rb.n_links
+    R0, _, _ = oracle.fk(rb, q[None])
+    Jw, Jv = np.zeros((L, 3, n)), np.zeros((L, 3, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = h
+        Rp, pp, _ = oracle.fk(rb, (q + e)[None])
+        Rm, pm, _ = oracle.fk(rb, (q - e)[None])
+        Jv[:, :, j] = (pp[0] - pm[0]) / (2 * h)
+        for k in range(L):
+            Jw[k, :, j] = energy._vee((Rp[0, k] - Rm[0, k]) / (2 * h) @ R0[0, k].T)
+    return R0[0], Jw, Jv
+
+
+@pytest.mark.parametrize("which", ["moment", "force"])
+@pytest.mark.parametrize("label,factory", [
+    ("chain7", lambda: synth.serial_chain(7, 1, seed=24, random_fixed_rotation=True)),
+    ("tree9", lambda: synth.random_tree(9, 1, seed=25, random_fixed_rotation=True)),
+    ("humanoid48", lambda: synth.humanoid48(seed=0)),
+])
+def test_external_force_is_virtual_work(oracle, label, factory, which):
+    """Alg. 4's external-force term against the principle of virtual work.
+
+    A wrench applied to link k -- moment n_k and force f_k in link k's axes,
+    the force acting at the link origin -- does work at the rate
+    (R_k n_k) . w_k + (R_k f_k) . v_k, with w_k and v_k the world angular
+    velocity and origin velocity of the link.  At rest (qd = qdd = 0) the
+    joint torques it relieves are therefore
+        tau(q, 0, 0, f) - tau(q, 0, 0, 0) = -sum_k Jw_k^T R_k n_k - Jv_k^T R_k f_k,
+    with the link Jacobians taken from forward kinematics only.  Moments and
+    forces are checked separately, so a flipped sign, forces read in world
+    axes or applied at another point of the link each fail one of them."""
+    rb = factory()
+    B = 2
+    st = synth.states(rb, B, seed=26, q_range=1.5)
+    rng = np.random.default_rng(27)
+    fext = rng.normal(size=(B, rb.n_links, 6))
+    fext[:, :, 3:] *= 10.0   # forces of tens of newtons beside moments of a few N m
+    if which == "moment":
+        fext[:, :, 3:] = 0.0
+    else:
+        fext[:, :, :3] = 0.0
+    fext[:, 0, :] = 0.0      # the fixed root takes no wrench into any joint
+    z = np.zeros_like(st.q)
+    dtau = oracle.rnea(rb, st.q, z, z, fext) - oracle.rnea(rb, st.q, z, z)
+    for b in range(B):
+        R, Jw, Jv = _link_jacobians(oracle, rb, st.q[b])
+        nw = np.einsum("kij,kj->ki", R, fext[b, :, :3])
+        fw = np.einsum("kij,kj->ki", R, fext[b, :, 3:])
+        ref = -(np.einsum("kin,ki->n", Jw, nw) + np.einsum("kin,ki->n", Jv, fw))
+        np.testing.assert_allclose(dtau[b], ref, rtol=1e-6, atol=1e-6 * np.abs(ref).max())
+        assert np.abs(ref).max() > 1.0   # the pin is not vacuous
+
+
 def test_mimic_torque_is_virtual_work(oracle):
     """Coupled links: tau_j = sum_k m_k tau_k of the expanded robot (virtual work)."""
     rb = synth.serial_chain(4, 1, seed=22)

@@ -73,26 +73,50 @@ def test_degenerate_no_pairs(oracle):
     assert np.all(np.isneginf(mp)) and np.all(am == -1) and np.all(nc == 0)
 
 
-def test_hinge_backward_matches_fd(oracle):
+@pytest.mark.parametrize("r_scale,margin", [(1.0, 0.01), (0.5, 0.03)])
+def test_hinge_backward_matches_fd(oracle, r_scale, margin):
+    """The hinge gradient against central differences of the hinge cost: all
+    three coordinates of both spheres of the most penetrating pair in every
+    state away from the non-smooth points, and every other sphere (which
+    must get exactly zero) in a few of them.  With smaller spheres and a
+    wider margin, some states sit inside the margin without touching (the
+    hinge is on) and some beyond it (the gradient is zero)."""
     rb = synth.random_tree(12, 3, seed=6)
-    st = synth.states(rb, 16, seed=7)
+    rb.sphere_r = synth._f32(rb.sphere_r * r_scale)
+    B = 16
+    st = synth.states(rb, B, seed=7)
     _, _, c = oracle.fk(rb, st.q)
-    margin = 0.01
     mp, am, _ = oracle.self_collision(rb, c)
+    if r_scale < 1.0:
+        assert ((mp < 0) & (mp + margin > 1e-4)).sum() >= 3 and (mp + margin < -1e-4).sum() >= 3
     pens = oracle.self_collision_pens(rb, c)
     srt = np.sort(pens, 1)
     gap = srt[:, -1] - srt[:, -2]
     ok = (gap > 1e-4) & (np.abs(mp + margin) > 1e-4)   # away from the non-smooth points
-    w = synth.weights(16, seed=8)
+    assert ok.sum() >= 12
+    w = synth.weights(B, seed=8)
     g = oracle.self_collision_backward(rb, c, am, mp, margin, w)
+    ps, pt = oracle.pairs(rb)
     h = 1e-7
-    for b in np.where(ok)[0][:6]:
-        for s in range(0, rb.n_spheres, 5):
+
+    def fd(b, s, i):
+        cp, cm = c[b:b + 1].copy(), c[b:b + 1].copy()
+        cp[0, s, i] += h
+        cm[0, s, i] -= h
+        return w[b] * (oracle.hinge(oracle.self_collision(rb, cp)[0], margin) -
+                       oracle.hinge(oracle.self_collision(rb, cm)[0], margin))[0] / (2 * h)
+
+    n_nonzero = 0
+    for k, b in enumerate(np.where(ok)[0]):
+        spheres = [ps[am[b]], pt[am[b]]]
+        if k < 3:
+            spheres = range(rb.n_spheres)
+        for s in spheres:
             for i in range(3):
-                cp, cm = c[b:b + 1].copy(), c[b:b + 1].copy()
-                cp[0, s, i] += h
-                cm[0, s, i] -= h
-                fd = w[b] * (oracle.hinge(oracle.self_collision(rb, cp)[0], margin) -
-                             oracle.hinge(oracle.self_collision(rb, cm)[0], margin)) / (2 * h)
-                assert abs(g[b, s, i] - fd[0]) < 1e-6
-    assert ok.sum() >= 6
+                ref = fd(b, s, i)
+                assert abs(g[b, s, i] - ref) < 1e-6 * max(1.0, abs(w[b]))
+                n_nonzero += abs(ref) > 1e-3
+        others = np.setdiff1d(np.arange(rb.n_spheres), [ps[am[b]], pt[am[b]]])
+        assert np.all(g[b, others] == 0.0)
+    # both spheres of each colliding pair carry a gradient
+    assert n_nonzero >= 2 * int((ok & (mp + margin > 0)).sum())
