@@ -480,7 +480,7 @@ def bench_kinematics(args, robot, q, reps: int = 50):
 def bench_edt(args, reps: int = 20):
     """The exact distance transform of a room-scan site grid: 256 x 256 x 128
     voxels (a 5.12 m x 5.12 m x 2.56 m room at the paper's 20 mm ESDF voxel),
-    nearest site and distance for every voxel, five launches timed together
+    nearest site and distance for every voxel, three launches timed together
     with HIP events on the launching stream."""
     import torch
     from paper_2603_05493_amd import sitegrid, wb

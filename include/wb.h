@@ -393,7 +393,7 @@ int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune);
  *     distance, +inf when there is no site;
  *   workspace: wb_edt_workspace_bytes bytes of device memory, 256-byte
  *     aligned, reused across calls on one stream.
- * Five launches whose shapes depend only on the grid size; never allocates
+ * Three launches whose shapes depend only on the grid size; never allocates
  * or synchronizes.  WB_ERR_INVALID_ARG for extents outside the range, a
  * non-finite or negative voxel_size, or missing pointers. */
 #define WB_EDT_MAX_DIM 1024

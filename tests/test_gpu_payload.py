@@ -46,6 +46,8 @@ def test_payload_update_matches_oracle(oracle, label, factory, link):
     n = rb.n_dof
     tau0 = torch.empty((n, B), device="cuda")
     wb.wb_rnea(r, q, qd, qdd, tau0)
+    plan = wb.Plan([r], [B])   # created before the update: its tables must pick up the new inertia
+    torch.cuda.synchronize()
     r.set_link_inertia(link, heavy.mass[link], heavy.com[link], _i6(heavy.inertia[link]))
     tau = torch.empty((n, B), device="cuda")
     wb.wb_rnea(r, q, qd, qdd, tau)
@@ -62,8 +64,7 @@ def test_payload_update_matches_oracle(oracle, label, factory, link):
           flush=True)
     assert e_plain < P.TOL and e_fused < P.TOL and e_before < P.TOL
     assert changed > 100 * P.TOL          # the payload really changes the torques
-    # a plan created before the update sees the new values too
-    plan = wb.Plan([r], [B])
+    # the plan created before the update sees the new values too
     tp = torch.empty((n, B), device="cuda")
     plan.run([dict(q=q.clone(), qd=qd.clone(), qdd=qdd.clone(), tau=tp)], 1e-3, 0.01, 1.0, 0.0)
     torch.cuda.synchronize()
