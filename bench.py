@@ -71,13 +71,32 @@ def fused_sources_sha1(sources=FUSED_SOURCES) -> str:
     return h.hexdigest()
 
 
-def algorithmic_flop_per_state(L: int, S: int, P: int, n: int) -> float:
-    """Work model of one iteration per state (FMA = 2 FLOP): FK 135/link +
-    18/sphere; pair sweep 11/pair; RNEA 290/link; VJP 860/link with
-    recomputed forward quantities; hinge FK adjoint 2 x 15 + 38/link;
-    cost head and step 10/joint."""
+def nonpair_flop_per_state(L: int, S: int, n: int) -> float:
+    """Work of one iteration per state outside the pair sweep (FMA = 2 FLOP),
+    the per-unit figures of the work model: FK 135/link + 18/sphere; RNEA
+    290/link; VJP 500/link (forward quantities kept, nothing recomputed, as
+    the fused kernel does); hinge FK adjoint 2 x 15 (its two spheres) +
+    38/link; cost head and step 10/joint.  Links are the jointed ones (the
+    fixed root is not counted)."""
     links = L - 1
-    return 135 * links + 18 * S + 11 * P + 290 * links + 860 * links + 30 + 38 * links + 10 * n
+    return 135 * links + 18 * S + 290 * links + 500 * links + 30 + 38 * links + 10 * n
+
+
+def algorithmic_flop_per_state(L: int, S: int, P: int, n: int) -> float:
+    """The method's own work per state: every checked pair gets one distance
+    (11 FLOP: difference 3, squared norm 5, radius sum and penetration 2,
+    square root 1), no pruning credited, plus nonpair_flop_per_state."""
+    return 11 * P + nonpair_flop_per_state(L, S, n)
+
+
+BLOCK_TEST_FLOP = 9   # one link-block test: difference 3, squared norm 5, compare 1
+
+
+def executed_flop_per_state(L: int, S: int, n: int, pairs_evaluated: float, block_tests: float) -> float:
+    """Work the fused kernel executes per state: the pairs its exact broad
+    phase sweeps (padded sphere slots included) and its block tests, plus
+    the same non-pair work as the model."""
+    return 11 * pairs_evaluated + BLOCK_TEST_FLOP * block_tests + nonpair_flop_per_state(L, S, n)
 
 
 # One VALU issue slot = one lane of one VALU instruction; the chip issues
@@ -92,8 +111,60 @@ def issue_slots_per_state(L: int, S: int, P: int, n: int) -> float:
     (difference 3, squared norm 3, sqrt 4 at quarter rate, radius sum and
     penetration 2, max / argmax / count selects 4); everything else is the
     FLOP model's non-pair work with every FMA paired (FLOP / 2)."""
-    other = algorithmic_flop_per_state(L, S, P, n) - 11 * P
-    return 16 * P + other / 2
+    return 16 * P + nonpair_flop_per_state(L, S, n) / 2
+
+
+def sweep_work(centres, radius, sph_link, pair_s, pair_t, nmax: int, lanes_per_state: int):
+    """Pair evaluations and link-block tests that the fused kernel's exact
+    broad phase executes, per state, from the kernel's own rule applied on
+    the host to sphere centres `centres` [B, S, 3] (radii [S], link of each
+    sphere [S], the checked pairs (pair_s, pair_t)):
+      link bound: centroid C_a of the link's centres, reach R_a = max |c - C_a| + r;
+      eps = 4e-6 (1 + max_a(|C_a| + R_a));
+      pass 1 sweeps the blocks with |C_a - C_b| <= R_a + R_b + eps;
+      if their maximum M0 < 0, pass 2 sweeps the other blocks whose bound
+      R_a + R_b - |C_a - C_b| >= t1 - eps, t1 = M0 or (when pass 1 swept
+      nothing) the exact maximum of the block with the largest bound, which
+      costs one more block.
+    A swept block costs nmax x nmax pair evaluations (rows of padded slots);
+    each pass tests every block of the table, padded to a multiple of
+    2 x lanes_per_state.  Returns (pairs_evaluated [B], block_tests [B],
+    blocks swept [B], blocks in the table)."""
+    c = np.asarray(centres, dtype=np.float64)
+    r = np.asarray(radius, dtype=np.float64)
+    sl = np.asarray(sph_link)
+    links = np.unique(sl)
+    Cl = np.stack([c[:, sl == a].mean(1) for a in links], 1)                       # [B, nl, 3]
+    Rl = np.stack([(np.linalg.norm(c[:, sl == a] - Cl[:, i:i + 1], axis=-1) + r[sl == a]).max(1)
+                   for i, a in enumerate(links)], 1)                                  # [B, nl]
+    ext = (np.linalg.norm(Cl, axis=-1) + Rl).max(1)
+    eps = 4e-6 * (1.0 + ext)
+    li = {int(a): i for i, a in enumerate(links)}
+    ps, pt = np.asarray(pair_s), np.asarray(pair_t)
+    key = np.array([li[int(a)] * len(links) + li[int(b)] for a, b in zip(sl[ps], sl[pt])])
+    blocks, inv = np.unique(key, return_inverse=True)
+    A, Bb = blocks // len(links), blocks % len(links)
+    d = Cl[:, A] - Cl[:, Bb]
+    d2 = (d * d).sum(-1)
+    s1 = Rl[:, A] + Rl[:, Bb] + eps[:, None]
+    surv1 = d2 <= s1 * np.abs(s1)
+    bound = Rl[:, A] + Rl[:, Bb] - np.sqrt(d2)
+    diff = c[:, ps] - c[:, pt]
+    pens = r[ps] + r[pt] - np.sqrt((diff * diff).sum(-1))                               # [B, P]
+    order = np.argsort(inv, kind="stable")
+    starts = np.searchsorted(inv[order], np.arange(len(blocks)))
+    bmax = np.maximum.reduceat(pens[:, order], starts, axis=1)                          # [B, n_blocks]
+    M0 = np.where(surv1, bmax, -np.inf).max(1)
+    need2 = M0 < 0
+    none1 = ~surv1.any(1)
+    seed = bmax[np.arange(len(c)), np.argmax(bound, 1)]
+    t1 = np.where(none1, seed, M0)
+    surv2 = need2[:, None] & ~surv1 & (bound >= (t1 - eps)[:, None])
+    swept = surv1.sum(1) + surv2.sum(1) + none1
+    G2 = 2 * lanes_per_state
+    nb = (len(blocks) + G2 - 1) // G2 * G2
+    tests = nb * (1 + need2)
+    return nmax * nmax * swept, tests, swept, len(blocks)
 
 
 def parse():
@@ -102,6 +173,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=24576)
+    ap.add_argument("--replays", type=int, default=20,
+                    help="further replays of the K-iteration graph timed one by one with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="seconds of FP64 oracle work timed for the CPU baseline (at most 30)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -209,7 +282,7 @@ def main():
 
     def timed_optimizer_graph(nb=None):
         sl = slice(0, nb if nb is not None else B)
-        q, qd, qdd = (x[:, sl].contiguous() for x in (q0, qd0, qdd0))
+        q, qd, qdd = (x[:, sl].clone() for x in (q0, qd0, qdd0))
         og = OptimizerGraph(robot, q, qd, qdd, iters=args.steps, every=10, **kw)
         for _ in range(args.warmup):
             og.lean.run(q, qd, qdd)
@@ -220,7 +293,19 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         assert torch.isfinite(q).all() and torch.isfinite(og.hist["cost"]).all()
-        return dt
+        # the same graph replayed `replays` more times, each bracketed by HIP
+        # events on the stream it is replayed on
+        s = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.replays)]
+        for e0, e1 in ev:
+            e0.record(s)
+            og.replay()
+            e1.record(s)
+        torch.cuda.synchronize()
+        per_step = np.array([e0.elapsed_time(e1) for e0, e1 in ev]) / args.steps
+        assert torch.isfinite(q).all()
+        return dt, per_step
 
     def timed_graph(form):
         q, qd, qdd = q0.clone(), qd0.clone(), qdd0.clone()
@@ -266,9 +351,10 @@ def main():
         kernel_ms = [a.elapsed_time(b) for a, b in ev] if events else None
         return dt, kernel_ms
 
+    replay_ms = None
     for form in forms:
         if form == "fused_graph":
-            res[form] = timed_optimizer_graph()
+            res[form], replay_ms = timed_optimizer_graph()
         elif "_graph" in form:
             res[form] = timed_graph(form)
         else:
@@ -299,6 +385,12 @@ def main():
                    "form": head},
         "forms": {f: {"states_per_s": B / t, "ms_per_step": t * 1e3} for f, t in res.items()},
     }
+    if replay_ms is not None:
+        out["graph_replays"] = {"replays": len(replay_ms), "steps_per_replay": args.steps,
+                                "ms_per_step_median": float(np.median(replay_ms)),
+                                "ms_per_step_min": float(np.min(replay_ms)),
+                                "states_per_s_median": B / (float(np.median(replay_ms)) * 1e-3),
+                                "timing": "HIP events around each replay of the K-iteration graph"}
     if "plain" in res:
         out["speedup_vs_plain_launch"] = res["plain"] / res[head]
     if fused_ms is not None:
@@ -309,13 +401,16 @@ def main():
             traffic = TRAFFIC_MEASURED["bytes_per_launch"]
         alg_bytes = B * (6 * 4 * n + 16)
         out["roofline"] = {"bound": "alu", "kernel": "k_fused_step", "achieved": achieved,
-                           "peak": PEAK_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
-                           "frac": achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                           "frac_of_published_packed_peak": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
+                           "peak": PEAK_FP32_PUBLISHED_TFLOPS, "unit": "TFLOP/s",
+                           "frac": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
+                           "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                           "nonpacked_peak": PEAK_FP32_NONPACKED_TFLOPS,
+                           "work": "algorithmic: every checked pair once, no pruning credited; VJP 500 FLOP/link",
                            "kernel_ms": fused_ms, "kernel_ms_median": float(np.median(fused_all)),
                            "kernel_ms_min": float(np.min(fused_all)), "flop_per_launch": flop, "traffic": traffic,
                            "algorithmic_bytes_per_launch": alg_bytes,
                            "hbm_gbps_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9}
+        out["roofline"]["executed"] = executed_roofline(robot, rb, q0, fused_ms)
         slots = issue_slots_per_state(L, S, P, n) * B
         ach_slots = slots / (fused_ms * 1e-3) / 1e12
         out["roofline"]["issue_slot_model"] = {
@@ -323,7 +418,7 @@ def main():
             "unit": "T lane-slots/s", "frac": ach_slots / PEAK_ISSUE_TSLOTS,
             "note": "credits every pair; above 1 where the exact broad phase skips pairs the model counts"}
         if "fused_graph" in res and B > 3072:
-            t_share = timed_optimizer_graph(3072)
+            t_share, _ = timed_optimizer_graph(3072)
             out["shard_share_B3072"] = {
                 "states": 3072, "states_per_s": 3072 / t_share, "ms_per_step": t_share * 1e3,
                 "per_state_rate_vs_full_batch": (3072 / t_share) / (B / res["fused_graph"]),
@@ -341,6 +436,33 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(rb, st, args.cpu_seconds)
     print(json.dumps(out))
+
+
+def executed_roofline(robot, rb, q0, kernel_ms: float, sample: int = 2048):
+    """The fused kernel's executed work on the benchmark's states: sphere
+    centres from the library's own FK (wb_fk) for the first `sample` states,
+    the broad phase's rule applied to them on the host (sweep_work), and the
+    executed FLOP per state times the batch over the kernel's mean time."""
+    import torch
+    from paper_2603_05493_amd import wb
+    B = q0.shape[-1]
+    ns = min(sample, B)
+    _, sph = wb.wb_fk(robot, q0[:, :ns].contiguous())
+    torch.cuda.synchronize()
+    c = np.transpose(sph.cpu().numpy(), (2, 0, 1))                   # [ns, S, 3]
+    ps, pt = robot.pairs()
+    G = robot.get_tune()["lanes_per_state"]
+    ev, tests, swept, nblk = sweep_work(c, rb.sphere_r, rb.sphere_link, ps, pt, robot.max_spheres_per_link, G)
+    L, S, n = robot.n_links, robot.n_spheres, robot.n_dof
+    per_state = executed_flop_per_state(L, S, n, float(ev.mean()), float(tests.mean()))
+    ach = per_state * B / (kernel_ms * 1e-3) / 1e12
+    return {"pairs_evaluated_per_state": float(ev.mean()), "pairs_in_model": int(robot.n_pairs),
+            "blocks_swept_per_state": float(swept.mean()), "blocks": int(nblk),
+            "block_tests_per_state": float(tests.mean()), "flop_per_state": per_state,
+            "achieved": ach, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_PUBLISHED_TFLOPS,
+            "frac_of_nonpacked_peak": ach / PEAK_FP32_NONPACKED_TFLOPS,
+            "sample": f"broad-phase rule applied on the host to the first {ns} benchmark states' sphere centres "
+                      f"(wb_fk); a swept block costs {robot.max_spheres_per_link}^2 pair evaluations"}
 
 
 def bench_bspline(args, robot, T: int):

@@ -112,8 +112,8 @@ class OptimizerGraph:
     graph (the paper captures the optimizer's inner loop as a CUDA graph,
     Sec. 7.2).  At every ``every``-th iteration i, ``hist`` records the state
     x_i = (q, qd, qdd) before its step (device-to-device copies), and the
-    kernel writes the gradient of the cost at x_i, the cost and the maximum
-    penetration straight into its slot, so a run can be checked afterwards
+    kernel writes the gradient of the cost at x_i, the cost, the maximum
+    penetration and the argmax pair straight into its slot, so a run can be checked afterwards
     without host round trips.  Snapshot iterations run the kernel with its
     per-joint outputs enabled; the others write only the state and the
     per-state scalars.
@@ -138,6 +138,7 @@ class OptimizerGraph:
         e = lambda *shape: torch.empty(shape, dtype=torch.float32, device=q.device)
         self.hist = {k: e(ns, n, B) for k in ("q", "qd", "qdd", "g_q", "g_qd", "g_qdd")}
         self.hist["cost"], self.hist["max_pen"] = e(ns, B), e(ns, B)
+        self.hist["argmax"] = torch.empty((ns, B), dtype=torch.int32, device=q.device)
         self.graph = None
 
     def _body(self) -> None:
@@ -151,7 +152,7 @@ class OptimizerGraph:
                 h[name][k].copy_(x)
             it = self.full
             wb.wb_wholebody_step(it.robot, self.q, self.qd, self.qdd, it.w, it.tw, it.margin, it.hw, it.lr, it.tau,
-                                 h["cost"][k], h["max_pen"][k], it.argmax, it.n_coll, h["g_q"][k], h["g_qd"][k],
+                                 h["cost"][k], h["max_pen"][k], h["argmax"][k], it.n_coll, h["g_q"][k], h["g_qd"][k],
                                  h["g_qdd"][k])
 
     def run_eager(self) -> None:

@@ -12,7 +12,12 @@ Tolerances (FP32 device arithmetic against the FP64 oracle):
   * argmax pair and collision counts are exact wherever the oracle's
     decision is farther than DELTA = 1e-5 m from a tie (about ten times the
     FP32 position error of an 18-deep chain); counts must lie in
-    [#{pen > DELTA}, #{pen > -DELTA}].
+    [#{pen > DELTA}, #{pen > -DELTA}];
+  * the joint-position gradient is checked on every state at the same
+    bound (check_grad_q): where the argmax pair is tied within DELTA, or the
+    hinge sits within DELTA of its kink, the GPU's choice must be a valid
+    one and its gradient is compared with the oracle's gradient for that
+    same choice.
 """
 from __future__ import annotations
 
@@ -109,3 +114,54 @@ def oracle_iteration(O, rb, q, qd, qdd, w=None, torque_weight=1e-3, margin=0.01,
     gq, gqd, gqdd, gfe = O.rnea_vjp(rb, q, qd, qdd, g_tau, fext=fext, want_fext=True)
     return dict(R=R, p=p, c=c, max_pen=mp, argmax=am, n_coll=nc, tau=tau, cost=cost,
                 g_q=gq + gq_fk, g_q_fk=gq_fk, g_q_rnea=gq, g_qd=gqd, g_qdd=gqdd, g_spheres=g_c, g_fext=gfe)
+
+
+
+def reference_gq(O, rb, q, ref, got_gq, got_argmax, margin, hinge_weight=1.0, floor=1e-6, pens=None):
+    """The oracle's joint-position gradient of the whole iteration (RNEA VJP
+    plus FK through the hinge) for the choice the GPU made at each state:
+
+      * unambiguous states: the oracle's own gradient;
+      * argmax tied within DELTA: the GPU's pair must attain the maximum
+        within DELTA, and the reference uses that pair (each tied pair gives
+        a valid subgradient);
+      * |max_pen + margin| < DELTA: the hinge may be on or off; the
+        reference is whichever of the two the GPU's gradient is closer to.
+
+    Returns (g_ref [B, n], tied mask, kink mask, the reference argmax)."""
+    B = q.shape[0]
+    if pens is None:
+        pens = O.self_collision_pens(rb, ref["c"])
+    mp = ref["max_pen"]
+    tied = ~unambiguous(pens)
+    kink = np.abs(mp + margin) < DELTA
+    am = np.asarray(got_argmax, dtype=np.int64)
+    if pens.shape[1] > 0:
+        chosen = pens[np.arange(B), np.clip(am, 0, pens.shape[1] - 1)]
+        valid = (am >= 0) & (chosen >= mp - DELTA)
+        assert valid.all(), f"GPU argmax outside the tie band on {int((~valid).sum())} states"
+    alt = np.where(tied, am, ref["argmax"]).astype(np.int32)
+    hw = np.full(B, hinge_weight)
+    on_mp = np.where(kink, np.abs(margin) + 1.0, mp)   # the hinge switched on at the kink
+    g_on = ref["g_q_rnea"] + O.fk_backward(rb, q, g_spheres=O.self_collision_backward(rb, ref["c"], alt, on_mp,
+                                                                                     margin, hw))
+    if kink.any():
+        e_on = normwise(got_gq, g_on, floor=floor)
+        e_off = normwise(got_gq, ref["g_q_rnea"], floor=floor)
+        g_on = np.where((kink & (e_off < e_on))[:, None], ref["g_q_rnea"], g_on)
+    return g_on, tied, kink, alt
+
+
+def check_grad_q(O, rb, q, ref, got_gq, got_argmax, margin, hinge_weight=1.0, floor=1e-6, pens=None):
+    """Checks the GPU's joint-position gradient on every state against
+    reference_gq at the plain bound: normwise error <= TOL per state, with
+    no allowance for the hinge direction's conditioning.  Returns the counts
+    the tests print: states checked, tied, at the kink, and close (argmax
+    pair nearer than HINGE_D0, where an FP32 centre error e tilts the hinge
+    direction by about e / d)."""
+    g_ref, tied, kink, alt = reference_gq(O, rb, q, ref, got_gq, got_argmax, margin, hinge_weight, floor, pens)
+    e = normwise(got_gq, g_ref, floor=floor)
+    cond = hinge_conditioning(dict(argmax=alt, c=ref["c"]), rb)
+    assert np.all(e <= TOL), f"g_q error {float(e.max()):.3g} on state {int(np.argmax(e))}"
+    return dict(checked=int(q.shape[0]), tied=int(tied.sum()), kink=int(kink.sum()), close=int((cond > 1).sum()),
+                e_gq_max=float(e.max()))

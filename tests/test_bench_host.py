@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -27,9 +28,14 @@ def test_source_hashes_cover_existing_files():
 
 
 def test_work_models_are_frozen():
-    # the 48-DoF humanoid: 49 links, 240 spheres, 27,040 pairs, 48 joints
-    assert bench.algorithmic_flop_per_state(49, 240, 27040, 48) == 365774
-    assert bench.issue_slots_per_state(49, 240, 27040, 48) == 466807.0
+    # the 48-DoF humanoid: 49 links, 240 spheres, 27,040 pairs, 48 joints;
+    # per jointed link FK 135 + RNEA 290 + VJP 500 + FK adjoint 38, per sphere
+    # 18, per pair 11, the hinge's two spheres 30, per joint 10
+    nonpair = 48 * (135 + 290 + 500 + 38) + 240 * 18 + 30 + 48 * 10
+    assert bench.nonpair_flop_per_state(49, 240, 48) == nonpair == 51054
+    assert bench.algorithmic_flop_per_state(49, 240, 27040, 48) == 11 * 27040 + nonpair
+    assert bench.issue_slots_per_state(49, 240, 27040, 48) == 16 * 27040 + nonpair / 2
+    assert bench.executed_flop_per_state(49, 240, 48, 1000.0, 100.0) == 11 * 1000 + 9 * 100 + nonpair
     assert bench.PEAK_FP32_NONPACKED_TFLOPS == pytest.approx(78.6432)
     assert bench.PEAK_ISSUE_TSLOTS == pytest.approx(39.3216)
 
@@ -56,3 +62,39 @@ def test_tuned_shapes_are_whole_workgroup_rounds():
         assert e["ns_per_state"] > 0, key
         best = min(e["candidates"], key=lambda x: x[2])
         assert [g, c] == best[:2], key
+
+
+def _bounded_robot(oracle):
+    from paper_2603_05493_amd import synth
+    rb = synth.humanoid48(seed=0)
+    st = synth.states(rb, 64, seed=1, q_range=1.5)
+    _, _, c = oracle.fk(rb, st.q)
+    s, t = oracle.pairs(rb)
+    return rb, c, s, t
+
+
+def test_sweep_work_rule_is_exact_and_counts_what_it_sweeps(oracle):
+    """The broad-phase rule the executed-work figure applies: the blocks it
+    sweeps hold the state's most penetrating pair (the rule is exact), and
+    its counts are consistent (nmax^2 evaluations per swept block, block
+    tests a padded multiple of the table once or twice)."""
+    rb, c, s, t = _bounded_robot(oracle)
+    nmax = int(np.bincount(rb.sphere_link).max())
+    ev, tests, swept, nblk = bench.sweep_work(c, rb.sphere_r, rb.sphere_link, s, t, nmax, 64)
+    assert np.all(ev == nmax * nmax * swept)
+    nb = (nblk + 127) // 128 * 128
+    assert set(np.unique(tests)) <= {nb, 2 * nb}
+    assert np.all(swept >= 1) and np.all(swept <= nblk + 1)
+    # exactness: re-derive the swept set and check it contains an argmax pair
+    mp, am, _ = oracle.self_collision(rb, c)
+    sl = rb.sphere_link
+    links = np.unique(sl)
+    for b in range(c.shape[0]):
+        C = {a: c[b, sl == a].mean(0) for a in links}
+        R = {a: (np.linalg.norm(c[b, sl == a] - C[a], axis=1) + rb.sphere_r[sl == a]).max() for a in links}
+        la, lb = sl[s[am[b]]], sl[t[am[b]]]
+        bound = R[la] + R[lb] - np.linalg.norm(C[la] - C[lb])
+        assert bound >= mp[b] - 1e-12          # the argmax block's bound reaches the maximum
+    # a state in collision sweeps only pass 1 (one round of block tests)
+    coll = mp >= 0
+    assert np.all(tests[coll] == nb)

@@ -147,10 +147,9 @@ def test_empty_batch():
 def test_control_point_iteration_matches_oracle(oracle, label, factory, T, K):
     """Splines -> fused iteration -> control-point gradient, against the
     oracle's composition evaluated at the oracle's own samples.  The
-    control-point gradient is checked on trajectories whose states are all
-    unambiguous (a flipped argmax in one sample changes its trajectory's
-    sum), with the fused tests' hinge-conditioning allowance taken at the
-    trajectory's worst state."""
+    control-point gradient is checked on every trajectory: where a sample's
+    argmax pair is tied or its hinge sits at the kink, the reference takes
+    the GPU's (valid) choice.  The bound is the plain 1e-4 normwise."""
     from paper_2603_05493_amd import wb
     from paper_2603_05493_amd.iteration import BsplineIteration
     rb = factory()
@@ -171,20 +170,19 @@ def test_control_point_iteration_matches_oracle(oracle, label, factory, T, K):
     q, qd, qdd = (Th[..., r].reshape(T * H, d) for r in range(3))
     ref = P.oracle_iteration(oracle, rb, q, qd, qdd, None, tw, margin, hw)
     pens = oracle.self_collision_pens(rb, ref["c"])
-    ok = P.unambiguous(pens) & (np.abs(ref["max_pen"] + margin) >= P.DELTA)
-    cond = P.hinge_conditioning(ref, rb)
-    e_cost = (np.abs(P.host(it.fused.cost) - ref["cost"]) / P.cost_scale(ref, None, tw, margin))[ok].max()
+    e_cost = (np.abs(P.host(it.fused.cost) - ref["cost"]) / P.cost_scale(ref, None, tw, margin)).max()
     assert e_cost < P.TOL
-    gref = np.stack([ref["g_q"], ref["g_qd"], ref["g_qdd"]], -1).reshape(T, H, d, 3)
+    # per sample, the oracle's gradient for the choice the GPU made where the
+    # argmax pair is tied or the hinge sits at its kink (both are valid)
+    g_q_ref, tied, kink, alt = P.reference_gq(oracle, rb, q, ref, P.host(it.fused.g_q),
+                                              it.fused.argmax.cpu().numpy(), margin, hw, pens=pens)
+    gref = np.stack([g_q_ref, ref["g_qd"], ref["g_qdd"]], -1).reshape(T, H, d, 3)
     gU_ref = bs.backward(gref, K, DT, n_interp)
     got = host_U(it.g_U)
-    good = ok.reshape(T, H).all(1)
-    traj_cond = np.maximum(cond.reshape(T, H).max(1), 1.0)      # the hinge conditioning reading, per trajectory
     e = P.normwise(got, gU_ref, floor=1e-6)
-    print(label, "trajectories checked", int(good.sum()), "of", T, "max err / cond",
-          float((e / traj_cond)[good].max()) if good.any() else None, flush=True)
-    assert good.sum() >= max(1, T // 4)
-    assert np.all(e[good] <= P.TOL * traj_cond[good])
+    print(label, "trajectories", T, "tied samples", int(tied.sum()), "kink samples", int(kink.sum()),
+          "max err", float(e.max()), flush=True)
+    assert np.all(e <= P.TOL)
     # the step moves the control points along -g_U
     U0 = it.U.clone()
     it.lr = 1e-4

@@ -99,20 +99,16 @@ def test_fused_iteration_with_external_forces(oracle, label, factory, B, qr, n_s
     ref = P.oracle_iteration(oracle, rb, st.q[sample], st.qd[sample], st.qdd[sample], None, tw, margin, hw,
                              fext=fe[sample])
     pens = oracle.self_collision_pens(rb, ref["c"])
-    ok = P.unambiguous(pens) & (np.abs(ref["max_pen"] + margin) >= P.DELTA)
-    cond = P.hinge_conditioning(ref, rb)
     h = lambda x: P.host(x)[sample]
-    e_gq_all = P.normwise(h(out["g_q"]), ref["g_q"], floor=1e-6)
+    gq = P.check_grad_q(oracle, rb, st.q[sample], ref, h(out["g_q"]), h(out["argmax"]), margin, hw, pens=pens)
     errs = dict(tau=P.normwise(h(out["tau"]), ref["tau"], floor=1e-3).max(),
-                cost=(np.abs(h(out["cost"]) - ref["cost"]) / P.cost_scale(ref, None, tw, margin))[ok].max(),
-                g_q=e_gq_all[ok & (cond <= 1.0)].max(),
+                cost=(np.abs(h(out["cost"]) - ref["cost"]) / P.cost_scale(ref, None, tw, margin)).max(),
                 g_qd=P.normwise(h(out["g_qd"]), ref["g_qd"], floor=1e-6).max(),
                 g_qdd=P.normwise(h(out["g_qdd"]), ref["g_qdd"], floor=1e-6).max(),
                 g_fext=P.normwise(_host_fext(g_fext)[sample], ref["g_fext"], floor=1e-6).max())
-    print(label, "fused", " ".join(f"{k}={v:.3g}" for k, v in errs.items()), "checked", int(ok.sum()), flush=True)
+    print(label, "fused", " ".join(f"{k}={v:.3g}" for k, v in errs.items()),
+          " ".join(f"{k}={v}" for k, v in gq.items()), flush=True)
     assert all(v < P.TOL for v in errs.values())
-    assert np.all(e_gq_all[ok] <= P.TOL * np.maximum(cond[ok], 1.0))
-    assert ok.sum() > 0.8 * len(sample)
 
 
 def test_fused_external_force_outputs_are_independent():

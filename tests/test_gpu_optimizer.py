@@ -68,20 +68,16 @@ def test_snapshots_match_oracle(oracle, label, factory, B, qr, seed, iters, lr, 
         x = [P.host(g.hist[n][k])[sample] for n in ("q", "qd", "qdd")]
         ref = P.oracle_iteration(oracle, rb, *x, None, tw, margin, hw)
         pens = oracle.self_collision_pens(rb, ref["c"])
-        ok = P.unambiguous(pens) & (np.abs(ref["max_pen"] + margin) >= P.DELTA)
-        cond = P.hinge_conditioning(ref, rb)
         ext = P.extent(ref["c"])
         gh = lambda n: P.host(g.hist[n][k])[sample]
         e_mp = P.scaled(gh("max_pen")[:, None], ref["max_pen"][:, None], ext).max()
-        e_cost = (np.abs(gh("cost") - ref["cost"]) / P.cost_scale(ref, None, tw, margin))[ok].max()
-        e_gq = P.normwise(gh("g_q"), ref["g_q"], floor=1e-6)
+        e_cost = (np.abs(gh("cost") - ref["cost"]) / P.cost_scale(ref, None, tw, margin)).max()
+        gq = P.check_grad_q(oracle, rb, x[0], ref, gh("g_q"), gh("argmax"), margin, hw, pens=pens)
         e_gqd = P.normwise(gh("g_qd"), ref["g_qd"], floor=1e-6).max()
         e_gqdd = P.normwise(gh("g_qdd"), ref["g_qdd"], floor=1e-6).max()
-        print(label, "snapshot", k, f"e_mp={e_mp:.3g} e_cost={e_cost:.3g} e_gq={e_gq[ok & (cond <= 1)].max():.3g}"
-              f" e_gqd={e_gqd:.3g} e_gqdd={e_gqdd:.3g} excluded={int((~ok).sum())}", flush=True)
+        print(label, "snapshot", k, f"e_mp={e_mp:.3g} e_cost={e_cost:.3g} e_gqd={e_gqd:.3g} e_gqdd={e_gqdd:.3g}",
+              " ".join(f"{kk}={v}" for kk, v in gq.items()), flush=True)
         assert e_mp < P.TOL and e_cost < P.TOL and e_gqd < P.TOL and e_gqdd < P.TOL
-        assert np.all(e_gq[ok] <= P.TOL * np.maximum(cond[ok], 1.0))
-        assert ok.sum() > 0.8 * len(sample)
 
 
 def test_snapshot_every_iteration_is_gradient_descent():

@@ -146,24 +146,26 @@ def _check_iteration(O, rb, st, label, w=None, torque_weight=1e-3, margin=0.01, 
     ref = P.oracle_iteration(O, rb, sub(st.q), sub(st.qd), sub(st.qdd), None if w is None else sub(w),
                              torque_weight, margin, 1.0)
     pens = O.self_collision_pens(rb, ref["c"])
-    ok = P.unambiguous(pens) & (np.abs(ref["max_pen"] + margin) >= P.DELTA)
     g = lambda t: sub(P.host(t))
     cscale = P.cost_scale(ref, w, torque_weight, margin)
-    e_cost = (np.abs(g(it.cost) - ref["cost"]) / cscale)[ok].max()
-    e_gq = P.normwise(g(it.g_q) + g(it.g_q_fk), ref["g_q"], floor=1e-6)[ok].max()
-    # the hinge direction u = (c_s - c_t)/d carries FP32 position error / d
-    cond = P.hinge_conditioning(ref, rb)
-    e_gqfk_all = P.normwise(g(it.g_q_fk), ref["g_q_fk"], floor=P.fk_grad_floor(ref))
-    well = ok & (cond <= 1.0)
-    e_gqfk = e_gqfk_all[well].max() if well.any() else 0.0
-    assert np.all(e_gqfk_all[ok] <= P.TOL * np.maximum(cond[ok], 1.0))
+    e_cost = (np.abs(g(it.cost) - ref["cost"]) / cscale).max()
+    am = sub(it.argmax.cpu().numpy())
+    gq = P.check_grad_q(O, rb, sub(st.q), ref, g(it.g_q) + g(it.g_q_fk), am, margin, pens=pens)
+    # the FK-through-hinge part on its own, against the same reference choice; for
+    # joints above both spheres of the pair the exact value is 0 and FP32 leaves
+    # rounding noise of order eps |c| |g|, so its scale is floored (fk_grad_floor)
+    g_ref, _, _, _ = P.reference_gq(O, rb, sub(st.q), ref, g(it.g_q) + g(it.g_q_fk), am, margin, pens=pens)
+    fk_ref = g_ref - ref["g_q_rnea"]
+    e_fk_plain = P.normwise(g(it.g_q_fk), fk_ref, floor=1e-6)
+    e_fk = P.normwise(g(it.g_q_fk), fk_ref, floor=P.fk_grad_floor(ref))
+    floored = int(((e_fk_plain > P.TOL) & (e_fk <= P.TOL)).sum())
     e_gqd = P.normwise(g(it.g_qd), ref["g_qd"], floor=1e-6).max()
     e_gqdd = P.normwise(g(it.g_qdd), ref["g_qdd"], floor=1e-6).max()
-    _log(label + " fwd+bwd", e_cost=e_cost, e_gq=e_gq, e_gq_fk=e_gqfk, e_gqd=e_gqd, e_gqdd=e_gqdd,
-         excluded=int((~ok).sum()), checked=int(ok.sum()))
-    assert ok.sum() > 0.8 * len(idx)
-    for e in (e_cost, e_gq, e_gqfk, e_gqd, e_gqdd):
+    _log(label + " fwd+bwd", e_cost=e_cost, e_gq_fk=float(e_fk.max()), fk_floor_decided=floored, e_gqd=e_gqd,
+         e_gqdd=e_gqdd, **gq)
+    for e in (e_cost, float(e_fk.max()), e_gqd, e_gqdd):
         assert e < P.TOL
+    ok = P.unambiguous(pens) & (np.abs(ref["max_pen"] + margin) >= P.DELTA)
     return it, ref, ok
 
 
@@ -265,12 +267,11 @@ def test_autograd_wrappers_match_abi(oracle):
     R, p, c = oracle.fk(rb, st.q)
     mpr, amr, _ = oracle.self_collision(rb, c)
     gc = oracle.self_collision_backward(rb, c, amr, mpr, 1e30, np.ones(B))
-    ref = oracle.fk_backward(rb, st.q, g_spheres=gc) + oracle.rnea_vjp(rb, st.q, st.qd, st.qdd,
-                                                                       synth.weights((B, rb.n_dof), seed=62))[0]
-    ok = P.unambiguous(oracle.self_collision_pens(rb, c))
-    e = P.normwise(P.host(q.grad), ref, floor=1e-6)[ok].max()
-    _log("autograd", e=e)
-    assert e < P.TOL
+    g_rnea = oracle.rnea_vjp(rb, st.q, st.qd, st.qdd, synth.weights((B, rb.n_dof), seed=62))[0]
+    # every state: the oracle's gradient for the pair the GPU chose where the maximum is tied
+    info = P.check_grad_q(oracle, rb, st.q, dict(c=c, max_pen=mpr, argmax=amr, g_q_rnea=g_rnea),
+                          P.host(q.grad), am.cpu().numpy(), margin=1e30)
+    _log("autograd", **info)
 
 
 def test_bitwise_deterministic():
