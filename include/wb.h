@@ -152,8 +152,11 @@ int wb_rnea_cache_bytes(const wb_robot *robot, int64_t B, size_t *bytes);
 /* ---------------------------------------------------------------- forward */
 
 /* Forward kinematics (Sec. 6.1).  q[n][B] joint positions ->
- *   link_pose[L][12][B] (required; also serves as the traversal storage),
- *   spheres[S][3][B] world sphere centres (NULL to skip). */
+ *   link_pose[L][12][B] world link poses, or NULL to skip them: a branch
+ *     link then recomposes its parent's pose from q along the parent's chain
+ *     instead of re-reading it;
+ *   spheres[S][3][B] world sphere centres, or NULL to skip them.
+ * WB_ERR_INVALID_ARG when both outputs are NULL. */
 int wb_fk(const wb_robot *robot, int64_t B, const float *q, float *link_pose, float *spheres,
           hipStream_t stream);
 
@@ -212,8 +215,11 @@ int wb_kinematics_backward(const wb_robot *robot, int64_t B, const float *q, con
  * f_ext[L][6][B] (NULL = none): external spatial force on each link in link
  * coordinates, moment then force about the link origin; it enters Alg. 4's
  * force line as f_k = I_k a_k + v_k x* I_k v_k - f_ext_k.  cache[L][18][B]
- * (required) receives v, a and the accumulated link forces (including
- * f_ext) for wb_rnea_backward. */
+ * receives v, a and the accumulated link forces (including f_ext) for
+ * wb_rnea_backward (Alg. 4's optional cache output), or is NULL: then
+ * nothing is stored (one group of lanes per state keeps every link quantity
+ * in registers) and the backward recomputes them.  Without a cache the
+ * robot must have at most 64 links (WB_ERR_UNSUPPORTED otherwise). */
 int wb_rnea(const wb_robot *robot, int64_t B, const float *q, const float *qd, const float *qdd,
             const float *f_ext, float *tau, float *cache, hipStream_t stream);
 
@@ -250,11 +256,16 @@ int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float
  * g_q, g_qd, g_qdd [n][B] (overwritten) and, when g_fext is not NULL, the
  * gradient on the external forces g_fext[L][6][B] (overwritten; link
  * coordinates like f_ext; it is minus the adjoint of each link's accumulated
- * force, Alg. 5's f-bar_ext).  cache is the one written by wb_rnea for the
- * same q, qd, qdd and f_ext.  Transforms are recomputed from q.
- * workspace: wb_workspace_bytes(robot, B). */
+ * force, Alg. 5's f-bar_ext).  Transforms are recomputed from q.
+ *   cache: the one written by wb_rnea for the same q, qd, qdd and f_ext
+ *     (f_ext is then ignored: the forces are in the cache); workspace:
+ *     wb_workspace_bytes(robot, B);
+ *   or cache = NULL: every forward quantity is recomputed from q, qd, qdd
+ *     and f_ext (NULL = none) in registers, one group of lanes per state;
+ *     workspace may be NULL; robots of at most 64 links
+ *     (WB_ERR_UNSUPPORTED otherwise). */
 int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const float *qd,
-                     const float *qdd, const float *cache, const float *g_tau, float *g_q,
+                     const float *qdd, const float *f_ext, const float *cache, const float *g_tau, float *g_q,
                      float *g_qd, float *g_qdd, float *g_fext, void *workspace, hipStream_t stream);
 
 /* ------------------------------------------------ cost head and update step
@@ -436,6 +447,22 @@ int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_tr
                    wb_plan **out);
 int wb_plan_run(const wb_plan *plan, const wb_tree_io *io, float torque_weight, float margin,
                 float hinge_weight, float lr, hipStream_t stream);
+/* Capture `iters` consecutive wb_plan_run calls with these io buffers and
+ * scalars into an executable HIP graph (the paper captures its iteration in
+ * CUDA graphs, Sec. 7.2): each iteration reads the states the previous one
+ * stepped (with lr != 0 they move in place).  *out is owned by the caller,
+ * launched with wb_graph_launch (or hipGraphLaunch) on any stream of the
+ * plan's device, and released with wb_graph_destroy.  The graph holds the io
+ * pointers: the buffers and the plan must outlive it.  Creates and
+ * destroys a capture stream on the plan's device; errors of wb_plan_run
+ * (checked on the first iteration, before anything is recorded) are
+ * returned as they are; WB_ERR_INVALID_ARG for iters outside [1, 2^20]. */
+int wb_plan_capture(const wb_plan *plan, const wb_tree_io *io, float torque_weight, float margin, float hinge_weight,
+                    float lr, int32_t iters, hipGraphExec_t *out);
+/* Enqueue a graph from wb_plan_capture on a stream (hipGraphLaunch), and
+ * release one (NULL is a no-op). */
+int wb_graph_launch(hipGraphExec_t graph, hipStream_t stream);
+int wb_graph_destroy(hipGraphExec_t graph);
 int wb_plan_get_info(const wb_plan *plan, int32_t *n_items, int32_t *n_workgroups);
 int wb_plan_destroy(wb_plan *plan);
 

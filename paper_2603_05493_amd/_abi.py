@@ -69,7 +69,7 @@ _SIGS = {
     "wb_self_collision": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp],
     "wb_self_collision_backward": [_vp, C.c_int64, _vp, _vp, _vp, C.c_float, _vp, _vp, _vp],
     "wb_fk_backward": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
-    "wb_rnea_backward": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "wb_rnea_backward": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "wb_cost_head": [C.c_int64, C.c_int32, _vp, _vp, C.c_float, _vp, C.c_float, C.c_float, _vp, _vp,
                      _vp, _vp],
     "wb_sgd_step": [C.c_int64, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
@@ -90,6 +90,10 @@ _SIGS = {
     "wb_robot_get_tune": [_vp, C.POINTER(WbTune)],
     "wb_plan_create": [C.POINTER(_vp), C.POINTER(C.c_int64), C.c_int32, C.POINTER(WbTune), C.POINTER(_vp)],
     "wb_plan_run": [_vp, C.POINTER(WbTreeIO), C.c_float, C.c_float, C.c_float, C.c_float, _vp],
+    "wb_plan_capture": [_vp, C.POINTER(WbTreeIO), C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32,
+                        C.POINTER(_vp)],
+    "wb_graph_launch": [_vp, _vp],
+    "wb_graph_destroy": [_vp],
     "wb_plan_get_info": [_vp, _i32p, _i32p],
     "wb_plan_destroy": [_vp],
 }

@@ -2,8 +2,9 @@
 //
 // Forward (cuRoboV2 Sec. 6.1): links are visited in index order (parents
 // first); the running pose stays in registers while the next link is the
-// current one's child and is re-read from the pose array otherwise, so a
-// serial chain never reloads.  Sphere centres are R c_local + p.
+// current one's child and is re-read from the pose array otherwise (or,
+// without one, recomposed from q along the parent's chain), so a serial
+// chain never reloads.  Sphere centres are R c_local + p.
 //
 // Backward (the gradient of Alg. 1): instead of walking every link's
 // ancestor chain, each link accumulates the force F = sum of point-gradient
@@ -38,7 +39,28 @@ __device__ __forceinline__ float joint_angle(const DevRobot &rb, const LinkF &f,
     return i.revolute ? f.mult * q[(int64_t)i.jidx * B + b] + f.offset : 0.0f;
 }
 
-// Full FK for one state; writes poses (always) and sphere centres (if given).
+// World pose of link k from q alone: the local transforms of its chain,
+// each ancestor's pre-multiplied onto the product of the links below it
+// (T_x o T = (R_x R, R_x p + p_x)), so no stored pose is read.
+__device__ __forceinline__ void chain_pose(const DevRobot &rb, int k, const float *__restrict__ q, int64_t B,
+                                           int64_t b, M3 &R, V3 &p) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) R.m[t] = (t % 4 == 0) ? 1.0f : 0.0f;
+    p = v3(0.f, 0.f, 0.f);
+    for (int x = k; x > 0;) {
+        const LinkI li = ldu(rb.li + x);
+        const LinkF lf = ldu(rb.lf + x);
+        const M3 Rl = local_rotation(lf, li, joint_angle(rb, lf, li, q, B, b));
+        p = mul(Rl, p) + v3(lf.fp[0], lf.fp[1], lf.fp[2]);
+        R = matmul(Rl, R);
+        x = li.parent;
+    }
+}
+
+// Full FK for one state; writes poses (if given) and sphere centres (if
+// given).  The running pose is carried while the next link is the current
+// one's child; at a branch the parent's pose is re-read from the pose array,
+// or recomposed along its chain when no pose array is given.
 __device__ __forceinline__ void fk_state(const DevRobot &rb, int64_t B, int64_t b,
                                          const float *__restrict__ q, float *__restrict__ pose,
                                          float *__restrict__ sph) {
@@ -50,12 +72,15 @@ __device__ __forceinline__ void fk_state(const DevRobot &rb, int64_t B, int64_t 
         const LinkI li = ldu(rb.li + k);
         if (k > 0) {
             const LinkF lf = ldu(rb.lf + k);
-            if (li.parent != k - 1) load_pose(pose, li.parent, B, b, R, p);
+            if (li.parent != k - 1) {
+                if (pose) load_pose(pose, li.parent, B, b, R, p);
+                else chain_pose(rb, li.parent, q, B, b, R, p);
+            }
             M3 Rl = local_rotation(lf, li, joint_angle(rb, lf, li, q, B, b));
             p = mul(R, v3(lf.fp[0], lf.fp[1], lf.fp[2])) + p;
             R = matmul(R, Rl);
         }
-        store_pose(pose, k, B, b, R, p);
+        if (pose) store_pose(pose, k, B, b, R, p);
         if (sph) {
             for (int s = li.sph_first; s < li.sph_first + li.sph_count; ++s) {
                 const float4 c4 = ldu(rb.sph + s);

@@ -52,90 +52,9 @@
 //   the per-link adjoints (q-bar, qd-bar, qdd-bar) come back the same way,
 //   each scaled by m_l, and lane j writes joint j's outputs and step.
 #include "sweep.h"
+#include "tree.h"
 
 namespace wb {
-
-// ------------------------------------------------------------ group shuffles
-__device__ __forceinline__ SV shfl_sv(SV x, int src, int G) {
-    return sv(v3(__shfl(x.w.x, src, G), __shfl(x.w.y, src, G), __shfl(x.w.z, src, G)),
-              v3(__shfl(x.l.x, src, G), __shfl(x.l.y, src, G), __shfl(x.l.z, src, G)));
-}
-__device__ __forceinline__ SV zsv() { return sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f)); }
-
-// Sum of x over the path from the root to this lane's link.  Lane 0 (the
-// fixed root) and the lanes past the robot must hold zero: a chain that has
-// reached the root keeps jumping to lane 0 and adds that zero, exactly, so
-// no lane needs a guard (and no masked copy of x) per step.
-__device__ __forceinline__ SV path_sum(SV x, int parent_lane, int glane, int steps, int G) {
-    (void)glane;
-    int anc = max(parent_lane, 0);
-    for (int s = 0; s < steps; ++s) {
-        const SV y = shfl_sv(x, anc, G);
-        anc = __shfl(anc, anc, G);
-        x += y;
-    }
-    return x;
-}
-
-// Sum of x over this lane's subtree (group lanes [glane, sub_end]): the
-// difference of two values of the group's inclusive scan.  Lanes outside the
-// robot must hold zero.
-__device__ __forceinline__ SV subtree_sum(SV x, int glane, int sub_end, int G) {
-    const SV s = sv(v3(group_scan(x.w.x, G), group_scan(x.w.y, G), group_scan(x.w.z, G)),
-                    v3(group_scan(x.l.x, G), group_scan(x.l.y, G), group_scan(x.l.z, G)));
-    const SV hi = shfl_sv(s, sub_end, G);
-    const SV lo = sv(v3(lane_prev(s.w.x), lane_prev(s.w.y), lane_prev(s.w.z)),
-                     v3(lane_prev(s.l.x), lane_prev(s.l.y), lane_prev(s.l.z)));
-    return glane > 0 ? hi - lo : hi;
-}
-
-// World-frame spatial inertia of a link: mass m, CoM cw and the rotational
-// inertia about the CoM in world axes, Iw = R Ic R^T (xx yy zz xy xz yz).
-struct WInertia {
-    float m;
-    V3 cw;
-    float I[6];
-};
-__device__ __forceinline__ SV iw_apply(const WInertia &J, SV u) {
-    const V3 h = J.m * (u.l + cross(u.w, J.cw));
-    const V3 Iw = v3(J.I[0] * u.w.x + J.I[3] * u.w.y + J.I[4] * u.w.z,
-                     J.I[3] * u.w.x + J.I[1] * u.w.y + J.I[5] * u.w.z,
-                     J.I[4] * u.w.x + J.I[5] * u.w.y + J.I[2] * u.w.z);
-    return sv(Iw + cross(J.cw, h), h);
-}
-// R Ic R^T for a symmetric Ic given as xx yy zz xy xz yz.
-__device__ __forceinline__ void rotate_inertia(const M3 &R, const float *Ic, float *Iw) {
-    float T[9];   // R Ic
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const float r0 = R.m[3 * i], r1 = R.m[3 * i + 1], r2 = R.m[3 * i + 2];
-        T[3 * i + 0] = r0 * Ic[0] + r1 * Ic[3] + r2 * Ic[4];
-        T[3 * i + 1] = r0 * Ic[3] + r1 * Ic[1] + r2 * Ic[5];
-        T[3 * i + 2] = r0 * Ic[4] + r1 * Ic[5] + r2 * Ic[2];
-    }
-    const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-    for (int e = 0; e < 6; ++e)
-        Iw[e] = T[3 * ii[e]] * R.m[3 * jj[e]] + T[3 * ii[e] + 1] * R.m[3 * jj[e] + 1] +
-                T[3 * ii[e] + 2] * R.m[3 * jj[e] + 2];
-}
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Sum over the links joint `glane` drives (connectedLinks, lanes of the
-// group) of their x; 0 in lanes past the last joint.
-__device__ __forceinline__ float gather_joint(float x, const DevFused &fz, int glane, int G) {
-    float acc = 0.f;
-    for (int kk = 0; kk < fz.mc; ++kk) {
-        const int l = fz.conn[kk * 64 + glane];
-        const float y = __shfl(x, l >= 0 ? l : glane, G);
-        if (l >= 0) acc += y;
-    }
-    return acc;
-}
 
 // The whole iteration for one state per group of G lanes.  Every lane of
 // the wavefront calls this (group-local shuffles need all lanes); `valid`

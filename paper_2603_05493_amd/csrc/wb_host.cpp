@@ -45,8 +45,10 @@ struct Tables {
     std::vector<int32_t> pair_off, pair_cnt, pair_s, pair_t;
     int64_t n_pairs = 0;
     float g[3] = {0, 0, 0};
-    // fused-kernel lane tables (depth-first lane order)
-    int fused = 0, jsteps = 0;
+    // lane tables (depth-first lane order) of the group-per-state kernels:
+    // built for every robot of at most 64 links (lanes); the fused iteration
+    // additionally needs its sweep tables within the LDS budget (fused)
+    int lanes = 0, fused = 0, jsteps = 0;
     std::vector<int> lane_of;         // link -> lane of the fused tables
     std::vector<int32_t> f_li;
     std::vector<float> f_lf;
@@ -157,16 +159,16 @@ void build_kin(Tables &T) {
 void build_fused(Tables &T) {
     const int L = T.L;
     T.fused = 0;
+    T.lanes = 0;
     if (L > 64) return;
     const int g_default = L <= 16 ? 16 : (L <= 32 ? 32 : 64);
-    if (wb::fused_lds_bytes(L, T.nmax, T.list_cap, g_default, (int)T.blocks.size()) > wb::LDS_LIMIT) return;
     std::vector<int> perm, size;
     std::vector<int> &lane_of = T.lane_of;
     dfs_lanes(T, perm, lane_of, size);
     T.f_li.assign(8 * 64, 0);
     T.f_lf.assign(31 * 64, 0.0f);
     std::vector<std::vector<int>> conn(T.n);
-    T.f_sph.assign((size_t)WB_MAX_SPHERES_PER_LINK * 64, make_float4(0, 0, 0, 0));
+    T.f_sph.assign((size_t)T.nmax * 64, make_float4(0, 0, 0, 0));
     for (int i = 0; i < L; ++i) {
         const int k = perm[i];
         const wb::LinkI &I = T.li[k];
@@ -227,7 +229,9 @@ void build_fused(Tables &T) {
     for (int j = 0; j < T.n; ++j)
         for (size_t c = 0; c < conn[j].size(); ++c) T.f_conn[c * 64 + j] = conn[j][c];
     T.jsteps = pointer_jump_steps(T.max_depth);
-    T.fused = 1;
+    T.lanes = 1;
+    T.fused = T.nmax <= wb::FUSED_MAX_SLOTS &&
+              wb::fused_lds_bytes(L, T.nmax, T.list_cap, g_default, (int)T.blocks.size()) <= wb::LDS_LIMIT;
 }
 
 int build_tables(const wb_robot_desc *d, Tables &T) {
@@ -670,8 +674,9 @@ int wb_fk(const wb_robot *robot, int64_t B, const float *q, float *link_pose, fl
     WB_TRY(check_B(B));
     if (B == 0) return WB_OK;
     WB_TRY(check_ptr(q, "q", robot->T.n > 0));
-    WB_TRY(check_ptr(link_pose, "link_pose", true));
+    WB_TRY(check_ptr(link_pose, "link_pose", false));
     WB_TRY(check_ptr(spheres, "spheres", false));
+    if (!link_pose && !spheres) return fail(WB_ERR_INVALID_ARG, "link_pose and spheres are both null");
     return finish(wb::launch_fk(robot->dev, B, q, link_pose, spheres, stream), "wb_fk launch");
 }
 
@@ -686,8 +691,11 @@ int wb_rnea(const wb_robot *robot, int64_t B, const float *q, const float *qd, c
     WB_TRY(check_ptr(qdd, "qdd", need));
     WB_TRY(check_ptr(f_ext, "f_ext", false));
     WB_TRY(check_ptr(tau, "tau", need));
-    WB_TRY(check_ptr(cache, "cache", true));
-    return finish(wb::launch_rnea(robot->dev, B, q, qd, qdd, f_ext, tau, cache, stream), "wb_rnea launch");
+    WB_TRY(check_ptr(cache, "cache", false));
+    if (cache) return finish(wb::launch_rnea(robot->dev, B, q, qd, qdd, f_ext, tau, cache, stream), "wb_rnea launch");
+    if (!robot->T.lanes)
+        return fail(WB_ERR_UNSUPPORTED, "a robot of %d links (more than 64) needs the cache", robot->T.L);
+    return finish(wb::launch_rnea_lanes(robot->dev, robot->fz, B, q, qd, qdd, f_ext, tau, stream), "wb_rnea launch");
 }
 
 int wb_self_collision(const wb_robot *robot, int64_t B, const float *spheres, float *max_pen,
@@ -740,7 +748,7 @@ int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float
 }
 
 int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const float *qd,
-                     const float *qdd, const float *cache, const float *g_tau, float *g_q,
+                     const float *qdd, const float *f_ext, const float *cache, const float *g_tau, float *g_q,
                      float *g_qd, float *g_qdd, float *g_fext, void *workspace, hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
@@ -749,12 +757,21 @@ int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const flo
     WB_TRY(check_ptr(q, "q", need));
     WB_TRY(check_ptr(qd, "qd", need));
     WB_TRY(check_ptr(qdd, "qdd", need));
-    WB_TRY(check_ptr(cache, "cache", true));
+    WB_TRY(check_ptr(f_ext, "f_ext", false));
+    WB_TRY(check_ptr(cache, "cache", false));
     WB_TRY(check_ptr(g_tau, "g_tau", need));
     WB_TRY(check_ptr(g_q, "g_q", need));
     WB_TRY(check_ptr(g_qd, "g_qd", need));
     WB_TRY(check_ptr(g_qdd, "g_qdd", need));
     WB_TRY(check_ptr(g_fext, "g_fext", false));
+    if (!cache) {
+        if (!robot->T.lanes)
+            return fail(WB_ERR_UNSUPPORTED, "a robot of %d links (more than 64) needs the cache", robot->T.L);
+        WB_TRY(check_ptr(workspace, "workspace", false));
+        return finish(wb::launch_rnea_backward_lanes(robot->dev, robot->fz, B, q, qd, qdd, f_ext, g_tau, g_q, g_qd,
+                                                     g_qdd, g_fext, stream),
+                      "wb_rnea_backward launch");
+    }
     WB_TRY(check_ptr(workspace, "workspace", true));
     return finish(wb::launch_rnea_backward(robot->dev, B, q, qd, qdd, cache, g_tau, g_q, g_qd, g_qdd, g_fext,
                                            static_cast<float *>(workspace), stream),
@@ -902,7 +919,7 @@ int wb_robot_set_link_inertia(wb_robot *robot, int32_t link, float mass, const f
     F.mass = mass;
     for (int c = 0; c < 3; ++c) F.com[c] = com[c];
     for (int c = 0; c < 6; ++c) F.I[c] = inertia[c];
-    if (T.fused) {
+    if (T.lanes) {
         const int i = T.lane_of[link];
         T.f_lf[15 * 64 + i] = mass;
         for (int c = 0; c < 3; ++c) T.f_lf[(16 + c) * 64 + i] = com[c];
@@ -923,7 +940,7 @@ int wb_robot_set_link_inertia(wb_robot *robot, int32_t link, float mass, const f
     if (e == hipSuccess)
         e = hipMemcpy(base + robot->o_lf + (size_t)link * sizeof(wb::LinkF), &F, sizeof(wb::LinkF),
                       hipMemcpyHostToDevice);
-    if (e == hipSuccess && T.fused)
+    if (e == hipSuccess && T.lanes)
         e = hipMemcpy(base + robot->o_ff, T.f_lf.data(), T.f_lf.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess && T.kin)
         e = hipMemcpy(base + robot->o_kf, T.k_lf.data(), T.k_lf.size() * sizeof(float), hipMemcpyHostToDevice);
@@ -1283,6 +1300,48 @@ int wb_plan_run(const wb_plan *plan, const wb_tree_io *io, float torque_weight, 
         ext = ext || x.f_ext || x.g_fext;
     }
     return finish(wb::launch_plan(a, plan->nmax, plan->n_wg, plan->lds, ext, stream), "wb_plan_run launch");
+}
+
+int wb_plan_capture(const wb_plan *plan, const wb_tree_io *io, float torque_weight, float margin, float hinge_weight,
+                    float lr, int32_t iters, hipGraphExec_t *out) {
+    if (!out) return fail(WB_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (!plan || !plan->dmem) return fail(WB_ERR_INVALID_ARG, "plan is null or destroyed");
+    if (iters < 1 || iters > (1 << 20)) return fail(WB_ERR_INVALID_ARG, "iters %d outside [1, 2^20]", iters);
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != plan->device) e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "selecting the plan's device");
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    int rc = WB_OK;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int i = 0; i < iters && rc == WB_OK; ++i)
+            rc = wb_plan_run(plan, io, torque_weight, margin, hinge_weight, lr, s);
+        const hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (rc == WB_OK) e = e2;
+    }
+    if (rc == WB_OK && e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (s) (void)hipStreamDestroy(s);
+    if (prev >= 0 && prev != plan->device) (void)hipSetDevice(prev);
+    if (rc != WB_OK) return rc;   // wb_plan_run's message stands
+    if (e != hipSuccess) return hip_fail(e, "capturing the plan into a graph");
+    *out = x;
+    return WB_OK;
+}
+
+int wb_graph_launch(hipGraphExec_t graph, hipStream_t stream) {
+    if (!graph) return fail(WB_ERR_INVALID_ARG, "graph is null");
+    return finish(hipGraphLaunch(graph, stream), "launching the graph");
+}
+
+int wb_graph_destroy(hipGraphExec_t graph) {
+    if (!graph) return WB_OK;
+    return finish(hipGraphExecDestroy(graph), "destroying the graph");
 }
 
 int wb_plan_get_info(const wb_plan *plan, int32_t *n_items, int32_t *n_workgroups) {

@@ -149,6 +149,13 @@ hipError_t launch_rnea(const DevRobot &rb, int64_t B, const float *q, const floa
 hipError_t launch_rnea_backward(const DevRobot &rb, int64_t B, const float *q, const float *qd,
                                 const float *qdd, const float *cache, const float *g_tau,
                                 float *g_q, float *g_qd, float *g_qdd, float *g_fext, float *ws, hipStream_t s);
+// Group-per-state RNEA and VJP without a cache (rnea_lanes.hip); robots of
+// at most 64 links.
+hipError_t launch_rnea_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, const float *q, const float *qd,
+                             const float *qdd, const float *f_ext, float *tau, hipStream_t s);
+hipError_t launch_rnea_backward_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, const float *q,
+                                      const float *qd, const float *qdd, const float *f_ext, const float *g_tau,
+                                      float *g_q, float *g_qd, float *g_qdd, float *g_fext, hipStream_t s);
 hipError_t launch_self_collision(const DevRobot &rb, int64_t B, const float *spheres,
                                  float *max_pen, int32_t *argmax, int32_t *n_coll, hipStream_t s);
 hipError_t launch_self_collision_backward(const DevRobot &rb, int64_t B, const float *spheres,
@@ -191,6 +198,8 @@ inline size_t fused_lds_bytes(int L, int nmax, int list_cap, int G, int n_blocks
     return (size_t)4 * (64 / G) * group_lds_bytes(L, nmax, list_cap) + tab_lds_bytes(n_blocks_pad);
 }
 constexpr size_t LDS_LIMIT = 65536;
+// Sphere slots per link the fused kernels are instantiated for.
+constexpr int FUSED_MAX_SLOTS = 8;
 
 // States per workgroup of the self-collision kernel (LDS tile).
 int self_collision_tile(int L, int nmax, int list_cap);

@@ -173,10 +173,11 @@ def _empty(shape, robot: Robot, dtype=torch.float32):
 
 # ------------------------------------------------------------------ the ABI
 
-def wb_fk(robot: Robot, q: torch.Tensor, link_pose=None, spheres=None, want_spheres=True):
+def wb_fk(robot: Robot, q: torch.Tensor, link_pose=None, spheres=None, want_spheres=True, want_pose=True):
     n, B = robot.n_dof, q.shape[-1]
     L, S = robot.n_links, robot.n_spheres
-    link_pose = _empty((L, 12, B), robot) if link_pose is None else link_pose
+    if link_pose is None and want_pose:
+        link_pose = _empty((L, 12, B), robot)
     if spheres is None and want_spheres:
         spheres = _empty((S, 3, B), robot)
     _chk(q, "q", (n, B), device=robot.device)
@@ -258,12 +259,15 @@ def wb_edt(sites: torch.Tensor, voxel_size: float = 1.0, nearest=True, dist=True
     return nearest, dist
 
 
-def wb_rnea(robot: Robot, q, qd, qdd, tau=None, cache=None, f_ext=None):
-    """tau [n,B] (and the cache for the backward); f_ext [L,6,B] external
+
+def wb_rnea(robot: Robot, q, qd, qdd, tau=None, cache=None, f_ext=None, want_cache=True):
+    """tau [n,B] and the cache for the backward (None with want_cache=False:
+    nothing is stored and the backward recomputes); f_ext [L,6,B] external
     link forces in link coordinates (moment, force), or None."""
     n, B, L = robot.n_dof, q.shape[-1], robot.n_links
     tau = _empty((n, B), robot) if tau is None else tau
-    cache = _empty((L, 18, B), robot) if cache is None else cache
+    if cache is None and want_cache:
+        cache = _empty((L, 18, B), robot)
     for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (tau, "tau")):
         _chk(t, nm, (n, B), device=robot.device)
     _chk(cache, "cache", (L, 18, B), device=robot.device)
@@ -318,23 +322,26 @@ def wb_fk_backward(robot: Robot, q, g_spheres=None, g_link_pose=None, link_pose=
 
 
 def wb_rnea_backward(robot: Robot, q, qd, qdd, cache, g_tau, g_q=None, g_qd=None, g_qdd=None,
-                     workspace=None, g_fext=None):
+                     workspace=None, g_fext=None, f_ext=None):
     """g_q, g_qd, g_qdd [n,B]; with g_fext [L,6,B] also the gradient on the
-    external forces of the forward call that wrote the cache."""
+    external forces.  cache: the forward call's (its forces included), or
+    None to recompute every forward quantity from q, qd, qdd and f_ext."""
     n, B, L = robot.n_dof, q.shape[-1], robot.n_links
     g_q = _empty((n, B), robot) if g_q is None else g_q
     g_qd = _empty((n, B), robot) if g_qd is None else g_qd
     g_qdd = _empty((n, B), robot) if g_qdd is None else g_qdd
-    workspace = robot.workspace(B) if workspace is None else workspace
+    if cache is not None and workspace is None:
+        workspace = robot.workspace(B)
     for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (g_tau, "g_tau"), (g_q, "g_q"), (g_qd, "g_qd"),
                   (g_qdd, "g_qdd")):
         _chk(t, nm, (n, B), device=robot.device)
     _chk(cache, "cache", (L, 18, B), device=robot.device)
     _chk(g_fext, "g_fext", (L, 6, B), device=robot.device)
-    if workspace.numel() * workspace.element_size() < robot.workspace_bytes(B):
+    _chk(f_ext, "f_ext", (L, 6, B), device=robot.device)
+    if workspace is not None and workspace.numel() * workspace.element_size() < robot.workspace_bytes(B):
         raise ValueError("workspace too small")
-    check(lib().wb_rnea_backward(robot.handle, B, _p(q), _p(qd), _p(qdd), _p(cache), _p(g_tau), _p(g_q),
-                                 _p(g_qd), _p(g_qdd), _p(g_fext), _p(workspace), _stream()))
+    check(lib().wb_rnea_backward(robot.handle, B, _p(q), _p(qd), _p(qdd), _p(f_ext), _p(cache), _p(g_tau),
+                                 _p(g_q), _p(g_qd), _p(g_qdd), _p(g_fext), _p(workspace), _stream()))
     return g_q, g_qd, g_qdd
 
 
@@ -459,6 +466,20 @@ class Plan:
         """ios: one dict per robot with keys q, qd, qdd and optional w, tau,
         cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd, f_ext, g_fext
         (device tensors)."""
+        arr = self._io_array(ios)
+        check(lib().wb_plan_run(self.handle, arr, float(torque_weight), float(margin), float(hinge_weight),
+                                float(lr), _stream()))
+
+    def capture(self, ios, torque_weight=0.0, margin=0.0, hinge_weight=0.0, lr=0.0, iters=1) -> "PlanGraph":
+        """`iters` runs with these buffers captured into an executable HIP
+        graph by the library (wb_plan_capture); the tensors must outlive it."""
+        arr = self._io_array(ios)
+        g = C.c_void_p()
+        check(lib().wb_plan_capture(self.handle, arr, float(torque_weight), float(margin), float(hinge_weight),
+                                    float(lr), int(iters), C.byref(g)))
+        return PlanGraph(g, ios)
+
+    def _io_array(self, ios):
         n = len(self.robots)
         arr = (_abi.WbTreeIO * n)()
         for i, (r, b, io) in enumerate(zip(self.robots, self.B, ios)):
@@ -474,12 +495,33 @@ class Plan:
             for key, _ in _abi.WbTreeIO._fields_:
                 t = io.get(key)
                 setattr(arr[i], key, None if t is None else t.data_ptr())
-        check(lib().wb_plan_run(self.handle, arr, float(torque_weight), float(margin), float(hinge_weight),
-                                float(lr), _stream()))
+        return arr
 
     def close(self):
         if getattr(self, "handle", None) is not None:
             check(lib().wb_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PlanGraph:
+    """An executable graph made by wb_plan_capture; launch() enqueues it on
+    the current stream (wb_graph_launch)."""
+
+    def __init__(self, handle, ios):
+        self.handle, self._ios = handle, ios   # the graph holds the buffers' addresses
+
+    def launch(self) -> None:
+        check(lib().wb_graph_launch(self.handle, _stream()))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            check(lib().wb_graph_destroy(self.handle))
             self.handle = None
 
     def __del__(self):
