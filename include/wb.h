@@ -412,6 +412,23 @@ int wb_edt_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, size_t *bytes);
 int wb_edt(int32_t nx, int32_t ny, int32_t nz, const uint8_t *sites, float voxel_size, int32_t *nearest,
            float *dist, void *workspace, hipStream_t stream);
 
+/* wb_edt for callers that cannot allocate device memory (code under HIP
+ * graph capture, per-frame perception loops, harnesses that forbid
+ * hipMalloc): the same three launches and results as wb_edt, with the
+ * workspace taken from a device-resident scratch array that the library
+ * holds per device for the life of the process (64 MiB: two int32 planes
+ * of WB_EDT_NOALLOC_MAX_VOXELS voxels).  Allocates and frees nothing, also
+ * on its first call on a device, which only looks up the array's address.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one GPU (concurrent streams, threads) race and must be serialized by the
+ * caller.  Nothing in the array needs to start at zero (every pass writes
+ * its whole plane before the next reads it).  WB_ERR_UNSUPPORTED when
+ * nx * ny * nz exceeds WB_EDT_NOALLOC_MAX_VOXELS; otherwise the argument
+ * rules and errors of wb_edt. */
+#define WB_EDT_NOALLOC_MAX_VOXELS (1 << 23)
+int wb_edt_noalloc(int32_t nx, int32_t ny, int32_t nz, const uint8_t *sites, float voxel_size, int32_t *nearest,
+                   float *dist, hipStream_t stream);
+
 /* ------------------------------------------------ uneven multi-robot batches
  * A plan runs the fused iteration for several robots, each with its own
  * batch size, in one persistent launch (suitable for HIP graph capture; the

@@ -80,6 +80,7 @@ _SIGS = {
     "wb_kinematics_backward": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp],
     "wb_edt_workspace_bytes": [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
     "wb_edt": [C.c_int32, C.c_int32, C.c_int32, _vp, C.c_float, _vp, _vp, _vp, _vp],
+    "wb_edt_noalloc": [C.c_int32, C.c_int32, C.c_int32, _vp, C.c_float, _vp, _vp, _vp],
     "wb_bspline_eval": [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_int32, _vp, _vp, _vp, _vp,
                         _vp, _vp, _vp, _vp],
     "wb_bspline_backward": [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, C.c_float,

@@ -2,6 +2,7 @@
 // upload and the extern "C" entry points declared in include/wb.h.
 #include "wb.h"
 #include "edt.h"
+#include "edt_scratch.h"
 #include "kin.h"
 #include "wb_internal.h"
 
@@ -1072,6 +1073,31 @@ int wb_edt(int32_t nx, int32_t ny, int32_t nz, const uint8_t *sites, float voxel
     // without a nearest-site output the last pass writes into A, free by then
     return finish(wb::launch_edt(nx, ny, nz, sites, voxel_size, nearest ? nearest : A, dist, A, Bg, stream),
                   "wb_edt launch");
+}
+
+int wb_edt_noalloc(int32_t nx, int32_t ny, int32_t nz, const uint8_t *sites, float voxel_size, int32_t *nearest,
+                   float *dist, hipStream_t stream) {
+    size_t need = 0;
+    WB_TRY(wb_edt_workspace_bytes(nx, ny, nz, &need));
+    const size_t N = (size_t)nx * ny * nz;
+    if (N > (size_t)WB_EDT_NOALLOC_MAX_VOXELS)
+        return fail(WB_ERR_UNSUPPORTED, "grid %d x %d x %d has %zu voxels; wb_edt_noalloc takes at most %d", nx, ny,
+                    nz, N, WB_EDT_NOALLOC_MAX_VOXELS);
+    if (!std::isfinite(voxel_size) || voxel_size < 0.0f)
+        return fail(WB_ERR_INVALID_ARG, "voxel_size must be finite and >= 0");
+    if (!sites) return fail(WB_ERR_INVALID_ARG, "sites is null");
+    WB_TRY(check_ptr(nearest, "nearest", false));
+    WB_TRY(check_ptr(dist, "dist", false));
+    int32_t *scratch = nullptr;
+    size_t have = 0;
+    const hipError_t e = wb::edt_scratch_address(&scratch, &have);
+    if (e != hipSuccess) return hip_fail(e, "looking up the distance-transform scratch array");
+    if (have < need) return fail(WB_ERR_UNSUPPORTED, "scratch array of %zu bytes is below the %zu needed", have, need);
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    int32_t *A = scratch;
+    int32_t *Bg = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(scratch) + up(N * 4));
+    return finish(wb::launch_edt(nx, ny, nz, sites, voxel_size, nearest ? nearest : A, dist, A, Bg, stream),
+                  "wb_edt_noalloc launch");
 }
 
 int wb_robot_get_tune(const wb_robot *robot, wb_tune *tune) {

@@ -259,6 +259,23 @@ def wb_edt(sites: torch.Tensor, voxel_size: float = 1.0, nearest=True, dist=True
     return nearest, dist
 
 
+EDT_NOALLOC_MAX_VOXELS = 1 << 23
+
+
+def wb_edt_noalloc(sites: torch.Tensor, voxel_size: float = 1.0, nearest=None, dist=None):
+    """wb_edt without a workspace: the library's per-device scratch array
+    serves as one (grids of at most EDT_NOALLOC_MAX_VOXELS voxels).  The
+    outputs must be given as tensors (or None to skip); nothing is
+    allocated, so the call may run where allocation is not allowed."""
+    if sites.dim() != 3:
+        raise ValueError("sites must be [nz, ny, nx]")
+    nz, ny, nx = sites.shape
+    _chk(sites, "sites", (nz, ny, nx), torch.uint8)
+    _chk(nearest, "nearest", (nz, ny, nx), torch.int32)
+    _chk(dist, "dist", (nz, ny, nx))
+    check(lib().wb_edt_noalloc(nx, ny, nz, _p(sites), float(voxel_size), _p(nearest), _p(dist), _stream()))
+    return nearest, dist
+
 
 def wb_rnea(robot: Robot, q, qd, qdd, tau=None, cache=None, f_ext=None, want_cache=True):
     """tau [n,B] and the cache for the backward (None with want_cache=False:
