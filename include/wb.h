@@ -12,10 +12,17 @@
  * Conventions shared by every call
  *   - Arithmetic is FP32 on the GPU.
  *   - Batched arrays are structure-of-arrays with the state index fastest:
- *     an array documented as [k][B] holds element (i, b) at i*B + b.  All
- *     such pointers are device pointers owned by the caller; the library
- *     never allocates, frees or synchronizes inside a launch call, so every
- *     launch call may be captured into a HIP graph.
+ *     an array documented as [k][B] holds element (i, b) at i*ld + b, where
+ *     ld >= B is the call's leading dimension (rows may be padded, e.g. to
+ *     a multiple of a cache line, or be a column slice of a wider batch;
+ *     ld = 0 means ld = B; ld < B is WB_ERR_INVALID_ARG).  The calls that
+ *     take an ld apply it to every [k][B] array they touch, their workspace
+ *     and cache included (size those for ld states); padding entries are
+ *     never read or written.  Per-state arrays [B] are dense.  Calls without
+ *     an ld (kinematics outputs, B-spline, distance transform) take dense
+ *     arrays.  All such pointers are device pointers owned by the caller;
+ *     the library never allocates, frees or synchronizes inside a launch
+ *     call, so every launch call may be captured into a HIP graph.
  *   - Every launch call enqueues its kernels on the given stream and returns
  *     immediately; results are valid once the stream reaches that point.
  *   - Every call returns WB_OK or an error code; wb_last_error() returns a
@@ -142,9 +149,9 @@ int wb_robot_get_info(const wb_robot *robot, wb_robot_info *info);
 
 /* Scratch needed by wb_fk_backward and wb_rnea_backward for B states, in
  * bytes (caller-allocated device memory, 256-byte aligned, reusable across
- * calls on one stream). */
+ * calls on one stream); with padded rows pass the calls' ld for B. */
 int wb_workspace_bytes(const wb_robot *robot, int64_t B, size_t *bytes);
-/* Size of the RNEA forward cache for B states: [L][18][B] floats holding,
+/* Size of the RNEA forward cache for B states (pass ld with padded rows): [L][18][B] floats holding,
  * per link, spatial velocity v (6), acceleration a (6) and the accumulated
  * force F (6) of Alg. 4 (the cache of Sec. 6.3 "Memory layout", unpadded). */
 int wb_rnea_cache_bytes(const wb_robot *robot, int64_t B, size_t *bytes);
@@ -157,7 +164,7 @@ int wb_rnea_cache_bytes(const wb_robot *robot, int64_t B, size_t *bytes);
  *     instead of re-reading it;
  *   spheres[S][3][B] world sphere centres, or NULL to skip them.
  * WB_ERR_INVALID_ARG when both outputs are NULL. */
-int wb_fk(const wb_robot *robot, int64_t B, const float *q, float *link_pose, float *spheres,
+int wb_fk(const wb_robot *robot, int64_t B, int64_t ld, const float *q, float *link_pose, float *spheres,
           hipStream_t stream);
 
 /* ------------------------------------------------------ kinematics outputs
@@ -220,7 +227,7 @@ int wb_kinematics_backward(const wb_robot *robot, int64_t B, const float *q, con
  * nothing is stored (one group of lanes per state keeps every link quantity
  * in registers) and the backward recomputes them.  Without a cache the
  * robot must have at most 64 links (WB_ERR_UNSUPPORTED otherwise). */
-int wb_rnea(const wb_robot *robot, int64_t B, const float *q, const float *qd, const float *qdd,
+int wb_rnea(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const float *qd, const float *qdd,
             const float *f_ext, float *tau, float *cache, hipStream_t stream);
 
 /* Self-collision map-reduce (Sec. 6.2).  spheres[S][3][B] -> per state
@@ -229,7 +236,7 @@ int wb_rnea(const wb_robot *robot, int64_t B, const float *q, const float *qd, c
  *   argmax[B]   lowest pair index attaining it (-1 when there is none),
  *   n_coll[B]   number of pairs with positive penetration.
  * Any of the three outputs may be NULL to skip it (not all three). */
-int wb_self_collision(const wb_robot *robot, int64_t B, const float *spheres, float *max_pen,
+int wb_self_collision(const wb_robot *robot, int64_t B, int64_t ld, const float *spheres, float *max_pen,
                       int32_t *argmax, int32_t *n_coll, hipStream_t stream);
 
 /* -------------------------------------------------------------- adjoints */
@@ -239,7 +246,7 @@ int wb_self_collision(const wb_robot *robot, int64_t B, const float *spheres, fl
  * two spheres of pair argmax[b], which receive -/+ g_cost[b] * u with u the
  * unit vector from sphere t to sphere s, when max_pen[b] + margin > 0 (and
  * zero otherwise, including coincident centres). */
-int wb_self_collision_backward(const wb_robot *robot, int64_t B, const float *spheres,
+int wb_self_collision_backward(const wb_robot *robot, int64_t B, int64_t ld, const float *spheres,
                                const int32_t *argmax, const float *max_pen, float margin,
                                const float *g_cost, float *g_spheres, hipStream_t stream);
 
@@ -248,7 +255,7 @@ int wb_self_collision_backward(const wb_robot *robot, int64_t B, const float *sp
  * be NULL, not both) -> g_q[n][B] (overwritten).  link_pose is the output of
  * wb_fk for the same q, or NULL to recompute the transforms from q inside
  * the kernel.  workspace: wb_workspace_bytes(robot, B). */
-int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float *link_pose,
+int wb_fk_backward(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const float *link_pose,
                    const float *g_link_pose, const float *g_spheres, float *g_q, void *workspace,
                    hipStream_t stream);
 
@@ -264,7 +271,7 @@ int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float
  *     and f_ext (NULL = none) in registers, one group of lanes per state;
  *     workspace may be NULL; robots of at most 64 links
  *     (WB_ERR_UNSUPPORTED otherwise). */
-int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const float *qd,
+int wb_rnea_backward(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const float *qd,
                      const float *qdd, const float *f_ext, const float *cache, const float *g_tau, float *g_q,
                      float *g_qd, float *g_qdd, float *g_fext, void *workspace, hipStream_t stream);
 
@@ -277,13 +284,13 @@ int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const flo
  *   g_maxpen[b] = hinge_weight * (max_pen[b] + margin > 0)
  * w may be NULL; max_pen may be NULL (no hinge term, g_maxpen untouched);
  * cost and g_maxpen may be NULL. */
-int wb_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float torque_weight,
+int wb_cost_head(int64_t B, int64_t ld, int32_t n, const float *tau, const float *w, float torque_weight,
                  const float *max_pen, float margin, float hinge_weight, float *cost,
                  float *g_tau, float *g_maxpen, hipStream_t stream);
 
 /* Gradient step in place: q -= lr * (g_q + g_q2), qd -= lr * g_qd,
  * qdd -= lr * g_qdd, all [n][B]; g_q2 may be NULL. */
-int wb_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd, const float *g_q,
+int wb_sgd_step(int64_t B, int64_t ld, int32_t n, float lr, float *q, float *qd, float *qdd, const float *g_q,
                 const float *g_q2, const float *g_qd, const float *g_qdd, hipStream_t stream);
 
 /* ---------------------------------------------- B-spline trajectory front end
@@ -349,7 +356,7 @@ int wb_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float
  * are ordered differently).  Needs n_links <= 64 and the per-state sweep
  * tables of a 256-lane workgroup within 64 KB of LDS
  * (wb_robot_info.fused_supported), else WB_ERR_UNSUPPORTED. */
-int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, float *qdd, const float *w,
+int wb_wholebody_step(const wb_robot *robot, int64_t B, int64_t ld, float *q, float *qd, float *qdd, const float *w,
                       float torque_weight, float margin, float hinge_weight, float lr, float *tau,
                       float *cost, float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q,
                       float *g_qd, float *g_qdd, const float *f_ext, float *g_fext, hipStream_t stream);
@@ -458,6 +465,7 @@ typedef struct wb_tree_io {
     float *g_q, *g_qd, *g_qdd;
     const float *f_ext;   /* [L][6][B] or NULL, as in wb_wholebody_step */
     float *g_fext;        /* [L][6][B] or NULL */
+    int64_t ld;           /* leading dimension of this tree's [k][B] arrays (0 = its B) */
 } wb_tree_io;
 typedef struct wb_plan wb_plan;
 int wb_plan_create(const wb_robot *const *robots, const int64_t *B, int32_t n_trees, const wb_tune *tune,

@@ -44,9 +44,12 @@ class WbTune(C.Structure):
     _fields_ = [("lanes_per_state", C.c_int32), ("states_per_item", C.c_int32), ("ns_per_state", C.c_float)]
 
 
+TREE_IO_POINTERS = ("q", "qd", "qdd", "w", "tau", "cost", "max_pen", "argmax", "n_coll", "g_q", "g_qd", "g_qdd",
+                    "f_ext", "g_fext")
+
+
 class WbTreeIO(C.Structure):
-    _fields_ = [(nm, _vp) for nm in ("q", "qd", "qdd", "w", "tau", "cost", "max_pen", "argmax", "n_coll",
-                                     "g_q", "g_qd", "g_qdd", "f_ext", "g_fext")]
+    _fields_ = [(nm, _vp) for nm in TREE_IO_POINTERS] + [("ld", C.c_int64)]
 
 
 class WbError(RuntimeError):
@@ -64,15 +67,15 @@ _SIGS = {
     "wb_robot_get_info": [_vp, C.POINTER(WbRobotInfo)],
     "wb_workspace_bytes": [_vp, C.c_int64, C.POINTER(C.c_size_t)],
     "wb_rnea_cache_bytes": [_vp, C.c_int64, C.POINTER(C.c_size_t)],
-    "wb_fk": [_vp, C.c_int64, _vp, _vp, _vp, _vp],
-    "wb_rnea": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
-    "wb_self_collision": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp],
-    "wb_self_collision_backward": [_vp, C.c_int64, _vp, _vp, _vp, C.c_float, _vp, _vp, _vp],
-    "wb_fk_backward": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
-    "wb_rnea_backward": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
-    "wb_cost_head": [C.c_int64, C.c_int32, _vp, _vp, C.c_float, _vp, C.c_float, C.c_float, _vp, _vp,
+    "wb_fk": [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp, _vp],
+    "wb_rnea": [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "wb_self_collision": [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp, _vp, _vp],
+    "wb_self_collision_backward": [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp, C.c_float, _vp, _vp, _vp],
+    "wb_fk_backward": [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "wb_rnea_backward": [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "wb_cost_head": [C.c_int64, C.c_int64, C.c_int32, _vp, _vp, C.c_float, _vp, C.c_float, C.c_float, _vp, _vp,
                      _vp, _vp],
-    "wb_sgd_step": [C.c_int64, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "wb_sgd_step": [C.c_int64, C.c_int64, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "wb_robot_set_link_inertia": [_vp, C.c_int32, C.c_float, _vp, _vp],
     "wb_robot_set_tool_frames": [_vp, C.c_int32, _vp, _vp],
     "wb_robot_get_tool_count": [_vp, _i32p],
@@ -85,7 +88,7 @@ _SIGS = {
                         _vp, _vp, _vp, _vp],
     "wb_bspline_backward": [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, C.c_float,
                             _vp, _vp],
-    "wb_wholebody_step": [_vp, C.c_int64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float,
+    "wb_wholebody_step": [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float,
                           _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "wb_robot_set_tune": [_vp, C.POINTER(WbTune)],
     "wb_robot_get_tune": [_vp, C.POINTER(WbTune)],

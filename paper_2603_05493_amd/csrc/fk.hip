@@ -94,22 +94,24 @@ __device__ __forceinline__ void fk_state(const DevRobot &rb, int64_t B, int64_t 
     }
 }
 
-__global__ void __launch_bounds__(256) k_fk(DevRobot rb, int64_t B, const float *__restrict__ q,
+// In the kernels below nb is the number of states and B the row length of
+// every [k][B] array (the ABI's leading dimension ld >= nb).
+__global__ void __launch_bounds__(256) k_fk(DevRobot rb, int64_t nb, int64_t B, const float *__restrict__ q,
                                             float *__restrict__ pose, float *__restrict__ sph) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    if (b >= nb) return;
     fk_state(rb, B, b, q, pose, sph);
 }
 
 // ws layout per state: [0, 12L) recomputed poses (when pose == nullptr),
 // [12L, 18L) per-link accumulators (F, M) for links with a non-adjacent child.
-__global__ void __launch_bounds__(256) k_fk_backward(DevRobot rb, int64_t B, const float *__restrict__ q,
+__global__ void __launch_bounds__(256) k_fk_backward(DevRobot rb, int64_t nb, int64_t B, const float *__restrict__ q,
                                                      const float *__restrict__ pose_in,
                                                      const float *__restrict__ g_pose,
                                                      const float *__restrict__ g_sph,
                                                      float *__restrict__ g_q, float *__restrict__ ws) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    if (b >= nb) return;
     const int L = rb.L;
     const float *pose = pose_in;
     if (!pose) {
@@ -184,20 +186,20 @@ __global__ void __launch_bounds__(256) k_fk_backward(DevRobot rb, int64_t B, con
     }
 }
 
-hipError_t launch_fk(const DevRobot &rb, int64_t B, const float *q, float *pose, float *spheres,
+hipError_t launch_fk(const DevRobot &rb, int64_t B, int64_t ld, const float *q, float *pose, float *spheres,
                      hipStream_t s) {
     if (B == 0) return hipSuccess;
     dim3 grid((unsigned)((B + 255) / 256));
-    hipLaunchKernelGGL(k_fk, grid, dim3(256), 0, s, rb, B, q, pose, spheres);
+    hipLaunchKernelGGL(k_fk, grid, dim3(256), 0, s, rb, B, ld, q, pose, spheres);
     return hipGetLastError();
 }
 
-hipError_t launch_fk_backward(const DevRobot &rb, int64_t B, const float *q, const float *pose,
+hipError_t launch_fk_backward(const DevRobot &rb, int64_t B, int64_t ld, const float *q, const float *pose,
                               const float *g_pose, const float *g_sph, float *g_q, float *ws,
                               hipStream_t s) {
     if (B == 0) return hipSuccess;
     dim3 grid((unsigned)((B + 255) / 256));
-    hipLaunchKernelGGL(k_fk_backward, grid, dim3(256), 0, s, rb, B, q, pose, g_pose, g_sph, g_q, ws);
+    hipLaunchKernelGGL(k_fk_backward, grid, dim3(256), 0, s, rb, B, ld, q, pose, g_pose, g_sph, g_q, ws);
     return hipGetLastError();
 }
 

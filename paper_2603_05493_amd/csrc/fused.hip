@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(256, EXT ? 3 : 4) k_fused_step(FusedArgs A) {
     uint16_t *tab = reinterpret_cast<uint16_t *>(lds + 4 * SLW);
     stage_table(A.rb, tab);
     __syncthreads();
-    run_states<NMAX, EXT>(A.rb, tab, A.fz, A.io, A.k, lds + wave * SLW, G, A.B, b0, count);
+    run_states<NMAX, EXT>(A.rb, tab, A.fz, A.io, A.k, lds + wave * SLW, G, A.io.ld, b0, count);
 }
 
 // Persistent launch over an uneven batch of robots: workgroup w processes
@@ -358,7 +358,8 @@ __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
             staged = item.tree;
         }
         // a fixed region per wave, sized for the plan's largest tree
-        run_states<NMAX, EXT>(T.rb, tab, T.fz, A.io[item.tree], A.k, lds + wave * A.wave_stride, G, T.B,
+        run_states<NMAX, EXT>(T.rb, tab, T.fz, A.io[item.tree], A.k, lds + wave * A.wave_stride, G,
+                              A.io[item.tree].ld,
                               item.b0, item.count);
     }
 }

@@ -1,6 +1,7 @@
 // Small per-state kernels of the optimizer iteration: the hinge adjoint of
 // self-collision, the cost head and the gradient step.  All are one state
-// per lane over [k][B] arrays (coalesced in B).
+// per lane over [k][B] arrays (coalesced in B); nb is the number of states
+// and B the row length of the arrays (the ABI's ld >= nb).
 #include "spatial.h"
 
 namespace wb {
@@ -8,13 +9,13 @@ namespace wb {
 // Hinge h = max(0, max_pen + margin) at the most penetrating pair: its
 // subgradient moves the two spheres of that pair apart along their centre
 // line (cuRoboV2 Sec. 6.2 reduces to one most-penetrating pair per state).
-__global__ void __launch_bounds__(256) k_sc_backward(DevRobot rb, int64_t B, const float *__restrict__ sph,
+__global__ void __launch_bounds__(256) k_sc_backward(DevRobot rb, int64_t nb, int64_t B, const float *__restrict__ sph,
                                                      const int32_t *__restrict__ argmax,
                                                      const float *__restrict__ max_pen, float margin,
                                                      const float *__restrict__ g_cost,
                                                      float *__restrict__ g_sph) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    if (b >= nb) return;
     for (int i = 0; i < rb.S * 3; ++i) g_sph[(int64_t)i * B + b] = 0.0f;
     const int p = argmax[b];
     if (p < 0 || p >= rb.n_pairs || !(max_pen[b] + margin > 0.0f)) return;
@@ -31,13 +32,13 @@ __global__ void __launch_bounds__(256) k_sc_backward(DevRobot rb, int64_t B, con
     gt[0] = g * d.x;  gt[B] = g * d.y;  gt[2 * B] = g * d.z;
 }
 
-__global__ void __launch_bounds__(256) k_cost_head(int64_t B, int n, const float *__restrict__ tau,
+__global__ void __launch_bounds__(256) k_cost_head(int64_t nb, int64_t B, int n, const float *__restrict__ tau,
                                                    const float *__restrict__ w, float tw,
                                                    const float *__restrict__ max_pen, float margin,
                                                    float hw, float *__restrict__ cost,
                                                    float *__restrict__ g_tau, float *__restrict__ g_mp) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    if (b >= nb) return;
     float c = 0.0f;
     for (int j = 0; j < n; ++j) {
         const int64_t o = (int64_t)j * B + b;
@@ -58,45 +59,47 @@ __global__ void __launch_bounds__(256) k_cost_head(int64_t B, int n, const float
     if (cost) cost[b] = c;
 }
 
-__global__ void __launch_bounds__(256) k_sgd_step(int64_t total, float lr, float *__restrict__ q,
-                                                  float *__restrict__ qd, float *__restrict__ qdd,
-                                                  const float *__restrict__ g_q, const float *__restrict__ g_q2,
-                                                  const float *__restrict__ g_qd,
+// One thread per (joint, state): i = j * nb + b, at element j * B + b.
+__global__ void __launch_bounds__(256) k_sgd_step(int64_t nb, int64_t B, int64_t total, float lr,
+                                                  float *__restrict__ q, float *__restrict__ qd,
+                                                  float *__restrict__ qdd, const float *__restrict__ g_q,
+                                                  const float *__restrict__ g_q2, const float *__restrict__ g_qd,
                                                   const float *__restrict__ g_qdd) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int64_t j = t / nb, i = j * B + (t - j * nb);
     const float gq = g_q[i] + (g_q2 ? g_q2[i] : 0.0f);
     q[i] -= lr * gq;
     qd[i] -= lr * g_qd[i];
     qdd[i] -= lr * g_qdd[i];
 }
 
-hipError_t launch_self_collision_backward(const DevRobot &rb, int64_t B, const float *spheres,
+hipError_t launch_self_collision_backward(const DevRobot &rb, int64_t B, int64_t ld, const float *spheres,
                                           const int32_t *argmax, const float *max_pen,
                                           float margin, const float *g_cost, float *g_sph,
                                           hipStream_t s) {
     if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sc_backward, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, rb, B, spheres,
+    hipLaunchKernelGGL(k_sc_backward, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, rb, B, ld, spheres,
                        argmax, max_pen, margin, g_cost, g_sph);
     return hipGetLastError();
 }
 
-hipError_t launch_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float tw,
+hipError_t launch_cost_head(int64_t B, int64_t ld, int32_t n, const float *tau, const float *w, float tw,
                             const float *max_pen, float margin, float hw, float *cost,
                             float *g_tau, float *g_maxpen, hipStream_t s) {
     if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cost_head, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, B, n, tau, w, tw,
+    hipLaunchKernelGGL(k_cost_head, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, B, ld, n, tau, w, tw,
                        max_pen, margin, hw, cost, g_tau, g_maxpen);
     return hipGetLastError();
 }
 
-hipError_t launch_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd,
+hipError_t launch_sgd_step(int64_t B, int64_t ld, int32_t n, float lr, float *q, float *qd, float *qdd,
                            const float *g_q, const float *g_q2, const float *g_qd,
                            const float *g_qdd, hipStream_t s) {
     const int64_t total = B * (int64_t)n;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sgd_step, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total, lr, q, qd,
-                       qdd, g_q, g_q2, g_qd, g_qdd);
+    hipLaunchKernelGGL(k_sgd_step, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, B, ld, total, lr, q,
+                       qd, qdd, g_q, g_q2, g_qd, g_qdd);
     return hipGetLastError();
 }
 

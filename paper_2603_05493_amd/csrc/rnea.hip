@@ -57,12 +57,13 @@ __device__ __forceinline__ JointIn joint_in(const LinkF &f, const LinkI &i, cons
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_rnea(DevRobot rb, int64_t B, const float *__restrict__ q,
+// nb: states; B: row length of every [k][B] array (the ABI's ld >= nb).
+__global__ void __launch_bounds__(256) k_rnea(DevRobot rb, int64_t nb, int64_t B, const float *__restrict__ q,
                                               const float *__restrict__ qd, const float *__restrict__ qdd,
                                               const float *__restrict__ f_ext, float *__restrict__ tau,
                                               float *__restrict__ cache) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    if (b >= nb) return;
     const int L = rb.L;
     const SV a0 = sv(v3(0.f, 0.f, 0.f), v3(-rb.gx, -rb.gy, -rb.gz));
     const SV zero = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256) k_rnea(DevRobot rb, int64_t B, const floa
 }
 
 // ws layout per state: [L][18]: Fb (6), ab (6), vb (6).
-__global__ void __launch_bounds__(256) k_rnea_backward(DevRobot rb, int64_t B, const float *__restrict__ q,
+__global__ void __launch_bounds__(256) k_rnea_backward(DevRobot rb, int64_t nb, int64_t B, const float *__restrict__ q,
                                                        const float *__restrict__ qd,
                                                        const float *__restrict__ qdd,
                                                        const float *__restrict__ cache,
@@ -141,7 +142,7 @@ __global__ void __launch_bounds__(256) k_rnea_backward(DevRobot rb, int64_t B, c
                                                        float *__restrict__ g_qdd, float *__restrict__ g_fext,
                                                        float *__restrict__ ws) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    if (b >= nb) return;
     const int L = rb.L;
     const SV a0 = sv(v3(0.f, 0.f, 0.f), v3(-rb.gx, -rb.gy, -rb.gz));
     const SV zero = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
@@ -248,20 +249,20 @@ __global__ void __launch_bounds__(256) k_rnea_backward(DevRobot rb, int64_t B, c
     }
 }
 
-hipError_t launch_rnea(const DevRobot &rb, int64_t B, const float *q, const float *qd,
+hipError_t launch_rnea(const DevRobot &rb, int64_t B, int64_t ld, const float *q, const float *qd,
                        const float *qdd, const float *f_ext, float *tau, float *cache, hipStream_t s) {
     if (B == 0) return hipSuccess;
     dim3 grid((unsigned)((B + 255) / 256));
-    hipLaunchKernelGGL(k_rnea, grid, dim3(256), 0, s, rb, B, q, qd, qdd, f_ext, tau, cache);
+    hipLaunchKernelGGL(k_rnea, grid, dim3(256), 0, s, rb, B, ld, q, qd, qdd, f_ext, tau, cache);
     return hipGetLastError();
 }
 
-hipError_t launch_rnea_backward(const DevRobot &rb, int64_t B, const float *q, const float *qd,
+hipError_t launch_rnea_backward(const DevRobot &rb, int64_t B, int64_t ld, const float *q, const float *qd,
                                 const float *qdd, const float *cache, const float *g_tau,
                                 float *g_q, float *g_qd, float *g_qdd, float *g_fext, float *ws, hipStream_t s) {
     if (B == 0) return hipSuccess;
     dim3 grid((unsigned)((B + 255) / 256));
-    hipLaunchKernelGGL(k_rnea_backward, grid, dim3(256), 0, s, rb, B, q, qd, qdd, cache, g_tau, g_q,
+    hipLaunchKernelGGL(k_rnea_backward, grid, dim3(256), 0, s, rb, B, ld, q, qd, qdd, cache, g_tau, g_q,
                        g_qd, g_qdd, g_fext, ws);
     return hipGetLastError();
 }

@@ -28,8 +28,9 @@
 
 namespace wb {
 
+// nb: states; B: row length of every [k][B] array (the ABI's ld >= nb).
 template <bool BACKWARD>
-__global__ void __launch_bounds__(256) k_rnea_lanes(DevRobot rb, DevFused fz, int64_t B, int G,
+__global__ void __launch_bounds__(256) k_rnea_lanes(DevRobot rb, DevFused fz, int64_t nb, int64_t B, int G,
                                                     const float *__restrict__ q, const float *__restrict__ qd,
                                                     const float *__restrict__ qdd, const float *__restrict__ f_ext,
                                                     float *__restrict__ tau, const float *__restrict__ g_tau,
@@ -39,9 +40,9 @@ __global__ void __launch_bounds__(256) k_rnea_lanes(DevRobot rb, DevFused fz, in
     const int per_wave = 64 / G, grp = lane / G, gl = lane - grp * G;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t s = wave * per_wave + grp;
-    if (wave * per_wave >= B) return;   // the whole wavefront is past the batch
-    const bool valid = s < B;
-    const int64_t b = valid ? s : B - 1;   // groups past the end compute on a valid state, store nothing
+    if (wave * per_wave >= nb) return;   // the whole wavefront is past the batch
+    const bool valid = s < nb;
+    const int64_t b = valid ? s : nb - 1;   // groups past the end compute on a valid state, store nothing
     const int *li = fz.li;
     const float *lf = fz.lf;
     const bool act = gl < rb.L;
@@ -153,26 +154,27 @@ __global__ void __launch_bounds__(256) k_rnea_lanes(DevRobot rb, DevFused fz, in
 
 static int lanes_for(int L) { return L <= 16 ? 16 : (L <= 32 ? 32 : 64); }
 
-hipError_t launch_rnea_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, const float *q, const float *qd,
-                             const float *qdd, const float *f_ext, float *tau, hipStream_t s) {
+hipError_t launch_rnea_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, int64_t ld, const float *q,
+                             const float *qd, const float *qdd, const float *f_ext, float *tau, hipStream_t s) {
     if (B == 0) return hipSuccess;
     const int G = lanes_for(rb.L);
     const int64_t per_wg = 4 * (64 / G);
     const dim3 grid((unsigned)((B + per_wg - 1) / per_wg));
-    hipLaunchKernelGGL(k_rnea_lanes<false>, grid, dim3(256), 0, s, rb, fz, B, G, q, qd, qdd, f_ext, tau,
+    hipLaunchKernelGGL(k_rnea_lanes<false>, grid, dim3(256), 0, s, rb, fz, B, ld, G, q, qd, qdd, f_ext, tau,
                        (const float *)nullptr, (float *)nullptr, (float *)nullptr, (float *)nullptr,
                        (float *)nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_rnea_backward_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, const float *q,
-                                      const float *qd, const float *qdd, const float *f_ext, const float *g_tau,
-                                      float *g_q, float *g_qd, float *g_qdd, float *g_fext, hipStream_t s) {
+hipError_t launch_rnea_backward_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, int64_t ld,
+                                      const float *q, const float *qd, const float *qdd, const float *f_ext,
+                                      const float *g_tau, float *g_q, float *g_qd, float *g_qdd, float *g_fext,
+                                      hipStream_t s) {
     if (B == 0) return hipSuccess;
     const int G = lanes_for(rb.L);
     const int64_t per_wg = 4 * (64 / G);
     const dim3 grid((unsigned)((B + per_wg - 1) / per_wg));
-    hipLaunchKernelGGL(k_rnea_lanes<true>, grid, dim3(256), 0, s, rb, fz, B, G, q, qd, qdd, f_ext,
+    hipLaunchKernelGGL(k_rnea_lanes<true>, grid, dim3(256), 0, s, rb, fz, B, ld, G, q, qd, qdd, f_ext,
                        (float *)nullptr, g_tau, g_q, g_qd, g_qdd, g_fext);
     return hipGetLastError();
 }

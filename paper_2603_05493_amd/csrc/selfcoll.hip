@@ -7,8 +7,9 @@ namespace wb {
 
 // LDS: TS states x [(L+1)*NMAX slots | (L+1) link bounds], then 4 lists of
 // rb.list_cap ints (one per wavefront), then (TAB_LDS) the block table.
+// nb: states; B: row length of the sphere array (the ABI's ld >= nb).
 template <int NMAX, bool TAB_LDS>
-__global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, int TS,
+__global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t nb, int64_t B, int TS,
                                                         const float *__restrict__ sph,
                                                         float *__restrict__ max_pen,
                                                         int32_t *__restrict__ argmax,
@@ -34,7 +35,7 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, 
     for (int i = tid; i < n3 * TS; i += 256) {
         const int st = i % TS, sc = i / TS;
         const int64_t b = b0 + st;
-        if (b < B) {
+        if (b < nb) {
             const int s = sc / 3, c = sc - 3 * s;
             reinterpret_cast<float *>(&lds[st * SLB + rb.sph_slot[s]])[c] = sph[(int64_t)sc * B + b];
         }
@@ -45,7 +46,7 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t B, 
     int *list = lists + wave * rb.list_cap;
     for (int st = wave; st < TS; st += 4) {
         const int64_t b = b0 + st;
-        if (b >= B) break;
+        if (b >= nb) break;
         float4 *P = lds + st * SLB;
         float4 *Bd = P + SL;
         link_bounds<NMAX>(rb, P, Bd, lane, 64);
@@ -80,7 +81,7 @@ int self_collision_tile(int L, int nmax, int list_cap) {
 // fit; otherwise the lists shrink to fit beside one state and the table is
 // read from device memory.
 template <int NMAX>
-static hipError_t launch_sc(const DevRobot &rb0, int64_t B, const float *sph, float *mp, int32_t *am,
+static hipError_t launch_sc(const DevRobot &rb0, int64_t B, int64_t ld, const float *sph, float *mp, int32_t *am,
                             int32_t *nc, hipStream_t s) {
     DevRobot rb = rb0;
     const size_t per_state = state_lds_bytes(rb.L, NMAX);
@@ -90,30 +91,30 @@ static hipError_t launch_sc(const DevRobot &rb0, int64_t B, const float *sph, fl
         const int TS = sc_tile(per_state, (size_t)16 * rb.list_cap + tab);
         const size_t lds = (size_t)TS * per_state + (size_t)16 * rb.list_cap + tab;
         dim3 grid((unsigned)((B + TS - 1) / TS));
-        hipLaunchKernelGGL((k_self_collision<NMAX, true>), grid, block, lds, s, rb, B, TS, sph, mp, am, nc);
+        hipLaunchKernelGGL((k_self_collision<NMAX, true>), grid, block, lds, s, rb, B, ld, TS, sph, mp, am, nc);
     } else {
         const int room = (int)((LDS_LIMIT - per_state) / 16) / 128 * 128;
         if (room < rb.list_cap) rb.list_cap = room;
         const int TS = self_collision_tile(rb.L, NMAX, rb.list_cap);
         const size_t lds = (size_t)TS * per_state + (size_t)16 * rb.list_cap;
         dim3 grid((unsigned)((B + TS - 1) / TS));
-        hipLaunchKernelGGL((k_self_collision<NMAX, false>), grid, block, lds, s, rb, B, TS, sph, mp, am, nc);
+        hipLaunchKernelGGL((k_self_collision<NMAX, false>), grid, block, lds, s, rb, B, ld, TS, sph, mp, am, nc);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_self_collision(const DevRobot &rb, int64_t B, const float *spheres,
+hipError_t launch_self_collision(const DevRobot &rb, int64_t B, int64_t ld, const float *spheres,
                                  float *max_pen, int32_t *argmax, int32_t *n_coll, hipStream_t s) {
     if (B == 0) return hipSuccess;
     switch (rb.nmax) {
-        case 1: return launch_sc<1>(rb, B, spheres, max_pen, argmax, n_coll, s);
-        case 2: return launch_sc<2>(rb, B, spheres, max_pen, argmax, n_coll, s);
-        case 3: return launch_sc<3>(rb, B, spheres, max_pen, argmax, n_coll, s);
-        case 4: return launch_sc<4>(rb, B, spheres, max_pen, argmax, n_coll, s);
-        case 5: return launch_sc<5>(rb, B, spheres, max_pen, argmax, n_coll, s);
-        case 6: return launch_sc<6>(rb, B, spheres, max_pen, argmax, n_coll, s);
-        case 7: return launch_sc<7>(rb, B, spheres, max_pen, argmax, n_coll, s);
-        case 8: return launch_sc<8>(rb, B, spheres, max_pen, argmax, n_coll, s);
+        case 1: return launch_sc<1>(rb, B, ld, spheres, max_pen, argmax, n_coll, s);
+        case 2: return launch_sc<2>(rb, B, ld, spheres, max_pen, argmax, n_coll, s);
+        case 3: return launch_sc<3>(rb, B, ld, spheres, max_pen, argmax, n_coll, s);
+        case 4: return launch_sc<4>(rb, B, ld, spheres, max_pen, argmax, n_coll, s);
+        case 5: return launch_sc<5>(rb, B, ld, spheres, max_pen, argmax, n_coll, s);
+        case 6: return launch_sc<6>(rb, B, ld, spheres, max_pen, argmax, n_coll, s);
+        case 7: return launch_sc<7>(rb, B, ld, spheres, max_pen, argmax, n_coll, s);
+        case 8: return launch_sc<8>(rb, B, ld, spheres, max_pen, argmax, n_coll, s);
         default: return hipErrorInvalidValue;
     }
 }

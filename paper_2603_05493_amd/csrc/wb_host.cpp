@@ -512,6 +512,15 @@ int check_B(int64_t B) {
     return WB_OK;
 }
 
+// The leading dimension of the [k][B] arrays of a call: 0 means B; any
+// other value must be >= B.
+int resolve_ld(int64_t B, int64_t ld, int64_t *out) {
+    if (ld == 0) ld = B;
+    if (ld < B) return fail(WB_ERR_INVALID_ARG, "ld %lld is below B %lld", (long long)ld, (long long)B);
+    *out = ld;
+    return WB_OK;
+}
+
 int check_ptr(const void *p, const char *name, bool required) {
     if (!p) return required ? fail(WB_ERR_INVALID_ARG, "%s is null", name) : WB_OK;
     if (!aligned4(p)) return fail(WB_ERR_INVALID_ARG, "%s is not 4-byte aligned", name);
@@ -669,22 +678,24 @@ int wb_rnea_cache_bytes(const wb_robot *robot, int64_t B, size_t *bytes) {
     return WB_OK;
 }
 
-int wb_fk(const wb_robot *robot, int64_t B, const float *q, float *link_pose, float *spheres,
+int wb_fk(const wb_robot *robot, int64_t B, int64_t ld, const float *q, float *link_pose, float *spheres,
           hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
+    WB_TRY(resolve_ld(B, ld, &ld));
     if (B == 0) return WB_OK;
     WB_TRY(check_ptr(q, "q", robot->T.n > 0));
     WB_TRY(check_ptr(link_pose, "link_pose", false));
     WB_TRY(check_ptr(spheres, "spheres", false));
     if (!link_pose && !spheres) return fail(WB_ERR_INVALID_ARG, "link_pose and spheres are both null");
-    return finish(wb::launch_fk(robot->dev, B, q, link_pose, spheres, stream), "wb_fk launch");
+    return finish(wb::launch_fk(robot->dev, B, ld, q, link_pose, spheres, stream), "wb_fk launch");
 }
 
-int wb_rnea(const wb_robot *robot, int64_t B, const float *q, const float *qd, const float *qdd,
+int wb_rnea(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const float *qd, const float *qdd,
             const float *f_ext, float *tau, float *cache, hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
+    WB_TRY(resolve_ld(B, ld, &ld));
     if (B == 0) return WB_OK;
     const bool need = robot->T.n > 0;
     WB_TRY(check_ptr(q, "q", need));
@@ -693,31 +704,35 @@ int wb_rnea(const wb_robot *robot, int64_t B, const float *q, const float *qd, c
     WB_TRY(check_ptr(f_ext, "f_ext", false));
     WB_TRY(check_ptr(tau, "tau", need));
     WB_TRY(check_ptr(cache, "cache", false));
-    if (cache) return finish(wb::launch_rnea(robot->dev, B, q, qd, qdd, f_ext, tau, cache, stream), "wb_rnea launch");
+    if (cache)
+        return finish(wb::launch_rnea(robot->dev, B, ld, q, qd, qdd, f_ext, tau, cache, stream), "wb_rnea launch");
     if (!robot->T.lanes)
         return fail(WB_ERR_UNSUPPORTED, "a robot of %d links (more than 64) needs the cache", robot->T.L);
-    return finish(wb::launch_rnea_lanes(robot->dev, robot->fz, B, q, qd, qdd, f_ext, tau, stream), "wb_rnea launch");
+    return finish(wb::launch_rnea_lanes(robot->dev, robot->fz, B, ld, q, qd, qdd, f_ext, tau, stream),
+                  "wb_rnea launch");
 }
 
-int wb_self_collision(const wb_robot *robot, int64_t B, const float *spheres, float *max_pen,
+int wb_self_collision(const wb_robot *robot, int64_t B, int64_t ld, const float *spheres, float *max_pen,
                       int32_t *argmax, int32_t *n_coll, hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
+    WB_TRY(resolve_ld(B, ld, &ld));
     if (B == 0) return WB_OK;
     if (!max_pen && !argmax && !n_coll) return fail(WB_ERR_INVALID_ARG, "all outputs are null");
     WB_TRY(check_ptr(spheres, "spheres", robot->T.S > 0));
     WB_TRY(check_ptr(max_pen, "max_pen", false));
     WB_TRY(check_ptr(argmax, "argmax", false));
     WB_TRY(check_ptr(n_coll, "n_coll", false));
-    return finish(wb::launch_self_collision(robot->dev, B, spheres, max_pen, argmax, n_coll, stream),
+    return finish(wb::launch_self_collision(robot->dev, B, ld, spheres, max_pen, argmax, n_coll, stream),
                   "wb_self_collision launch");
 }
 
-int wb_self_collision_backward(const wb_robot *robot, int64_t B, const float *spheres,
+int wb_self_collision_backward(const wb_robot *robot, int64_t B, int64_t ld, const float *spheres,
                                const int32_t *argmax, const float *max_pen, float margin,
                                const float *g_cost, float *g_spheres, hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
+    WB_TRY(resolve_ld(B, ld, &ld));
     if (!std::isfinite(margin)) return fail(WB_ERR_INVALID_ARG, "margin is not finite");
     if (B == 0) return WB_OK;
     WB_TRY(check_ptr(spheres, "spheres", robot->T.S > 0));
@@ -725,16 +740,17 @@ int wb_self_collision_backward(const wb_robot *robot, int64_t B, const float *sp
     WB_TRY(check_ptr(max_pen, "max_pen", true));
     WB_TRY(check_ptr(g_cost, "g_cost", true));
     WB_TRY(check_ptr(g_spheres, "g_spheres", robot->T.S > 0));
-    return finish(wb::launch_self_collision_backward(robot->dev, B, spheres, argmax, max_pen, margin, g_cost,
+    return finish(wb::launch_self_collision_backward(robot->dev, B, ld, spheres, argmax, max_pen, margin, g_cost,
                                                      g_spheres, stream),
                   "wb_self_collision_backward launch");
 }
 
-int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float *link_pose,
+int wb_fk_backward(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const float *link_pose,
                    const float *g_link_pose, const float *g_spheres, float *g_q, void *workspace,
                    hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
+    WB_TRY(resolve_ld(B, ld, &ld));
     if (B == 0) return WB_OK;
     if (!g_link_pose && !g_spheres) return fail(WB_ERR_INVALID_ARG, "both gradient inputs are null");
     WB_TRY(check_ptr(q, "q", robot->T.n > 0));
@@ -743,16 +759,17 @@ int wb_fk_backward(const wb_robot *robot, int64_t B, const float *q, const float
     WB_TRY(check_ptr(g_spheres, "g_spheres", false));
     WB_TRY(check_ptr(g_q, "g_q", robot->T.n > 0));
     WB_TRY(check_ptr(workspace, "workspace", true));
-    return finish(wb::launch_fk_backward(robot->dev, B, q, link_pose, g_link_pose, g_spheres, g_q,
+    return finish(wb::launch_fk_backward(robot->dev, B, ld, q, link_pose, g_link_pose, g_spheres, g_q,
                                          static_cast<float *>(workspace), stream),
                   "wb_fk_backward launch");
 }
 
-int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const float *qd,
+int wb_rnea_backward(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const float *qd,
                      const float *qdd, const float *f_ext, const float *cache, const float *g_tau, float *g_q,
                      float *g_qd, float *g_qdd, float *g_fext, void *workspace, hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
+    WB_TRY(resolve_ld(B, ld, &ld));
     if (B == 0) return WB_OK;
     const bool need = robot->T.n > 0;
     WB_TRY(check_ptr(q, "q", need));
@@ -769,20 +786,21 @@ int wb_rnea_backward(const wb_robot *robot, int64_t B, const float *q, const flo
         if (!robot->T.lanes)
             return fail(WB_ERR_UNSUPPORTED, "a robot of %d links (more than 64) needs the cache", robot->T.L);
         WB_TRY(check_ptr(workspace, "workspace", false));
-        return finish(wb::launch_rnea_backward_lanes(robot->dev, robot->fz, B, q, qd, qdd, f_ext, g_tau, g_q, g_qd,
-                                                     g_qdd, g_fext, stream),
+        return finish(wb::launch_rnea_backward_lanes(robot->dev, robot->fz, B, ld, q, qd, qdd, f_ext, g_tau, g_q,
+                                                     g_qd, g_qdd, g_fext, stream),
                       "wb_rnea_backward launch");
     }
     WB_TRY(check_ptr(workspace, "workspace", true));
-    return finish(wb::launch_rnea_backward(robot->dev, B, q, qd, qdd, cache, g_tau, g_q, g_qd, g_qdd, g_fext,
+    return finish(wb::launch_rnea_backward(robot->dev, B, ld, q, qd, qdd, cache, g_tau, g_q, g_qd, g_qdd, g_fext,
                                            static_cast<float *>(workspace), stream),
                   "wb_rnea_backward launch");
 }
 
-int wb_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float torque_weight,
+int wb_cost_head(int64_t B, int64_t ld, int32_t n, const float *tau, const float *w, float torque_weight,
                  const float *max_pen, float margin, float hinge_weight, float *cost, float *g_tau,
                  float *g_maxpen, hipStream_t stream) {
     WB_TRY(check_B(B));
+    WB_TRY(resolve_ld(B, ld, &ld));
     if (n < 0) return fail(WB_ERR_INVALID_ARG, "n must be >= 0");
     if (!std::isfinite(torque_weight) || !std::isfinite(margin) || !std::isfinite(hinge_weight))
         return fail(WB_ERR_INVALID_ARG, "weights and margin must be finite");
@@ -793,14 +811,15 @@ int wb_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float t
     WB_TRY(check_ptr(cost, "cost", false));
     WB_TRY(check_ptr(g_tau, "g_tau", false));
     WB_TRY(check_ptr(g_maxpen, "g_maxpen", false));
-    return finish(wb::launch_cost_head(B, n, tau, w, torque_weight, max_pen, margin, hinge_weight, cost, g_tau,
+    return finish(wb::launch_cost_head(B, ld, n, tau, w, torque_weight, max_pen, margin, hinge_weight, cost, g_tau,
                                        g_maxpen, stream),
                   "wb_cost_head launch");
 }
 
-int wb_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd, const float *g_q,
+int wb_sgd_step(int64_t B, int64_t ld, int32_t n, float lr, float *q, float *qd, float *qdd, const float *g_q,
                 const float *g_q2, const float *g_qd, const float *g_qdd, hipStream_t stream) {
     WB_TRY(check_B(B));
+    WB_TRY(resolve_ld(B, ld, &ld));
     if (n < 0) return fail(WB_ERR_INVALID_ARG, "n must be >= 0");
     if (!std::isfinite(lr)) return fail(WB_ERR_INVALID_ARG, "lr must be finite");
     if (B == 0 || n == 0) return WB_OK;
@@ -811,7 +830,7 @@ int wb_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd,
     WB_TRY(check_ptr(g_q2, "g_q2", false));
     WB_TRY(check_ptr(g_qd, "g_qd", true));
     WB_TRY(check_ptr(g_qdd, "g_qdd", true));
-    return finish(wb::launch_sgd_step(B, n, lr, q, qd, qdd, g_q, g_q2, g_qd, g_qdd, stream), "wb_sgd_step launch");
+    return finish(wb::launch_sgd_step(B, ld, n, lr, q, qd, qdd, g_q, g_q2, g_qd, g_qdd, stream), "wb_sgd_step launch");
 }
 
 namespace {
@@ -863,12 +882,13 @@ int wb_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float
                   "wb_bspline_backward launch");
 }
 
-int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, float *qdd, const float *w,
+int wb_wholebody_step(const wb_robot *robot, int64_t B, int64_t ld, float *q, float *qd, float *qdd, const float *w,
                       float torque_weight, float margin, float hinge_weight, float lr, float *tau, float *cost,
                       float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q, float *g_qd, float *g_qdd,
                       const float *f_ext, float *g_fext, hipStream_t stream) {
     WB_TRY(check_robot(robot));
     WB_TRY(check_B(B));
+    WB_TRY(resolve_ld(B, ld, &ld));
     if (!robot->fz.supported)
         return fail(WB_ERR_UNSUPPORTED, "the fused iteration needs <= 64 links and sweep tables within %zu bytes of LDS",
                     wb::LDS_LIMIT);
@@ -896,7 +916,7 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, float *q, float *qd, flo
     a.B = B;
     a.chunk = small_batch_chunk(robot->tune, B, robot->cus);
     a.lanes_per_state = robot->tune.lanes_per_state;
-    a.io = wb::TreeIO{q, qd, qdd, w, tau, cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd, f_ext, g_fext};
+    a.io = wb::TreeIO{q, qd, qdd, w, tau, cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd, f_ext, g_fext, ld};
     a.k = wb::StepScalars{torque_weight, margin, hinge_weight, lr};
     return finish(wb::launch_fused(a, stream), "wb_wholebody_step launch");
 }
@@ -1321,8 +1341,10 @@ int wb_plan_run(const wb_plan *plan, const wb_tree_io *io, float torque_weight, 
         WB_TRY(check_ptr(x.g_qdd, "io.g_qdd", false));
         WB_TRY(check_ptr(x.f_ext, "io.f_ext", false));
         WB_TRY(check_ptr(x.g_fext, "io.g_fext", false));
+        int64_t ld = 0;
+        WB_TRY(resolve_ld(plan->B[i], x.ld, &ld));
         a.io[i] = wb::TreeIO{x.q,     x.qd,     x.qdd, x.w,    x.tau,   x.cost,   x.max_pen, x.argmax,
-                             x.n_coll, x.g_q, x.g_qd, x.g_qdd, x.f_ext, x.g_fext};
+                             x.n_coll, x.g_q, x.g_qd, x.g_qdd, x.f_ext, x.g_fext, ld};
         ext = ext || x.f_ext || x.g_fext;
     }
     return finish(wb::launch_plan(a, plan->nmax, plan->n_wg, plan->lds, ext, stream), "wb_plan_run launch");

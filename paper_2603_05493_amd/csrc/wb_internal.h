@@ -90,6 +90,7 @@ struct TreeIO {
     float *g_q, *g_qd, *g_qdd;
     const float *f_ext;           // [L][6][B] external link forces (link coordinates) or null
     float *g_fext;                // [L][6][B] their gradient or null
+    int64_t ld;                   // row length B of the [k][B] arrays (>= the states)
 };
 
 // Scalars of the cost head and the step.
@@ -103,7 +104,7 @@ struct FusedArgs {
     DevFused fz;
     TreeIO io;
     StepScalars k;
-    int64_t B;
+    int64_t B;                // states (the arrays' row length is io.ld)
     int32_t chunk;            // states per workgroup
     int32_t lanes_per_state;  // G: 16, 32 or 64
 };
@@ -112,7 +113,7 @@ struct FusedArgs {
 struct PlanTree {
     DevRobot rb;              // tables re-derived for the plan's slots per link
     DevFused fz;
-    int64_t B;
+    int64_t B;                // states (the arrays' row length is the run's io.ld)
     int32_t lanes_per_state;
     int32_t pad;
 };
@@ -139,33 +140,34 @@ hipError_t launch_plan(const PlanArgs &a, int nmax, int n_wg, size_t lds, bool e
 int plan_workgroups_per_cu(int nmax, bool ext, size_t lds);
 
 // Kernel launchers (each defined next to its kernels).
-hipError_t launch_fk(const DevRobot &rb, int64_t B, const float *q, float *pose, float *spheres,
+hipError_t launch_fk(const DevRobot &rb, int64_t B, int64_t ld, const float *q, float *pose, float *spheres,
                      hipStream_t s);
-hipError_t launch_fk_backward(const DevRobot &rb, int64_t B, const float *q, const float *pose,
+hipError_t launch_fk_backward(const DevRobot &rb, int64_t B, int64_t ld, const float *q, const float *pose,
                               const float *g_pose, const float *g_sph, float *g_q, float *ws,
                               hipStream_t s);
-hipError_t launch_rnea(const DevRobot &rb, int64_t B, const float *q, const float *qd,
+hipError_t launch_rnea(const DevRobot &rb, int64_t B, int64_t ld, const float *q, const float *qd,
                        const float *qdd, const float *f_ext, float *tau, float *cache, hipStream_t s);
-hipError_t launch_rnea_backward(const DevRobot &rb, int64_t B, const float *q, const float *qd,
+hipError_t launch_rnea_backward(const DevRobot &rb, int64_t B, int64_t ld, const float *q, const float *qd,
                                 const float *qdd, const float *cache, const float *g_tau,
                                 float *g_q, float *g_qd, float *g_qdd, float *g_fext, float *ws, hipStream_t s);
 // Group-per-state RNEA and VJP without a cache (rnea_lanes.hip); robots of
 // at most 64 links.
-hipError_t launch_rnea_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, const float *q, const float *qd,
-                             const float *qdd, const float *f_ext, float *tau, hipStream_t s);
-hipError_t launch_rnea_backward_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, const float *q,
-                                      const float *qd, const float *qdd, const float *f_ext, const float *g_tau,
-                                      float *g_q, float *g_qd, float *g_qdd, float *g_fext, hipStream_t s);
-hipError_t launch_self_collision(const DevRobot &rb, int64_t B, const float *spheres,
+hipError_t launch_rnea_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, int64_t ld, const float *q,
+                             const float *qd, const float *qdd, const float *f_ext, float *tau, hipStream_t s);
+hipError_t launch_rnea_backward_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, int64_t ld,
+                                      const float *q, const float *qd, const float *qdd, const float *f_ext,
+                                      const float *g_tau, float *g_q, float *g_qd, float *g_qdd, float *g_fext,
+                                      hipStream_t s);
+hipError_t launch_self_collision(const DevRobot &rb, int64_t B, int64_t ld, const float *spheres,
                                  float *max_pen, int32_t *argmax, int32_t *n_coll, hipStream_t s);
-hipError_t launch_self_collision_backward(const DevRobot &rb, int64_t B, const float *spheres,
+hipError_t launch_self_collision_backward(const DevRobot &rb, int64_t B, int64_t ld, const float *spheres,
                                           const int32_t *argmax, const float *max_pen,
                                           float margin, const float *g_cost, float *g_sph,
                                           hipStream_t s);
-hipError_t launch_cost_head(int64_t B, int32_t n, const float *tau, const float *w, float tw,
+hipError_t launch_cost_head(int64_t B, int64_t ld, int32_t n, const float *tau, const float *w, float tw,
                             const float *max_pen, float margin, float hw, float *cost,
                             float *g_tau, float *g_maxpen, hipStream_t s);
-hipError_t launch_sgd_step(int64_t B, int32_t n, float lr, float *q, float *qd, float *qdd,
+hipError_t launch_sgd_step(int64_t B, int64_t ld, int32_t n, float lr, float *q, float *qd, float *qdd,
                            const float *g_q, const float *g_q2, const float *g_qd,
                            const float *g_qdd, hipStream_t s);
 

@@ -172,18 +172,33 @@ def _empty(shape, robot: Robot, dtype=torch.float32):
 
 
 # ------------------------------------------------------------------ the ABI
+#
+# The [k][B] arrays of the hot-path calls may have padded rows: their last
+# dimension is the leading dimension ld, and `nb` (default ld) states are
+# processed; per-state arrays have nb entries.
 
-def wb_fk(robot: Robot, q: torch.Tensor, link_pose=None, spheres=None, want_spheres=True, want_pose=True):
-    n, B = robot.n_dof, q.shape[-1]
+
+def _nb(ld: int, nb: Optional[int]) -> int:
+    if nb is None:
+        return ld
+    if not 0 <= nb <= ld:
+        raise ValueError(f"nb={nb} must be within [0, {ld}] (the arrays' last dimension)")
+    return int(nb)
+
+
+def wb_fk(robot: Robot, q: torch.Tensor, link_pose=None, spheres=None, want_spheres=True, want_pose=True,
+          nb=None):
+    n, ld = robot.n_dof, q.shape[-1]
+    B = _nb(ld, nb)
     L, S = robot.n_links, robot.n_spheres
     if link_pose is None and want_pose:
-        link_pose = _empty((L, 12, B), robot)
+        link_pose = _empty((L, 12, ld), robot)
     if spheres is None and want_spheres:
-        spheres = _empty((S, 3, B), robot)
-    _chk(q, "q", (n, B), device=robot.device)
-    _chk(link_pose, "link_pose", (L, 12, B), device=robot.device)
-    _chk(spheres, "spheres", (S, 3, B), device=robot.device)
-    check(lib().wb_fk(robot.handle, B, _p(q), _p(link_pose), _p(spheres), _stream()))
+        spheres = _empty((S, 3, ld), robot)
+    _chk(q, "q", (n, ld), device=robot.device)
+    _chk(link_pose, "link_pose", (L, 12, ld), device=robot.device)
+    _chk(spheres, "spheres", (S, 3, ld), device=robot.device)
+    check(lib().wb_fk(robot.handle, B, ld, _p(q), _p(link_pose), _p(spheres), _stream()))
     return link_pose, spheres
 
 
@@ -277,113 +292,120 @@ def wb_edt_noalloc(sites: torch.Tensor, voxel_size: float = 1.0, nearest=None, d
     return nearest, dist
 
 
-def wb_rnea(robot: Robot, q, qd, qdd, tau=None, cache=None, f_ext=None, want_cache=True):
+def wb_rnea(robot: Robot, q, qd, qdd, tau=None, cache=None, f_ext=None, want_cache=True, nb=None):
     """tau [n,B] and the cache for the backward (None with want_cache=False:
     nothing is stored and the backward recomputes); f_ext [L,6,B] external
     link forces in link coordinates (moment, force), or None."""
-    n, B, L = robot.n_dof, q.shape[-1], robot.n_links
-    tau = _empty((n, B), robot) if tau is None else tau
+    n, ld, L = robot.n_dof, q.shape[-1], robot.n_links
+    B = _nb(ld, nb)
+    tau = _empty((n, ld), robot) if tau is None else tau
     if cache is None and want_cache:
-        cache = _empty((L, 18, B), robot)
+        cache = _empty((L, 18, ld), robot)
     for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (tau, "tau")):
-        _chk(t, nm, (n, B), device=robot.device)
-    _chk(cache, "cache", (L, 18, B), device=robot.device)
-    _chk(f_ext, "f_ext", (L, 6, B), device=robot.device)
-    check(lib().wb_rnea(robot.handle, B, _p(q), _p(qd), _p(qdd), _p(f_ext), _p(tau), _p(cache), _stream()))
+        _chk(t, nm, (n, ld), device=robot.device)
+    _chk(cache, "cache", (L, 18, ld), device=robot.device)
+    _chk(f_ext, "f_ext", (L, 6, ld), device=robot.device)
+    check(lib().wb_rnea(robot.handle, B, ld, _p(q), _p(qd), _p(qdd), _p(f_ext), _p(tau), _p(cache), _stream()))
     return tau, cache
 
 
-def wb_self_collision(robot: Robot, spheres, max_pen=None, argmax=None, n_coll=None):
-    S, B = robot.n_spheres, spheres.shape[-1]
+def wb_self_collision(robot: Robot, spheres, max_pen=None, argmax=None, n_coll=None, nb=None):
+    S, ld = robot.n_spheres, spheres.shape[-1]
+    B = _nb(ld, nb)
     max_pen = _empty((B,), robot) if max_pen is None else max_pen
     argmax = _empty((B,), robot, torch.int32) if argmax is None else argmax
     n_coll = _empty((B,), robot, torch.int32) if n_coll is None else n_coll
-    _chk(spheres, "spheres", (S, 3, B), device=robot.device)
+    _chk(spheres, "spheres", (S, 3, ld), device=robot.device)
     _chk(max_pen, "max_pen", (B,), device=robot.device)
     _chk(argmax, "argmax", (B,), torch.int32, device=robot.device)
     _chk(n_coll, "n_coll", (B,), torch.int32, device=robot.device)
-    check(lib().wb_self_collision(robot.handle, B, _p(spheres), _p(max_pen), _p(argmax), _p(n_coll),
+    check(lib().wb_self_collision(robot.handle, B, ld, _p(spheres), _p(max_pen), _p(argmax), _p(n_coll),
                                   _stream()))
     return max_pen, argmax, n_coll
 
 
 def wb_self_collision_backward(robot: Robot, spheres, argmax, max_pen, margin: float, g_cost,
-                               g_spheres=None):
-    S, B = robot.n_spheres, spheres.shape[-1]
-    g_spheres = _empty((S, 3, B), robot) if g_spheres is None else g_spheres
-    _chk(spheres, "spheres", (S, 3, B), device=robot.device)
+                               g_spheres=None, nb=None):
+    S, ld = robot.n_spheres, spheres.shape[-1]
+    B = _nb(ld, nb)
+    g_spheres = _empty((S, 3, ld), robot) if g_spheres is None else g_spheres
+    _chk(spheres, "spheres", (S, 3, ld), device=robot.device)
     _chk(argmax, "argmax", (B,), torch.int32, device=robot.device)
     _chk(max_pen, "max_pen", (B,), device=robot.device)
     _chk(g_cost, "g_cost", (B,), device=robot.device)
-    _chk(g_spheres, "g_spheres", (S, 3, B), device=robot.device)
-    check(lib().wb_self_collision_backward(robot.handle, B, _p(spheres), _p(argmax), _p(max_pen),
+    _chk(g_spheres, "g_spheres", (S, 3, ld), device=robot.device)
+    check(lib().wb_self_collision_backward(robot.handle, B, ld, _p(spheres), _p(argmax), _p(max_pen),
                                            float(margin), _p(g_cost), _p(g_spheres), _stream()))
     return g_spheres
 
 
 def wb_fk_backward(robot: Robot, q, g_spheres=None, g_link_pose=None, link_pose=None, g_q=None,
-                   workspace=None):
-    n, B, L, S = robot.n_dof, q.shape[-1], robot.n_links, robot.n_spheres
-    g_q = _empty((n, B), robot) if g_q is None else g_q
-    workspace = robot.workspace(B) if workspace is None else workspace
-    _chk(q, "q", (n, B), device=robot.device)
-    _chk(g_spheres, "g_spheres", (S, 3, B), device=robot.device)
-    _chk(g_link_pose, "g_link_pose", (L, 12, B), device=robot.device)
-    _chk(link_pose, "link_pose", (L, 12, B), device=robot.device)
-    _chk(g_q, "g_q", (n, B), device=robot.device)
-    if workspace.numel() * workspace.element_size() < robot.workspace_bytes(B):
+                   workspace=None, nb=None):
+    n, ld, L, S = robot.n_dof, q.shape[-1], robot.n_links, robot.n_spheres
+    B = _nb(ld, nb)
+    g_q = _empty((n, ld), robot) if g_q is None else g_q
+    workspace = robot.workspace(ld) if workspace is None else workspace
+    _chk(q, "q", (n, ld), device=robot.device)
+    _chk(g_spheres, "g_spheres", (S, 3, ld), device=robot.device)
+    _chk(g_link_pose, "g_link_pose", (L, 12, ld), device=robot.device)
+    _chk(link_pose, "link_pose", (L, 12, ld), device=robot.device)
+    _chk(g_q, "g_q", (n, ld), device=robot.device)
+    if workspace.numel() * workspace.element_size() < robot.workspace_bytes(ld):
         raise ValueError("workspace too small")
-    check(lib().wb_fk_backward(robot.handle, B, _p(q), _p(link_pose), _p(g_link_pose), _p(g_spheres),
+    check(lib().wb_fk_backward(robot.handle, B, ld, _p(q), _p(link_pose), _p(g_link_pose), _p(g_spheres),
                                _p(g_q), _p(workspace), _stream()))
     return g_q
 
 
 def wb_rnea_backward(robot: Robot, q, qd, qdd, cache, g_tau, g_q=None, g_qd=None, g_qdd=None,
-                     workspace=None, g_fext=None, f_ext=None):
+                     workspace=None, g_fext=None, f_ext=None, nb=None):
     """g_q, g_qd, g_qdd [n,B]; with g_fext [L,6,B] also the gradient on the
     external forces.  cache: the forward call's (its forces included), or
     None to recompute every forward quantity from q, qd, qdd and f_ext."""
-    n, B, L = robot.n_dof, q.shape[-1], robot.n_links
-    g_q = _empty((n, B), robot) if g_q is None else g_q
-    g_qd = _empty((n, B), robot) if g_qd is None else g_qd
-    g_qdd = _empty((n, B), robot) if g_qdd is None else g_qdd
+    n, ld, L = robot.n_dof, q.shape[-1], robot.n_links
+    B = _nb(ld, nb)
+    g_q = _empty((n, ld), robot) if g_q is None else g_q
+    g_qd = _empty((n, ld), robot) if g_qd is None else g_qd
+    g_qdd = _empty((n, ld), robot) if g_qdd is None else g_qdd
     if cache is not None and workspace is None:
-        workspace = robot.workspace(B)
+        workspace = robot.workspace(ld)
     for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (g_tau, "g_tau"), (g_q, "g_q"), (g_qd, "g_qd"),
                   (g_qdd, "g_qdd")):
-        _chk(t, nm, (n, B), device=robot.device)
-    _chk(cache, "cache", (L, 18, B), device=robot.device)
-    _chk(g_fext, "g_fext", (L, 6, B), device=robot.device)
-    _chk(f_ext, "f_ext", (L, 6, B), device=robot.device)
-    if workspace is not None and workspace.numel() * workspace.element_size() < robot.workspace_bytes(B):
+        _chk(t, nm, (n, ld), device=robot.device)
+    _chk(cache, "cache", (L, 18, ld), device=robot.device)
+    _chk(g_fext, "g_fext", (L, 6, ld), device=robot.device)
+    _chk(f_ext, "f_ext", (L, 6, ld), device=robot.device)
+    if workspace is not None and workspace.numel() * workspace.element_size() < robot.workspace_bytes(ld):
         raise ValueError("workspace too small")
-    check(lib().wb_rnea_backward(robot.handle, B, _p(q), _p(qd), _p(qdd), _p(f_ext), _p(cache), _p(g_tau),
+    check(lib().wb_rnea_backward(robot.handle, B, ld, _p(q), _p(qd), _p(qdd), _p(f_ext), _p(cache), _p(g_tau),
                                  _p(g_q), _p(g_qd), _p(g_qdd), _p(g_fext), _p(workspace), _stream()))
     return g_q, g_qd, g_qdd
 
 
 def wb_cost_head(tau, w=None, torque_weight=0.0, max_pen=None, margin=0.0, hinge_weight=0.0,
-                 cost=None, g_tau=None, g_maxpen=None):
-    n, B = tau.shape
+                 cost=None, g_tau=None, g_maxpen=None, nb=None):
+    n, ld = tau.shape
+    B = _nb(ld, nb)
     dev = tau.device
     cost = torch.empty(B, dtype=torch.float32, device=dev) if cost is None else cost
     g_tau = torch.empty_like(tau) if g_tau is None else g_tau
     if max_pen is not None and g_maxpen is None:
         g_maxpen = torch.empty(B, dtype=torch.float32, device=dev)
-    for t, nm, shp in ((tau, "tau", (n, B)), (w, "w", (n, B)), (max_pen, "max_pen", (B,)), (cost, "cost", (B,)),
-                       (g_tau, "g_tau", (n, B)), (g_maxpen, "g_maxpen", (B,))):
+    for t, nm, shp in ((tau, "tau", (n, ld)), (w, "w", (n, ld)), (max_pen, "max_pen", (B,)), (cost, "cost", (B,)),
+                       (g_tau, "g_tau", (n, ld)), (g_maxpen, "g_maxpen", (B,))):
         _chk(t, nm, shp, device=dev)
-    check(lib().wb_cost_head(B, n, _p(tau), _p(w), float(torque_weight), _p(max_pen), float(margin),
+    check(lib().wb_cost_head(B, ld, n, _p(tau), _p(w), float(torque_weight), _p(max_pen), float(margin),
                              float(hinge_weight), _p(cost), _p(g_tau), _p(g_maxpen), _stream()))
     return cost, g_tau, g_maxpen
 
 
-def wb_sgd_step(lr: float, q, qd, qdd, g_q, g_qd, g_qdd, g_q2=None):
-    n, B = q.shape
+def wb_sgd_step(lr: float, q, qd, qdd, g_q, g_qd, g_qdd, g_q2=None, nb=None):
+    n, ld = q.shape
+    B = _nb(ld, nb)
     for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (g_q, "g_q"), (g_qd, "g_qd"), (g_qdd, "g_qdd"),
                   (g_q2, "g_q2")):
-        _chk(t, nm, (n, B), device=q.device)
-    check(lib().wb_sgd_step(B, n, float(lr), _p(q), _p(qd), _p(qdd), _p(g_q), _p(g_q2), _p(g_qd),
+        _chk(t, nm, (n, ld), device=q.device)
+    check(lib().wb_sgd_step(B, ld, n, float(lr), _p(q), _p(qd), _p(qdd), _p(g_q), _p(g_q2), _p(g_qd),
                             _p(g_qdd), _stream()))
 
 
@@ -439,22 +461,23 @@ def wb_bspline_backward(K: int, T: int, dt: float, n_interp: int = 4, g_q=None, 
 
 def wb_wholebody_step(robot: Robot, q, qd, qdd, w=None, torque_weight=0.0, margin=0.0, hinge_weight=0.0,
                       lr=0.0, tau=None, cost=None, max_pen=None, argmax=None, n_coll=None, g_q=None,
-                      g_qd=None, g_qdd=None, f_ext=None, g_fext=None):
+                      g_qd=None, g_qdd=None, f_ext=None, g_fext=None, nb=None):
     """One fused iteration (FK, self-collision, RNEA, cost head, adjoints,
     optional in-place step on q, qd, qdd).  Outputs left as None are skipped.
     f_ext [L,6,B]: external link forces (link coordinates, moment then force);
     g_fext [L,6,B]: their gradient."""
-    n, B, L = robot.n_dof, q.shape[-1], robot.n_links
-    _chk(f_ext, "f_ext", (L, 6, B), device=robot.device)
-    _chk(g_fext, "g_fext", (L, 6, B), device=robot.device)
+    n, ld, L = robot.n_dof, q.shape[-1], robot.n_links
+    B = _nb(ld, nb)
+    _chk(f_ext, "f_ext", (L, 6, ld), device=robot.device)
+    _chk(g_fext, "g_fext", (L, 6, ld), device=robot.device)
     for t, nm in ((q, "q"), (qd, "qd"), (qdd, "qdd"), (w, "w"), (tau, "tau"), (g_q, "g_q"), (g_qd, "g_qd"),
                   (g_qdd, "g_qdd")):
-        _chk(t, nm, (n, B), device=robot.device)
+        _chk(t, nm, (n, ld), device=robot.device)
     _chk(cost, "cost", (B,), device=robot.device)
     _chk(max_pen, "max_pen", (B,), device=robot.device)
     _chk(argmax, "argmax", (B,), torch.int32, device=robot.device)
     _chk(n_coll, "n_coll", (B,), torch.int32, device=robot.device)
-    check(lib().wb_wholebody_step(robot.handle, B, _p(q), _p(qd), _p(qdd), _p(w), float(torque_weight),
+    check(lib().wb_wholebody_step(robot.handle, B, ld, _p(q), _p(qd), _p(qdd), _p(w), float(torque_weight),
                                   float(margin), float(hinge_weight), float(lr), _p(tau), _p(cost),
                                   _p(max_pen), _p(argmax), _p(n_coll), _p(g_q), _p(g_qd), _p(g_qdd),
                                   _p(f_ext), _p(g_fext), _stream()))
@@ -501,17 +524,21 @@ class Plan:
         arr = (_abi.WbTreeIO * n)()
         for i, (r, b, io) in enumerate(zip(self.robots, self.B, ios)):
             nd = r.n_dof
+            ld = io["q"].shape[-1] if io.get("q") is not None else b   # padded rows: the arrays' last dimension
+            if ld < b:
+                raise ValueError(f"tree {i}: arrays of {ld} columns for {b} states")
             for key in ("q", "qd", "qdd", "w", "tau", "g_q", "g_qd", "g_qdd"):
-                _chk(io.get(key), key, (nd, b), device=r.device)
+                _chk(io.get(key), key, (nd, ld), device=r.device)
             for key in ("f_ext", "g_fext"):
-                _chk(io.get(key), key, (r.n_links, 6, b), device=r.device)
+                _chk(io.get(key), key, (r.n_links, 6, ld), device=r.device)
             for key in ("cost", "max_pen"):
                 _chk(io.get(key), key, (b,), device=r.device)
             for key in ("argmax", "n_coll"):
                 _chk(io.get(key), key, (b,), torch.int32, device=r.device)
-            for key, _ in _abi.WbTreeIO._fields_:
+            for key in _abi.TREE_IO_POINTERS:
                 t = io.get(key)
                 setattr(arr[i], key, None if t is None else t.data_ptr())
+            arr[i].ld = ld
         return arr
 
     def close(self):

@@ -134,12 +134,22 @@ def test_null_descriptor_and_outputs(abi):
 
 def test_launch_calls_reject_null_robot(abi):
     lib = abi.lib()
-    assert lib.wb_fk(None, 4, None, None, None, None) == abi.WB_ERR_INVALID_ARG
-    assert lib.wb_self_collision(None, 4, None, None, None, None, None) == abi.WB_ERR_INVALID_ARG
-    assert lib.wb_cost_head(-1, 3, None, None, 0.0, None, 0.0, 0.0, None, None, None, None) == \
+    assert lib.wb_fk(None, 4, 0, None, None, None, None) == abi.WB_ERR_INVALID_ARG
+    assert lib.wb_self_collision(None, 4, 0, None, None, None, None, None) == abi.WB_ERR_INVALID_ARG
+    assert lib.wb_cost_head(-1, 0, 3, None, None, 0.0, None, 0.0, 0.0, None, None, None, None) == \
         abi.WB_ERR_INVALID_ARG
     # B = 0 with no pointers is a valid no-op for the robot-free kernels
-    assert lib.wb_sgd_step(0, 3, 0.1, None, None, None, None, None, None, None, None) == abi.WB_OK
+    assert lib.wb_sgd_step(0, 0, 3, 0.1, None, None, None, None, None, None, None, None) == abi.WB_OK
+
+
+def test_leading_dimension_below_B_is_rejected(abi):
+    """ld = 0 means ld = B; an ld below B is refused before any launch."""
+    lib = abi.lib()
+    E = abi.WB_ERR_INVALID_ARG
+    assert lib.wb_cost_head(8, 7, 3, None, None, 0.0, None, 0.0, 0.0, None, None, None, None) == E
+    assert "ld 7 is below B 8" in lib.wb_last_error().decode()
+    assert lib.wb_sgd_step(8, 5, 3, 0.1, None, None, None, None, None, None, None, None) == E
+    assert lib.wb_sgd_step(0, 0, 3, 0.1, None, None, None, None, None, None, None, None) == abi.WB_OK
 
 
 def test_bspline_calls_validate_arguments(abi):

@@ -200,3 +200,104 @@ def test_plan_capture_rejects_bad_arguments():
         plan.capture(ios, iters=2)
     assert _abi.lib().wb_graph_destroy(None) == _abi.WB_OK
     assert _abi.lib().wb_graph_launch(None, None) == _abi.WB_ERR_INVALID_ARG
+
+
+def _pad(x: torch.Tensor, extra: int, fill=float("nan")) -> torch.Tensor:
+    """x [..., B] -> a [..., B + extra] tensor holding x in its first B columns and `fill` after."""
+    out = torch.full((*x.shape[:-1], x.shape[-1] + extra), fill, dtype=x.dtype, device=x.device)
+    out[..., : x.shape[-1]] = x
+    return out
+
+
+def _same_and_untouched(padded, dense, extra, label):
+    B = dense.shape[-1]
+    assert torch.equal(padded[..., :B], dense), label
+    tail = padded[..., B:]
+    assert torch.isnan(tail).all() if tail.is_floating_point() else True, f"{label}: padding written"
+
+
+@pytest.mark.parametrize("label,factory,B", [("humanoid48", lambda: synth.humanoid48(seed=0), 1000),
+                                             ("tree12", lambda: synth.random_tree(12, 6, seed=1), 777)])
+def test_padded_rows_give_the_dense_results(label, factory, B):
+    """Every call that takes a leading dimension, run on arrays whose rows
+    are padded by 37 columns of NaN: the first B columns equal the dense
+    call's bit for bit and the padding is never written (or read: NaN
+    there would spread)."""
+    from paper_2603_05493_amd import wb
+    rb = factory()
+    r = _robot(rb)
+    st = synth.states(rb, B, seed=140, q_range=1.5)
+    X = 37
+    n = rb.n_dof
+    q, qd, qdd = P.dev(st.q), P.dev(st.qd), P.dev(st.qdd)
+    qp, qdp, qddp = _pad(q, X), _pad(qd, X), _pad(qdd, X)
+    # forward kinematics, self-collision and its adjoint
+    L, S = rb.n_links, rb.n_spheres
+    nanpad = lambda *shape: _pad(torch.zeros((*shape, B), device="cuda"), X)
+    pose, sph = wb.wb_fk(r, q)
+    pose_p, sph_p = wb.wb_fk(r, qp, link_pose=nanpad(L, 12), spheres=nanpad(S, 3), nb=B)
+    mp, am, nc = wb.wb_self_collision(r, sph)
+    mp_p, am_p, nc_p = wb.wb_self_collision(r, sph_p, nb=B)
+    gcost = torch.ones(B, device="cuda")
+    gs = wb.wb_self_collision_backward(r, sph, am, mp, 0.01, gcost)
+    gs_p = wb.wb_self_collision_backward(r, sph_p, am_p, mp_p, 0.01, gcost, g_spheres=_pad(torch.zeros_like(gs), X),
+                                         nb=B)
+    gfk = wb.wb_fk_backward(r, q, g_spheres=gs, link_pose=pose)
+    gfk_p = wb.wb_fk_backward(r, qp, g_spheres=gs_p, link_pose=pose_p, g_q=_pad(torch.zeros_like(gfk), X), nb=B)
+    # RNEA with and without its cache, the cost head and the step
+    tau, cache = wb.wb_rnea(r, q, qd, qdd)
+    tau_p, cache_p = wb.wb_rnea(r, qp, qdp, qddp, tau=_pad(torch.zeros_like(tau), X), cache=nanpad(L, 18), nb=B)
+    tau2_p, _ = wb.wb_rnea(r, qp, qdp, qddp, tau=_pad(torch.zeros_like(tau), X), want_cache=False, nb=B)
+    tau2, _ = wb.wb_rnea(r, q, qd, qdd, want_cache=False)
+    cost, gtau, gmp = wb.wb_cost_head(tau, None, 1e-3, mp, 0.01, 1.0)
+    cost_p, gtau_p, gmp_p = wb.wb_cost_head(tau_p, None, 1e-3, mp_p, 0.01, 1.0, g_tau=_pad(torch.zeros_like(tau), X),
+                                            nb=B)
+    z = lambda: _pad(torch.zeros((n, B), device="cuda"), X)
+    g = wb.wb_rnea_backward(r, q, qd, qdd, cache, gtau)
+    g_p = wb.wb_rnea_backward(r, qp, qdp, qddp, cache_p, gtau_p, z(), z(), z(), nb=B)
+    g2 = wb.wb_rnea_backward(r, q, qd, qdd, None, gtau)
+    g2_p = wb.wb_rnea_backward(r, qp, qdp, qddp, None, gtau_p, z(), z(), z(), nb=B)
+    # the fused iteration with its step
+    outs = lambda ld: dict(tau=torch.zeros((n, ld), device="cuda"), g_q=torch.zeros((n, ld), device="cuda"),
+                           cost=torch.empty(B, device="cuda"), argmax=torch.empty(B, dtype=torch.int32, device="cuda"))
+    fd, fp = outs(B), {k: (_pad(v, X) if v.dim() == 2 else v) for k, v in outs(B).items()}
+    qf, qdf, qddf = q.clone(), qd.clone(), qdd.clone()
+    qfp, qdfp, qddfp = qp.clone(), qdp.clone(), qddp.clone()
+    wb.wb_wholebody_step(r, qf, qdf, qddf, torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=1e-3, **fd)
+    wb.wb_wholebody_step(r, qfp, qdfp, qddfp, torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=1e-3, nb=B,
+                         **fp)
+    # the plain step
+    qs, qs_p = q.clone(), qp.clone()
+    wb.wb_sgd_step(1e-3, qs, qd.clone(), qdd.clone(), g[0], g[1], g[2], g_q2=gfk)
+    wb.wb_sgd_step(1e-3, qs_p, qdp.clone(), qddp.clone(), g_p[0], g_p[1], g_p[2], g_q2=gfk_p, nb=B)
+    torch.cuda.synchronize()
+    for a, b, nm in ((pose_p, pose, "pose"), (sph_p, sph, "spheres"), (gs_p, gs, "g_spheres"), (gfk_p, gfk, "g_q_fk"),
+                     (tau_p, tau, "tau"), (cache_p, cache, "cache"), (tau2_p, tau2, "tau (no cache)"),
+                     (gtau_p, gtau, "g_tau"), (qs_p, qs, "sgd q"), (qfp, qf, "fused q"), (qdfp, qdf, "fused qd"),
+                     (fp["tau"], fd["tau"], "fused tau"), (fp["g_q"], fd["g_q"], "fused g_q")):
+        _same_and_untouched(a, b, X, f"{label} {nm}")
+    for a, b in zip(g_p, g):
+        _same_and_untouched(a, b, X, f"{label} rnea backward")
+    for a, b in zip(g2_p, g2):
+        _same_and_untouched(a, b, X, f"{label} rnea backward (no cache)")
+    for a, b in ((mp_p, mp), (am_p, am), (nc_p, nc), (cost_p, cost), (gmp_p, gmp), (fp["cost"], fd["cost"]),
+                 (fp["argmax"], fd["argmax"])):
+        assert torch.equal(a, b), label
+
+
+def test_padded_plan_rows():
+    """A plan run on padded rows equals the run on dense rows, and the padding is left alone."""
+    from paper_2603_05493_amd import wb
+    jobs, robots, sts = _plan_setup(150)
+    plan = wb.Plan(robots, [B for _, B in jobs])
+    dense = [_io(rb, st) for (rb, _), st in zip(jobs, sts)]
+    padded = [{k: (_pad(v, 13) if v.dim() == 2 else v.clone()) for k, v in d.items()} for d in dense]
+    plan.run(dense, 1e-3, 0.01, 1.0, 1e-3)
+    plan.run(padded, 1e-3, 0.01, 1.0, 1e-3)
+    torch.cuda.synchronize()
+    for d, p in zip(dense, padded):
+        for k, v in d.items():
+            if v.dim() == 2:
+                _same_and_untouched(p[k], v, 13, f"plan {k}")
+            else:
+                assert torch.equal(p[k], v), k
