@@ -470,23 +470,27 @@ def bench_bspline(args, robot, T: int):
     T trajectories of 9 control points sampled 4 times per knot interval
     (48 states each), splines -> fused iteration -> control-point gradient
     and step, one iteration captured in a HIP graph and replayed.  The
-    control-point gradients are large (acceleration samples carry dt^-2), so
-    the step is small enough that the trajectories stay physical over the
-    whole run."""
+    control-point gradient carries the samples' dt^-1 and dt^-2 scaling, so
+    the step is the row-normalized one: each joint's row of control points
+    moves by lr = 0.01 rad RMS per iteration.  The summed cost before the
+    first and after the last timed iteration shows the step working."""
     import torch
+    from paper_2603_05493_amd import wb
     from paper_2603_05493_amd.iteration import BsplineIteration
     d, K, n_interp = robot.n_dof, 9, 4
     g = torch.Generator(device="cpu").manual_seed(3)
     U = (torch.rand((d, T, K), generator=g) * 3.0 - 1.5).cuda()
     th0 = (torch.rand((d, T), generator=g) * 3.0 - 1.5).cuda()
+    lr = 1e-2
     it = BsplineIteration(robot, U, th0, torch.zeros_like(th0), torch.zeros_like(th0), dt=0.05, n_interp=n_interp,
-                          torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=1e-7)
+                          torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=lr, step_rule=wb.STEP_ROW_RMS)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
         it.run(step=False)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
+    cost0 = float(it.fused.cost.double().sum())
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         it.run(step=True)
@@ -498,10 +502,15 @@ def bench_bspline(args, robot, T: int):
         graph.replay()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    assert torch.isfinite(U).all()
+    it.run(step=False)
+    torch.cuda.synchronize()
+    cost1 = float(it.fused.cost.double().sum())
+    assert torch.isfinite(U).all() and np.isfinite(cost1)
     states = T * it.H
     return {"trajectories": T, "control_points": K, "n_interp": n_interp, "states": states,
             "states_per_s": states / dt, "ms_per_step": dt * 1e3,
+            "step": {"rule": "row-normalized (each joint's control points move lr / rms(g) * g)", "lr": lr,
+                     "iterations": args.warmup + args.steps + 1, "cost_sum_first": cost0, "cost_sum_last": cost1},
             "form": "bspline_eval + fused iteration (per-joint outputs) + control-point gradient and step, graph"}
 
 

@@ -323,13 +323,26 @@ int wb_bspline_eval(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt,
                     const float *U, const float *theta0, const float *dtheta0, const float *ddtheta0,
                     float *q, float *qd, float *qdd, hipStream_t stream);
 
-/* Control-point gradient g_U [d][T][K] (overwritten; may be NULL when lr != 0)
- * from upstream gradients on the samples g_q, g_qd, g_qdd [d][T*H] (each
- * may be NULL = zero).  The initial state is not a variable: ghost knots
- * take no gradient; copies of u_{K-1} add into it.  When lr != 0, U is
- * updated in place, U -= lr * g_U. */
+/* Control-point gradient g_U [d][T][K] (overwritten; may be NULL when lr != 0
+ * with the plain step) from upstream gradients on the samples g_q, g_qd,
+ * g_qdd [d][T*H] (each may be NULL = zero).  The initial state is not a
+ * variable: ghost knots take no gradient; copies of u_{K-1} add into it.
+ * When lr != 0, U is updated in place by the step rule:
+ *   WB_STEP_PLAIN    U -= lr * g_U;
+ *   WB_STEP_ROW_RMS  U_row -= lr * g_row / rms(g_row) for every (joint,
+ *                    trajectory) row of K control points (no step for an
+ *                    all-zero row); g_U is required.  The samples' velocity
+ *                    and acceleration gradients reach g_U scaled by dt^-1
+ *                    and dt^-2 (Eqs. 11-12), so a plain step stable at the
+ *                    optimizer's scales barely moves the control points;
+ *                    dividing each row by its own positive scale is a
+ *                    diagonal preconditioner (still a descent direction)
+ *                    whose lr is the RMS change of a row per step.
+ * WB_ERR_INVALID_ARG for an unknown step rule. */
+#define WB_STEP_PLAIN 0
+#define WB_STEP_ROW_RMS 1
 int wb_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, const float *g_q,
-                        const float *g_qd, const float *g_qdd, float *g_U, float lr, float *U,
+                        const float *g_qd, const float *g_qdd, float *g_U, float lr, int32_t step_rule, float *U,
                         hipStream_t stream);
 
 /* ------------------------------------------------------ fused iteration

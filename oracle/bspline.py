@@ -122,3 +122,16 @@ def backward(g, K: int, dt: float, n_interp: int = 4):
     gU = gE[..., 3:3 + K].copy()
     gU[..., -1] += gE[..., 3 + K:].sum(-1)                 # copies of the final control point
     return gU
+
+
+def row_rms_step(U, gU, lr: float):
+    """The row-normalized control-point step: every (trajectory, joint) row
+    of K control points moves by lr * g / rms(g), rms over the row; an
+    all-zero row stays.  Dividing each row by its own positive scale is a
+    positive diagonal preconditioner, so the step is a descent direction
+    whatever the rows' scales (the acceleration samples reach the gradient
+    scaled by dt^-2)."""
+    U = np.asarray(U, float)
+    g = np.asarray(gU, float)
+    rms = np.sqrt((g * g).mean(-1, keepdims=True))
+    return U - lr * np.where(rms > 0, g / np.where(rms > 0, rms, 1.0), 0.0)

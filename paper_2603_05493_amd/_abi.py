@@ -87,7 +87,7 @@ _SIGS = {
     "wb_bspline_eval": [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_int32, _vp, _vp, _vp, _vp,
                         _vp, _vp, _vp, _vp],
     "wb_bspline_backward": [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_float, _vp, _vp, _vp, _vp, C.c_float,
-                            _vp, _vp],
+                            C.c_int32, _vp, _vp],
     "wb_wholebody_step": [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float,
                           _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "wb_robot_set_tune": [_vp, C.POINTER(WbTune)],

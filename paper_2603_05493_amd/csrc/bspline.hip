@@ -195,6 +195,11 @@ __global__ void __launch_bounds__(256) k_bspline_eval4(int32_t T, int32_t K, flo
 // (trajectory, s) for s >= 3 sums knot s over the (at most four) segments
 // that contain it -- the final control point also over its three copies --
 // in a fixed order.
+//
+// With the row-normalized step (ROW_RMS) the K lanes of each (joint,
+// trajectory) row also sum their squared gradients through LDS, every lane
+// in the same order, and step by lr * g / rms(row).
+template <bool ROW_RMS>
 __global__ void __launch_bounds__(256) k_bspline_backward4(int32_t T, int32_t K, float dt,
                                                            const float *__restrict__ g_q,
                                                            const float *__restrict__ g_qd,
@@ -202,6 +207,7 @@ __global__ void __launch_bounds__(256) k_bspline_backward4(int32_t T, int32_t K,
                                                            float *__restrict__ g_U, float lr,
                                                            float *__restrict__ U) {
     __shared__ float4 gw[256];
+    __shared__ float g2[256];
     const int S = K + 3, tpb = 256 / S;
     const int lt = threadIdx.x / S, seg = threadIdx.x - lt * S;
     const int traj = blockIdx.x * tpb + lt;
@@ -222,19 +228,49 @@ __global__ void __launch_bounds__(256) k_bspline_backward4(int32_t T, int32_t K,
     }
     gw[threadIdx.x] = make_float4(r0, r1, r2, r3);
     __syncthreads();
-    if (!act || seg < 3) return;   // ghost knots take no gradient
-    const float4 *row = gw + lt * S;
-    // knot e = seg is slot m of segment seg - m
-    float g = row[seg].x + row[seg - 1].y + row[seg - 2].z + row[seg - 3].w;
-    if (seg == S - 1) {
-        // copies e = S .. S+2 of the final control point: slot e - s of segment s
-        g += row[S - 1].y + row[S - 2].z + row[S - 3].w;   // e = S
-        g += row[S - 1].z + row[S - 2].w;                  // e = S + 1
-        g += row[S - 1].w;                                 // e = S + 2
+    const bool knot = act && seg >= 3;   // ghost knots take no gradient
+    float g = 0.f;
+    if (knot) {
+        const float4 *row = gw + lt * S;
+        // knot e = seg is slot m of segment seg - m
+        g = row[seg].x + row[seg - 1].y + row[seg - 2].z + row[seg - 3].w;
+        if (seg == S - 1) {
+            // copies e = S .. S+2 of the final control point: slot e - s of segment s
+            g += row[S - 1].y + row[S - 2].z + row[S - 3].w;   // e = S
+            g += row[S - 1].z + row[S - 2].w;                  // e = S + 1
+            g += row[S - 1].w;                                 // e = S + 2
+        }
     }
+    float step = lr;
+    if (ROW_RMS) {
+        g2[threadIdx.x] = g * g;
+        __syncthreads();
+        if (knot) {
+            float ss = 0.f;
+            for (int k = 0; k < K; ++k) ss += g2[lt * S + 3 + k];
+            step = ss > 0.f ? lr * rsqrtf(ss / (float)K) : 0.f;
+        }
+    }
+    if (!knot) return;
     const int64_t o = ((int64_t)j * T + traj) * K + (seg - 3);
     if (g_U) g_U[o] = g;
-    if (lr != 0.f) U[o] -= lr * g;
+    if (lr != 0.f) U[o] -= step * g;
+}
+
+// The row-normalized step on a computed gradient: one lane per (joint,
+// trajectory) row of K control points, U -= lr * g / rms(g) over the row
+// (no step for an all-zero row).
+__global__ void __launch_bounds__(256) k_bspline_row_step(int64_t rows, int32_t K, const float *__restrict__ g_U,
+                                                          float lr, float *__restrict__ U) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= rows) return;
+    const float *g = g_U + r * K;
+    float ss = 0.f;
+    for (int k = 0; k < K; ++k) ss += g[k] * g[k];
+    if (!(ss > 0.f)) return;
+    const float step = lr * rsqrtf(ss / (float)K);
+    float *u = U + r * K;
+    for (int k = 0; k < K; ++k) u[k] -= step * g[k];
 }
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
@@ -258,17 +294,32 @@ hipError_t launch_bspline_eval(int64_t T, int32_t d, int32_t K, int32_t n_interp
 }
 
 hipError_t launch_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, const float *g_q,
-                                   const float *g_qd, const float *g_qdd, float *g_U, float lr, float *U,
-                                   hipStream_t s) {
+                                   const float *g_qd, const float *g_qdd, float *g_U, float lr, int32_t rule,
+                                   float *U, hipStream_t s) {
     if (T == 0 || d == 0) return hipSuccess;
+    const bool rms = rule == WB_STEP_ROW_RMS && lr != 0.f;
     if (n_interp == 4 && K + 3 <= 256 && aligned16(g_q) && aligned16(g_qd) && aligned16(g_qdd)) {
         const int tpb = 256 / (K + 3);
         dim3 grid((unsigned)((T + tpb - 1) / tpb), (unsigned)d);
-        hipLaunchKernelGGL(k_bspline_backward4, grid, dim3(256), 0, s, (int32_t)T, K, dt, g_q, g_qd, g_qdd, g_U, lr, U);
+        if (rms)
+            hipLaunchKernelGGL(k_bspline_backward4<true>, grid, dim3(256), 0, s, (int32_t)T, K, dt, g_q, g_qd, g_qdd,
+                               g_U, lr, U);
+        else
+            hipLaunchKernelGGL(k_bspline_backward4<false>, grid, dim3(256), 0, s, (int32_t)T, K, dt, g_q, g_qd, g_qdd,
+                               g_U, lr, U);
         return hipGetLastError();
     }
     dim3 grid((unsigned)((T * K + 255) / 256), (unsigned)d);
-    hipLaunchKernelGGL(k_bspline_backward, grid, dim3(256), 0, s, T, K, n_interp, dt, g_q, g_qd, g_qdd, g_U, lr, U);
+    // the row-normalized step needs the whole row's gradient first: g_U, then a row pass
+    hipLaunchKernelGGL(k_bspline_backward, grid, dim3(256), 0, s, T, K, n_interp, dt, g_q, g_qd, g_qdd, g_U,
+                       rms ? 0.f : lr, U);
+    if (rms) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int64_t rows = (int64_t)d * T;
+        hipLaunchKernelGGL(k_bspline_row_step, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, rows, K, g_U, lr,
+                           U);
+    }
     return hipGetLastError();
 }
 

@@ -868,17 +868,19 @@ int wb_bspline_eval(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt,
 }
 
 int wb_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, const float *g_q,
-                        const float *g_qd, const float *g_qdd, float *g_U, float lr, float *U,
+                        const float *g_qd, const float *g_qdd, float *g_U, float lr, int32_t step_rule, float *U,
                         hipStream_t stream) {
     WB_TRY(check_bspline(T, d, K, n_interp, dt));
     if (!std::isfinite(lr)) return fail(WB_ERR_INVALID_ARG, "lr must be finite");
+    if (step_rule != WB_STEP_PLAIN && step_rule != WB_STEP_ROW_RMS)
+        return fail(WB_ERR_INVALID_ARG, "unknown step rule %d", step_rule);
     if (T == 0 || d == 0) return WB_OK;
     WB_TRY(check_ptr(g_q, "g_q", false));
     WB_TRY(check_ptr(g_qd, "g_qd", false));
     WB_TRY(check_ptr(g_qdd, "g_qdd", false));
-    WB_TRY(check_ptr(g_U, "g_U", lr == 0.0f));
+    WB_TRY(check_ptr(g_U, "g_U", lr == 0.0f || step_rule == WB_STEP_ROW_RMS));
     WB_TRY(check_ptr(U, "U", lr != 0.0f));
-    return finish(wb::launch_bspline_backward(T, d, K, n_interp, dt, g_q, g_qd, g_qdd, g_U, lr, U, stream),
+    return finish(wb::launch_bspline_backward(T, d, K, n_interp, dt, g_q, g_qd, g_qdd, g_U, lr, step_rule, U, stream),
                   "wb_bspline_backward launch");
 }
 

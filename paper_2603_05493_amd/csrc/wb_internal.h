@@ -175,8 +175,8 @@ hipError_t launch_bspline_eval(int64_t T, int32_t d, int32_t K, int32_t n_interp
                                const float *U, const float *th0, const float *dth0, const float *ddth0, float *q,
                                float *qd, float *qdd, hipStream_t s);
 hipError_t launch_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_interp, float dt, const float *g_q,
-                                   const float *g_qd, const float *g_qdd, float *g_U, float lr, float *U,
-                                   hipStream_t s);
+                                   const float *g_qd, const float *g_qdd, float *g_U, float lr, int32_t rule,
+                                   float *U, hipStream_t s);
 
 // LDS of one state's sweep: (L+1)*nmax sphere slots and L+1 link bounding
 // spheres (float4 each); plus, per sweeping group, a list of list_cap

@@ -185,21 +185,22 @@ class BsplineIteration:
     states without its own step, then pull the state gradients back onto the
     control points and step them (wb_bspline_backward).
 
-    U [d][T][K] control points (updated in place when stepping); theta0,
-    dtheta0, ddtheta0 [d][T] the initial state of each trajectory; the
-    samples are the states b = traj * H + t of the fused iteration.
+    U [d][T][K] control points (updated in place when stepping, by the
+    plain or the row-normalized rule); theta0, dtheta0, ddtheta0 [d][T] the
+    initial state of each trajectory; the samples are the states
+    b = traj * H + t of the fused iteration.
     """
 
     def __init__(self, robot: wb.Robot, U: torch.Tensor, theta0: torch.Tensor,
                  dtheta0: Optional[torch.Tensor] = None, ddtheta0: Optional[torch.Tensor] = None,
                  dt: float = 0.05, n_interp: int = 4, reading: int = wb.GHOST_EXACT,
                  w: Optional[torch.Tensor] = None, torque_weight: float = 1e-3, margin: float = 0.01,
-                 hinge_weight: float = 1.0, lr: float = 0.0):
+                 hinge_weight: float = 1.0, lr: float = 0.0, step_rule: int = wb.STEP_PLAIN):
         d, T, K = U.shape
         if d != robot.n_dof:
             raise ValueError(f"U has {d} joints, the robot {robot.n_dof}")
         self.U, self.theta0, self.dtheta0, self.ddtheta0 = U, theta0, dtheta0, ddtheta0
-        self.dt, self.n_interp, self.reading, self.lr = dt, n_interp, reading, lr
+        self.dt, self.n_interp, self.reading, self.lr, self.step_rule = dt, n_interp, reading, lr, step_rule
         self.K, self.T = K, T
         self.H = wb.bspline_horizon(K, n_interp)
         B = T * self.H
@@ -215,4 +216,4 @@ class BsplineIteration:
         self.fused.run(self.q, self.qd, self.qdd, step=False)
         f = self.fused
         wb.wb_bspline_backward(self.K, self.T, self.dt, self.n_interp, g_q=f.g_q, g_qd=f.g_qd, g_qdd=f.g_qdd,
-                               g_U=self.g_U, lr=self.lr if step else 0.0, U=self.U)
+                               g_U=self.g_U, lr=self.lr if step else 0.0, U=self.U, step_rule=self.step_rule)

@@ -441,21 +441,26 @@ def wb_bspline_eval(U, theta0, dt: float, n_interp: int = 4, dtheta0=None, ddthe
     return tuple(outs)
 
 
+STEP_PLAIN, STEP_ROW_RMS = 0, 1
+
+
 def wb_bspline_backward(K: int, T: int, dt: float, n_interp: int = 4, g_q=None, g_qd=None, g_qdd=None, g_U=None,
-                        lr: float = 0.0, U=None):
+                        lr: float = 0.0, U=None, step_rule: int = STEP_PLAIN):
     """Control-point gradient [d][T][K] of upstream sample gradients
-    [d][T*H]; with lr != 0 also U -= lr * g_U in place."""
+    [d][T*H]; with lr != 0 also the step on U in place: U -= lr * g_U
+    (STEP_PLAIN), or each (joint, trajectory) row of K control points moved
+    by lr * g / rms(g) (STEP_ROW_RMS)."""
     ref = next(t for t in (g_q, g_qd, g_qdd) if t is not None)
     d = ref.shape[0]
     H = bspline_horizon(K, n_interp)
     for t, nm in ((g_q, "g_q"), (g_qd, "g_qd"), (g_qdd, "g_qdd")):
         _chk(t, nm, (d, T * H), device=ref.device)
-    if g_U is None and lr == 0.0:
+    if g_U is None and (lr == 0.0 or step_rule == STEP_ROW_RMS):
         g_U = torch.empty((d, T, K), dtype=torch.float32, device=ref.device)
     _chk(g_U, "g_U", (d, T, K), device=ref.device)
     _chk(U, "U", (d, T, K), device=ref.device)
     check(lib().wb_bspline_backward(T, d, K, n_interp, float(dt), _p(g_q), _p(g_qd), _p(g_qdd), _p(g_U),
-                                    float(lr), _p(U), _stream()))
+                                    float(lr), int(step_rule), _p(U), _stream()))
     return g_U
 
 

@@ -159,7 +159,7 @@ def test_bspline_calls_validate_arguments(abi):
                                                                                   None, q, None, None, None)
     # empty batches are valid no-ops
     assert ev(0, 4, 9, 4, 0.05, 0) == abi.WB_OK
-    assert lib.wb_bspline_backward(0, 4, 9, 4, 0.05, None, None, None, None, 0.0, None, None) == abi.WB_OK
+    assert lib.wb_bspline_backward(0, 4, 9, 4, 0.05, None, None, None, None, 0.0, 0, None, None) == abi.WB_OK
     # shape and parameter checks come before any launch
     assert ev(1, 4, 0, 4, 0.05, 0) == E                      # no control points
     assert ev(1, 4, 9, 0, 0.05, 0) == E                      # no samples per interval
@@ -170,6 +170,12 @@ def test_bspline_calls_validate_arguments(abi):
     assert ev(1, 4, 9, 4, 0.05, 0) == E                      # U, theta0 and q are required
     assert "U" in lib.wb_last_error().decode()
     # the gradient needs somewhere to go: g_U, or U with a step
-    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, 0.0, None, None) == E
-    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, 0.1, None, None) == E
-    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, float("inf"), None, None) == E
+    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, 0.0, 0, None, None) == E
+    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, 0.1, 0, None, None) == E
+    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, float("inf"), 0, None, None) == E
+    # an unknown step rule, and the row-normalized step without g_U
+    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, 0.1, 2, None, None) == E
+    assert "step rule" in lib.wb_last_error().decode()
+    dummy = C.c_void_p(256)   # never dereferenced: the check fails first
+    assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, 0.1, 1, dummy, None) == E
+    assert "g_U" in lib.wb_last_error().decode()

@@ -132,6 +132,32 @@ def test_backward_step_in_place():
     _assert_step(Ud, U0, lr, gU)
 
 
+@pytest.mark.parametrize("T,d,K,n", [(200, 9, 7, 4), (512, 48, 9, 4), (60, 5, 11, 3)])
+def test_row_normalized_step(T, d, K, n):
+    """STEP_ROW_RMS: every (joint, trajectory) row of control points moves by
+    lr * g / rms(g) with the kernel's own g_U (the fused form for four samples
+    per interval, the gradient-then-row pass otherwise); a row whose gradient
+    is all zero stays put."""
+    from oracle import bspline as obs
+    from paper_2603_05493_amd import wb
+    H = bs.horizon(K, n)
+    U, _, _, _ = _problem(T, d, K, seed=13)
+    g = [torch.randn(d, T * H, device="cuda") for _ in range(3)]
+    for t in g:                        # trajectory 1 gets no upstream gradient at all
+        t.view(d, T, H)[:, 1] = 0.0
+    Ud = dev_U(U)
+    U0 = Ud.clone()
+    gU = torch.full((d, T, K), float("nan"), device="cuda")
+    wb.wb_bspline_backward(K, T, DT, n, *g, g_U=gU, lr=1e-2, U=Ud, step_rule=wb.STEP_ROW_RMS)
+    plain = wb.wb_bspline_backward(K, T, DT, n, *g)
+    torch.cuda.synchronize()
+    assert torch.equal(gU, plain)      # the gradient is the plain call's
+    expect = obs.row_rms_step(host_U(U0), host_U(gU), 1e-2)
+    got = host_U(Ud)
+    np.testing.assert_allclose(got, expect, rtol=0, atol=1e-6)
+    assert torch.equal(Ud[:, 1], U0[:, 1])
+
+
 def test_empty_batch():
     from paper_2603_05493_amd import wb
     U = torch.empty((4, 0, 9), device="cuda")
@@ -189,3 +215,27 @@ def test_control_point_iteration_matches_oracle(oracle, label, factory, T, K):
     it.run(step=True)
     torch.cuda.synchronize()
     _assert_step(it.U, U0, 1e-4, it.g_U)
+    # the row-normalized step at the benchmark's rate, against the oracle's
+    # step from the oracle's gradient (taken at the current control points)
+    from oracle import bspline as obs
+    U1 = host_U(it.U)
+    Th1 = bs.evaluate(U1, th0, v0, a0, DT, n_interp)
+    q1, qd1, qdd1 = (Th1[..., r].reshape(T * H, d) for r in range(3))
+    ref1 = P.oracle_iteration(oracle, rb, q1, qd1, qdd1, None, tw, margin, hw)
+    it.lr, it.step_rule = 1e-2, wb.STEP_ROW_RMS
+    it.run(step=True)
+    torch.cuda.synchronize()
+    g_q1, _, _, _ = P.reference_gq(oracle, rb, q1, ref1, P.host(it.fused.g_q), it.fused.argmax.cpu().numpy(),
+                                   margin, hw)
+    gU1 = bs.backward(np.stack([g_q1, ref1["g_qd"], ref1["g_qdd"]], -1).reshape(T, H, d, 3), K, DT, n_interp)
+    expect = obs.row_rms_step(U1, gU1, 1e-2)
+    err = np.abs(host_U(it.U) - expect).max(-1)                 # per (trajectory, joint) row
+    # g_U agrees to TOL of its trajectory's largest entry; dividing a row by
+    # its own rms amplifies that by max|g_traj| / rms(row), so the step of a
+    # row may differ by lr * TOL * that ratio (twice, for the two rms's)
+    rms = np.sqrt((gU1 * gU1).mean(-1))
+    ratio = np.abs(gU1).max(axis=(1, 2))[:, None] / np.maximum(rms, 1e-30)
+    bound = 2 * 1e-2 * P.TOL * ratio + 1e-6
+    print(label, "row-normalized step, max |U - U_oracle|", float(err.max()), "worst err/bound",
+          float((err / bound).max()), flush=True)
+    assert np.all(err <= bound)

@@ -156,3 +156,31 @@ def test_backward_matches_central_fd():
         Um[idx] -= h
         fd = (loss(Up) - loss(Um)) / (2 * h)
         np.testing.assert_allclose(gU[idx], fd, rtol=1e-6, atol=1e-3)
+
+
+def test_control_point_gradient_scales_as_dt_powers():
+    """With the sample gradients held fixed, the part of the control-point
+    gradient that comes through the velocity samples scales as 1/dt and the
+    part through the acceleration samples as 1/dt^2 (the time scaling of
+    Eqs. 11-12), exactly."""
+    T, d, K = 2, 3, 9
+    H = bs.horizon(K, 4)
+    g = np.random.default_rng(4).normal(size=(T, H, d, 3))
+    only = lambda c: np.where(np.arange(3) == c, g, 0.0)
+    for c, power in ((0, 0), (1, 1), (2, 2)):
+        a = bs.backward(only(c), K, DT, 4)
+        b = bs.backward(only(c), K, DT / 2, 4)
+        np.testing.assert_allclose(b, a * 2.0 ** power, rtol=1e-12, atol=1e-12)
+
+
+def test_row_rms_step_moves_every_row_by_lr():
+    U, _, _, _ = _rand(T=3, d=4, K=9, seed=5)
+    g = np.random.default_rng(6).normal(size=U.shape) * np.array([1e-3, 1.0, 1e3, 1e6])[None, :, None]
+    g[1, 2] = 0.0                                   # an all-zero row does not move
+    U1 = bs.row_rms_step(U, g, 0.01)
+    dU = U - U1
+    rms = np.sqrt((dU * dU).mean(-1))
+    expect = np.full(rms.shape, 0.01)
+    expect[1, 2] = 0.0
+    np.testing.assert_allclose(rms, expect, rtol=1e-12, atol=1e-15)
+    assert np.all(np.sign(dU) == np.sign(g))        # along the gradient, row by row
