@@ -469,49 +469,95 @@ def bench_bspline(args, robot, T: int):
     """The same optimizer load with B-spline control points as the variables:
     T trajectories of 9 control points sampled 4 times per knot interval
     (48 states each), splines -> fused iteration -> control-point gradient
-    and step, one iteration captured in a HIP graph and replayed.  The
-    control-point gradient carries the samples' dt^-1 and dt^-2 scaling, so
-    the step is the row-normalized one: each joint's row of control points
-    moves by lr = 0.01 rad RMS per iteration.  The summed cost before the
-    first and after the last timed iteration shows the step working."""
+    and step, one iteration captured in a HIP graph and replayed, in three
+    forms: the sampling kernel writing the states for the fused iteration
+    (two_launch), the fused kernel forming the samples itself from the
+    control points (fused_sampling), and one kernel that also reduces the
+    control-point gradient of its trajectory and steps (one_launch).  The control-point gradient carries the
+    samples' dt^-1 and dt^-2 scaling, so the step is the row-normalized one:
+    each joint's row of control points moves by lr = 0.01 rad RMS per
+    iteration.  The summed cost before the first and after the last timed
+    iteration shows the step working."""
     import torch
     from paper_2603_05493_amd import wb
     from paper_2603_05493_amd.iteration import BsplineIteration
     d, K, n_interp = robot.n_dof, 9, 4
-    g = torch.Generator(device="cpu").manual_seed(3)
-    U = (torch.rand((d, T, K), generator=g) * 3.0 - 1.5).cuda()
-    th0 = (torch.rand((d, T), generator=g) * 3.0 - 1.5).cuda()
     lr = 1e-2
-    it = BsplineIteration(robot, U, th0, torch.zeros_like(th0), torch.zeros_like(th0), dt=0.05, n_interp=n_interp,
-                          torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=lr, step_rule=wb.STEP_ROW_RMS)
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
+    out = {"trajectories": T, "control_points": K, "n_interp": n_interp}
+    for form in ("two_launch", "fused_sampling", "one_launch"):
+        g = torch.Generator(device="cpu").manual_seed(3)
+        U = (torch.rand((d, T, K), generator=g) * 3.0 - 1.5).cuda()
+        th0 = (torch.rand((d, T), generator=g) * 3.0 - 1.5).cuda()
+        it = BsplineIteration(robot, U, th0, torch.zeros_like(th0), torch.zeros_like(th0), dt=0.05,
+                              n_interp=n_interp, torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=lr,
+                              step_rule=wb.STEP_ROW_RMS, form=form, sample_outputs=False)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            it.run(step=False)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        cost0 = float(it.fused.cost.double().sum())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            it.run(step=True)
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
         it.run(step=False)
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    cost0 = float(it.fused.cost.double().sum())
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        it.run(step=True)
-    for _ in range(args.warmup):
-        graph.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        graph.replay()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    it.run(step=False)
-    torch.cuda.synchronize()
-    cost1 = float(it.fused.cost.double().sum())
-    assert torch.isfinite(U).all() and np.isfinite(cost1)
-    states = T * it.H
-    return {"trajectories": T, "control_points": K, "n_interp": n_interp, "states": states,
-            "states_per_s": states / dt, "ms_per_step": dt * 1e3,
-            "step": {"rule": "row-normalized (each joint's control points move lr / rms(g) * g)", "lr": lr,
-                     "iterations": args.warmup + args.steps + 1, "cost_sum_first": cost0, "cost_sum_last": cost1},
-            "form": "bspline_eval + fused iteration (per-joint outputs) + control-point gradient and step, graph"}
+        torch.cuda.synchronize()
+        cost1 = float(it.fused.cost.double().sum())
+        assert torch.isfinite(U).all() and np.isfinite(cost1)
+        states = T * it.H
+        out["states"] = states
+        out[form] = {"states_per_s": states / dt, "ms_per_step": dt * 1e3,
+                     "cost_sum_first": cost0, "cost_sum_last": cost1}
+    out["step"] = {"rule": "row-normalized (each joint's control points move lr / rms(g) * g)", "lr": lr,
+                   "iterations": args.warmup + args.steps + 1}
+    out["whole_trajectory_workgroups"] = trajectory_workgroup_probe(robot, T * 48, 48)
+    out["form"] = ("two_launch: bspline_eval + fused iteration (per-joint outputs) + control-point gradient and "
+                   "step; fused_sampling: the fused kernel forms the samples + the gradient and step; one_launch: "
+                   "one kernel forms the samples, runs the iteration, reduces the control-point gradient of its "
+                   "trajectory and steps; each captured in a graph")
+    return out
+
+
+def trajectory_workgroup_probe(robot, B: int, H: int, reps: int = 50):
+    """What reducing the control-point gradient inside the fused kernel would
+    cost in occupancy: a workgroup would have to own whole trajectories (H
+    states), so the fused kernel is timed (HIP events) at H states per
+    workgroup against the tuned shape, on the same batch."""
+    import torch
+    from paper_2603_05493_amd import synth
+    rb = synth.humanoid48(seed=0)
+    st = synth.states(rb, B, seed=1, q_range=1.5)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a.T.astype(np.float32))).cuda()
+    q, qd, qdd = d(st.q), d(st.qd), d(st.qdd)
+    tuned = robot.get_tune()
+    res = {}
+    from paper_2603_05493_amd import wb
+    for name, spi in (("tuned", tuned["states_per_item"]), ("trajectory", H)):
+        robot.set_tune(tuned["lanes_per_state"], spi, tuned["ns_per_state"])
+        run = lambda: wb.wb_wholebody_step(robot, q, qd, qdd, torque_weight=1e-3, margin=0.01, hinge_weight=1.0)
+        for _ in range(5):
+            run()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            run()
+        e1.record(s)
+        torch.cuda.synchronize()
+        res[name] = {"states_per_workgroup": spi, "workgroups": (B + spi - 1) // spi,
+                     "kernel_us": e0.elapsed_time(e1) / reps * 1e3}
+    robot.set_tune(tuned["lanes_per_state"], tuned["states_per_item"], tuned["ns_per_state"])
+    res["slowdown"] = res["trajectory"]["kernel_us"] / res["tuned"]["kernel_us"]
+    return res
 
 
 def bench_ext_variant(args, st, reps: int = 50):

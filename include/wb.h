@@ -120,6 +120,7 @@ typedef struct wb_robot_info {
     int32_t max_spheres_per_link;
     int32_t fused_supported;  /* 1 if wb_wholebody_step accepts this robot */
     int32_t kinematics_supported;  /* 1 if wb_kinematics accepts this robot (L <= 64, n <= 64) */
+    int32_t mimic;            /* 1 if some joint drives several links or has a multiplier != 1 or offset != 0 */
 } wb_robot_info;
 
 typedef struct wb_robot wb_robot;   /* opaque; owns a device copy of the tables */
@@ -373,6 +374,33 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, int64_t ld, float *q, fl
                       float torque_weight, float margin, float hinge_weight, float lr, float *tau,
                       float *cost, float *max_pen, int32_t *argmax, int32_t *n_coll, float *g_q,
                       float *g_qd, float *g_qdd, const float *f_ext, float *g_fext, hipStream_t stream);
+
+/* The whole B-spline optimizer iteration in one launch (Sec. 3's loop with
+ * Sec. 4's splines in front of the whole-body terms and their control-point
+ * gradient behind them): each state's joint positions, velocities and
+ * accelerations are formed in the kernel from the control points --
+ * the samples wb_bspline_eval writes for four samples per knot interval --
+ * instead of being read from state arrays; with g_U or lr != 0 each
+ * workgroup owns one whole trajectory, pulls every sample's gradient back
+ * onto its four-knot window in LDS, reduces them (the result of
+ * wb_bspline_backward, summed in a fixed order) and steps U in place by the
+ * step rule, so nothing per state reaches device memory.
+ *   T, K, dt, reading, U [d][T][K], theta0, dtheta0, ddtheta0 [d][T] as in
+ *   wb_bspline_eval (d = n_dof, n_interp = 4); the B = T * (K + 3) * 4
+ *   states are ordered as there.
+ *   g_U [d][T][K] (NULL to skip), lr, step_rule: as wb_bspline_backward.
+ *   tau, cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd: optional outputs of
+ *   wb_wholebody_step for the batch, dense [n][B] and [B] (g_q, g_qd, g_qdd
+ *   are the per-sample gradients wb_bspline_backward takes).
+ * WB_ERR_UNSUPPORTED for robots with mimic joints or outside the fused
+ * iteration's limits, and when the control-point gradient's LDS (partial
+ * sums of 4 * 64 / lanes_per_state groups over d x (K + 6) knots) does not
+ * fit beside the fused kernel's in 64 KB. */
+int wb_wholebody_step_bspline(const wb_robot *robot, int64_t T, int32_t K, float dt, int32_t reading,
+                              float *U, const float *theta0, const float *dtheta0, const float *ddtheta0,
+                              const float *w, float torque_weight, float margin, float hinge_weight, float *g_U,
+                              float lr, int32_t step_rule, float *tau, float *cost, float *max_pen, int32_t *argmax,
+                              int32_t *n_coll, float *g_q, float *g_qd, float *g_qdd, hipStream_t stream);
 
 /* Launch shape of the fused iteration for one robot (the paper dispatches
  * FK differently by robot size, Sec. 6.1 "adaptive kernel dispatch"; here the

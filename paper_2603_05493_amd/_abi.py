@@ -36,7 +36,7 @@ class WbRobotInfo(C.Structure):
         ("n_links", C.c_int32), ("n_dof", C.c_int32), ("n_spheres", C.c_int32),
         ("max_depth", C.c_int32), ("n_pairs", C.c_int64), ("n_blocks", C.c_int32),
         ("max_spheres_per_link", C.c_int32), ("fused_supported", C.c_int32),
-        ("kinematics_supported", C.c_int32),
+        ("kinematics_supported", C.c_int32), ("mimic", C.c_int32),
     ]
 
 
@@ -90,6 +90,9 @@ _SIGS = {
                             C.c_int32, _vp, _vp],
     "wb_wholebody_step": [_vp, C.c_int64, C.c_int64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float,
                           _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "wb_wholebody_step_bspline": [_vp, C.c_int64, C.c_int32, C.c_float, C.c_int32, _vp, _vp, _vp, _vp, _vp,
+                                  C.c_float, C.c_float, C.c_float, _vp, C.c_float, C.c_int32, _vp, _vp, _vp, _vp,
+                                  _vp, _vp, _vp, _vp, _vp],
     "wb_robot_set_tune": [_vp, C.POINTER(WbTune)],
     "wb_robot_get_tune": [_vp, C.POINTER(WbTune)],
     "wb_plan_create": [C.POINTER(_vp), C.POINTER(C.c_int64), C.c_int32, C.POINTER(WbTune), C.POINTER(_vp)],

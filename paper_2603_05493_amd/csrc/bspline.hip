@@ -21,48 +21,10 @@
 // its knot, reading the trajectory's samples through the cache, and writes
 // its gradient (contiguous across the wavefront), optionally taking the
 // gradient step.  Both kernels are bound by HBM.
-#include "wb_internal.h"
+#include "spline.h"
 
 namespace wb {
 
-// Window gradient of one sample at alpha: B(alpha)^T [gp, gv, ga] added to
-// (r0, r1, r2, r3), with gv, ga already divided by dt, dt^2.
-__device__ __forceinline__ void window_grad(float alpha, float gp, float gv, float ga, float &r0, float &r1,
-                                            float &r2, float &r3) {
-    // gradient on the monomial coefficients (alpha^3, alpha^2, alpha, 1)
-    const float a2 = alpha * alpha;
-    const float d3 = gp * a2 * alpha + gv * 3.f * a2 + ga * 6.f * alpha;
-    const float d2 = gp * a2 + gv * 2.f * alpha + ga * 2.f;
-    const float d1 = gp * alpha + gv;
-    const float d0 = gp;
-    // C^T: onto the window
-    r0 += (-d3 + 3.f * d2 - 3.f * d1 + d0) * (1.f / 6.f);
-    r1 += (3.f * d3 - 6.f * d2 + 4.f * d0) * (1.f / 6.f);
-    r2 += (-3.f * d3 + 3.f * d2 + 3.f * d1 + d0) * (1.f / 6.f);
-    r3 += d3 * (1.f / 6.f);
-}
-
-// Knots of segment seg of one trajectory and joint, ghost knots blended in.
-// Every load is issued unconditionally (indices clamped, a missing initial
-// derivative read from theta0 with weight 0), so no load waits behind a
-// branch.
-__device__ __forceinline__ void segment_window(const float *__restrict__ Uj, int K, int seg, float th, float v,
-                                               float a, bool printed, float w[4]) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) w[m] = Uj[min(max(seg + m - 3, 0), K - 1)];
-    // ghost knots from the initial state: the paper's printed formulas, or
-    // the exact anchoring theta(0) = theta_0, theta_dot(0) = theta_dot_0,
-    // theta_ddot(0) = theta_ddot_0
-    const float g0 = printed ? th - a * (1.f / 6.f) : th - v + a * (1.f / 3.f);
-    const float g1 = printed ? th + v + a * (1.f / 3.f) : th - a * (1.f / 6.f);
-    const float g2 = printed ? th + 2.f * v + a * (11.f / 6.f) : th + v + a * (1.f / 3.f);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int e = seg + m;
-        const float f0 = e == 0 ? 1.f : 0.f, f1 = e == 1 ? 1.f : 0.f, f2 = e == 2 ? 1.f : 0.f;
-        w[m] = w[m] * (1.f - f0 - f1 - f2) + f0 * g0 + f1 * g1 + f2 * g2;
-    }
-}
 
 __global__ void __launch_bounds__(256) k_bspline_eval(int64_t T, int32_t K, int32_t n_interp, float dt,
                                                       int32_t printed, const float *__restrict__ U,
@@ -84,18 +46,15 @@ __global__ void __launch_bounds__(256) k_bspline_eval(int64_t T, int32_t K, int3
     const float th = th0[o0];
     const float v = pv[o0] * (dth0 ? dt : 0.f);
     const float a = pa[o0] * (ddth0 ? dt * dt : 0.f);
-    float w[4];
+    float w[4], c[4];
     segment_window(U + ((int64_t)j * T + traj) * K, K, seg, th, v, a, printed != 0, w);
-    // polynomial coefficients C w of alpha^3, alpha^2, alpha, 1
-    const float c3 = (-w[0] + 3.f * w[1] - 3.f * w[2] + w[3]) * (1.f / 6.f);
-    const float c2 = (3.f * w[0] - 6.f * w[1] + 3.f * w[2]) * (1.f / 6.f);
-    const float c1 = (-3.f * w[0] + 3.f * w[2]) * (1.f / 6.f);
-    const float c0 = (w[0] + 4.f * w[1] + w[2]) * (1.f / 6.f);
-    const float inv = 1.f / dt;
+    window_coefficients(w, c);
+    float p, pd, pdd;
+    sample_at(c, alpha, 1.f / dt, p, pd, pdd);
     const int64_t o = (int64_t)j * NB + b;
-    q[o] = ((c3 * alpha + c2) * alpha + c1) * alpha + c0;
-    if (qd) qd[o] = ((3.f * c3 * alpha + 2.f * c2) * alpha + c1) * inv;
-    if (qdd) qdd[o] = (6.f * c3 * alpha + 2.f * c2) * (inv * inv);
+    q[o] = p;
+    if (qd) qd[o] = pd;
+    if (qdd) qdd[o] = pdd;
 }
 
 // One lane per (joint, trajectory, control point), the control point
@@ -168,21 +127,13 @@ __global__ void __launch_bounds__(256) k_bspline_eval4(int32_t T, int32_t K, flo
     const float th = th0[o0];
     const float v = pv[o0] * (dth0 ? dt : 0.f);
     const float a = pa[o0] * (ddth0 ? dt * dt : 0.f);
-    float w[4];
+    float w[4], c[4];
     segment_window(U + o0 * K, K, seg, th, v, a, printed != 0, w);
-    const float c3 = (-w[0] + 3.f * w[1] - 3.f * w[2] + w[3]) * (1.f / 6.f);
-    const float c2 = (3.f * w[0] - 6.f * w[1] + 3.f * w[2]) * (1.f / 6.f);
-    const float c1 = (-3.f * w[0] + 3.f * w[2]) * (1.f / 6.f);
-    const float c0 = (w[0] + 4.f * w[1] + w[2]) * (1.f / 6.f);
+    window_coefficients(w, c);
     const float inv = 1.f / dt;
     float p[4], pd[4], pdd[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float al = 0.25f * i;
-        p[i] = ((c3 * al + c2) * al + c1) * al + c0;
-        pd[i] = ((3.f * c3 * al + 2.f * c2) * al + c1) * inv;
-        pdd[i] = (6.f * c3 * al + 2.f * c2) * (inv * inv);
-    }
+    for (int i = 0; i < 4; ++i) sample_at(c, 0.25f * i, inv, p[i], pd[i], pdd[i]);
     const int64_t o = (int64_t)j * NS * 4 + (int64_t)idx * 4;   // = j * T * H + traj * H + seg * 4
     *reinterpret_cast<float4 *>(q + o) = make_float4(p[0], p[1], p[2], p[3]);
     if (qd) *reinterpret_cast<float4 *>(qd + o) = make_float4(pd[0], pd[1], pd[2], pd[3]);

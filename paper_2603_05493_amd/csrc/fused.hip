@@ -51,6 +51,7 @@
 //   runs the cost head, and its tau-bar returns to each link as m_l tau-bar_j;
 //   the per-link adjoints (q-bar, qd-bar, qdd-bar) come back the same way,
 //   each scaled by m_l, and lane j writes joint j's outputs and step.
+#include "spline.h"
 #include "sweep.h"
 #include "tree.h"
 
@@ -62,11 +63,19 @@ namespace wb {
 // a valid state and store nothing.  The lane's link constants are read from
 // the lane tables at the point of use in every state (they stay in the L1
 // cache), so that no register holds them across the sweep.
-template <int NMAX, bool FULL, bool EXT>
+// SPL >= 1: the lane's joint position, velocity and acceleration are the
+// spline sample of state b (trajectory b / H, segment, quarter of the
+// interval) formed from the control points, with the arithmetic of the
+// B-spline kernels; the state arrays are not read and the state step is off.
+// SPL == 2: the sample's gradient also goes back onto its four-knot window
+// and is added to this group's partial sums gpart[d][K + 6] in LDS (one
+// group at a time per partial, states in a fixed order: deterministic).
+// With SPL the state is sample t of trajectory traj (b = traj * H + t).
+template <int NMAX, bool FULL, bool EXT, int SPL>
 __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t *tab, const DevFused &fz,
-                                              const TreeIO &io, const StepScalars &k, float4 *P, float4 *Bd,
-                                              uint16_t *list, int G, int grp, int glane, int64_t B, int64_t b,
-                                              bool valid) {
+                                              const TreeIO &io, const SplineIn &sp, const StepScalars &k,
+                                              float4 *P, float4 *Bd, uint16_t *list, float *gpart, int G, int grp,
+                                              int glane, int64_t B, int64_t b, bool valid, int traj, int t) {
     int gl = glane;
     asm volatile("" : "+v"(gl));   // keeps the table reads inside the state loop
     const int *li = fz.li;
@@ -77,7 +86,16 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     const int64_t jo = (int64_t)li[3 * 64 + gl] * B + b;
     const bool mim = EXT && fz.mimic;
     float th = 0.f, thd = 0.f, thdd = 0.f, mult = 1.f;
-    if (revolute) {
+    if (SPL > 0 && revolute) {
+        const int64_t o0 = (int64_t)li[3 * 64 + gl] * sp.T + traj;
+        const float t0 = sp.th0[o0];
+        const float v0 = sp.dth0 ? sp.dth0[o0] * sp.dt : 0.f;
+        const float a0 = sp.ddth0 ? sp.ddth0[o0] * (sp.dt * sp.dt) : 0.f;
+        float w[4], c[4];
+        segment_window(sp.U + o0 * sp.K, sp.K, t >> 2, t0, v0, a0, sp.printed != 0, w);
+        window_coefficients(w, c);
+        sample_at(c, 0.25f * (t & 3), 1.f / sp.dt, th, thd, thdd);
+    } else if (revolute) {
         th = io.q[jo];
         thd = io.qd[jo];
         thdd = io.qdd[jo];
@@ -246,6 +264,17 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     }
     // ---- outputs and the gradient step
     if (!valid) return;
+    if (SPL == 2 && revolute) {   // the sample's gradient onto its window of extended knots
+        const int seg = t >> 2;
+        const float inv = 1.f / sp.dt;
+        float r0 = 0.f, r1 = 0.f, r2 = 0.f, r3 = 0.f;
+        window_grad(0.25f * (t & 3), th_b, thd_b * inv, thdd_b * (inv * inv), r0, r1, r2, r3);
+        float *row = gpart + li[3 * 64 + gl] * (sp.K + 6) + seg;
+        row[0] += r0;
+        row[1] += r1;
+        row[2] += r2;
+        row[3] += r3;
+    }
     if (EXT && io.g_fext && act) {
         // -X*^T fb: moment part -R^T fb_w, force part -R^T (fb_l + fb_w x p)
         const V3 gn = mulT(R, fb.w), gf = mulT(R, fb.l + cross(fb.w, p));
@@ -258,7 +287,7 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
         if (io.g_q) io.g_q[jrow] = th_b;
         if (io.g_qd) io.g_qd[jrow] = thd_o;
         if (io.g_qdd) io.g_qdd[jrow] = thdd_o;
-        if (k.lr != 0.f) {
+        if (SPL == 0 && k.lr != 0.f) {
             if (mim) {   // the joint's own values (a link lane holds m_l q + o_l)
                 io.q[jrow] -= k.lr * th_b;
                 io.qd[jrow] -= k.lr * thd_o;
@@ -281,10 +310,10 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
 // Process `count` states starting at b0 of one robot with the 4 waves of
 // this workgroup, 64/G states per wavefront at a time; tab is the robot's
 // block table staged in LDS.
-template <int NMAX, bool EXT>
+template <int NMAX, bool EXT, int SPL>
 __device__ __forceinline__ void run_states(const DevRobot &rb, const uint16_t *tab, const DevFused &fz, const TreeIO &io,
-                                           const StepScalars &k, float4 *lds_wave, int G, int64_t B,
-                                           int64_t b0, int count) {
+                                           const SplineIn &sp, const StepScalars &k, float4 *lds_wave,
+                                           float *gparts, int G, int64_t B, int64_t b0, int count, int traj) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int per_wave = 64 / G, grp = lane / G, glane = lane - grp * G;
     const int SL = (rb.L + 1) * NMAX;
@@ -299,8 +328,21 @@ __device__ __forceinline__ void run_states(const DevRobot &rb, const uint16_t *t
         const int s = base + grp;
         const bool valid = s < count;
         const int64_t b = b0 + (valid ? s : base);
-        if (G == 64) iterate_state<NMAX, true, EXT>(rb, tab, fz, io, k, P, Bd, list, 64, 0, glane, B, b, valid);
-        else iterate_state<NMAX, false, EXT>(rb, tab, fz, io, k, P, Bd, list, G, grp, glane, B, b, valid);
+        float *gpart = SPL == 2 ? gparts + (wave * per_wave + grp) * rb.n * (sp.K + 6) : nullptr;
+        // SPL == 2: the workgroup's trajectory, sample s; SPL == 1: chunks
+        // span trajectories (the spline form keeps B below 2^31)
+        int tr = traj, t = valid ? s : base;
+        if (SPL == 1) {
+            const int bi = (int)b;
+            tr = bi / sp.H;
+            t = bi - tr * sp.H;
+        }
+        if (G == 64)
+            iterate_state<NMAX, true, EXT, SPL>(rb, tab, fz, io, sp, k, P, Bd, list, gpart, 64, 0, glane, B, b, valid,
+                                                tr, t);
+        else
+            iterate_state<NMAX, false, EXT, SPL>(rb, tab, fz, io, sp, k, P, Bd, list, gpart, G, grp, glane, B, b,
+                                                 valid, tr, t);
     }
 }
 
@@ -317,7 +359,43 @@ __device__ __forceinline__ void stage_table(const DevRobot &rb, uint16_t *tab) {
 // variant with external link forces and mimic joints, holds the forces, the
 // joint-to-link map and their adjoints as well: at 128 VGPRs it spilled ~48
 // registers, so it runs three wavefronts per SIMD (168 VGPRs) without spills.
-template <int NMAX, bool EXT>
+// The control-point gradient of the workgroup's trajectory (SPL == 2): the
+// groups' partial sums over the extended knots, added in a fixed order; knot
+// e = k + 3 is control point k, and the three copies of the final control
+// point add into it; then the step, plain or row-normalized (the row's sum
+// of squares taken by every lane of the row in the same order).
+__device__ __forceinline__ void spline_reduce_step(const SplineIn &sp, const float *gparts, float *gsum, int d,
+                                                   int nparts, int traj) {
+    const int KE = sp.K + 6;
+    for (int i = threadIdx.x; i < d * sp.K; i += 256) {
+        const int j = i / sp.K, kk = i - j * sp.K;
+        float g = 0.f;
+        for (int p = 0; p < nparts; ++p) {
+            const float *row = gparts + (p * d + j) * KE;
+            g += row[kk + 3];
+            if (kk == sp.K - 1) g += row[sp.K + 3] + row[sp.K + 4] + row[sp.K + 5];
+        }
+        gsum[i] = g;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < d * sp.K; i += 256) {
+        const int j = i / sp.K, kk = i - j * sp.K;
+        const float g = gsum[i];
+        const int64_t o = ((int64_t)j * sp.T + traj) * sp.K + kk;
+        if (sp.g_U) sp.g_U[o] = g;
+        if (sp.lr != 0.f) {
+            float step = sp.lr;
+            if (sp.rule == WB_STEP_ROW_RMS) {
+                float ss = 0.f;
+                for (int m = 0; m < sp.K; ++m) ss += gsum[j * sp.K + m] * gsum[j * sp.K + m];
+                step = ss > 0.f ? sp.lr * rsqrtf(ss / (float)sp.K) : 0.f;
+            }
+            sp.U[o] -= step * g;
+        }
+    }
+}
+
+template <int NMAX, bool EXT, int SPL>
 __global__ void __launch_bounds__(256, EXT ? 3 : 4) k_fused_step(FusedArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
@@ -331,9 +409,21 @@ __global__ void __launch_bounds__(256, EXT ? 3 : 4) k_fused_step(FusedArgs A) {
     const int64_t rem = A.B - b0;
     const int count = rem < A.chunk ? (int)rem : A.chunk;
     uint16_t *tab = reinterpret_cast<uint16_t *>(lds + 4 * SLW);
+    // the control-point partial sums follow the block table (n_blocks_pad is a multiple of 128)
+    float *gparts = reinterpret_cast<float *>(tab + A.rb.n_blocks_pad);
+    const int nparts = 256 / G, d = A.rb.n;
     stage_table(A.rb, tab);
+    if (SPL == 2)
+        for (int i = threadIdx.x; i < nparts * d * (A.sp.K + 6); i += 256) gparts[i] = 0.f;
     __syncthreads();
-    run_states<NMAX, EXT>(A.rb, tab, A.fz, A.io, A.k, lds + wave * SLW, G, A.io.ld, b0, count);
+    // with SPL == 2 each workgroup owns one trajectory (chunk == H)
+    const int traj = SPL == 2 ? chunk : 0;
+    run_states<NMAX, EXT, SPL>(A.rb, tab, A.fz, A.io, A.sp, A.k, lds + wave * SLW, gparts, G, A.io.ld, b0, count,
+                               traj);
+    if (SPL == 2) {
+        __syncthreads();
+        spline_reduce_step(A.sp, gparts, gparts + nparts * d * (A.sp.K + 6), d, nparts, traj);
+    }
 }
 
 // Persistent launch over an uneven batch of robots: workgroup w processes
@@ -358,19 +448,25 @@ __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
             staged = item.tree;
         }
         // a fixed region per wave, sized for the plan's largest tree
-        run_states<NMAX, EXT>(T.rb, tab, T.fz, A.io[item.tree], A.k, lds + wave * A.wave_stride, G,
-                              A.io[item.tree].ld,
-                              item.b0, item.count);
+        run_states<NMAX, EXT, 0>(T.rb, tab, T.fz, A.io[item.tree], SplineIn{}, A.k, lds + wave * A.wave_stride,
+                                 nullptr, G, A.io[item.tree].ld,
+                              item.b0, item.count, 0);
     }
 }
 
 template <int NMAX>
 static hipError_t launch_fused_t(const FusedArgs &a, hipStream_t s) {
-    const size_t lds = fused_lds_bytes(a.rb.L, NMAX, a.rb.list_cap, a.lanes_per_state, a.rb.n_blocks_pad);
+    size_t lds = fused_lds_bytes(a.rb.L, NMAX, a.rb.list_cap, a.lanes_per_state, a.rb.n_blocks_pad);
     const unsigned nwg = (unsigned)((a.B + a.chunk - 1) / a.chunk);
-    if (a.io.f_ext || a.io.g_fext || a.fz.mimic)
-        hipLaunchKernelGGL((k_fused_step<NMAX, true>), dim3(nwg), dim3(256), lds, s, a);
-    else hipLaunchKernelGGL((k_fused_step<NMAX, false>), dim3(nwg), dim3(256), lds, s, a);
+    const bool reduce = a.sp.U && (a.sp.g_U || a.sp.lr != 0.f);
+    if (reduce) {
+        lds += spline_lds_bytes(a.lanes_per_state, a.rb.n, a.sp.K);
+        hipLaunchKernelGGL((k_fused_step<NMAX, false, 2>), dim3(nwg), dim3(256), lds, s, a);
+    } else if (a.sp.U)
+        hipLaunchKernelGGL((k_fused_step<NMAX, false, 1>), dim3(nwg), dim3(256), lds, s, a);
+    else if (a.io.f_ext || a.io.g_fext || a.fz.mimic)
+        hipLaunchKernelGGL((k_fused_step<NMAX, true, 0>), dim3(nwg), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_fused_step<NMAX, false, 0>), dim3(nwg), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 

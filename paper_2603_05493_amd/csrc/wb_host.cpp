@@ -430,6 +430,7 @@ void fill_info(const Tables &T, wb_robot_info *info) {
     info->n_blocks = T.n_blocks;
     info->max_spheres_per_link = T.nmax;
     info->fused_supported = T.fused;
+    info->mimic = T.simple ? 0 : 1;
     info->kinematics_supported = T.kin;
 }
 
@@ -921,6 +922,60 @@ int wb_wholebody_step(const wb_robot *robot, int64_t B, int64_t ld, float *q, fl
     a.io = wb::TreeIO{q, qd, qdd, w, tau, cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd, f_ext, g_fext, ld};
     a.k = wb::StepScalars{torque_weight, margin, hinge_weight, lr};
     return finish(wb::launch_fused(a, stream), "wb_wholebody_step launch");
+}
+
+int wb_wholebody_step_bspline(const wb_robot *robot, int64_t T, int32_t K, float dt, int32_t reading,
+                              float *U, const float *theta0, const float *dtheta0, const float *ddtheta0,
+                              const float *w, float torque_weight, float margin, float hinge_weight, float *g_U,
+                              float lr, int32_t step_rule, float *tau, float *cost, float *max_pen, int32_t *argmax,
+                              int32_t *n_coll, float *g_q, float *g_qd, float *g_qdd, hipStream_t stream) {
+    WB_TRY(check_robot(robot));
+    WB_TRY(check_bspline(T, robot->T.n, K, 4, dt));
+    if (reading != WB_GHOST_EXACT && reading != WB_GHOST_PRINTED)
+        return fail(WB_ERR_INVALID_ARG, "unknown ghost-knot reading %d", reading);
+    if (!robot->fz.supported)
+        return fail(WB_ERR_UNSUPPORTED, "the fused iteration needs <= 64 links and sweep tables within %zu bytes of LDS",
+                    wb::LDS_LIMIT);
+    if (robot->fz.mimic)
+        return fail(WB_ERR_UNSUPPORTED, "the spline-sampling form takes robots without mimic joints");
+    if (!std::isfinite(torque_weight) || !std::isfinite(margin) || !std::isfinite(hinge_weight) || !std::isfinite(lr))
+        return fail(WB_ERR_INVALID_ARG, "weights, margin and lr must be finite");
+    if (step_rule != WB_STEP_PLAIN && step_rule != WB_STEP_ROW_RMS)
+        return fail(WB_ERR_INVALID_ARG, "unknown step rule %d", step_rule);
+    const int64_t H = (int64_t)(K + 3) * 4, B = T * H;
+    const bool reduce = g_U || lr != 0.0f;
+    const int G = robot->tune.lanes_per_state;
+    if (reduce && wb::fused_lds_bytes(robot->T.L, robot->T.nmax, robot->T.list_cap, G, (int)robot->T.blocks.size()) +
+                          wb::spline_lds_bytes(G, robot->T.n, K) > wb::LDS_LIMIT)
+        return fail(WB_ERR_UNSUPPORTED, "the control-point gradient of %d joints x %d control points does not fit "
+                    "the workgroup's LDS; take the per-sample gradients and wb_bspline_backward", robot->T.n, K);
+    if (B == 0 || robot->T.n == 0) return WB_OK;
+    WB_TRY(check_ptr(U, "U", true));
+    WB_TRY(check_ptr(g_U, "g_U", false));
+    WB_TRY(check_ptr(theta0, "theta0", true));
+    WB_TRY(check_ptr(dtheta0, "dtheta0", false));
+    WB_TRY(check_ptr(ddtheta0, "ddtheta0", false));
+    WB_TRY(check_ptr(w, "w", false));
+    WB_TRY(check_ptr(tau, "tau", false));
+    WB_TRY(check_ptr(cost, "cost", false));
+    WB_TRY(check_ptr(max_pen, "max_pen", false));
+    WB_TRY(check_ptr(argmax, "argmax", false));
+    WB_TRY(check_ptr(n_coll, "n_coll", false));
+    WB_TRY(check_ptr(g_q, "g_q", false));
+    WB_TRY(check_ptr(g_qd, "g_qd", false));
+    WB_TRY(check_ptr(g_qdd, "g_qdd", false));
+    wb::FusedArgs a{};
+    a.rb = robot->dev;
+    a.fz = robot->fz;
+    a.B = B;
+    // with the control-point gradient reduced in LDS a workgroup owns one whole trajectory
+    a.chunk = reduce ? (int32_t)H : small_batch_chunk(robot->tune, B, robot->cus);
+    a.lanes_per_state = G;
+    a.io = wb::TreeIO{nullptr, nullptr, nullptr, w, tau, cost, max_pen, argmax, n_coll, g_q, g_qd, g_qdd,
+                      nullptr, nullptr, B};
+    a.sp = wb::SplineIn{U, theta0, dtheta0, ddtheta0, (int32_t)T, K, (int32_t)H, reading, dt, g_U, lr, step_rule};
+    a.k = wb::StepScalars{torque_weight, margin, hinge_weight, 0.0f};
+    return finish(wb::launch_fused(a, stream), "wb_wholebody_step_bspline launch");
 }
 
 int wb_robot_set_tune(wb_robot *robot, const wb_tune *tune) {

@@ -98,11 +98,28 @@ struct StepScalars {
     float torque_weight, margin, hinge_weight, lr;
 };
 
+// The spline-sampling form of the fused iteration: its states are the
+// samples of uniform cubic B-splines (four per knot interval), formed in the
+// kernel from the control points instead of read from q, qd, qdd.
+struct SplineIn {
+    float *U;                              // [d][T][K] control points, or null (states from io.q, qd, qdd)
+    const float *th0, *dth0, *ddth0;       // [d][T] initial states (dth0, ddth0 may be null: at rest)
+    int32_t T, K, H, printed;              // trajectories, control points, samples per trajectory, ghost reading
+    float dt;
+    // the control-point gradient reduced in the kernel (each workgroup owns
+    // whole trajectories), then the step: g_U [d][T][K] (may be null), lr,
+    // step rule (WB_STEP_*)
+    float *g_U;
+    float lr;
+    int32_t rule;
+};
+
 // Arguments of the single-robot fused kernel (by value).
 struct FusedArgs {
     DevRobot rb;
     DevFused fz;
     TreeIO io;
+    SplineIn sp;
     StepScalars k;
     int64_t B;                // states (the arrays' row length is io.ld)
     int32_t chunk;            // states per workgroup
@@ -198,6 +215,12 @@ __host__ __device__ inline size_t tab_lds_bytes(int n_blocks_pad) { return (size
 // four wavefronts' group regions, then the block table.
 inline size_t fused_lds_bytes(int L, int nmax, int list_cap, int G, int n_blocks_pad) {
     return (size_t)4 * (64 / G) * group_lds_bytes(L, nmax, list_cap) + tab_lds_bytes(n_blocks_pad);
+}
+// LDS of the in-kernel control-point gradient beyond the fused kernel's:
+// one partial sum per group of lanes (4 * 64 / G of them) over the
+// d x (K + 6) extended knots, then the d x K reduced gradient.
+inline size_t spline_lds_bytes(int G, int d, int K) {
+    return ((size_t)(256 / G) * (K + 6) + (size_t)K) * d * 4;
 }
 constexpr size_t LDS_LIMIT = 65536;
 // Sphere slots per link the fused kernels are instantiated for.

@@ -188,15 +188,28 @@ class BsplineIteration:
     U [d][T][K] control points (updated in place when stepping, by the
     plain or the row-normalized rule); theta0, dtheta0, ddtheta0 [d][T] the
     initial state of each trajectory; the samples are the states
-    b = traj * H + t of the fused iteration.
+    b = traj * H + t of the fused iteration.  Three forms: two_launch
+    (wb_bspline_eval writes the samples, the fused iteration reads them,
+    wb_bspline_backward reduces their gradients and steps), fused_sampling
+    (the fused kernel forms the samples itself, wb_bspline_backward
+    follows) and one_launch (wb_wholebody_step_bspline does all of it,
+    reducing the control-point gradient inside the kernel; per-sample
+    outputs only with sample_outputs).
     """
 
     def __init__(self, robot: wb.Robot, U: torch.Tensor, theta0: torch.Tensor,
                  dtheta0: Optional[torch.Tensor] = None, ddtheta0: Optional[torch.Tensor] = None,
                  dt: float = 0.05, n_interp: int = 4, reading: int = wb.GHOST_EXACT,
                  w: Optional[torch.Tensor] = None, torque_weight: float = 1e-3, margin: float = 0.01,
-                 hinge_weight: float = 1.0, lr: float = 0.0, step_rule: int = wb.STEP_PLAIN):
+                 hinge_weight: float = 1.0, lr: float = 0.0, step_rule: int = wb.STEP_PLAIN,
+                 form: Optional[str] = None, sample_outputs: bool = True):
         d, T, K = U.shape
+        if form is None:   # the fastest form the robot and the sampling allow
+            form = "fused_sampling" if n_interp == 4 and not robot.has_mimic else "two_launch"
+        if form not in ("two_launch", "fused_sampling", "one_launch"):
+            raise ValueError(f"unknown form {form!r}")
+        if form != "two_launch" and n_interp != 4:
+            raise ValueError("the fused forms take four samples per knot interval")
         if d != robot.n_dof:
             raise ValueError(f"U has {d} joints, the robot {robot.n_dof}")
         self.U, self.theta0, self.dtheta0, self.ddtheta0 = U, theta0, dtheta0, ddtheta0
@@ -207,13 +220,28 @@ class BsplineIteration:
         e = lambda *shape: torch.empty(shape, dtype=torch.float32, device=U.device)
         self.q, self.qd, self.qdd = e(d, B), e(d, B), e(d, B)
         self.fused = FusedIteration(robot, B, w=w, torque_weight=torque_weight, margin=margin,
-                                    hinge_weight=hinge_weight, lr=0.0, outputs=True)
+                                    hinge_weight=hinge_weight, lr=0.0,
+                                    outputs=form != "one_launch" or sample_outputs)
         self.g_U = e(d, T, K)
+        self.form = form
 
     def run(self, step: bool = True) -> None:
-        wb.wb_bspline_eval(self.U, self.theta0, self.dt, self.n_interp, self.dtheta0, self.ddtheta0,
-                           q=self.q, qd=self.qd, qdd=self.qdd, reading=self.reading)
-        self.fused.run(self.q, self.qd, self.qdd, step=False)
         f = self.fused
+        if self.form == "one_launch":   # samples, iteration, control-point gradient and step in one kernel
+            wb.wb_wholebody_step_bspline(f.robot, self.U, self.theta0, self.dt, self.dtheta0, self.ddtheta0,
+                                         self.reading, f.w, f.tw, f.margin, f.hw, g_U=self.g_U,
+                                         lr=self.lr if step else 0.0, step_rule=self.step_rule, tau=f.tau,
+                                         cost=f.cost, max_pen=f.max_pen, argmax=f.argmax, n_coll=f.n_coll, g_q=f.g_q,
+                                         g_qd=f.g_qd, g_qdd=f.g_qdd)
+            return
+        if self.form == "fused_sampling":   # the samples are formed inside the fused kernel
+            wb.wb_wholebody_step_bspline(f.robot, self.U, self.theta0, self.dt, self.dtheta0, self.ddtheta0,
+                                         self.reading, f.w, f.tw, f.margin, f.hw, tau=f.tau, cost=f.cost,
+                                         max_pen=f.max_pen, argmax=f.argmax, n_coll=f.n_coll, g_q=f.g_q,
+                                         g_qd=f.g_qd, g_qdd=f.g_qdd)
+        else:
+            wb.wb_bspline_eval(self.U, self.theta0, self.dt, self.n_interp, self.dtheta0, self.ddtheta0,
+                               q=self.q, qd=self.qd, qdd=self.qdd, reading=self.reading)
+            f.run(self.q, self.qd, self.qdd, step=False)
         wb.wb_bspline_backward(self.K, self.T, self.dt, self.n_interp, g_q=f.g_q, g_qd=f.g_qd, g_qdd=f.g_qdd,
                                g_U=self.g_U, lr=self.lr if step else 0.0, U=self.U, step_rule=self.step_rule)

@@ -83,6 +83,7 @@ class Robot:
         self.max_spheres_per_link = inf.max_spheres_per_link
         self.fused_supported = bool(inf.fused_supported)
         self.kinematics_supported = bool(inf.kinematics_supported)
+        self.has_mimic = bool(inf.mimic)
         self.n_tools = 0
         self.handle = None
         self.device = None
@@ -486,6 +487,35 @@ def wb_wholebody_step(robot: Robot, q, qd, qdd, w=None, torque_weight=0.0, margi
                                   float(margin), float(hinge_weight), float(lr), _p(tau), _p(cost),
                                   _p(max_pen), _p(argmax), _p(n_coll), _p(g_q), _p(g_qd), _p(g_qdd),
                                   _p(f_ext), _p(g_fext), _stream()))
+
+
+def wb_wholebody_step_bspline(robot: Robot, U, theta0, dt: float, dtheta0=None, ddtheta0=None,
+                              reading: int = GHOST_EXACT, w=None, torque_weight=0.0, margin=0.0, hinge_weight=0.0,
+                              g_U=None, lr: float = 0.0, step_rule: int = STEP_PLAIN, tau=None, cost=None,
+                              max_pen=None, argmax=None, n_coll=None, g_q=None, g_qd=None, g_qdd=None):
+    """The B-spline iteration in one launch: the fused iteration over the
+    four-per-interval samples of the splines U [d][T][K] (formed in the
+    kernel), and with g_U or lr != 0 the control-point gradient reduced in
+    the kernel and the step on U; per-state outputs as wb_wholebody_step for
+    the T * H states, None to skip."""
+    d, T, K = U.shape
+    H = bspline_horizon(K, 4)
+    B = T * H
+    _chk(U, "U", (d, T, K), device=robot.device)
+    for t, nm in ((theta0, "theta0"), (dtheta0, "dtheta0"), (ddtheta0, "ddtheta0")):
+        _chk(t, nm, (d, T), device=robot.device)
+    for t, nm in ((w, "w"), (tau, "tau"), (g_q, "g_q"), (g_qd, "g_qd"), (g_qdd, "g_qdd")):
+        _chk(t, nm, (d, B), device=robot.device)
+    _chk(cost, "cost", (B,), device=robot.device)
+    _chk(max_pen, "max_pen", (B,), device=robot.device)
+    _chk(argmax, "argmax", (B,), torch.int32, device=robot.device)
+    _chk(n_coll, "n_coll", (B,), torch.int32, device=robot.device)
+    _chk(g_U, "g_U", (d, T, K), device=robot.device)
+    check(lib().wb_wholebody_step_bspline(robot.handle, T, K, float(dt), int(reading), _p(U), _p(theta0),
+                                          _p(dtheta0), _p(ddtheta0), _p(w), float(torque_weight), float(margin),
+                                          float(hinge_weight), _p(g_U), float(lr), int(step_rule), _p(tau), _p(cost),
+                                          _p(max_pen), _p(argmax), _p(n_coll), _p(g_q), _p(g_qd), _p(g_qdd),
+                                          _stream()))
 
 
 class Plan:

@@ -239,3 +239,85 @@ def test_control_point_iteration_matches_oracle(oracle, label, factory, T, K):
     print(label, "row-normalized step, max |U - U_oracle|", float(err.max()), "worst err/bound",
           float((err / bound).max()), flush=True)
     assert np.all(err <= bound)
+
+
+@pytest.mark.parametrize("label,factory,T,K,reading", [
+    ("chain7", lambda: synth.serial_chain(7, 5, seed=0), 24, 9, "exact"),
+    ("humanoid48_T512", lambda: synth.humanoid48(seed=0), 512, 9, "exact"),
+    ("tree23_printed", lambda: synth.random_tree(23, 6, seed=2), 37, 5, "printed")])
+def test_fused_sampling_matches_the_two_launch_form(oracle, label, factory, T, K, reading):
+    """The one-launch form's control-point gradient (reduced in the kernel)
+    matches the two-launch form's; the fused kernel forming the spline samples itself
+    (wb_wholebody_step_bspline) gives the two-launch form's results (sampling
+    kernel, then the fused iteration on the written states) to the parity
+    tolerance -- one sampling routine serves both, but the compiler may
+    contract its multiply-adds differently in the two kernels, so not bit
+    for bit -- and matches the oracle at the oracle's samples."""
+    from paper_2603_05493_amd import wb
+    from paper_2603_05493_amd.iteration import BsplineIteration
+    rb = factory()
+    d = rb.n_dof
+    rng = np.random.default_rng(17)
+    U = dev_U(synth._f32(rng.uniform(-1.2, 1.2, (T, d, K))))
+    th0 = synth._f32(rng.uniform(-1.2, 1.2, (T, d)))
+    v0 = synth._f32(rng.normal(scale=0.5, size=(T, d)))
+    a0 = synth._f32(rng.normal(scale=0.5, size=(T, d)))
+    r = wb.Robot(rb).to_device("cuda:0")
+    rd = wb.GHOST_EXACT if reading == "exact" else wb.GHOST_PRINTED
+    its = [BsplineIteration(r, U.clone(), dev_init(th0), dev_init(v0), dev_init(a0), dt=DT, n_interp=4, reading=rd,
+                            torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=0.0, form=f)
+           for f in ("two_launch", "fused_sampling", "one_launch")]
+    for it in its:
+        it.run(step=False)
+    torch.cuda.synchronize()
+    a, b, c = its
+    # the one-launch form reduces the same per-sample gradients in the kernel
+    e_gU = P.normwise(host_U(c.g_U), host_U(a.g_U), floor=1e-6).max()
+    print(label, f"one launch: g_U against the two-launch form {e_gU:.3g}", flush=True)
+    assert e_gU < P.TOL
+    assert torch.equal(c.fused.cost, b.fused.cost) and torch.equal(c.fused.g_q, b.fused.g_q)
+    H = bs.horizon(K, 4)
+    same = {k: bool(torch.equal(getattr(a.fused, k), getattr(b.fused, k)))
+            for k in ("cost", "max_pen", "argmax", "n_coll", "tau", "g_q", "g_qd", "g_qdd")}
+    print(label, "bitwise equal outputs:", same, "g_U equal:", bool(torch.equal(a.g_U, b.g_U)), flush=True)
+    for k in ("tau", "g_qd", "g_qdd"):
+        assert P.normwise(P.host(b.fused.__dict__[k]), P.host(a.fused.__dict__[k]), floor=1e-6).max() < P.TOL, k
+    # against the oracle at its own samples, every state
+    Th = bs.evaluate(host_U(U), th0, v0, a0, DT, 4, reading)
+    q, qd, qdd = (Th[..., c].reshape(T * H, d) for c in range(3))
+    ref = P.oracle_iteration(oracle, rb, q, qd, qdd, None, 1e-3, 0.01, 1.0)
+    pens = oracle.self_collision_pens(rb, ref["c"])
+    gq = P.check_grad_q(oracle, rb, q, ref, P.host(b.fused.g_q), b.fused.argmax.cpu().numpy(), 0.01, pens=pens)
+    e_tau = P.normwise(P.host(b.fused.tau), ref["tau"], floor=1e-3).max()
+    e_cost = (np.abs(P.host(b.fused.cost) - ref["cost"]) / P.cost_scale(ref, None, 1e-3, 0.01)).max()
+    print(label, f"fused sampling vs oracle: e_tau={e_tau:.3g} e_cost={e_cost:.3g}",
+          " ".join(f"{k}={v}" for k, v in gq.items()), flush=True)
+    assert e_tau < P.TOL and e_cost < P.TOL
+
+
+@pytest.mark.parametrize("rule", ["plain", "row_rms"])
+def test_one_launch_step(rule):
+    """Stepping in the kernel: U after an iteration of the one-launch form is
+    U0 moved by the step rule along the kernel's own control-point gradient
+    (which matches the two-launch form's, checked above)."""
+    from oracle import bspline as obs
+    from paper_2603_05493_amd import wb
+    from paper_2603_05493_amd.iteration import BsplineIteration
+    rb = synth.humanoid48(seed=0)
+    T, K, d = 64, 9, rb.n_dof
+    rng = np.random.default_rng(21)
+    U = dev_U(synth._f32(rng.uniform(-1.2, 1.2, (T, d, K))))
+    th0 = dev_init(synth._f32(rng.uniform(-1.2, 1.2, (T, d))))
+    r = wb.Robot(rb).to_device("cuda:0")
+    lr, sr = (1e-2, wb.STEP_ROW_RMS) if rule == "row_rms" else (1e-7, wb.STEP_PLAIN)
+    it = BsplineIteration(r, U.clone(), th0, None, None, dt=DT, n_interp=4, torque_weight=1e-3, margin=0.01,
+                          hinge_weight=1.0, lr=lr, step_rule=sr, form="one_launch", sample_outputs=False)
+    U0 = it.U.clone()
+    it.run(step=True)
+    torch.cuda.synchronize()
+    assert not torch.equal(it.U, U0)
+    if rule == "plain":
+        _assert_step(it.U, U0, lr, it.g_U)
+    else:
+        expect = obs.row_rms_step(host_U(U0), host_U(it.g_U), lr)
+        np.testing.assert_allclose(host_U(it.U), expect, rtol=0, atol=1e-6)
