@@ -185,6 +185,8 @@ def parse():
                     help="skip the kinematics-outputs line (tool poses, CoM, Jacobians)")
     ap.add_argument("--no-ext", dest="ext", action="store_false",
                     help="skip the line of the fused variant with mimic joints and external forces")
+    ap.add_argument("--no-paper-scale", dest="paper_scale", action="store_false",
+                    help="skip the 162k-pair humanoid's kinematics and self-collision line")
     ap.add_argument("--no-edt", dest="edt", action="store_false",
                     help="skip the distance-transform line")
     ap.add_argument("--no-bspline", dest="bspline", action="store_false",
@@ -427,6 +429,8 @@ def main():
         out["uneven_batch"] = bench_uneven(args)
     if args.ext:
         out["ext_variant"] = bench_ext_variant(args, st)
+    if args.paper_scale:
+        out["paper_scale_selfcollision"] = bench_paper_scale(args)
     if args.kinematics and robot.kinematics_supported:
         out["kinematics"] = bench_kinematics(args, robot, q0)
     if args.edt:
@@ -560,6 +564,69 @@ def trajectory_workgroup_probe(robot, B: int, H: int, reps: int = 50):
     return res
 
 
+def bench_paper_scale(args, batches=(1000, 3072), reps: int = 20):
+    """Kinematics and self-collision at the paper's self-collision scale: the
+    48-DoF humanoid with 588 spheres (162,432 checked pairs, up to 12 per
+    link) at the paper's kinematics batch of 1000 states and at one GPU's
+    3072-state share.  Forward: FK sphere centres (no link poses) and the
+    self-collision sweep; forward + backward: FK with poses, the sweep, the
+    hinge adjoint and the FK adjoint.  The sweep is also timed alone in each
+    of its two forms (one state per wavefront; one state per workgroup with
+    its blocks over four wavefronts and a second reduce).  HIP events on the
+    launching stream."""
+    import torch
+    from paper_2603_05493_amd import synth, wb
+    rb = synth.humanoid48_paper_scale()
+    r = wb.Robot(rb).to_device("cuda:0")
+    out = {"robot": "humanoid48, 588 spheres", "pairs": int(r.n_pairs), "spheres_per_link_max": r.max_spheres_per_link}
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    for B in batches:
+        st = synth.states(rb, B, seed=41, q_range=1.5)
+        q = torch.from_numpy(np.ascontiguousarray(st.q.T.astype(np.float32))).cuda()
+        S, L = r.n_spheres, r.n_links
+        sph = torch.empty((S, 3, B), device="cuda")
+        pose = torch.empty((L, 12, B), device="cuda")
+        mp = torch.empty(B, device="cuda")
+        am = torch.empty(B, dtype=torch.int32, device="cuda")
+        nc = torch.empty(B, dtype=torch.int32, device="cuda")
+        g_cost = torch.ones(B, device="cuda")
+        g_sph = torch.empty((S, 3, B), device="cuda")
+        g_q = torch.empty((r.n_dof, B), device="cuda")
+        ws = r.workspace(B)
+        fwd = lambda: (wb.wb_fk(r, q, spheres=sph, want_pose=False), wb.wb_self_collision(r, sph, mp, am, nc))
+
+        def fwd_bwd():
+            wb.wb_fk(r, q, link_pose=pose, spheres=sph)
+            wb.wb_self_collision(r, sph, mp, am, nc)
+            wb.wb_self_collision_backward(r, sph, am, mp, 0.01, g_cost, g_sph)
+            wb.wb_fk_backward(r, q, g_spheres=g_sph, link_pose=pose, g_q=g_q, workspace=ws)
+
+        t_f, t_fb = timed(fwd), timed(fwd_bwd)
+        forms = {}
+        for name, below in (("wave_per_state", 0), ("workgroup_per_state", 1 << 40)):
+            r.set_sweep_split(below)
+            forms[name] = timed(lambda: wb.wb_self_collision(r, sph, mp, am, nc)) * 1e6
+        r.set_sweep_split(-1)
+        out[f"B{B}"] = {"states": B, "forward": {"states_per_s": B / t_f, "us": t_f * 1e6,
+                                                  "pairs_per_s": B * r.n_pairs / t_f},
+                        "forward_backward": {"states_per_s": B / t_fb, "us": t_fb * 1e6},
+                        "sweep_us": forms, "sweep_form_by_default": "workgroup_per_state"
+                        if B < 16 * torch.cuda.get_device_properties(0).multi_processor_count else "wave_per_state"}
+    return out
+
+
 def bench_ext_variant(args, st, reps: int = 50):
     """The fused iteration's variant with mimic joints and external link
     forces on the optimizer batch: the humanoid with each finger's distal
@@ -691,9 +758,11 @@ def bench_edt(args, reps: int = 20):
 
 def bench_uneven(args):
     """Random trees of 7/12/23/48 DoF with 8192/4096/2048/1024 states: one
-    persistent plan launch (plan shapes: narrowest lanes, one round per
-    work item, costs from the tuned table) replayed from a HIP graph,
-    against one plain launch sequence per tree."""
+    persistent plan launch (the trees' shapes measured inside the plan by
+    the tuner when the table has them, else the narrowest lanes with one
+    round per work item; costs from the tuned table) replayed from a HIP
+    graph, against one plain launch sequence per tree; the plan kernel's
+    roofline from HIP events around eager launches."""
     import torch
     from paper_2603_05493_amd import synth, tune, wb
     from paper_2603_05493_amd.iteration import PlainIteration, PlanIteration
@@ -712,7 +781,8 @@ def bench_uneven(args):
     total = sum(Bs)
     kw = dict(torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=0.0)
 
-    shapes = [tune.plan_tune(r, table) for r in robots]
+    shapes = tune.plan_shapes(robots, Bs, table)
+    measured = tune.plan_key(robots, Bs) in table
     plan = PlanIteration(robots, Bs, tunes=shapes, outputs=False, **kw)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -731,6 +801,18 @@ def bench_uneven(args):
         g.replay()
     torch.cuda.synchronize()
     t_plan = (time.perf_counter() - t0) / args.steps
+    # the plan kernel alone, HIP events around each eager launch on its stream
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in ev:
+        e0.record(s)
+        plan.run(states)
+        e1.record(s)
+    torch.cuda.synchronize()
+    k_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    flop = sum(algorithmic_flop_per_state(r.n_links, r.n_spheres, r.n_pairs, r.n_dof) * B
+               for r, B in zip(robots, Bs))
+    ach = flop / (k_ms * 1e-3) / 1e12
 
     plains = [PlainIteration(r, B, **kw) for r, B in zip(robots, Bs)]
     for _ in range(args.warmup):
@@ -748,7 +830,12 @@ def bench_uneven(args):
                            "items": plan.plan.n_items, "workgroups": plan.plan.n_workgroups},
             "plain_per_tree": {"states_per_s": total / t_plain, "ms_per_step": t_plain * 1e3},
             "speedup": t_plain / t_plan,
-            "shapes": shapes}
+            "shapes": shapes, "shapes_from": "measured inside the plan" if measured else "fixed rule",
+            "roofline": {"bound": "alu", "kernel": "k_plan_step", "achieved": ach, "peak": PEAK_FP32_PUBLISHED_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / PEAK_FP32_PUBLISHED_TFLOPS,
+                         "frac_of_nonpacked_peak": ach / PEAK_FP32_NONPACKED_TFLOPS, "kernel_ms": k_ms,
+                         "flop_per_launch": flop,
+                         "work": "algorithmic: every checked pair once, no pruning credited; VJP 500 FLOP/link"}}
 
 
 if __name__ == "__main__":

@@ -62,7 +62,7 @@ enum wb_joint_type { WB_JOINT_FIXED = 0, WB_JOINT_REVOLUTE = 1 };
 
 /* Limits of this build (WB_ERR_UNSUPPORTED beyond them). */
 #define WB_MAX_LINKS 1024
-#define WB_MAX_SPHERES_PER_LINK 8
+#define WB_MAX_SPHERES_PER_LINK 64
 
 /*
  * Robot description (runtime robot binding, Sec. 6.3 "Our RNEA
@@ -81,7 +81,8 @@ enum wb_joint_type { WB_JOINT_FIXED = 0, WB_JOINT_REVOLUTE = 1 };
  *                  symmetric rotational inertia about the CoM in link axes.
  *   n_spheres      S >= 0; sphere_link[S] nondecreasing link indices;
  *   sphere[S][4]   centre (link frame) and radius (> 0) of each sphere;
- *                  at most WB_MAX_SPHERES_PER_LINK spheres per link.
+ *                  at most WB_MAX_SPHERES_PER_LINK spheres per link (the
+ *                  fused iteration takes at most 8).
  *   allow[L][L]    symmetric link-pair allow matrix for self-collision, or
  *                  NULL for the default: every pair of distinct links that
  *                  are not parent and child (Sec. 6.2 checks all sphere pairs
@@ -231,7 +232,15 @@ int wb_kinematics_backward(const wb_robot *robot, int64_t B, const float *q, con
 int wb_rnea(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const float *qd, const float *qdd,
             const float *f_ext, float *tau, float *cache, hipStream_t stream);
 
-/* Self-collision map-reduce (Sec. 6.2).  spheres[S][3][B] -> per state
+/* Self-collision map-reduce (Sec. 6.2; the paper splits the pairs of a
+ * large robot over blocks and reduces the block maxima in a second stage).
+ * Two forms, chosen by batch size: one state per wavefront (the states of a
+ * workgroup tile swept side by side), or -- for batches below the robot's
+ * split threshold, where one wavefront per state would leave the chip
+ * underfilled -- one state per workgroup, its link blocks dealt over four
+ * wavefronts that each compact and sweep their share, then a second reduce
+ * of the wavefronts' maxima, counts and argmax keys through LDS.  Both give
+ * the full sweep's results.  spheres[S][3][B] -> per state
  *   max_pen[B]  largest r_s + r_t - |c_s - c_t| over the checked pairs
  *               (-inf when the robot has no checked pair),
  *   argmax[B]   lowest pair index attaining it (-1 when there is none),
@@ -239,6 +248,11 @@ int wb_rnea(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const 
  * Any of the three outputs may be NULL to skip it (not all three). */
 int wb_self_collision(const wb_robot *robot, int64_t B, int64_t ld, const float *spheres, float *max_pen,
                       int32_t *argmax, int32_t *n_coll, hipStream_t stream);
+/* Split threshold of wb_self_collision for this robot: batches of fewer
+ * than `below` states take the one-state-per-workgroup form (set by the
+ * autotuner from measurement); below < 0 restores the default, 16 states
+ * per compute unit of the robot's device. */
+int wb_robot_set_sweep_split(wb_robot *robot, int64_t below);
 
 /* -------------------------------------------------------------- adjoints */
 

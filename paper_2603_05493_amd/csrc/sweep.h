@@ -292,6 +292,121 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const E *tab, co
     cnt_out = FULL ? cnt : group_reduce_sum_u(cnt, G);
 }
 
+// Sweep one state with the four wavefronts of a workgroup (the map of the
+// paper's two-stage self-collision split over wavefronts, then a second
+// reduce through LDS): the block table's 128-entry chunks are dealt
+// round-robin to the wavefronts (chunk c to wavefront c % 4); each compacts
+// and sweeps its chunks as sweep_state does with G = 64 (one chunk at a
+// time, so its list holds 128 entries), and the workgroup combines the
+// wavefronts' maxima, counts and argmax keys.  Pass 2, the seed block and
+// the tie rescan follow the single-wavefront rules with workgroup-wide
+// values, so the result is the full sweep's.  red: 8 words of LDS.  Every
+// thread of the workgroup must call this (it synchronizes the workgroup).
+__device__ __forceinline__ float wg_max4(float v, float *red, int wave, int lane) {
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    __syncthreads();
+    return m;
+}
+__device__ __forceinline__ int wg_min4(int v, int *red, int wave, int lane) {
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    const int m = min(min(red[0], red[1]), min(red[2], red[3]));
+    __syncthreads();
+    return m;
+}
+
+template <int NMAX, typename E>
+__device__ __forceinline__ void sweep_state_wg(const DevRobot &rb, const E *tab, const float4 *P, const float4 *Bd,
+                                               E *list, float *red, int wave, int lane, float &M_out, int &key_out,
+                                               unsigned &cnt_out) {
+    typedef PairCode<E> PC;
+    const int n = rb.n_blocks;
+    const int nb = (n + 127) / 128 * 128;   // <= n_blocks_pad
+    int *redi = reinterpret_cast<int *>(red);
+    float ext = 0.f;
+    for (int a = lane; a < rb.L; a += 64) {
+        const float4 c = Bd[a];
+        if (c.w > -1e29f)
+            ext = fmaxf(ext, __builtin_amdgcn_sqrtf(__builtin_fmaf(c.x, c.x, __builtin_fmaf(c.y, c.y, c.z * c.z))) + c.w);
+    }
+    const float eps = 4e-6f * (1.f + group_reduce_max(ext, 64));
+
+    float best = -INFINITY;
+    int best_code = -1;
+    bool tie = false;
+    unsigned cnt = 0;
+    for (int c0 = wave * 128; c0 < nb; c0 += 4 * 128) {
+        const int nl = compact_blocks<true>(tab, Bd, list, c0, c0 + 128, eps, 0.f, lane, 64, 0, ~0ull);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        sweep_rows<NMAX, true>(rb, P, list, nl, lane, 64, best, best_code, tie, cnt);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    float M = wg_max4(group_reduce_max(best, 64), red, wave, lane);
+    if (!(M >= 0.f) && n > 0) {
+        float lb = M;
+        if (lb == -INFINITY) {
+            // the block with the largest bound over the whole table (lowest index among equals)
+            float bmax = -INFINITY;
+            int bblk = INT_MAX;
+            for (int c0 = wave * 128; c0 < nb; c0 += 4 * 128)
+                for (int k = c0 + lane; k < min(c0 + 128, n); k += 64) {
+                    const int ab = tab[k];
+                    const float d = block_bound(Bd, PC::a(ab), PC::b(ab));
+                    if (d > bmax) {
+                        bmax = d;
+                        bblk = k;
+                    }
+                }
+            const float gbmax = wg_max4(group_reduce_max(bmax, 64), red, wave, lane);
+            const int cand = wg_min4(group_reduce_min(bmax == gbmax ? bblk : INT_MAX, 64), redi, wave, lane);
+            float seed = -INFINITY;
+            if (cand != INT_MAX) {
+                const int ab = tab[cand];
+                const int a = PC::a(ab), bb = PC::b(ab);
+                for (int j = lane; j < NMAX * NMAX; j += 64) {
+                    const int i = j / NMAX, k = j - i * NMAX;
+                    seed = fmaxf(seed, pair_pen(P[a * NMAX + i], P[bb * NMAX + k]));
+                }
+            }
+            lb = group_reduce_max(seed, 64);   // the same in every wavefront
+        }
+        const float theta1 = lb - eps;
+        for (int c0 = wave * 128; c0 < nb; c0 += 4 * 128) {
+            const int nl = compact_blocks<false>(tab, Bd, list, c0, c0 + 128, eps, theta1, lane, 64, 0, ~0ull);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            sweep_rows<NMAX, true>(rb, P, list, nl, lane, 64, best, best_code, tie, cnt);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        M = wg_max4(group_reduce_max(best, 64), red, wave, lane);
+    }
+    int key = INT_MAX;
+    const bool holder = best == M && M > -INFINITY && best_code >= 0;
+    const bool rescan = wg_min4(group_reduce_min((holder && tie) ? 0 : 1, 64), redi, wave, lane) == 0;
+    if (rescan) {
+        for (int c0 = wave * 128; c0 < nb; c0 += 4 * 128)
+            for (int blk = c0 + lane; blk < min(c0 + 128, n); blk += 64) {
+                const int ab = tab[blk];
+                key = min(key, block_min_key<NMAX>(rb, P, PC::a(ab), PC::b(ab), M));
+            }
+    } else if (holder) {
+        const int ab = best_code / NMAX;
+        key = row_min_key<NMAX>(rb, P, PC::a(ab), PC::b(ab), best_code - ab * NMAX, M);
+    }
+    M_out = M;
+    key_out = wg_min4(group_reduce_min(key, 64), redi, wave, lane);
+    // counts: the wavefronts' (uniform) counts summed in a fixed order
+    if (lane == 0) redi[4 + wave] = (int)cnt;
+    __syncthreads();
+    cnt_out = (unsigned)redi[4] + (unsigned)redi[5] + (unsigned)redi[6] + (unsigned)redi[7];
+    __syncthreads();
+}
+
 // Pair index (lexicographic in (s, t)) of a sphere key s*S + t.
 __device__ __forceinline__ int32_t pair_index(const DevRobot &rb, int key) {
     if (key == INT_MAX) return -1;

@@ -34,7 +34,7 @@ int hip_fail(hipError_t e, const char *what) {
 
 // Everything derived from a descriptor, in host memory.
 struct Tables {
-    int L = 0, n = 0, S = 0, nmax = 1, max_depth = 0, simple = 1;
+    int L = 0, n = 0, S = 0, nmax = 1, most = 1, max_depth = 0, simple = 1;   // nmax: slots per link; most: spheres
     std::vector<wb::LinkF> lf;
     std::vector<wb::LinkI> li;
     std::vector<float4> sph;
@@ -339,15 +339,27 @@ int build_tables(const wb_robot_desc *d, Tables &T) {
         if (count[l] == 0) T.li[l].sph_first = s;
         ++count[l];
     }
-    int nmax = 1;
+    int most = 1;
     for (int k = 0; k < L; ++k) {
         T.li[k].sph_count = count[k];
         if (count[k] == 0) T.li[k].sph_first = 0;
-        if (count[k] > nmax) nmax = count[k];
+        if (count[k] > most) most = count[k];
     }
-    if (nmax > WB_MAX_SPHERES_PER_LINK)
-        return fail(WB_ERR_UNSUPPORTED, "%d spheres on one link exceeds %d", nmax, WB_MAX_SPHERES_PER_LINK);
+    if (most > WB_MAX_SPHERES_PER_LINK)
+        return fail(WB_ERR_UNSUPPORTED, "%d spheres on one link exceeds %d", most, WB_MAX_SPHERES_PER_LINK);
+    // sphere slots per link: the most spheres on a link, rounded up above 8
+    // to a size the sweep kernels are built for
+    int nmax = most;
+    if (nmax > 8) {
+        const int sizes[] = {12, 16, 24, 32, 48, 64};
+        for (int z : sizes)
+            if (nmax <= z) {
+                nmax = z;
+                break;
+            }
+    }
     T.nmax = nmax;
+    T.most = most;
     if (wb::state_lds_bytes(L, nmax) + 16 * 128 > wb::LDS_LIMIT)
         return fail(WB_ERR_UNSUPPORTED, "(links + 1) x spheres-per-link slots (%d x %d) exceed the 64 KB LDS tile",
                     L + 1, nmax);
@@ -428,7 +440,7 @@ void fill_info(const Tables &T, wb_robot_info *info) {
     info->max_depth = T.max_depth;
     info->n_pairs = T.n_pairs;
     info->n_blocks = T.n_blocks;
-    info->max_spheres_per_link = T.nmax;
+    info->max_spheres_per_link = T.most;
     info->fused_supported = T.fused;
     info->mimic = T.simple ? 0 : 1;
     info->kinematics_supported = T.kin;
@@ -450,6 +462,7 @@ struct wb_robot {
     size_t o_tl = 0, o_to = 0, o_ta = 0;   // tool lanes, offsets and affects masks (WB_MAX_TOOLS each)
     int device = -1;
     int cus = 256;   // compute units of that device
+    int64_t sweep_split_below = -1;   // wb_self_collision splits states below this batch (-1: the default rule)
 };
 
 namespace {
@@ -713,6 +726,23 @@ int wb_rnea(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const 
                   "wb_rnea launch");
 }
 
+namespace {
+// wb_self_collision's form for a batch: one state per workgroup (its pairs
+// split over the four wavefronts) below the robot's threshold, one state
+// per wavefront above.  Default threshold: 16 states per compute unit (below
+// it one state per wavefront leaves most SIMDs with under four wavefronts).
+bool sweep_split(const wb_robot *r, int64_t B) {
+    const int64_t below = r->sweep_split_below >= 0 ? r->sweep_split_below : (int64_t)16 * r->cus;
+    return B < below;
+}
+}  // namespace
+
+int wb_robot_set_sweep_split(wb_robot *robot, int64_t below) {
+    WB_TRY(check_robot(robot));
+    robot->sweep_split_below = below < 0 ? -1 : below;
+    return WB_OK;
+}
+
 int wb_self_collision(const wb_robot *robot, int64_t B, int64_t ld, const float *spheres, float *max_pen,
                       int32_t *argmax, int32_t *n_coll, hipStream_t stream) {
     WB_TRY(check_robot(robot));
@@ -724,7 +754,8 @@ int wb_self_collision(const wb_robot *robot, int64_t B, int64_t ld, const float 
     WB_TRY(check_ptr(max_pen, "max_pen", false));
     WB_TRY(check_ptr(argmax, "argmax", false));
     WB_TRY(check_ptr(n_coll, "n_coll", false));
-    return finish(wb::launch_self_collision(robot->dev, B, ld, spheres, max_pen, argmax, n_coll, stream),
+    return finish(wb::launch_self_collision(robot->dev, B, ld, spheres, max_pen, argmax, n_coll,
+                                            sweep_split(robot, B), stream),
                   "wb_self_collision launch");
 }
 

@@ -175,8 +175,11 @@ hipError_t launch_rnea_backward_lanes(const DevRobot &rb, const DevFused &fz, in
                                       const float *q, const float *qd, const float *qdd, const float *f_ext,
                                       const float *g_tau, float *g_q, float *g_qd, float *g_qdd, float *g_fext,
                                       hipStream_t s);
+// split: one state per workgroup with its pairs over the four wavefronts
+// (else one state per wavefront).
 hipError_t launch_self_collision(const DevRobot &rb, int64_t B, int64_t ld, const float *spheres,
-                                 float *max_pen, int32_t *argmax, int32_t *n_coll, hipStream_t s);
+                                 float *max_pen, int32_t *argmax, int32_t *n_coll, bool split, hipStream_t s);
+size_t self_collision_wg_lds(int L, int nmax, int n_blocks_pad);
 hipError_t launch_self_collision_backward(const DevRobot &rb, int64_t B, int64_t ld, const float *spheres,
                                           const int32_t *argmax, const float *max_pen,
                                           float margin, const float *g_cost, float *g_sph,

@@ -337,6 +337,17 @@ def humanoid48(seed: int = 0, n_spheres: int = 240) -> Robot:
                    sl, np.concatenate(sp), np.concatenate(sr))
 
 
+# The 48-DoF humanoid at the paper's self-collision scale: 588 spheres (12
+# on the 31 longest links, 11 on the others) give 162,432 checked pairs, the
+# paper's 162k pairs of its 48-DoF humanoid.
+PAPER_SCALE_SPHERES = 588
+
+
+def humanoid48_paper_scale(seed: int = 0) -> Robot:
+    """humanoid48 with PAPER_SCALE_SPHERES spheres (162,432 checked pairs)."""
+    return humanoid48(seed=seed, n_spheres=PAPER_SCALE_SPHERES)
+
+
 def humanoid48_tool_links() -> dict:
     """Links of humanoid48 that carry its natural tool frames, by the
     generator's depth-first numbering: the last link of each leg (feet), of

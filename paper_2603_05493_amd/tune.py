@@ -10,7 +10,10 @@ state, which the multi-robot plan uses to balance its work list.
 
 Results are a JSON table keyed by ``Robot.topology_key()``:
     {key: {"lanes_per_state": G, "states_per_item": c, "ns_per_state": t,
-           "B": batch, "candidates": [[G, c, ns_per_state], ...]}}
+           "B": batch, "candidates": [[G, c, ns_per_state], ...],
+           "sweep_split_below": n, "sweep_us": [[B, wave form us, workgroup form us], ...]}}
+plus, for the uneven batch, an entry keyed by ``plan_key`` with the trees'
+shapes measured inside the plan (``tune_plan``).
 
 Usage (on the GPU):  python -m paper_2603_05493_amd.tune --out tuned.json
 """
@@ -78,13 +81,116 @@ def tune_robot(robot: wb.Robot, desc, B: int, lanes: Iterable[int] = LANES, item
             "candidates": cands}
 
 
+SWEEP_BATCHES = (256, 512, 1024, 2048, 3072, 4096, 6144, 8192, 16384)
+
+
+def tune_sweep_split(robot: wb.Robot, desc, batches: Iterable[int] = SWEEP_BATCHES, reps: int = 10,
+                     rounds: int = 3) -> Dict:
+    """The batch size below which wb_self_collision should sweep one state
+    per workgroup (its blocks over four wavefronts) instead of one state per
+    wavefront: both forms are timed at each batch size (interleaved rounds,
+    median), and the threshold is the smallest batch from which the
+    wavefront form stays at least as fast."""
+    batches = list(batches)
+    qs = _states(robot, desc, max(batches), seed=1)
+    _, sph = wb.wb_fk(robot, qs[0], want_pose=False)
+    outs = [torch.empty(max(batches), device=robot.device),
+            torch.empty(max(batches), dtype=torch.int32, device=robot.device),
+            torch.empty(max(batches), dtype=torch.int32, device=robot.device)]
+    times = {(B, f): [] for B in batches for f in (0, 1)}
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(rounds):
+        for B in batches:
+            sp = sph[:, :, :B].contiguous()
+            o = [t[:B] for t in outs]
+            for f in (0, 1):
+                robot.set_sweep_split((1 << 40) if f else 0)
+                for _ in range(2):
+                    wb.wb_self_collision(robot, sp, *o)
+                start.record()
+                for _ in range(reps):
+                    wb.wb_self_collision(robot, sp, *o)
+                stop.record()
+                torch.cuda.synchronize()
+                times[(B, f)].append(start.elapsed_time(stop) * 1e3 / reps)
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    below = 0
+    for B in batches:
+        if med[(B, 1)] < med[(B, 0)]:
+            below = B + 1   # the split form still wins at B
+    robot.set_sweep_split(below)
+    return {"sweep_split_below": below, "sweep_us": [[B, med[(B, 0)], med[(B, 1)]] for B in batches]}
+
+
 def apply(robot: wb.Robot, table: Dict) -> bool:
-    """Set the robot's tune record from a table entry for its topology, if any."""
+    """Set the robot's tune record (and its sweep split threshold) from a
+    table entry for its topology, if any."""
     e = table.get(robot.topology_key())
-    if e is None or e["lanes_per_state"] < robot.n_links:
+    if e is None:
+        return False
+    if "sweep_split_below" in e:
+        robot.set_sweep_split(int(e["sweep_split_below"]))
+    if "lanes_per_state" not in e or e["lanes_per_state"] < robot.n_links or not robot.fused_supported:
         return False
     robot.set_tune(e["lanes_per_state"], e["states_per_item"], e.get("ns_per_state", 0.0))
     return True
+
+
+def plan_key(robots, Bs) -> str:
+    """Table key of an uneven batch: its trees' topologies and batch sizes."""
+    return "plan:" + "|".join(f"{r.topology_key()}x{int(b)}" for r, b in zip(robots, Bs))
+
+
+def _plan_seconds(robots, Bs, shapes, states, reps: int = 20) -> float:
+    from .iteration import PlanIteration
+    it = PlanIteration(robots, Bs, tunes=shapes, outputs=False, torque_weight=1e-3, margin=0.01,
+                       hinge_weight=1.0, lr=0.0)
+    for _ in range(3):
+        it.run(states, step=False)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        it.run(states, step=False)
+    stop.record()
+    torch.cuda.synchronize()
+    it.plan.close()
+    return start.elapsed_time(stop) * 1e-3 / reps
+
+
+def tune_plan(robots, descs, Bs, table: Optional[Dict] = None, passes: int = 2, rounds: int = 3) -> Dict:
+    """Launch shapes of the trees of one uneven batch measured inside the
+    plan: starting from plan_tune's rule, each tree's candidates (every
+    group width that holds its links, one to three rounds of the workgroup
+    per work item) are timed with the others held fixed -- the whole plan
+    launch, median of `rounds` interleaved timings -- and the fastest kept;
+    `passes` sweeps over the trees."""
+    states = [_states(r, d, B, seed=7 + i) for i, (r, d, B) in enumerate(zip(robots, descs, Bs))]
+    shapes = [plan_tune(r, table) for r in robots]
+    history = []
+    for _ in range(passes):
+        for i, r in enumerate(robots):
+            cands = [(g, k * 4 * (64 // g)) for g in LANES if g >= r.n_links for k in (1, 2, 3)]
+            times = {c: [] for c in cands}
+            for _ in range(rounds):
+                for g, c in cands:
+                    trial = [dict(x) for x in shapes]
+                    trial[i].update(lanes_per_state=g, states_per_item=c)
+                    times[(g, c)].append(_plan_seconds(robots, Bs, trial, states))
+            med = {c: float(np.median(v)) for c, v in times.items()}
+            g, c = min(med, key=med.get)
+            shapes[i].update(lanes_per_state=g, states_per_item=c)
+            history.append([i, g, c, med[(g, c)] * 1e6])
+    t = _plan_seconds(robots, Bs, shapes, states)
+    return {"shapes": shapes, "us": t * 1e6, "states_per_s": sum(Bs) / t, "history": history}
+
+
+def plan_shapes(robots, Bs, table: Optional[Dict] = None):
+    """The plan's shapes: measured ones from the table when it has this
+    uneven batch, else plan_tune's rule."""
+    e = (table or {}).get(plan_key(robots, Bs))
+    if e is not None:
+        return [dict(x) for x in e["shapes"]]
+    return [plan_tune(r, table) for r in robots]
 
 
 def plan_tune(robot: wb.Robot, table: Optional[Dict] = None, rounds: int = 1) -> Dict:
@@ -123,11 +229,28 @@ def main():
     table = {}
     jobs = [(synth.humanoid48(seed=0), 24576), (synth.serial_chain(7, 5, seed=0), 4096)]
     jobs += [(synth.random_tree(n, 6, seed=i), b) for i, (n, b) in enumerate(synth.UNEVEN_TREES)]
+    robots = []
     for desc, B in jobs:
         r = wb.Robot(desc).to_device()
         res = tune_robot(r, desc, B, reps=args.reps)
+        res.update(tune_sweep_split(r, desc))
         table[r.topology_key()] = res
-        print(desc.name, r.topology_key(), {k: v for k, v in res.items() if k != "candidates"}, flush=True)
+        robots.append((r, desc, B))
+        print(desc.name, r.topology_key(), {k: v for k, v in res.items() if k not in ("candidates", "sweep_us")},
+              flush=True)
+    # the paper-scale humanoid (the fused iteration takes up to 8 spheres per link: the sweep split only)
+    desc = synth.humanoid48_paper_scale()
+    r = wb.Robot(desc).to_device()
+    table[r.topology_key()] = tune_sweep_split(r, desc)
+    print(desc.name, "paper scale", table[r.topology_key()]["sweep_split_below"], flush=True)
+    # the uneven batch's shapes, measured inside the plan
+    trees = robots[2:]
+    pr = [t[0] for t in trees]
+    Bs = [t[2] for t in trees]
+    res = tune_plan(pr, [t[1] for t in trees], Bs, table)
+    table[plan_key(pr, Bs)] = res
+    print("plan", [(s["lanes_per_state"], s["states_per_item"]) for s in res["shapes"]], res["states_per_s"],
+          flush=True)
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)

@@ -118,6 +118,12 @@ class Robot:
         t = _abi.WbTune(int(lanes_per_state), int(states_per_item), float(ns_per_state))
         check(lib().wb_robot_set_tune(self.handle, C.byref(t)))
 
+    def set_sweep_split(self, below: int) -> None:
+        """wb_self_collision sweeps batches of fewer than `below` states one
+        state per workgroup (pairs split over its wavefronts); < 0 restores
+        the default threshold."""
+        check(lib().wb_robot_set_sweep_split(self.handle, int(below)))
+
     def set_link_inertia(self, link: int, mass: float, com, inertia) -> None:
         """Replace one link's mass, CoM and inertia about the CoM (xx yy zz xy
         xz yz, link axes) on the device, e.g. for a payload; blocking, call

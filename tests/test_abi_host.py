@@ -102,11 +102,21 @@ def test_rejects_bad_descriptors(abi):
 
 
 def test_rejects_unsupported_sizes(abi):
-    rb = synth.serial_chain(3, 9, seed=0)                 # nine spheres on one link
     from paper_2603_05493_amd.wb import Robot
+    rb = synth.serial_chain(3, 65, seed=0)                # 65 spheres on one link
     with pytest.raises(abi.WbError) as e:
         Robot(rb)
     assert e.value.code == abi.WB_ERR_UNSUPPORTED
+    # nine per link are fine, padded to 12 slots; the fused iteration takes at most 8
+    r = Robot(synth.serial_chain(3, 9, seed=0))
+    assert r.max_spheres_per_link == 9 and not r.fused_supported
+
+
+def test_paper_scale_humanoid_sizes(abi):
+    from paper_2603_05493_amd.wb import Robot
+    r = Robot(synth.humanoid48_paper_scale())
+    assert (r.n_links, r.n_dof, r.n_spheres) == (49, 48, 588)
+    assert r.n_pairs == 162432 and r.max_spheres_per_link == 12 and r.n_blocks == 1128
 
 
 def test_asymmetric_allow_rejected(abi):
