@@ -160,7 +160,11 @@ int wb_rnea_cache_bytes(const wb_robot *robot, int64_t B, size_t *bytes);
 
 /* ---------------------------------------------------------------- forward */
 
-/* Forward kinematics (Sec. 6.1).  q[n][B] joint positions ->
+/* Forward kinematics (Sec. 6.1; the paper dispatches its kernels by robot
+ * size).  Batches below 48 states per compute unit on robots of at most 64
+ * links run one group of lanes per state (pointer jumping over the links, as
+ * wb_kinematics); larger ones one lane per state.
+ * q[n][B] joint positions ->
  *   link_pose[L][12][B] world link poses, or NULL to skip them: a branch
  *     link then recomposes its parent's pose from q along the parent's chain
  *     instead of re-reading it;
@@ -248,11 +252,17 @@ int wb_rnea(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const 
  * Any of the three outputs may be NULL to skip it (not all three). */
 int wb_self_collision(const wb_robot *robot, int64_t B, int64_t ld, const float *spheres, float *max_pen,
                       int32_t *argmax, int32_t *n_coll, hipStream_t stream);
-/* Split threshold of wb_self_collision for this robot: batches of fewer
- * than `below` states take the one-state-per-workgroup form (set by the
- * autotuner from measurement); below < 0 restores the default, 16 states
- * per compute unit of the robot's device. */
-int wb_robot_set_sweep_split(wb_robot *robot, int64_t below);
+/* Adaptive dispatch of the per-operation calls for this robot (Sec. 6.1
+ * dispatches FK kernels by robot size; here the forms are chosen by batch
+ * size, with thresholds the autotuner measures):
+ *   sweep_split_below  wb_self_collision takes the one-state-per-workgroup
+ *                      form for batches of fewer states (default 16 per
+ *                      compute unit of the robot's device);
+ *   fk_groups_below    wb_fk and wb_fk_backward take one group of lanes per
+ *                      state for batches of fewer states (default 48 per
+ *                      compute unit; robots of at most 64 links).
+ * A negative value restores that default; 0 never takes the form. */
+int wb_robot_set_dispatch(wb_robot *robot, int64_t sweep_split_below, int64_t fk_groups_below);
 
 /* -------------------------------------------------------------- adjoints */
 
@@ -269,7 +279,12 @@ int wb_self_collision_backward(const wb_robot *robot, int64_t B, int64_t ld, con
  * g_link_pose[L][12][B] and/or sphere centres g_spheres[S][3][B] (either may
  * be NULL, not both) -> g_q[n][B] (overwritten).  link_pose is the output of
  * wb_fk for the same q, or NULL to recompute the transforms from q inside
- * the kernel.  workspace: wb_workspace_bytes(robot, B). */
+ * the kernel.  workspace: wb_workspace_bytes(robot, B).
+ * Like wb_fk, batches below 48 states per compute unit (robots of at most
+ * 64 links) run one group of lanes per state: each link's
+ * wrench about the world origin summed over its subtree and projected on
+ * the joint axis, transforms recomputed in registers; link_pose is then not
+ * read and workspace may be NULL. */
 int wb_fk_backward(const wb_robot *robot, int64_t B, int64_t ld, const float *q, const float *link_pose,
                    const float *g_link_pose, const float *g_spheres, float *g_q, void *workspace,
                    hipStream_t stream);

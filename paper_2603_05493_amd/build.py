@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwb.so")
 
 SOURCES = ["wb_host.cpp", "fk.hip", "rnea.hip", "selfcoll.hip", "misc.hip", "fused.hip", "bspline.hip",
-           "kinematics.hip", "edt.hip", "edt_scratch.hip", "rnea_lanes.hip"]
+           "kinematics.hip", "edt.hip", "edt_scratch.hip", "tree_kernels.hip"]
 ARCH = os.environ.get("WB_OFFLOAD_ARCH", "gfx950")
 
 

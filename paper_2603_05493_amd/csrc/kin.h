@@ -51,7 +51,9 @@ struct KinGrad {
     float *g_q;            // [n][B], overwritten
 };
 
-hipError_t launch_kinematics(const DevKin &k, int64_t B, const float *q, const KinOut &o, hipStream_t s);
+// ld: row length of the [k][B] arrays (the state-major Jacobians are dense).
+hipError_t launch_kinematics(const DevKin &k, int64_t B, int64_t ld, const float *q, const KinOut &o,
+                             hipStream_t s);
 hipError_t launch_kinematics_backward(const DevKin &k, int64_t B, const float *q, const KinGrad &g,
                                       hipStream_t s);
 

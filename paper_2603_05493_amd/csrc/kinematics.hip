@@ -258,9 +258,11 @@ __device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b,
 // Each workgroup takes `spb` consecutive states (a multiple of its 256 / G
 // groups), so the rows of every [k][B] output are written in runs of
 // consecutive states by one workgroup.
+// nb: states; B: row length of the [k][B] arrays (>= nb).
 template <bool BWD>
-__global__ void __launch_bounds__(KIN_WG, 5) k_kinematics(DevKin k, int64_t B, const float *__restrict__ q, KinOut o,
-                                                       KinGrad g, int32_t spb) {
+__global__ void __launch_bounds__(KIN_WG, 5) k_kinematics(DevKin k, int64_t nb_states, int64_t B,
+                                                       const float *__restrict__ q, KinOut o, KinGrad g,
+                                                       int32_t spb) {
     const int G = k.G;
     const int gl = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
@@ -273,10 +275,10 @@ __global__ void __launch_bounds__(KIN_WG, 5) k_kinematics(DevKin k, int64_t B, c
     const int64_t base = (int64_t)bid * spb;
     for (int it = 0; it < spb / gpw; ++it) {
         const int64_t b0 = base + (int64_t)it * gpw;
-        if (b0 >= B) break;   // uniform over the workgroup
+        if (b0 >= nb_states) break;   // uniform over the workgroup
         const int64_t br = b0 + grp;
-        const bool valid = br < B;
-        kin_state<BWD>(k, B, valid ? br : B - 1, valid, gl, q, o, g);
+        const bool valid = br < nb_states;
+        kin_state<BWD>(k, B, valid ? br : nb_states - 1, valid, gl, q, o, g);
     }
 }
 
@@ -293,11 +295,12 @@ int32_t states_per_block(const DevKin &k, int64_t B) {
 
 }  // namespace
 
-hipError_t launch_kinematics(const DevKin &k, int64_t B, const float *q, const KinOut &o, hipStream_t s) {
+hipError_t launch_kinematics(const DevKin &k, int64_t B, int64_t ld, const float *q, const KinOut &o,
+                             hipStream_t s) {
     if (B == 0) return hipSuccess;
     const int32_t spb = states_per_block(k, B);
     const dim3 grid((unsigned)((B + spb - 1) / spb));
-    hipLaunchKernelGGL(k_kinematics<false>, grid, dim3(KIN_WG), 0, s, k, B, q, o, KinGrad{}, spb);
+    hipLaunchKernelGGL(k_kinematics<false>, grid, dim3(KIN_WG), 0, s, k, B, ld, q, o, KinGrad{}, spb);
     return hipGetLastError();
 }
 
@@ -306,7 +309,7 @@ hipError_t launch_kinematics_backward(const DevKin &k, int64_t B, const float *q
     if (B == 0) return hipSuccess;
     const int32_t spb = states_per_block(k, B);
     const dim3 grid((unsigned)((B + spb - 1) / spb));
-    hipLaunchKernelGGL(k_kinematics<true>, grid, dim3(KIN_WG), 0, s, k, B, q, KinOut{}, g, spb);
+    hipLaunchKernelGGL(k_kinematics<true>, grid, dim3(KIN_WG), 0, s, k, B, B, q, KinOut{}, g, spb);
     return hipGetLastError();
 }
 

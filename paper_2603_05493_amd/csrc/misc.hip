@@ -2,6 +2,7 @@
 // self-collision, the cost head and the gradient step.  All are one state
 // per lane over [k][B] arrays (coalesced in B); nb is the number of states
 // and B the row length of the arrays (the ABI's ld >= nb).
+#include <algorithm>
 #include "spatial.h"
 
 namespace wb {
@@ -9,6 +10,10 @@ namespace wb {
 // Hinge h = max(0, max_pen + margin) at the most penetrating pair: its
 // subgradient moves the two spheres of that pair apart along their centre
 // line (cuRoboV2 Sec. 6.2 reduces to one most-penetrating pair per state).
+// One thread per (sphere coordinate row, state), the state fastest, so the
+// whole [3S][B] output -- zero but for the pair's six entries -- is written
+// in coalesced rows; the argmax and the penetration of a state are read by
+// every row from the cache.
 __global__ void __launch_bounds__(256) k_sc_backward(DevRobot rb, int64_t nb, int64_t B, const float *__restrict__ sph,
                                                      const int32_t *__restrict__ argmax,
                                                      const float *__restrict__ max_pen, float margin,
@@ -16,20 +21,25 @@ __global__ void __launch_bounds__(256) k_sc_backward(DevRobot rb, int64_t nb, in
                                                      float *__restrict__ g_sph) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
-    for (int i = 0; i < rb.S * 3; ++i) g_sph[(int64_t)i * B + b] = 0.0f;
     const int p = argmax[b];
-    if (p < 0 || p >= rb.n_pairs || !(max_pen[b] + margin > 0.0f)) return;
-    const int s = rb.pair_s[p], t = rb.pair_t[p];
-    const float *cs = sph + (int64_t)s * 3 * B + b;
-    const float *ct = sph + (int64_t)t * 3 * B + b;
-    const V3 d = v3(cs[0] - ct[0], cs[B] - ct[B], cs[2 * B] - ct[2 * B]);
-    const float n = sqrtf(dot(d, d));
-    if (!(n > 0.0f)) return;
-    const float g = g_cost[b] / n;
-    float *gs = g_sph + (int64_t)s * 3 * B + b;
-    float *gt = g_sph + (int64_t)t * 3 * B + b;
-    gs[0] = -g * d.x; gs[B] = -g * d.y; gs[2 * B] = -g * d.z;
-    gt[0] = g * d.x;  gt[B] = g * d.y;  gt[2 * B] = g * d.z;
+    const bool on = p >= 0 && p < rb.n_pairs && max_pen[b] + margin > 0.0f;
+    const int s = on ? rb.pair_s[p] : -1, t = on ? rb.pair_t[p] : -1;
+    for (int row = blockIdx.y; row < 3 * rb.S; row += gridDim.y) {   // sphere * 3 + coordinate
+        const int sphere = row / 3, c = row - 3 * sphere;
+        float out = 0.0f;
+        if (sphere == s || sphere == t) {
+            const float *cs = sph + (int64_t)s * 3 * B + b;
+            const float *ct = sph + (int64_t)t * 3 * B + b;
+            const V3 d = v3(cs[0] - ct[0], cs[B] - ct[B], cs[2 * B] - ct[2 * B]);
+            const float n = sqrtf(dot(d, d));
+            if (n > 0.0f) {
+                const float g = g_cost[b] / n;
+                const float dc = c == 0 ? d.x : (c == 1 ? d.y : d.z);
+                out = sphere == s ? -g * dc : g * dc;
+            }
+        }
+        g_sph[(int64_t)row * B + b] = out;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_cost_head(int64_t nb, int64_t B, int n, const float *__restrict__ tau,
@@ -78,9 +88,10 @@ hipError_t launch_self_collision_backward(const DevRobot &rb, int64_t B, int64_t
                                           const int32_t *argmax, const float *max_pen,
                                           float margin, const float *g_cost, float *g_sph,
                                           hipStream_t s) {
-    if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sc_backward, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, rb, B, ld, spheres,
-                       argmax, max_pen, margin, g_cost, g_sph);
+    if (B == 0 || rb.S == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sc_backward, dim3((unsigned)((B + 255) / 256), (unsigned)std::min(3 * rb.S, 65535)),
+                       dim3(256), 0, s, rb,
+                       B, ld, spheres, argmax, max_pen, margin, g_cost, g_sph);
     return hipGetLastError();
 }
 

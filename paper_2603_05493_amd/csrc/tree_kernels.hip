@@ -1,7 +1,9 @@
-// RNEA and its vector-Jacobian product without a cache (cuRoboV2 Alg. 4 and
-// the role of Alg. 5, with transforms and every forward quantity recomputed
-// in the backward): one state per group of G lanes, lane i holding link
-// perm[i] in depth-first pre-order, as in the fused iteration.
+// Storage-free per-operation kernels with one state per group of G lanes,
+// lane i holding link perm[i] in depth-first pre-order as in the fused
+// iteration: RNEA and its vector-Jacobian product without a cache (cuRoboV2
+// Alg. 4 and the role of Alg. 5, with transforms and every forward quantity
+// recomputed in the backward), and the adjoint of forward kinematics
+// (Alg. 1) from sphere and pose gradients.
 //
 // The recursions are carried in world coordinates (Plucker vectors about
 // the world origin), where they become tree sums:
@@ -152,7 +154,93 @@ __global__ void __launch_bounds__(256) k_rnea_lanes(DevRobot rb, DevFused fz, in
     }
 }
 
+// Adjoint of forward kinematics (Alg. 1) from gradients on sphere centres
+// g_sph[S][3][B] and/or link poses g_pose[L][12][B], one state per group of
+// lanes: the lane of link l forms the wrench its gradients exert about the
+// world origin, W_l = sum over its spheres of [c x g; g] plus, for a pose
+// gradient (G on R, g_p on p), [sum_c r_c x G_c + p x g_p; g_p]; the
+// subtree sum of W, projected on the joint's world axis S = [s; p x s],
+// is the joint's gradient (a rotation about s moves every point and frame
+// of the subtree).  Transforms are recomputed by pointer jumping; nothing is
+// stored.  Mimic joints gather m_l times their links' values.
+__global__ void __launch_bounds__(256) k_fk_backward_lanes(DevRobot rb, DevFused fz, int64_t nb, int64_t B, int G,
+                                                           const float *__restrict__ q,
+                                                           const float *__restrict__ g_pose,
+                                                           const float *__restrict__ g_sph,
+                                                           float *__restrict__ g_q) {
+    const int lane = threadIdx.x & 63;
+    const int per_wave = 64 / G, grp = lane / G, gl = lane - grp * G;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t s = wave * per_wave + grp;
+    if (wave * per_wave >= nb) return;
+    const bool valid = s < nb;
+    const int64_t b = valid ? s : nb - 1;
+    const int *li = fz.li;
+    const float *lf = fz.lf;
+    const bool act = gl < rb.L;
+    const int parent_lane = li[1 * 64 + gl];
+    const bool revolute = li[5 * 64 + gl] != 0;
+    const int jidx = li[3 * 64 + gl];
+    const int link = li[0 * 64 + gl];
+    const int sub_end = li[2 * 64 + gl];
+    const bool mim = fz.mimic != 0;
+    float th = 0.f, mult = 1.f;
+    if (revolute) {
+        th = q[(int64_t)jidx * B + b];
+        if (mim) {
+            mult = lf[29 * 64 + gl];
+            th = mult * th + lf[30 * 64 + gl];
+        }
+    }
+    M3 R;
+    V3 p;
+    lane_world_pose(fz, gl, revolute, th, parent_lane, G, R, p);
+    SV W = zsv();
+    if (act) {
+        if (g_sph) {
+            const int first = rb.li[link].sph_first, cnt = rb.li[link].sph_count;
+            for (int j = 0; j < cnt; ++j) {
+                const float4 c4 = rb.sph[first + j];
+                const V3 c = mul(R, v3(c4.x, c4.y, c4.z)) + p;
+                const float *gp = g_sph + (int64_t)(first + j) * 3 * B + b;
+                const V3 g = v3(gp[0], gp[B], gp[2 * B]);
+                W += sv(cross(c, g), g);
+            }
+        }
+        if (g_pose) {
+            const float *gp = g_pose + (int64_t)link * 12 * B + b;
+            M3 Gm;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) Gm.m[t] = gp[t * B];
+            const V3 gt = v3(gp[9 * B], gp[10 * B], gp[11 * B]);
+            V3 m = cross(p, gt);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) m += cross(col(R, c), col(Gm, c));
+            W += sv(m, gt);
+        }
+    }
+    const SV Ws = subtree_sum(W, gl, sub_end, G);
+    float th_b = 0.f;
+    if (revolute) {
+        const V3 sw = mul(R, v3(lf[0 * 64 + gl], lf[1 * 64 + gl], lf[2 * 64 + gl]));
+        th_b = dot(sv(sw, cross(p, sw)), Ws);
+    }
+    if (mim) th_b = gather_joint(mult * th_b, fz, gl, G);
+    const bool jlane = mim ? gl < rb.n : revolute;
+    if (valid && jlane) g_q[(int64_t)(mim ? gl : jidx) * B + b] = th_b;
+}
+
 static int lanes_for(int L) { return L <= 16 ? 16 : (L <= 32 ? 32 : 64); }
+
+hipError_t launch_fk_backward_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, int64_t ld, const float *q,
+                                    const float *g_pose, const float *g_sph, float *g_q, hipStream_t s) {
+    if (B == 0) return hipSuccess;
+    const int G = lanes_for(rb.L);
+    const int64_t per_wg = 4 * (64 / G);
+    const dim3 grid((unsigned)((B + per_wg - 1) / per_wg));
+    hipLaunchKernelGGL(k_fk_backward_lanes, grid, dim3(256), 0, s, rb, fz, B, ld, G, q, g_pose, g_sph, g_q);
+    return hipGetLastError();
+}
 
 hipError_t launch_rnea_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, int64_t ld, const float *q,
                              const float *qd, const float *qdd, const float *f_ext, float *tau, hipStream_t s) {

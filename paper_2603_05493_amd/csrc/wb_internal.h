@@ -167,7 +167,7 @@ hipError_t launch_rnea(const DevRobot &rb, int64_t B, int64_t ld, const float *q
 hipError_t launch_rnea_backward(const DevRobot &rb, int64_t B, int64_t ld, const float *q, const float *qd,
                                 const float *qdd, const float *cache, const float *g_tau,
                                 float *g_q, float *g_qd, float *g_qdd, float *g_fext, float *ws, hipStream_t s);
-// Group-per-state RNEA and VJP without a cache (rnea_lanes.hip); robots of
+// Group-per-state RNEA and VJP without a cache (tree_kernels.hip); robots of
 // at most 64 links.
 hipError_t launch_rnea_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, int64_t ld, const float *q,
                              const float *qd, const float *qdd, const float *f_ext, float *tau, hipStream_t s);
@@ -177,6 +177,10 @@ hipError_t launch_rnea_backward_lanes(const DevRobot &rb, const DevFused &fz, in
                                       hipStream_t s);
 // split: one state per workgroup with its pairs over the four wavefronts
 // (else one state per wavefront).
+// Group-per-state FK adjoint from sphere and/or pose gradients (dense
+// arrays, robots of at most 64 links).
+hipError_t launch_fk_backward_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, int64_t ld, const float *q,
+                                    const float *g_pose, const float *g_sph, float *g_q, hipStream_t s);
 hipError_t launch_self_collision(const DevRobot &rb, int64_t B, int64_t ld, const float *spheres,
                                  float *max_pen, int32_t *argmax, int32_t *n_coll, bool split, hipStream_t s);
 size_t self_collision_wg_lds(int L, int nmax, int n_blocks_pad);
