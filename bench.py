@@ -44,16 +44,16 @@ PEAK_HBM_GBPS = 8000.0
 # calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
 # and the launch shape (states per workgroup) it was measured with; reported
 # as null once either changes.
-TRAFFIC_MEASURED = {"sources_sha1": "525888b65b98bd1b0279e5cdd2334260a750b910", "states": 24576,
-                    "states_per_item": 8, "bytes_per_launch": 29712.7 * 1024}
-FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "spatial.h", "wb_internal.h")
+TRAFFIC_MEASURED = {"sources_sha1": "8f77b32d6a4aa720c15f4970d8829bb0ef70fba4", "states": 24576,
+                    "states_per_item": 8, "bytes_per_launch": (14398.8 + 15338.8) * 1024}
+FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "tree.h", "spline.h", "spatial.h", "wb_internal.h")
 
 
 # HBM traffic of the kinematics-outputs kernel, measured the same way
 # (profiles/k_kinematics_humanoid48_B24576.md; 4 tool frames), per launch.
-KIN_TRAFFIC_MEASURED = {"sources_sha1": "3ab2f81f4a04f9d1a92a4e4dc8a96f08b93d823f", "states": 24576, "tools": 4,
-                        "forward_bytes": (5473.2 + 133170.7) * 1024,
-                        "backward_bytes": (9685.0 + 4608.0) * 1024}
+KIN_TRAFFIC_MEASURED = {"sources_sha1": "07aeac455aa65f03659e09febacec3f6bc752074", "states": 24576, "tools": 4,
+                        "forward_bytes": (5480.6 + 133240.3) * 1024,
+                        "backward_bytes": (9686.0 + 4608.0) * 1024}
 KIN_SOURCES = ("kinematics.hip", "kin.h", "lanes.h", "spatial.h", "wb_internal.h")
 # ... and of the three distance-transform launches on the 256 x 256 x 128 room
 # (profiles/edt_room256_kernel_trace.md), summed per transform.
@@ -442,28 +442,36 @@ def main():
     print(json.dumps(out))
 
 
-def executed_roofline(robot, rb, q0, kernel_ms: float, sample: int = 2048):
-    """The fused kernel's executed work on the benchmark's states: sphere
-    centres from the library's own FK (wb_fk) for the first `sample` states,
-    the broad phase's rule applied to them on the host (sweep_work), and the
-    executed FLOP per state times the batch over the kernel's mean time."""
+def executed_work(robot, rb, q0, G=None, sample: int = 2048):
+    """The fused iteration's executed work per state on the given states:
+    sphere centres from the library's own FK (wb_fk) for the first `sample`
+    states and the broad phase's rule applied to them on the host
+    (sweep_work) with G lanes per state (default: the robot's tuned shape)."""
     import torch
     from paper_2603_05493_amd import wb
-    B = q0.shape[-1]
-    ns = min(sample, B)
-    _, sph = wb.wb_fk(robot, q0[:, :ns].contiguous())
+    ns = min(sample, q0.shape[-1])
+    _, sph = wb.wb_fk(robot, q0[:, :ns].contiguous(), want_pose=False)
     torch.cuda.synchronize()
     c = np.transpose(sph.cpu().numpy(), (2, 0, 1))                   # [ns, S, 3]
     ps, pt = robot.pairs()
-    G = robot.get_tune()["lanes_per_state"]
+    G = G or robot.get_tune()["lanes_per_state"]
     ev, tests, swept, nblk = sweep_work(c, rb.sphere_r, rb.sphere_link, ps, pt, robot.max_spheres_per_link, G)
     L, S, n = robot.n_links, robot.n_spheres, robot.n_dof
-    per_state = executed_flop_per_state(L, S, n, float(ev.mean()), float(tests.mean()))
-    ach = per_state * B / (kernel_ms * 1e-3) / 1e12
     return {"pairs_evaluated_per_state": float(ev.mean()), "pairs_in_model": int(robot.n_pairs),
             "blocks_swept_per_state": float(swept.mean()), "blocks": int(nblk),
-            "block_tests_per_state": float(tests.mean()), "flop_per_state": per_state,
-            "achieved": ach, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_PUBLISHED_TFLOPS,
+            "block_tests_per_state": float(tests.mean()),
+            "flop_per_state": executed_flop_per_state(L, S, n, float(ev.mean()), float(tests.mean())),
+            "sampled_states": ns}
+
+
+def executed_roofline(robot, rb, q0, kernel_ms: float, sample: int = 2048):
+    """The fused kernel's executed work on the benchmark's states
+    (executed_work) times the batch over the kernel's mean time."""
+    B = q0.shape[-1]
+    w = executed_work(robot, rb, q0, sample=sample)
+    ach = w["flop_per_state"] * B / (kernel_ms * 1e-3) / 1e12
+    ns = w.pop("sampled_states")
+    return {**w, "achieved": ach, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_PUBLISHED_TFLOPS,
             "frac_of_nonpacked_peak": ach / PEAK_FP32_NONPACKED_TFLOPS,
             "sample": f"broad-phase rule applied on the host to the first {ns} benchmark states' sphere centres "
                       f"(wb_fk); a swept block costs {robot.max_spheres_per_link}^2 pair evaluations"}
@@ -523,45 +531,11 @@ def bench_bspline(args, robot, T: int):
                      "cost_sum_first": cost0, "cost_sum_last": cost1}
     out["step"] = {"rule": "row-normalized (each joint's control points move lr / rms(g) * g)", "lr": lr,
                    "iterations": args.warmup + args.steps + 1}
-    out["whole_trajectory_workgroups"] = trajectory_workgroup_probe(robot, T * 48, 48)
     out["form"] = ("two_launch: bspline_eval + fused iteration (per-joint outputs) + control-point gradient and "
                    "step; fused_sampling: the fused kernel forms the samples + the gradient and step; one_launch: "
                    "one kernel forms the samples, runs the iteration, reduces the control-point gradient of its "
                    "trajectory and steps; each captured in a graph")
     return out
-
-
-def trajectory_workgroup_probe(robot, B: int, H: int, reps: int = 50):
-    """What reducing the control-point gradient inside the fused kernel would
-    cost in occupancy: a workgroup would have to own whole trajectories (H
-    states), so the fused kernel is timed (HIP events) at H states per
-    workgroup against the tuned shape, on the same batch."""
-    import torch
-    from paper_2603_05493_amd import synth
-    rb = synth.humanoid48(seed=0)
-    st = synth.states(rb, B, seed=1, q_range=1.5)
-    d = lambda a: torch.from_numpy(np.ascontiguousarray(a.T.astype(np.float32))).cuda()
-    q, qd, qdd = d(st.q), d(st.qd), d(st.qdd)
-    tuned = robot.get_tune()
-    res = {}
-    from paper_2603_05493_amd import wb
-    for name, spi in (("tuned", tuned["states_per_item"]), ("trajectory", H)):
-        robot.set_tune(tuned["lanes_per_state"], spi, tuned["ns_per_state"])
-        run = lambda: wb.wb_wholebody_step(robot, q, qd, qdd, torque_weight=1e-3, margin=0.01, hinge_weight=1.0)
-        for _ in range(5):
-            run()
-        s = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(reps):
-            run()
-        e1.record(s)
-        torch.cuda.synchronize()
-        res[name] = {"states_per_workgroup": spi, "workgroups": (B + spi - 1) // spi,
-                     "kernel_us": e0.elapsed_time(e1) / reps * 1e3}
-    robot.set_tune(tuned["lanes_per_state"], tuned["states_per_item"], tuned["ns_per_state"])
-    res["slowdown"] = res["trajectory"]["kernel_us"] / res["tuned"]["kernel_us"]
-    return res
 
 
 def bench_paper_scale(args, batches=(1000, 3072), reps: int = 20):
@@ -577,7 +551,12 @@ def bench_paper_scale(args, batches=(1000, 3072), reps: int = 20):
     import torch
     from paper_2603_05493_amd import synth, wb
     rb = synth.humanoid48_paper_scale()
+    from paper_2603_05493_amd import tune
     r = wb.Robot(rb).to_device("cuda:0")
+    entry = tune.load().get(r.topology_key(), {})
+    tune.apply(r, {r.topology_key(): entry})   # measured dispatch thresholds, if any
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    split_below = int(entry.get("sweep_split_below", 16 * cus))
     out = {"robot": "humanoid48, 588 spheres", "pairs": int(r.n_pairs), "spheres_per_link_max": r.max_spheres_per_link}
 
     def timed(fn):
@@ -618,12 +597,12 @@ def bench_paper_scale(args, batches=(1000, 3072), reps: int = 20):
         for name, below in (("wave_per_state", 0), ("workgroup_per_state", 1 << 40)):
             r.set_sweep_split(below)
             forms[name] = timed(lambda: wb.wb_self_collision(r, sph, mp, am, nc)) * 1e6
-        r.set_sweep_split(-1)
+        r.set_sweep_split(split_below)
         out[f"B{B}"] = {"states": B, "forward": {"states_per_s": B / t_f, "us": t_f * 1e6,
                                                   "pairs_per_s": B * r.n_pairs / t_f},
                         "forward_backward": {"states_per_s": B / t_fb, "us": t_fb * 1e6},
                         "sweep_us": forms, "sweep_form_by_default": "workgroup_per_state"
-                        if B < 16 * torch.cuda.get_device_properties(0).multi_processor_count else "wave_per_state"}
+                        if B < split_below else "wave_per_state"}
     return out
 
 
@@ -813,6 +792,11 @@ def bench_uneven(args):
     flop = sum(algorithmic_flop_per_state(r.n_links, r.n_spheres, r.n_pairs, r.n_dof) * B
                for r, B in zip(robots, Bs))
     ach = flop / (k_ms * 1e-3) / 1e12
+    # executed work: each tree's broad-phase survivors at its plan shape
+    ex_trees = [executed_work(r, rb, st[0], G=shp["lanes_per_state"])
+                for r, (rb, _), st, shp in zip(robots, jobs, states, shapes)]
+    ex_flop = sum(w["flop_per_state"] * B for w, B in zip(ex_trees, Bs))
+    ach_ex = ex_flop / (k_ms * 1e-3) / 1e12
 
     plains = [PlainIteration(r, B, **kw) for r, B in zip(robots, Bs)]
     for _ in range(args.warmup):
@@ -835,7 +819,16 @@ def bench_uneven(args):
                          "unit": "TFLOP/s", "frac": ach / PEAK_FP32_PUBLISHED_TFLOPS,
                          "frac_of_nonpacked_peak": ach / PEAK_FP32_NONPACKED_TFLOPS, "kernel_ms": k_ms,
                          "flop_per_launch": flop,
-                         "work": "algorithmic: every checked pair once, no pruning credited; VJP 500 FLOP/link"}}
+                         "work": "algorithmic: every checked pair once, no pruning credited; VJP 500 FLOP/link",
+                         "executed": {"flop_per_launch": ex_flop, "achieved": ach_ex, "unit": "TFLOP/s",
+                                      "frac": ach_ex / PEAK_FP32_PUBLISHED_TFLOPS,
+                                      "frac_of_nonpacked_peak": ach_ex / PEAK_FP32_NONPACKED_TFLOPS,
+                                      "per_tree": [{"tree": rb.name, "states": B, "model_flop_per_state":
+                                                    algorithmic_flop_per_state(r.n_links, r.n_spheres, r.n_pairs,
+                                                                               r.n_dof), **w}
+                                                   for (rb, B), r, w in zip(jobs, robots, ex_trees)],
+                                      "sample": "broad-phase rule applied on the host to each tree's first "
+                                                "2048 states' sphere centres (wb_fk) at its plan shape"}}}
 
 
 if __name__ == "__main__":

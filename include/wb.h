@@ -255,14 +255,22 @@ int wb_self_collision(const wb_robot *robot, int64_t B, int64_t ld, const float 
 /* Adaptive dispatch of the per-operation calls for this robot (Sec. 6.1
  * dispatches FK kernels by robot size; here the forms are chosen by batch
  * size, with thresholds the autotuner measures):
- *   sweep_split_below  wb_self_collision takes the one-state-per-workgroup
- *                      form for batches of fewer states (default 16 per
- *                      compute unit of the robot's device);
- *   fk_groups_below    wb_fk and wb_fk_backward take one group of lanes per
- *                      state for batches of fewer states (default 48 per
- *                      compute unit; robots of at most 64 links).
+ *   sweep_split_below     wb_self_collision takes the one-state-per-workgroup
+ *                         form for batches of fewer states (default 16 per
+ *                         compute unit of the robot's device);
+ *   fk_groups_below       wb_fk without link poses and wb_fk_backward
+ *                         without them take one group of lanes per state for
+ *                         batches of fewer states (default 48 per compute
+ *                         unit; robots of at most 64 links);
+ *   fk_pose_groups_below  the same for wb_fk writing link poses and
+ *                         wb_fk_backward reading poses or a pose gradient
+ *                         (the group form writes
+ *                         one state's 12L pose values across 12L rows and
+ *                         recomputes instead of reading; the lane form's rows
+ *                         are coalesced, so its crossover lies lower).
  * A negative value restores that default; 0 never takes the form. */
-int wb_robot_set_dispatch(wb_robot *robot, int64_t sweep_split_below, int64_t fk_groups_below);
+int wb_robot_set_dispatch(wb_robot *robot, int64_t sweep_split_below, int64_t fk_groups_below,
+                          int64_t fk_pose_groups_below);
 
 /* -------------------------------------------------------------- adjoints */
 

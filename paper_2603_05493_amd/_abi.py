@@ -94,7 +94,7 @@ _SIGS = {
                                   C.c_float, C.c_float, C.c_float, _vp, C.c_float, C.c_int32, _vp, _vp, _vp, _vp,
                                   _vp, _vp, _vp, _vp, _vp],
     "wb_robot_set_tune": [_vp, C.POINTER(WbTune)],
-    "wb_robot_set_dispatch": [_vp, C.c_int64, C.c_int64],
+    "wb_robot_set_dispatch": [_vp, C.c_int64, C.c_int64, C.c_int64],
     "wb_robot_get_tune": [_vp, C.POINTER(WbTune)],
     "wb_plan_create": [C.POINTER(_vp), C.POINTER(C.c_int64), C.c_int32, C.POINTER(WbTune), C.POINTER(_vp)],
     "wb_plan_run": [_vp, C.POINTER(WbTreeIO), C.c_float, C.c_float, C.c_float, C.c_float, _vp],

@@ -426,6 +426,30 @@ __global__ void __launch_bounds__(256, EXT ? 3 : 4) k_fused_step(FusedArgs A) {
     }
 }
 
+// A plan tree's descriptors, read from device memory, with every table
+// pointer re-derived as a global one (see as_global).
+__device__ __forceinline__ PlanTree load_tree(const PlanTree *t) {
+    PlanTree T = ldu(t);
+    DevRobot &r = T.rb;
+    r.lf = as_global(r.lf);
+    r.li = as_global(r.li);
+    r.sph = as_global(r.sph);
+    r.sph_link = as_global(r.sph_link);
+    r.sph_slot = as_global(r.sph_slot);
+    r.slot_r = as_global(r.slot_r);
+    r.blocks = as_global(r.blocks);
+    r.pair_off = as_global(r.pair_off);
+    r.pair_cnt = as_global(r.pair_cnt);
+    r.pair_s = as_global(r.pair_s);
+    r.pair_t = as_global(r.pair_t);
+    DevFused &z = T.fz;
+    z.li = as_global(z.li);
+    z.lf = as_global(z.lf);
+    z.lsph = as_global(z.lsph);
+    z.conn = as_global(z.conn);
+    return T;
+}
+
 // Persistent launch over an uneven batch of robots: workgroup w processes
 // the items [item_start[w], item_start[w+1]) of the plan's work list, each a
 // contiguous range of states of one robot.  EXT as for k_fused_step, chosen
@@ -439,7 +463,7 @@ __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
     int staged = -1;   // tree whose block table is in LDS
     for (int it = A.item_start[w]; it < A.item_start[w + 1]; ++it) {
         const PlanItem item = A.items[it];
-        const PlanTree T = ldu(A.trees + item.tree);
+        const PlanTree T = load_tree(A.trees + item.tree);
         const int G = T.lanes_per_state;
         if (item.tree != staged) {
             __syncthreads();   // every wave is done with the previous table

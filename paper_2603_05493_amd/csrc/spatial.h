@@ -9,6 +9,15 @@
 
 namespace wb {
 
+// A pointer read from memory as raw bits (as ldu below does) carries no
+// address space, so accesses through it compile to flat instructions, which
+// wait on the LDS and the vector-memory counters alike.  Re-deriving it from
+// its integer value as a global pointer lets the compiler emit global ones.
+template <typename T>
+__device__ __forceinline__ T *as_global(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
 // Uniform (same address in every lane) descriptor read through the scalar cache.
 template <typename T>
 __device__ __forceinline__ T ldu(const T *p) {

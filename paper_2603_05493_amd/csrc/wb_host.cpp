@@ -464,6 +464,7 @@ struct wb_robot {
     int cus = 256;   // compute units of that device
     int64_t sweep_split_below = -1;   // wb_self_collision splits states below this batch (-1: the default rule)
     int64_t fk_groups_below = -1;     // wb_fk and wb_fk_backward take a group per state below it (-1: default)
+    int64_t fk_pose_groups_below = -1;  // the same when link poses are written or read
 };
 
 namespace {
@@ -695,13 +696,16 @@ int wb_rnea_cache_bytes(const wb_robot *robot, int64_t B, size_t *bytes) {
 
 namespace {
 // Forward kinematics and its adjoint take one group of lanes per state
-// (pointer jumping over the links, nothing stored) for batches below 48
-// states per compute unit, and one lane per state above: measured on the
-// humanoid (240 and 588 spheres) and the 7-link chain, the group form is
-// 4-10x faster up to 8,192 states and the lane form faster at 24,576, where
-// its coalesced rows win.  The group form takes robots of at most 64 links.
-bool lanes_form(const wb_robot *r, int64_t B) {
-    const int64_t below = r->fk_groups_below >= 0 ? r->fk_groups_below : (int64_t)48 * r->cus;
+// (pointer jumping over the links, nothing stored) for batches below a
+// threshold, and one lane per state above, where the lane form's coalesced
+// rows win.  Calls that write or read link poses have a threshold of their
+// own: the group form writes a state's poses across 12L rows and its
+// adjoint recomputes them, while the lane form's adjoint reads them.
+// Default for both: 48 states per compute unit.  The group form takes
+// robots of at most 64 links.
+bool lanes_form(const wb_robot *r, int64_t B, bool pose) {
+    const int64_t set = pose ? r->fk_pose_groups_below : r->fk_groups_below;
+    const int64_t below = set >= 0 ? set : (int64_t)48 * r->cus;
     return r->T.lanes && B < below;
 }
 }  // namespace
@@ -716,7 +720,7 @@ int wb_fk(const wb_robot *robot, int64_t B, int64_t ld, const float *q, float *l
     WB_TRY(check_ptr(link_pose, "link_pose", false));
     WB_TRY(check_ptr(spheres, "spheres", false));
     if (!link_pose && !spheres) return fail(WB_ERR_INVALID_ARG, "link_pose and spheres are both null");
-    if (lanes_form(robot, B) && robot->T.kin) {
+    if (lanes_form(robot, B, link_pose != nullptr) && robot->T.kin) {
         const wb::KinOut o{link_pose, spheres, nullptr, nullptr, nullptr, nullptr};
         return finish(wb::launch_kinematics(robot->kin, B, ld, q, o, stream), "wb_fk launch");
     }
@@ -755,10 +759,12 @@ bool sweep_split(const wb_robot *r, int64_t B) {
 }
 }  // namespace
 
-int wb_robot_set_dispatch(wb_robot *robot, int64_t sweep_split_below, int64_t fk_groups_below) {
+int wb_robot_set_dispatch(wb_robot *robot, int64_t sweep_split_below, int64_t fk_groups_below,
+                          int64_t fk_pose_groups_below) {
     WB_TRY(check_robot(robot));
     robot->sweep_split_below = sweep_split_below < 0 ? -1 : sweep_split_below;
     robot->fk_groups_below = fk_groups_below < 0 ? -1 : fk_groups_below;
+    robot->fk_pose_groups_below = fk_pose_groups_below < 0 ? -1 : fk_pose_groups_below;
     return WB_OK;
 }
 
@@ -809,7 +815,7 @@ int wb_fk_backward(const wb_robot *robot, int64_t B, int64_t ld, const float *q,
     WB_TRY(check_ptr(g_link_pose, "g_link_pose", false));
     WB_TRY(check_ptr(g_spheres, "g_spheres", false));
     WB_TRY(check_ptr(g_q, "g_q", robot->T.n > 0));
-    if (lanes_form(robot, B)) {
+    if (lanes_form(robot, B, link_pose != nullptr || g_link_pose != nullptr)) {
         WB_TRY(check_ptr(workspace, "workspace", false));
         return finish(wb::launch_fk_backward_lanes(robot->dev, robot->fz, B, ld, q, g_link_pose, g_spheres, g_q, stream),
                       "wb_fk_backward launch");

@@ -11,7 +11,9 @@ state, which the multi-robot plan uses to balance its work list.
 Results are a JSON table keyed by ``Robot.topology_key()``:
     {key: {"lanes_per_state": G, "states_per_item": c, "ns_per_state": t,
            "B": batch, "candidates": [[G, c, ns_per_state], ...],
-           "sweep_split_below": n, "sweep_us": [[B, wave form us, workgroup form us], ...]}}
+           "sweep_split_below": n, "sweep_us": [[B, wave form us, workgroup form us], ...],
+           "fk_groups_below": m, "fk_us": [[B, lane form us, group form us], ...],
+           "fk_pose_groups_below": m2, "fk_pose_us": [...]}}
 plus, for the uneven batch, an entry keyed by ``plan_key`` with the trees'
 shapes measured inside the plan (``tune_plan``).
 
@@ -104,7 +106,7 @@ def tune_sweep_split(robot: wb.Robot, desc, batches: Iterable[int] = SWEEP_BATCH
             sp = sph[:, :, :B].contiguous()
             o = [t[:B] for t in outs]
             for f in (0, 1):
-                robot.set_sweep_split((1 << 40) if f else 0)
+                robot.set_dispatch((1 << 40) if f else 0, -1, -1)
                 for _ in range(2):
                     wb.wb_self_collision(robot, sp, *o)
                 start.record()
@@ -118,8 +120,57 @@ def tune_sweep_split(robot: wb.Robot, desc, batches: Iterable[int] = SWEEP_BATCH
     for B in batches:
         if med[(B, 1)] < med[(B, 0)]:
             below = B + 1   # the split form still wins at B
-    robot.set_sweep_split(below)
+    robot.set_dispatch(below, -1, -1)
     return {"sweep_split_below": below, "sweep_us": [[B, med[(B, 0)], med[(B, 1)]] for B in batches]}
+
+
+FK_BATCHES = (256, 1024, 3072, 8192, 12288, 16384, 24576)
+
+
+def tune_fk_groups(robot: wb.Robot, desc, pose: bool = False, batches: Iterable[int] = FK_BATCHES, reps: int = 10,
+                   rounds: int = 3) -> Dict:
+    """The batch size below which wb_fk and wb_fk_backward should take one
+    group of lanes per state rather than one lane per state, timed in both
+    forms at each batch size (interleaved rounds, median).  pose=False: FK
+    to sphere centres plus the adjoint of a sphere gradient, no link poses
+    (key fk_groups_below); pose=True: FK writing link poses and sphere
+    centres plus the adjoint reading the poses, as the per-operation
+    iteration calls them (key fk_pose_groups_below)."""
+    key = "fk_pose" if pose else "fk"
+    if robot.n_links > 64:
+        return {f"{key}_groups_below": 0, f"{key}_us": []}
+    batches = list(batches)
+    Bm = max(batches)
+    qs = _states(robot, desc, Bm, seed=2)
+    times = {(B, f): [] for B in batches for f in (0, 1)}
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(rounds):
+        for B in batches:
+            q = qs[0][:, :B].contiguous()
+            s_ = torch.empty((robot.n_spheres, 3, B), device=robot.device)
+            lp = torch.empty((robot.n_links, 12, B), device=robot.device) if pose else None
+            gq = torch.empty((robot.n_dof, B), device=robot.device)
+            ws = robot.workspace(B)
+            for f in (0, 1):
+                t = (1 << 40) if f else 0
+                robot.set_dispatch(-1, -1 if pose else t, t if pose else -1)
+                run = lambda: (wb.wb_fk(robot, q, link_pose=lp, spheres=s_, want_pose=pose),
+                               wb.wb_fk_backward(robot, q, g_spheres=s_, link_pose=lp, g_q=gq, workspace=ws))
+                for _ in range(2):
+                    run()
+                start.record()
+                for _ in range(reps):
+                    run()
+                stop.record()
+                torch.cuda.synchronize()
+                times[(B, f)].append(start.elapsed_time(stop) * 1e3 / reps)
+    robot.set_dispatch(-1, -1, -1)
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    below = 0
+    for B in batches:
+        if med[(B, 1)] < med[(B, 0)]:
+            below = B + 1
+    return {f"{key}_groups_below": below, f"{key}_us": [[B, med[(B, 0)], med[(B, 1)]] for B in batches]}
 
 
 def apply(robot: wb.Robot, table: Dict) -> bool:
@@ -128,8 +179,8 @@ def apply(robot: wb.Robot, table: Dict) -> bool:
     e = table.get(robot.topology_key())
     if e is None:
         return False
-    if "sweep_split_below" in e:
-        robot.set_sweep_split(int(e["sweep_split_below"]))
+    robot.set_dispatch(int(e.get("sweep_split_below", -1)), int(e.get("fk_groups_below", -1)),
+                       int(e.get("fk_pose_groups_below", -1)))
     if "lanes_per_state" not in e or e["lanes_per_state"] < robot.n_links or not robot.fused_supported:
         return False
     robot.set_tune(e["lanes_per_state"], e["states_per_item"], e.get("ns_per_state", 0.0))
@@ -234,15 +285,21 @@ def main():
         r = wb.Robot(desc).to_device()
         res = tune_robot(r, desc, B, reps=args.reps)
         res.update(tune_sweep_split(r, desc))
+        res.update(tune_fk_groups(r, desc))
+        res.update(tune_fk_groups(r, desc, pose=True))
         table[r.topology_key()] = res
         robots.append((r, desc, B))
-        print(desc.name, r.topology_key(), {k: v for k, v in res.items() if k not in ("candidates", "sweep_us")},
-              flush=True)
+        print(desc.name, r.topology_key(),
+              {k: v for k, v in res.items() if k not in ("candidates", "sweep_us", "fk_us", "fk_pose_us")}, flush=True)
     # the paper-scale humanoid (the fused iteration takes up to 8 spheres per link: the sweep split only)
     desc = synth.humanoid48_paper_scale()
     r = wb.Robot(desc).to_device()
-    table[r.topology_key()] = tune_sweep_split(r, desc)
-    print(desc.name, "paper scale", table[r.topology_key()]["sweep_split_below"], flush=True)
+    e = tune_sweep_split(r, desc)
+    e.update(tune_fk_groups(r, desc))
+    e.update(tune_fk_groups(r, desc, pose=True))
+    table[r.topology_key()] = e
+    print(desc.name, "paper scale", e["sweep_split_below"], e["fk_groups_below"], e["fk_pose_groups_below"],
+          flush=True)
     # the uneven batch's shapes, measured inside the plan
     trees = robots[2:]
     pr = [t[0] for t in trees]

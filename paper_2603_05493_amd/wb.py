@@ -118,17 +118,19 @@ class Robot:
         t = _abi.WbTune(int(lanes_per_state), int(states_per_item), float(ns_per_state))
         check(lib().wb_robot_set_tune(self.handle, C.byref(t)))
 
-    def set_dispatch(self, sweep_split_below: int = -1, fk_groups_below: int = -1) -> None:
+    def set_dispatch(self, sweep_split_below: int = -1, fk_groups_below: int = -1,
+                     fk_pose_groups_below: int = -1) -> None:
         """Batch thresholds of the per-operation forms (wb_robot_set_dispatch):
         wb_self_collision sweeps one state per workgroup below the first,
         wb_fk / wb_fk_backward take one group of lanes per state below the
-        second; < 0 restores a default, 0 never takes the form."""
-        self._dispatch = (int(sweep_split_below), int(fk_groups_below))
+        second (no link poses involved) or the third (poses written or
+        read); < 0 restores a default, 0 never takes the form."""
+        self._dispatch = (int(sweep_split_below), int(fk_groups_below), int(fk_pose_groups_below))
         check(lib().wb_robot_set_dispatch(self.handle, *self._dispatch))
 
     def set_sweep_split(self, below: int) -> None:
-        """Only the self-collision threshold of set_dispatch (the other kept)."""
-        self.set_dispatch(below, getattr(self, "_dispatch", (-1, -1))[1])
+        """Only the self-collision threshold of set_dispatch (the others kept)."""
+        self.set_dispatch(below, *getattr(self, "_dispatch", (-1, -1, -1))[1:])
 
     def set_link_inertia(self, link: int, mass: float, com, inertia) -> None:
         """Replace one link's mass, CoM and inertia about the CoM (xx yy zz xy

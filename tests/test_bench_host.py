@@ -63,6 +63,9 @@ def test_tuned_shapes_are_whole_workgroup_rounds():
             continue
         if "sweep_split_below" in e:
             assert e["sweep_split_below"] >= 0 and len(e["sweep_us"]) > 0, key
+        for k in ("fk_groups_below", "fk_pose_groups_below"):
+            if k in e:
+                assert e[k] >= 0, key
         if "lanes_per_state" not in e:   # a robot beyond the fused iteration: the sweep split only
             continue
         g, c = e["lanes_per_state"], e["states_per_item"]

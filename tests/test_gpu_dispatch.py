@@ -36,7 +36,8 @@ def test_fk_forms_against_oracle(oracle, label, factory, B, form):
     from paper_2603_05493_amd import wb
     rb = factory()
     r = wb.Robot(rb).to_device("cuda:0")
-    r.set_dispatch(-1, (1 << 40) if form == "group" else 0)
+    f = (1 << 40) if form == "group" else 0
+    r.set_dispatch(-1, f, f)
     st = synth.states(rb, B, seed=3, q_range=1.5)
     q = P.dev(st.q)
     pose, sph = wb.wb_fk(r, q)
