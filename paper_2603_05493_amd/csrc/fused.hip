@@ -309,8 +309,12 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
 
 // Process `count` states starting at b0 of one robot with the 4 waves of
 // this workgroup, 64/G states per wavefront at a time; tab is the robot's
-// block table staged in LDS.
-template <int NMAX, bool EXT, int SPL>
+// block table staged in LDS.  GSEL: 64 builds only the one-state-per-
+// wavefront path (G must be 64), 0 only the path for G = 16 or 32, -1 both
+// (a plan mixes trees of every G).  A kernel holding one path keeps far
+// fewer values live across the state loop (the two paths' scalars spilled
+// to VGPR lanes and were re-read per state).
+template <int NMAX, bool EXT, int SPL, int GSEL>
 __device__ __forceinline__ void run_states(const DevRobot &rb, const uint16_t *tab, const DevFused &fz, const TreeIO &io,
                                            const SplineIn &sp, const StepScalars &k, float4 *lds_wave,
                                            float *gparts, int G, int64_t B, int64_t b0, int count, int traj) {
@@ -337,7 +341,7 @@ __device__ __forceinline__ void run_states(const DevRobot &rb, const uint16_t *t
             tr = bi / sp.H;
             t = bi - tr * sp.H;
         }
-        if (G == 64)
+        if (GSEL == 64 || (GSEL < 0 && G == 64))
             iterate_state<NMAX, true, EXT, SPL>(rb, tab, fz, io, sp, k, P, Bd, list, gpart, 64, 0, glane, B, b, valid,
                                                 tr, t);
         else
@@ -395,11 +399,11 @@ __device__ __forceinline__ void spline_reduce_step(const SplineIn &sp, const flo
     }
 }
 
-template <int NMAX, bool EXT, int SPL>
+template <int NMAX, bool EXT, int SPL, int GSEL>
 __global__ void __launch_bounds__(256, EXT ? 3 : 4) k_fused_step(FusedArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
-    const int G = A.lanes_per_state;
+    const int G = GSEL == 64 ? 64 : A.lanes_per_state;
     const int SLW = (64 / G) * (int)(group_lds_bytes(A.rb.L, NMAX, A.rb.list_cap) / 16);
     // XCD-aware chunk order: consecutive chunks stay on one XCD's L2.
     const int nwg = gridDim.x, x = blockIdx.x & 7, y = blockIdx.x >> 3;
@@ -418,7 +422,7 @@ __global__ void __launch_bounds__(256, EXT ? 3 : 4) k_fused_step(FusedArgs A) {
     __syncthreads();
     // with SPL == 2 each workgroup owns one trajectory (chunk == H)
     const int traj = SPL == 2 ? chunk : 0;
-    run_states<NMAX, EXT, SPL>(A.rb, tab, A.fz, A.io, A.sp, A.k, lds + wave * SLW, gparts, G, A.io.ld, b0, count,
+    run_states<NMAX, EXT, SPL, GSEL>(A.rb, tab, A.fz, A.io, A.sp, A.k, lds + wave * SLW, gparts, G, A.io.ld, b0, count,
                                traj);
     if (SPL == 2) {
         __syncthreads();
@@ -472,26 +476,31 @@ __global__ void __launch_bounds__(256) k_plan_step(PlanArgs A) {
             staged = item.tree;
         }
         // a fixed region per wave, sized for the plan's largest tree
-        run_states<NMAX, EXT, 0>(T.rb, tab, T.fz, A.io[item.tree], SplineIn{}, A.k, lds + wave * A.wave_stride,
+        run_states<NMAX, EXT, 0, -1>(T.rb, tab, T.fz, A.io[item.tree], SplineIn{}, A.k, lds + wave * A.wave_stride,
                                  nullptr, G, A.io[item.tree].ld,
                               item.b0, item.count, 0);
     }
 }
 
-template <int NMAX>
-static hipError_t launch_fused_t(const FusedArgs &a, hipStream_t s) {
-    size_t lds = fused_lds_bytes(a.rb.L, NMAX, a.rb.list_cap, a.lanes_per_state, a.rb.n_blocks_pad);
-    const unsigned nwg = (unsigned)((a.B + a.chunk - 1) / a.chunk);
+template <int NMAX, int GSEL>
+static hipError_t launch_fused_g(const FusedArgs &a, size_t lds, unsigned nwg, hipStream_t s) {
     const bool reduce = a.sp.U && (a.sp.g_U || a.sp.lr != 0.f);
     if (reduce) {
         lds += spline_lds_bytes(a.lanes_per_state, a.rb.n, a.sp.K);
-        hipLaunchKernelGGL((k_fused_step<NMAX, false, 2>), dim3(nwg), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_fused_step<NMAX, false, 2, GSEL>), dim3(nwg), dim3(256), lds, s, a);
     } else if (a.sp.U)
-        hipLaunchKernelGGL((k_fused_step<NMAX, false, 1>), dim3(nwg), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_fused_step<NMAX, false, 1, GSEL>), dim3(nwg), dim3(256), lds, s, a);
     else if (a.io.f_ext || a.io.g_fext || a.fz.mimic)
-        hipLaunchKernelGGL((k_fused_step<NMAX, true, 0>), dim3(nwg), dim3(256), lds, s, a);
-    else hipLaunchKernelGGL((k_fused_step<NMAX, false, 0>), dim3(nwg), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_fused_step<NMAX, true, 0, GSEL>), dim3(nwg), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_fused_step<NMAX, false, 0, GSEL>), dim3(nwg), dim3(256), lds, s, a);
     return hipGetLastError();
+}
+
+template <int NMAX>
+static hipError_t launch_fused_t(const FusedArgs &a, hipStream_t s) {
+    const size_t lds = fused_lds_bytes(a.rb.L, NMAX, a.rb.list_cap, a.lanes_per_state, a.rb.n_blocks_pad);
+    const unsigned nwg = (unsigned)((a.B + a.chunk - 1) / a.chunk);
+    return a.lanes_per_state == 64 ? launch_fused_g<NMAX, 64>(a, lds, nwg, s) : launch_fused_g<NMAX, 0>(a, lds, nwg, s);
 }
 
 hipError_t launch_fused(const FusedArgs &a, hipStream_t s) {
