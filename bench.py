@@ -92,11 +92,13 @@ def algorithmic_flop_per_state(L: int, S: int, P: int, n: int) -> float:
 BLOCK_TEST_FLOP = 9   # one link-block test: difference 3, squared norm 5, compare 1
 
 
-def executed_flop_per_state(L: int, S: int, n: int, pairs_evaluated: float, block_tests: float) -> float:
+def executed_flop_per_state(L: int, S: int, n: int, pairs_evaluated: float, block_tests: float,
+                            row_tests: float = 0.0) -> float:
     """Work the fused kernel executes per state: the pairs its exact broad
-    phase sweeps (padded sphere slots included) and its block tests, plus
-    the same non-pair work as the model."""
-    return 11 * pairs_evaluated + BLOCK_TEST_FLOP * block_tests + nonpair_flop_per_state(L, S, n)
+    phase sweeps (padded sphere slots included), its block tests and row
+    tests, plus the same non-pair work as the model."""
+    return (11 * pairs_evaluated + BLOCK_TEST_FLOP * (block_tests + row_tests)
+            + nonpair_flop_per_state(L, S, n))
 
 
 # One VALU issue slot = one lane of one VALU instruction; the chip issues
@@ -115,25 +117,29 @@ def issue_slots_per_state(L: int, S: int, P: int, n: int) -> float:
 
 
 def sweep_work(centres, radius, sph_link, pair_s, pair_t, nmax: int, lanes_per_state: int):
-    """Pair evaluations and link-block tests that the fused kernel's exact
-    broad phase executes, per state, from the kernel's own rule applied on
-    the host to sphere centres `centres` [B, S, 3] (radii [S], link of each
-    sphere [S], the checked pairs (pair_s, pair_t)):
+    """Pair evaluations, link-block tests and row tests that the fused
+    kernel's exact broad phase executes, per state, from the kernel's own
+    rule applied on the host to sphere centres `centres` [B, S, 3] (radii
+    [S], link of each sphere [S], the checked pairs (pair_s, pair_t)):
       link bound: centroid C_a of the link's centres, reach R_a = max |c - C_a| + r;
       eps = 4e-6 (1 + max_a(|C_a| + R_a));
-      pass 1 sweeps the blocks with |C_a - C_b| <= R_a + R_b + eps;
-      if their maximum M0 < 0, pass 2 sweeps the other blocks whose bound
-      R_a + R_b - |C_a - C_b| >= t1 - eps, t1 = M0 or (when pass 1 swept
-      nothing) the exact maximum of the block with the largest bound, which
-      costs one more block.
-    A swept block costs nmax x nmax pair evaluations (rows of padded slots);
-    each pass tests every block of the table, padded to a multiple of
-    2 x lanes_per_state.  Returns (pairs_evaluated [B], block_tests [B],
-    blocks swept [B], blocks in the table)."""
+      pass 1 takes the blocks (a, b) with |C_a - C_b| <= R_a + R_b + eps and,
+      in them, tests the nmax rows (sphere slots of a) against b's bound,
+      evaluating the rows with |c_s - C_b| <= r_s + R_b + eps;
+      if their maximum M0 < 0, pass 2 takes every block whose bound
+      R_a + R_b - |C_a - C_b| >= t1 - eps, t1 = M0 or (when pass 1 evaluated
+      no row) the exact maximum of the block with the largest bound, which
+      costs one more block, and evaluates its rows whose row bound reaches
+      t1 - eps and that pass 1 did not evaluate.
+    A row costs nmax pair evaluations; each pass tests every block of the
+    table, padded to a multiple of 2 x lanes_per_state.  Returns
+    (pairs_evaluated [B], block_tests [B], blocks swept [B], blocks in the
+    table, row_tests [B])."""
     c = np.asarray(centres, dtype=np.float64)
     r = np.asarray(radius, dtype=np.float64)
     sl = np.asarray(sph_link)
     links = np.unique(sl)
+    nst = len(c)
     Cl = np.stack([c[:, sl == a].mean(1) for a in links], 1)                       # [B, nl, 3]
     Rl = np.stack([(np.linalg.norm(c[:, sl == a] - Cl[:, i:i + 1], axis=-1) + r[sl == a]).max(1)
                    for i, a in enumerate(links)], 1)                                  # [B, nl]
@@ -141,30 +147,50 @@ def sweep_work(centres, radius, sph_link, pair_s, pair_t, nmax: int, lanes_per_s
     eps = 4e-6 * (1.0 + ext)
     li = {int(a): i for i, a in enumerate(links)}
     ps, pt = np.asarray(pair_s), np.asarray(pair_t)
-    key = np.array([li[int(a)] * len(links) + li[int(b)] for a, b in zip(sl[ps], sl[pt])])
+    la = np.array([li[int(a)] for a in sl[ps]])
+    lb = np.array([li[int(b)] for b in sl[pt]])
+    key = la * len(links) + lb
     blocks, inv = np.unique(key, return_inverse=True)
     A, Bb = blocks // len(links), blocks % len(links)
     d = Cl[:, A] - Cl[:, Bb]
     d2 = (d * d).sum(-1)
     s1 = Rl[:, A] + Rl[:, Bb] + eps[:, None]
-    surv1 = d2 <= s1 * np.abs(s1)
+    surv1 = d2 <= s1 * np.abs(s1)                                                     # [B, nblk]
     bound = Rl[:, A] + Rl[:, Bb] - np.sqrt(d2)
     diff = c[:, ps] - c[:, pt]
     pens = r[ps] + r[pt] - np.sqrt((diff * diff).sum(-1))                               # [B, P]
-    order = np.argsort(inv, kind="stable")
-    starts = np.searchsorted(inv[order], np.arange(len(blocks)))
-    bmax = np.maximum.reduceat(pens[:, order], starts, axis=1)                          # [B, n_blocks]
-    M0 = np.where(surv1, bmax, -np.inf).max(1)
+    # rows: (sphere s of the first link, block); their test against the second link's bound
+    rkey = ps.astype(np.int64) * len(blocks) + inv
+    rows, rinv = np.unique(rkey, return_inverse=True)
+    r_s, r_blk = rows // len(blocks), rows % len(blocks)
+    dr = c[:, r_s] - Cl[:, Bb[r_blk]]
+    dr2 = (dr * dr).sum(-1)
+    sr = r[r_s] + Rl[:, Bb[r_blk]] + eps[:, None]
+    rpass1 = dr2 <= sr * np.abs(sr)                                                   # [B, nrows]
+    rbound = r[r_s] + Rl[:, Bb[r_blk]] - np.sqrt(dr2)
+    order = np.argsort(rinv, kind="stable")
+    starts = np.searchsorted(rinv[order], np.arange(len(rows)))
+    rmax = np.maximum.reduceat(pens[:, order], starts, axis=1)                         # [B, nrows]
+    ev1 = surv1[:, r_blk] & rpass1
+    M0 = np.where(ev1, rmax, -np.inf).max(1)
     need2 = M0 < 0
-    none1 = ~surv1.any(1)
-    seed = bmax[np.arange(len(c)), np.argmax(bound, 1)]
+    none1 = ~ev1.any(1)
+    border = np.argsort(inv, kind="stable")
+    bstarts = np.searchsorted(inv[border], np.arange(len(blocks)))
+    bmax = np.maximum.reduceat(pens[:, border], bstarts, axis=1)                       # [B, nblk]
+    seed = bmax[np.arange(nst), np.argmax(bound, 1)]
     t1 = np.where(none1, seed, M0)
-    surv2 = need2[:, None] & ~surv1 & (bound >= (t1 - eps)[:, None])
-    swept = surv1.sum(1) + surv2.sum(1) + none1
+    lo = (t1 - eps)[:, None]
+    blk2 = need2[:, None] & (bound >= lo)
+    ev2 = blk2[:, r_blk] & (rbound >= lo) & ~ev1
+    rows_evaluated = ev1.sum(1) + ev2.sum(1)
+    swept = surv1.sum(1) + blk2.sum(1) + (need2 & none1)
     G2 = 2 * lanes_per_state
     nb = (len(blocks) + G2 - 1) // G2 * G2
     tests = nb * (1 + need2)
-    return nmax * nmax * swept, tests, swept, len(blocks)
+    row_tests = nmax * (surv1.sum(1) + blk2.sum(1))
+    pairs = nmax * rows_evaluated + nmax * nmax * (need2 & none1)
+    return pairs, tests, swept, len(blocks), row_tests
 
 
 def parse():
@@ -455,12 +481,14 @@ def executed_work(robot, rb, q0, G=None, sample: int = 2048):
     c = np.transpose(sph.cpu().numpy(), (2, 0, 1))                   # [ns, S, 3]
     ps, pt = robot.pairs()
     G = G or robot.get_tune()["lanes_per_state"]
-    ev, tests, swept, nblk = sweep_work(c, rb.sphere_r, rb.sphere_link, ps, pt, robot.max_spheres_per_link, G)
+    ev, tests, swept, nblk, rtests = sweep_work(c, rb.sphere_r, rb.sphere_link, ps, pt,
+                                                robot.max_spheres_per_link, G)
     L, S, n = robot.n_links, robot.n_spheres, robot.n_dof
     return {"pairs_evaluated_per_state": float(ev.mean()), "pairs_in_model": int(robot.n_pairs),
             "blocks_swept_per_state": float(swept.mean()), "blocks": int(nblk),
-            "block_tests_per_state": float(tests.mean()),
-            "flop_per_state": executed_flop_per_state(L, S, n, float(ev.mean()), float(tests.mean())),
+            "block_tests_per_state": float(tests.mean()), "row_tests_per_state": float(rtests.mean()),
+            "flop_per_state": executed_flop_per_state(L, S, n, float(ev.mean()), float(tests.mean()),
+                                                      float(rtests.mean())),
             "sampled_states": ns}
 
 
@@ -474,7 +502,7 @@ def executed_roofline(robot, rb, q0, kernel_ms: float, sample: int = 2048):
     return {**w, "achieved": ach, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_PUBLISHED_TFLOPS,
             "frac_of_nonpacked_peak": ach / PEAK_FP32_NONPACKED_TFLOPS,
             "sample": f"broad-phase rule applied on the host to the first {ns} benchmark states' sphere centres "
-                      f"(wb_fk); a swept block costs {robot.max_spheres_per_link}^2 pair evaluations"}
+                      f"(wb_fk); an evaluated row costs {robot.max_spheres_per_link} pair evaluations"}
 
 
 def bench_bspline(args, robot, T: int):

@@ -163,7 +163,9 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     float M;
     int key;
     unsigned cnt;
-    sweep_state<NMAX, FULL>(rb, tab, P, Bd, list, glane, G, grp, M, key, cnt);
+    // the group's row ring follows its list
+    sweep_state<NMAX, FULL>(rb, tab, P, Bd, list, reinterpret_cast<uint32_t *>(list + rb.list_cap), glane, G, grp, M,
+                            key, cnt);
     const float hmarg = M + k.margin;
     const bool hinge_on = key != INT_MAX && hmarg > 0.f && k.hinge_weight != 0.f;
     SV W = zsv();   // adjoint of the lane's joint rotation, before the subtree sum

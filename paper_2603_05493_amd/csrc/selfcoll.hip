@@ -7,7 +7,8 @@
 namespace wb {
 
 // LDS: TS states x [(L+1)*NMAX slots | (L+1) link bounds], then 4 lists of
-// rb.list_cap ints (one per wavefront), then (TAB_LDS) the block table.
+// rb.list_cap ints and 4 row rings of SWEEP_ROW_RING words (one of each per
+// wavefront), then (TAB_LDS) the block table.
 // nb: states; B: row length of the sphere array (the ABI's ld >= nb).
 template <int NMAX, bool TAB_LDS>
 __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t nb, int64_t B, int TS,
@@ -21,9 +22,10 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t nb,
     const int64_t b0 = (int64_t)blockIdx.x * TS;
     const int tid = threadIdx.x;
     int *lists = reinterpret_cast<int *>(lds + TS * SLB);
+    uint32_t *rings = reinterpret_cast<uint32_t *>(lists + 4 * rb.list_cap);
     const int *tab = rb.blocks;
     if (TAB_LDS) {
-        int *t = lists + 4 * rb.list_cap;
+        int *t = reinterpret_cast<int *>(rings + 4 * SWEEP_ROW_RING);
         for (int i = tid; i < rb.n_blocks_pad; i += 256) t[i] = rb.blocks[i];
         tab = t;
     }
@@ -56,7 +58,7 @@ __global__ void __launch_bounds__(256) k_self_collision(DevRobot rb, int64_t nb,
         float M;
         int key;
         unsigned cnt;
-        sweep_state<NMAX, true>(rb, tab, P, Bd, list, lane, 64, 0, M, key, cnt);
+        sweep_state<NMAX, true>(rb, tab, P, Bd, list, rings + wave * SWEEP_ROW_RING, lane, 64, 0, M, key, cnt);
         if (lane == 0) {
             if (max_pen) max_pen[b] = M;
             if (argmax) argmax[b] = pair_index(rb, key);
@@ -122,8 +124,11 @@ static int sc_tile(size_t per_state, size_t fixed) {
     return ts;
 }
 
+// LDS of the four wavefronts' lists and row rings.
+static size_t sc_lists_bytes(int list_cap) { return (size_t)16 * list_cap + (size_t)16 * SWEEP_ROW_RING; }
+
 int self_collision_tile(int L, int nmax, int list_cap) {
-    return sc_tile(state_lds_bytes(L, nmax), (size_t)16 * list_cap);
+    return sc_tile(state_lds_bytes(L, nmax), sc_lists_bytes(list_cap));
 }
 
 // The block table goes to LDS when one state, the four lists and the table
@@ -136,16 +141,16 @@ static hipError_t launch_sc(const DevRobot &rb0, int64_t B, int64_t ld, const fl
     const size_t per_state = state_lds_bytes(rb.L, NMAX);
     const size_t tab = (size_t)rb.n_blocks_pad * 4;
     dim3 block(256);
-    if (per_state + (size_t)16 * rb.list_cap + tab <= LDS_LIMIT) {
-        const int TS = sc_tile(per_state, (size_t)16 * rb.list_cap + tab);
-        const size_t lds = (size_t)TS * per_state + (size_t)16 * rb.list_cap + tab;
+    if (per_state + sc_lists_bytes(rb.list_cap) + tab <= LDS_LIMIT) {
+        const int TS = sc_tile(per_state, sc_lists_bytes(rb.list_cap) + tab);
+        const size_t lds = (size_t)TS * per_state + sc_lists_bytes(rb.list_cap) + tab;
         dim3 grid((unsigned)((B + TS - 1) / TS));
         hipLaunchKernelGGL((k_self_collision<NMAX, true>), grid, block, lds, s, rb, B, ld, TS, sph, mp, am, nc);
     } else {
-        const int room = (int)((LDS_LIMIT - per_state) / 16) / 128 * 128;
+        const int room = (int)((LDS_LIMIT - per_state - (size_t)16 * SWEEP_ROW_RING) / 16) / 128 * 128;
         if (room < rb.list_cap) rb.list_cap = room;
         const int TS = self_collision_tile(rb.L, NMAX, rb.list_cap);
-        const size_t lds = (size_t)TS * per_state + (size_t)16 * rb.list_cap;
+        const size_t lds = (size_t)TS * per_state + sc_lists_bytes(rb.list_cap);
         dim3 grid((unsigned)((B + TS - 1) / TS));
         hipLaunchKernelGGL((k_self_collision<NMAX, false>), grid, block, lds, s, rb, B, ld, TS, sph, mp, am, nc);
     }

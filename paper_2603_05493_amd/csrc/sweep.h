@@ -25,7 +25,16 @@
 // The surviving link pairs of each pass are compacted into the group's LDS
 // list (ballot + popcount), and the pair loop runs over rows -- (link pair,
 // sphere slot of the first link) against the NMAX slots of the second link
-// -- so that the lanes stay dense whatever the number of survivors.  Robots
+// -- so that the lanes stay dense whatever the number of survivors.
+// Row test (the same broad phase one level down, in the per-group sweeps):
+// no pair of a row penetrates more than r_A + R_b - |c_A - C_b|, sphere A of
+// the first link against the second link's bounding sphere, so a row is
+// evaluated only where that bound may reach the pass's threshold.  Passing
+// rows are queued in a 128-entry LDS ring per group (ballot + popcount) and
+// evaluated G at a time, so the lanes stay dense.  Pass 2 then takes every
+// block whose bound reaches t1 - eps and, in it, the rows pass 1 did not
+// evaluate whose row bound reaches t1 - eps: the rows of the two passes
+// partition the rows of the table exactly, with the same eps argument.  Robots
 // with more blocks than the list holds are swept in chunks.  The block
 // table is read from LDS where the caller has staged it; it is padded to a
 // multiple of 128 entries with the empty pair (L, L), whose bounding sphere
@@ -141,7 +150,10 @@ __device__ __forceinline__ bool may_reach(const float4 *Bd, int a, int b, float 
 // Appends to list[0, nl) the link pairs of blocks [c0, cend) that pass the
 // pass-1 test (PASS1) or, for pass 2, fail it with bound >= lo; returns nl.
 // cend - c0 is a multiple of 2G and every entry below cend is a table entry.
-template <bool PASS1, typename E>
+// MODE 1: the pass-1 test; 2: blocks that fail it with bound >= lo (pass 2
+// of the row-by-row sweep); 3: every block with bound >= lo (pass 2 of the
+// row-culled sweep, which filters the rows itself).
+template <int MODE, typename E>
 __device__ __forceinline__ int compact_blocks(const E *tab, const float4 *Bd, E *list, int c0, int cend, float eps,
                                               float lo, int glane, int G, int gshift, uint64_t gmask) {
     typedef PairCode<E> PC;
@@ -150,10 +162,17 @@ __device__ __forceinline__ int compact_blocks(const E *tab, const float4 *Bd, E 
     for (int base = c0; base < cend; base += 2 * G) {
         const int k0 = base + glane, k1 = k0 + G;
         const int ab0 = tab[k0], ab1 = tab[k1];
-        bool s0 = may_reach(Bd, PC::a(ab0), PC::b(ab0), eps), s1 = may_reach(Bd, PC::a(ab1), PC::b(ab1), eps);
-        if (!PASS1) {
-            s0 = !s0 && block_bound(Bd, PC::a(ab0), PC::b(ab0)) >= lo;
-            s1 = !s1 && block_bound(Bd, PC::a(ab1), PC::b(ab1)) >= lo;
+        bool s0, s1;
+        if (MODE == 3) {
+            s0 = block_bound(Bd, PC::a(ab0), PC::b(ab0)) >= lo;
+            s1 = block_bound(Bd, PC::a(ab1), PC::b(ab1)) >= lo;
+        } else {
+            s0 = may_reach(Bd, PC::a(ab0), PC::b(ab0), eps);
+            s1 = may_reach(Bd, PC::a(ab1), PC::b(ab1), eps);
+            if (MODE == 2) {
+                s0 = !s0 && block_bound(Bd, PC::a(ab0), PC::b(ab0)) >= lo;
+                s1 = !s1 && block_bound(Bd, PC::a(ab1), PC::b(ab1)) >= lo;
+            }
         }
         const uint64_t m0 = (__ballot(s0) >> gshift) & gmask;
         const uint64_t m1 = (__ballot(s1) >> gshift) & gmask;
@@ -197,16 +216,102 @@ __device__ __forceinline__ void sweep_rows(const DevRobot &rb, const float4 *P, 
     }
 }
 
+// Row test: sphere slot A against link bound Bb may hold a pair reaching
+// -eps (squared, as may_reach; an empty slot never passes), and the row
+// bound itself.
+__device__ __forceinline__ bool row_may_reach(float4 A, float4 Bb, float eps) {
+    const float dx = A.x - Bb.x, dy = A.y - Bb.y, dz = A.z - Bb.z;
+    const float s = (A.w + Bb.w) + eps;
+    const float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    return d2 <= s * fabsf(s);
+}
+__device__ __forceinline__ float row_bound(float4 A, float4 Bb) {
+    const float dx = A.x - Bb.x, dy = A.y - Bb.y, dz = A.z - Bb.z;
+    return (A.w + Bb.w) - __builtin_amdgcn_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
+}
+
+constexpr int ROW_RING = SWEEP_ROW_RING;   // queued rows per group (a power of two, >= 2 G - 1)
+
+// Evaluates the n queued rows at ring[head, head + n) (mod ROW_RING), one
+// per lane; a row code is (slot of A) << 16 | (first slot of the second
+// link), and best_code keeps the code of the row that set the running max.
+template <int NMAX, bool FULL>
+__device__ __forceinline__ void eval_rows(const float4 *P, const uint32_t *ring, int head, int n, int glane,
+                                          float &best, int &best_code, bool &tie, unsigned &cnt) {
+    if (glane < n) {
+        const uint32_t code = ring[(head + glane) & (ROW_RING - 1)];
+        const float4 A = P[code >> 16];
+        const float4 *Bp = P + (code & 0xffffu);
+        float m = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) {
+            const float pen = pair_pen(A, Bp[k]);
+            m = fmaxf(m, pen);
+            if (FULL) cnt += (unsigned)__popcll(__ballot(pen > 0.0f));
+            else cnt += pen > 0.0f ? 1u : 0u;
+        }
+        if (m > best) {
+            best = m;
+            best_code = (int)code;
+            tie = false;
+        } else if (m == best) {
+            tie = true;
+        }
+    }
+}
+
+// The rows of list[0, nl) that pass the row test (pass 1: may reach -eps;
+// PASS2: row bound >= lo and not evaluated by pass 1), queued in the ring
+// and evaluated G at a time: running maximum, its row code, ties, count.
+template <int NMAX, bool FULL, bool PASS2, typename E>
+__device__ __forceinline__ void sweep_rows_culled(const float4 *P, const float4 *Bd, const E *list, int nl,
+                                                  uint32_t *ring, float eps, float lo, int glane, int G, int gshift,
+                                                  uint64_t gmask, float &best, int &best_code, bool &tie,
+                                                  unsigned &cnt) {
+    typedef PairCode<E> PC;
+    const uint64_t below = (1ull << glane) - 1ull;
+    const int items = nl * NMAX;
+    int head = 0, pending = 0;   // the same in every lane of the group
+    for (int j0 = 0; j0 < items; j0 += G) {
+        const int it = j0 + glane;
+        bool pass = false;
+        uint32_t code = 0;
+        if (it < items) {
+            const int e = it / NMAX, row = it - e * NMAX;
+            const int ab = list[e];
+            const int a = PC::a(ab), bb = PC::b(ab);
+            const float4 A = P[a * NMAX + row], Bb = Bd[bb];
+            const bool may = row_may_reach(A, Bb, eps);
+            pass = PASS2 ? (row_bound(A, Bb) >= lo && !(may && may_reach(Bd, a, bb, eps))) : may;
+            code = ((uint32_t)(a * NMAX + row) << 16) | (uint32_t)(bb * NMAX);
+        }
+        const uint64_t m = (__ballot(pass) >> gshift) & gmask;
+        if (pass) ring[(head + pending + __popcll(m & below)) & (ROW_RING - 1)] = code;
+        pending += __popcll(m);
+        if (pending >= G) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            eval_rows<NMAX, FULL>(P, ring, head, G, glane, best, best_code, tie, cnt);
+            head = (head + G) & (ROW_RING - 1);
+            pending -= G;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (pending > 0) eval_rows<NMAX, FULL>(P, ring, head, pending, glane, best, best_code, tie, cnt);
+}
+
 // Sweep one state.  tab: the robot's block table (rb.blocks, or an LDS copy
 // in the entry type E); P: the state's (L+1)*NMAX sphere slots; Bd: its link
 // bounding spheres; list: rb.list_cap entries of LDS scratch for this group.
 // Every lane of the group returns the maximum penetration M, the sphere key
 // s*S + t of the lowest pair attaining it (INT_MAX if none) and the number
-// of pairs with positive penetration.  FULL: G == 64.
+// of pairs with positive penetration.  FULL: G == 64.  ring: ROW_RING words
+// of LDS scratch for this group (the row-culled sweep).
 template <int NMAX, bool FULL, typename E>
 __device__ __forceinline__ void sweep_state(const DevRobot &rb, const E *tab, const float4 *P, const float4 *Bd,
-                                            E *list, int glane, int G, int grp, float &M_out, int &key_out,
-                                            unsigned &cnt_out) {
+                                            E *list, uint32_t *ring, int glane, int G, int grp, float &M_out,
+                                            int &key_out, unsigned &cnt_out) {
     typedef PairCode<E> PC;
     const int n = rb.n_blocks;
     const int nb = (n + 2 * G - 1) / (2 * G) * (2 * G);   // <= n_blocks_pad, a multiple of 128
@@ -228,10 +333,11 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const E *tab, co
     unsigned cnt = 0;
     // pass 1: blocks that may hold a collision
     for (int c0 = 0; c0 < nb; c0 += cap) {
-        const int nl = compact_blocks<true>(tab, Bd, list, c0, min(c0 + cap, nb), eps, 0.f, glane, G, gshift, gmask);
+        const int nl = compact_blocks<1>(tab, Bd, list, c0, min(c0 + cap, nb), eps, 0.f, glane, G, gshift, gmask);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        sweep_rows<NMAX, FULL>(rb, P, list, nl, glane, G, best, best_code, tie, cnt);
+        sweep_rows_culled<NMAX, FULL, false>(P, Bd, list, nl, ring, eps, 0.f, glane, G, gshift, gmask, best,
+                                             best_code, tie, cnt);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
@@ -265,11 +371,12 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const E *tab, co
         }
         const float theta1 = lb - eps;
         for (int c0 = 0; c0 < nb; c0 += cap) {
-            const int nl = compact_blocks<false>(tab, Bd, list, c0, min(c0 + cap, nb), eps, theta1, glane, G,
-                                                 gshift, gmask);
+            const int nl = compact_blocks<3>(tab, Bd, list, c0, min(c0 + cap, nb), eps, theta1, glane, G, gshift,
+                                             gmask);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            sweep_rows<NMAX, FULL>(rb, P, list, nl, glane, G, best, best_code, tie, cnt);
+            sweep_rows_culled<NMAX, FULL, true>(P, Bd, list, nl, ring, eps, theta1, glane, G, gshift, gmask, best,
+                                                best_code, tie, cnt);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
@@ -283,9 +390,9 @@ __device__ __forceinline__ void sweep_state(const DevRobot &rb, const E *tab, co
             const int ab = tab[blk];
             key = min(key, block_min_key<NMAX>(rb, P, PC::a(ab), PC::b(ab), M));
         }
-    } else if (holder) {
-        const int ab = best_code / NMAX;
-        key = row_min_key<NMAX>(rb, P, PC::a(ab), PC::b(ab), best_code - ab * NMAX, M);
+    } else if (holder) {   // the row code: slot of A (link a, row i) and the first slot of link bb
+        const int sa = best_code >> 16, a = sa / NMAX;
+        key = row_min_key<NMAX>(rb, P, a, (best_code & 0xffff) / NMAX, sa - a * NMAX, M);
     }
     M_out = M;
     key_out = group_reduce_min(key, G);
@@ -338,7 +445,7 @@ __device__ __forceinline__ void sweep_state_wg(const DevRobot &rb, const E *tab,
     bool tie = false;
     unsigned cnt = 0;
     for (int c0 = wave * 128; c0 < nb; c0 += 4 * 128) {
-        const int nl = compact_blocks<true>(tab, Bd, list, c0, c0 + 128, eps, 0.f, lane, 64, 0, ~0ull);
+        const int nl = compact_blocks<1>(tab, Bd, list, c0, c0 + 128, eps, 0.f, lane, 64, 0, ~0ull);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         sweep_rows<NMAX, true>(rb, P, list, nl, lane, 64, best, best_code, tie, cnt);
@@ -376,7 +483,7 @@ __device__ __forceinline__ void sweep_state_wg(const DevRobot &rb, const E *tab,
         }
         const float theta1 = lb - eps;
         for (int c0 = wave * 128; c0 < nb; c0 += 4 * 128) {
-            const int nl = compact_blocks<false>(tab, Bd, list, c0, c0 + 128, eps, theta1, lane, 64, 0, ~0ull);
+            const int nl = compact_blocks<2>(tab, Bd, list, c0, c0 + 128, eps, theta1, lane, 64, 0, ~0ull);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             sweep_rows<NMAX, true>(rb, P, list, nl, lane, 64, best, best_code, tie, cnt);

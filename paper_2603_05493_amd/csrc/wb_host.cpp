@@ -360,7 +360,7 @@ int build_tables(const wb_robot_desc *d, Tables &T) {
     }
     T.nmax = nmax;
     T.most = most;
-    if (wb::state_lds_bytes(L, nmax) + 16 * 128 > wb::LDS_LIMIT)
+    if (wb::state_lds_bytes(L, nmax) + 16 * 128 + 16 * wb::SWEEP_ROW_RING > wb::LDS_LIMIT)
         return fail(WB_ERR_UNSUPPORTED, "(links + 1) x spheres-per-link slots (%d x %d) exceed the 64 KB LDS tile",
                     L + 1, nmax);
     T.sph.resize(S);

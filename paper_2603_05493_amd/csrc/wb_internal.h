@@ -205,15 +205,17 @@ hipError_t launch_bspline_backward(int64_t T, int32_t d, int32_t K, int32_t n_in
 // LDS of one state's sweep: (L+1)*nmax sphere slots and L+1 link bounding
 // spheres (float4 each); plus, per sweeping group, a list of list_cap
 // surviving link pairs (16-bit entries in the fused kernels, 32-bit in the
-// standalone self-collision kernel).
+// standalone self-collision kernel) and a ring of SWEEP_ROW_RING row codes.
 constexpr int SWEEP_LIST_MAX = 2048;
 inline int sweep_list_cap(int n_blocks) {
     int c = (n_blocks + 127) / 128 * 128;
     return c < 128 ? 128 : (c > SWEEP_LIST_MAX ? SWEEP_LIST_MAX : c);
 }
 __host__ __device__ inline size_t state_lds_bytes(int L, int nmax) { return (size_t)(L + 1) * (nmax + 1) * 16; }
+// Rows queued per sweeping group by the row-culled sweep (32-bit codes).
+constexpr int SWEEP_ROW_RING = 128;
 __host__ __device__ inline size_t group_lds_bytes(int L, int nmax, int list_cap) {
-    return state_lds_bytes(L, nmax) + (size_t)list_cap * 2;
+    return state_lds_bytes(L, nmax) + (size_t)list_cap * 2 + (size_t)SWEEP_ROW_RING * 4;
 }
 // LDS copy of the block table in the fused kernels (n_blocks_pad 16-bit
 // entries, a multiple of 128).

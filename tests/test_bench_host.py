@@ -86,27 +86,32 @@ def _bounded_robot(oracle):
 
 
 def test_sweep_work_rule_is_exact_and_counts_what_it_sweeps(oracle):
-    """The broad-phase rule the executed-work figure applies: the blocks it
-    sweeps hold the state's most penetrating pair (the rule is exact), and
-    its counts are consistent (nmax^2 evaluations per swept block, block
-    tests a padded multiple of the table once or twice)."""
+    """The broad-phase rule the executed-work figure applies: the block and
+    the row it keeps hold the state's most penetrating pair (the rule is
+    exact), and its counts are consistent (nmax evaluations per evaluated
+    row, nmax row tests per swept block, block tests a padded multiple of
+    the table once or twice)."""
     rb, c, s, t = _bounded_robot(oracle)
     nmax = int(np.bincount(rb.sphere_link).max())
-    ev, tests, swept, nblk = bench.sweep_work(c, rb.sphere_r, rb.sphere_link, s, t, nmax, 64)
-    assert np.all(ev == nmax * nmax * swept)
+    ev, tests, swept, nblk, rtests = bench.sweep_work(c, rb.sphere_r, rb.sphere_link, s, t, nmax, 64)
+    assert np.all(ev % nmax == 0) and np.all(ev >= nmax)
+    assert np.all(ev <= nmax * nmax * swept)
+    assert np.all(rtests <= nmax * swept) and np.all(rtests >= nmax)
     nb = (nblk + 127) // 128 * 128
     assert set(np.unique(tests)) <= {nb, 2 * nb}
     assert np.all(swept >= 1) and np.all(swept <= nblk + 1)
-    # exactness: re-derive the swept set and check it contains an argmax pair
+    # exactness: re-derive the kept block and row of an argmax pair
     mp, am, _ = oracle.self_collision(rb, c)
     sl = rb.sphere_link
     links = np.unique(sl)
     for b in range(c.shape[0]):
         C = {a: c[b, sl == a].mean(0) for a in links}
         R = {a: (np.linalg.norm(c[b, sl == a] - C[a], axis=1) + rb.sphere_r[sl == a]).max() for a in links}
-        la, lb = sl[s[am[b]]], sl[t[am[b]]]
+        sa, la, lb = s[am[b]], sl[s[am[b]]], sl[t[am[b]]]
         bound = R[la] + R[lb] - np.linalg.norm(C[la] - C[lb])
         assert bound >= mp[b] - 1e-12          # the argmax block's bound reaches the maximum
+        row = rb.sphere_r[sa] + R[lb] - np.linalg.norm(c[b, sa] - C[lb])
+        assert row >= mp[b] - 1e-12            # and so does its row's
     # a state in collision sweeps only pass 1 (one round of block tests)
     coll = mp >= 0
     assert np.all(tests[coll] == nb)
