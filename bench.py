@@ -7,8 +7,11 @@ One "step" is one optimizer iteration over the whole batch.  Four forms are
 timed on the same inputs:
   fused_graph   K iterations of the fused kernel (wb_wholebody_step) with the
                 gradient step, captured in one HIP graph with a snapshot of
-                state, gradient and cost every 10th iteration; the timed
-                region is one replay (exactly K steps) -- the reported value;
+                state, gradient and cost every 10th iteration; after W
+                eager warm-up iterations and one untimed replay (a graph's
+                first launch also uploads it), the timed region is one
+                replay (exactly K steps) -- the reported value; 20 more
+                replays timed one by one with HIP events give its median;
   fused_graph1  a one-iteration graph of the same kernel, replayed K times;
   plain_graph   one launch per operation, captured in a HIP graph;
   plain         one launch per operation, issued eagerly (the "plain launch").
@@ -44,16 +47,16 @@ PEAK_HBM_GBPS = 8000.0
 # calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
 # and the launch shape (states per workgroup) it was measured with; reported
 # as null once either changes.
-TRAFFIC_MEASURED = {"sources_sha1": "8f77b32d6a4aa720c15f4970d8829bb0ef70fba4", "states": 24576,
-                    "states_per_item": 8, "bytes_per_launch": (14398.8 + 15338.8) * 1024}
+TRAFFIC_MEASURED = {"sources_sha1": "2e7553f4b37de3cfc0fbe4db9391c8b329b5c58e", "states": 24576,
+                    "states_per_item": 8, "bytes_per_launch": (14329.4 + 14278.1) * 1024}
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "tree.h", "spline.h", "spatial.h", "wb_internal.h")
 
 
 # HBM traffic of the kinematics-outputs kernel, measured the same way
 # (profiles/k_kinematics_humanoid48_B24576.md; 4 tool frames), per launch.
-KIN_TRAFFIC_MEASURED = {"sources_sha1": "07aeac455aa65f03659e09febacec3f6bc752074", "states": 24576, "tools": 4,
-                        "forward_bytes": (5480.6 + 133240.3) * 1024,
-                        "backward_bytes": (9686.0 + 4608.0) * 1024}
+KIN_TRAFFIC_MEASURED = {"sources_sha1": "bc5135b773aeb642dd8a7f145c3b52251cf24570", "states": 24576, "tools": 4,
+                        "forward_bytes": (5477.6 + 133262.6) * 1024,
+                        "backward_bytes": (9686.0 + 4609.0) * 1024}
 KIN_SOURCES = ("kinematics.hip", "kin.h", "lanes.h", "spatial.h", "wb_internal.h")
 # ... and of the three distance-transform launches on the 256 x 256 x 128 room
 # (profiles/edt_room256_kernel_trace.md), summed per transform.
@@ -315,6 +318,8 @@ def main():
         for _ in range(args.warmup):
             og.lean.run(q, qd, qdd)
         og.capture()
+        # one untimed replay: a captured graph's first launch also uploads it
+        og.replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         og.replay()
