@@ -272,6 +272,68 @@ def cpu_baseline(rb, st, seconds: float, chunk: int = 2048):
             "host_cpu": host_cpu_model()}
 
 
+def measure_valu_peak(reps: int = 5, blocks: int = 8192, iters: int = 4096):
+    """The sustained FP32 FMA rate of the GPU's vector ALUs (libwb_peak.so:
+    16 independent v_fma_f32 chains per lane, packed FP32 off as in the
+    library), HIP events around each launch, best of `reps`; with the clock
+    it implies (256 CUs x 4 SIMDs x 16 lanes x 2 FLOP per cycle) and what
+    rocminfo reports for the agent."""
+    import ctypes as C
+    import torch
+    path = os.path.join(ROOT, "paper_2603_05493_amd", "libwb_peak.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run paper_2603_05493_amd/build.py")
+    lib = C.CDLL(path)
+    lib.wb_peak_fma.argtypes = [C.c_int64, C.c_int32, C.c_float, C.c_float, C.c_void_p, C.c_void_p]
+    lib.wb_peak_fma.restype = C.c_int
+    lib.wb_peak_fma_flop.argtypes = [C.c_int64, C.c_int32]
+    lib.wb_peak_fma_flop.restype = C.c_double
+    out = torch.empty(blocks * 256, device="cuda")
+    s = torch.cuda.current_stream()
+    launch = lambda: lib.wb_peak_fma(blocks, iters, 0.99999994, 1e-7, out.data_ptr(), s.cuda_stream)
+    if launch() != 0:
+        raise RuntimeError("wb_peak_fma launch failed")
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        launch()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    assert torch.isfinite(out).all()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    tf = lib.wb_peak_fma_flop(blocks, iters) / min(ts) / 1e12
+    return {"fma_tflops": tf, "implied_clock_ghz": tf * 1e3 / (cus * 4 * 16 * 2), "cus": cus,
+            "kernel": "k_fma_peak: 16 independent v_fma_f32 chains per lane, 8,192 x 256 lanes x 4,096 trips",
+            "rocminfo": rocminfo_agent()}
+
+
+def rocminfo_agent() -> dict:
+    """Compute units and maximum engine clock of the first GPU agent, as
+    rocminfo prints them (empty if rocminfo is not there)."""
+    import shutil
+    import subprocess
+    exe = shutil.which("rocminfo") or "/opt/rocm/bin/rocminfo"
+    try:
+        txt = subprocess.run([exe], capture_output=True, text=True, timeout=60).stdout
+    except (OSError, subprocess.SubprocessError):
+        return {}
+    info, in_gpu = {}, False
+    for line in txt.splitlines():
+        line = line.strip()
+        if line.startswith("Name:") and "gfx" in line:
+            in_gpu = True
+            info["name"] = line.split(":", 1)[1].strip()
+        elif in_gpu and line.startswith("Max Clock Freq. (MHz):"):
+            info["max_clock_mhz"] = int(line.split(":", 1)[1].split()[0])
+        elif in_gpu and line.startswith("Compute Unit:"):
+            info["compute_units"] = int(line.split(":", 1)[1].split()[0])
+        if in_gpu and "max_clock_mhz" in info and "compute_units" in info:
+            break
+    return info
+
+
 def host_cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -444,6 +506,10 @@ def main():
                            "algorithmic_bytes_per_launch": alg_bytes,
                            "hbm_gbps_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9}
         out["roofline"]["executed"] = executed_roofline(robot, rb, q0, fused_ms)
+        pk = measure_valu_peak()
+        pk["frac_model"] = achieved / pk["fma_tflops"]
+        pk["frac_executed"] = out["roofline"]["executed"]["achieved"] / pk["fma_tflops"]
+        out["roofline"]["peak_measured"] = pk
         slots = issue_slots_per_state(L, S, P, n) * B
         ach_slots = slots / (fused_ms * 1e-3) / 1e12
         out["roofline"]["issue_slot_model"] = {

@@ -189,3 +189,21 @@ def test_bspline_calls_validate_arguments(abi):
     dummy = C.c_void_p(256)   # never dereferenced: the check fails first
     assert lib.wb_bspline_backward(1, 4, 9, 4, 0.05, None, None, None, None, 0.1, 1, dummy, None) == E
     assert "g_U" in lib.wb_last_error().decode()
+
+
+def test_peak_probe_library_loads_and_rejects_bad_sizes():
+    """The benchmark's FP32 FMA-rate probe (libwb_peak.so) loads, exports its
+    two calls, counts its FLOP, and refuses empty launches without touching
+    the device."""
+    import ctypes as C
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2603_05493_amd",
+                        "libwb_peak.so")
+    lib = C.CDLL(path)
+    lib.wb_peak_fma_flop.argtypes = [C.c_int64, C.c_int32]
+    lib.wb_peak_fma_flop.restype = C.c_double
+    assert lib.wb_peak_fma_flop(8192, 4096) == 8192 * 256 * 4096 * 16 * 2
+    lib.wb_peak_fma.argtypes = [C.c_int64, C.c_int32, C.c_float, C.c_float, C.c_void_p, C.c_void_p]
+    lib.wb_peak_fma.restype = C.c_int
+    assert lib.wb_peak_fma(0, 10, 1.0, 0.0, None, None) != 0
+    assert lib.wb_peak_fma(16, 0, 1.0, 0.0, None, None) != 0
