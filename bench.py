@@ -643,7 +643,8 @@ def bench_paper_scale(args, batches=(1000, 3072), reps: int = 20):
     link) at the paper's kinematics batch of 1000 states and at one GPU's
     3072-state share.  Forward: FK sphere centres (no link poses) and the
     self-collision sweep; forward + backward: FK with poses, the sweep, the
-    hinge adjoint and the FK adjoint.  The sweep is also timed alone in each
+    hinge adjoint and the FK adjoint; fused iteration: the whole optimizer
+    iteration (with RNEA and its adjoint and the step) in one launch.  The sweep is also timed alone in each
     of its two forms (one state per wavefront; one state per workgroup with
     its blocks over four wavefronts and a second reduce).  HIP events on the
     launching stream."""
@@ -697,9 +698,20 @@ def bench_paper_scale(args, batches=(1000, 3072), reps: int = 20):
             r.set_sweep_split(below)
             forms[name] = timed(lambda: wb.wb_self_collision(r, sph, mp, am, nc)) * 1e6
         r.set_sweep_split(split_below)
+        # the whole optimizer iteration in one launch (FK, RNEA, self-collision,
+        # cost head, every adjoint, the step), as for the 240-sphere humanoid
+        from paper_2603_05493_amd.iteration import FusedIteration
+        it = FusedIteration(r, B, outputs=False, torque_weight=1e-3, margin=0.01, hinge_weight=1.0, lr=1e-3)
+        qs, qds, qdds = q.clone(), torch.from_numpy(np.ascontiguousarray(st.qd.T.astype(np.float32))).cuda(), \
+            torch.from_numpy(np.ascontiguousarray(st.qdd.T.astype(np.float32))).cuda()
+        t_it = timed(lambda: it.run(qs, qds, qdds))
+        assert torch.isfinite(qs).all()
         out[f"B{B}"] = {"states": B, "forward": {"states_per_s": B / t_f, "us": t_f * 1e6,
                                                   "pairs_per_s": B * r.n_pairs / t_f},
                         "forward_backward": {"states_per_s": B / t_fb, "us": t_fb * 1e6},
+                        "fused_iteration": {"states_per_s": B / t_it, "us": t_it * 1e6,
+                                            "form": "wb_wholebody_step with the gradient step, 12 sphere slots "
+                                                    "per link, HIP events over eager launches"},
                         "sweep_us": forms, "sweep_form_by_default": "workgroup_per_state"
                         if B < split_below else "wave_per_state"}
     return out

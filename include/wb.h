@@ -82,7 +82,7 @@ enum wb_joint_type { WB_JOINT_FIXED = 0, WB_JOINT_REVOLUTE = 1 };
  *   n_spheres      S >= 0; sphere_link[S] nondecreasing link indices;
  *   sphere[S][4]   centre (link frame) and radius (> 0) of each sphere;
  *                  at most WB_MAX_SPHERES_PER_LINK spheres per link (the
- *                  fused iteration takes at most 8).
+ *                  fused iteration takes at most 12).
  *   allow[L][L]    symmetric link-pair allow matrix for self-collision, or
  *                  NULL for the default: every pair of distinct links that
  *                  are not parent and child (Sec. 6.2 checks all sphere pairs

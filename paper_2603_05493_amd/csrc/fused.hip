@@ -361,10 +361,6 @@ __device__ __forceinline__ void stage_table(const DevRobot &rb, uint16_t *tab) {
     }
 }
 
-// Four wavefronts per SIMD: the register budget is 128 VGPRs.  EXT, the
-// variant with external link forces and mimic joints, holds the forces, the
-// joint-to-link map and their adjoints as well: at 128 VGPRs it spilled ~48
-// registers, so it runs three wavefronts per SIMD (168 VGPRs) without spills.
 // The control-point gradient of the workgroup's trajectory (SPL == 2): the
 // groups' partial sums over the extended knots, added in a fixed order; knot
 // e = k + 3 is control point k, and the three copies of the final control
@@ -401,8 +397,17 @@ __device__ __forceinline__ void spline_reduce_step(const SplineIn &sp, const flo
     }
 }
 
+// Waves per SIMD the register budget is set for: 4 (128 VGPRs) for the lean
+// iteration; 3 for EXT, the variant with external link forces and mimic
+// joints, which holds the forces, the joint-to-link map and their adjoints
+// as well (at 128 VGPRs it spilled ~48 registers); 2 for 12 sphere slots
+// per link, where the group regions (about 55 KB per workgroup) leave room
+// for two workgroups per CU anyway.
+template <int NMAX, bool EXT>
+constexpr int fused_waves() { return NMAX > 8 ? 2 : (EXT ? 3 : 4); }
+
 template <int NMAX, bool EXT, int SPL, int GSEL>
-__global__ void __launch_bounds__(256, EXT ? 3 : 4) k_fused_step(FusedArgs A) {
+__global__ void __launch_bounds__(256, (fused_waves<NMAX, EXT>())) k_fused_step(FusedArgs A) {
     extern __shared__ float4 lds[];
     const int wave = threadIdx.x >> 6;
     const int G = GSEL == 64 ? 64 : A.lanes_per_state;
@@ -516,6 +521,7 @@ hipError_t launch_fused(const FusedArgs &a, hipStream_t s) {
         case 6: return launch_fused_t<6>(a, s);
         case 7: return launch_fused_t<7>(a, s);
         case 8: return launch_fused_t<8>(a, s);
+        case 12: return launch_fused_t<12>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -545,6 +551,7 @@ int plan_workgroups_per_cu(int nmax, bool ext, size_t lds) {
         case 6: return plan_workgroups_per_cu_t<6>(ext, lds);
         case 7: return plan_workgroups_per_cu_t<7>(ext, lds);
         case 8: return plan_workgroups_per_cu_t<8>(ext, lds);
+        case 12: return plan_workgroups_per_cu_t<12>(ext, lds);
         default: return 1;
     }
 }
@@ -560,6 +567,7 @@ hipError_t launch_plan(const PlanArgs &a, int nmax, int n_wg, size_t lds, bool e
         case 6: return launch_plan_t<6>(a, n_wg, lds, ext, s);
         case 7: return launch_plan_t<7>(a, n_wg, lds, ext, s);
         case 8: return launch_plan_t<8>(a, n_wg, lds, ext, s);
+        case 12: return launch_plan_t<12>(a, n_wg, lds, ext, s);
         default: return hipErrorInvalidValue;
     }
 }

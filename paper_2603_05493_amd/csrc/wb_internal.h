@@ -232,8 +232,9 @@ inline size_t spline_lds_bytes(int G, int d, int K) {
     return ((size_t)(256 / G) * (K + 6) + (size_t)K) * d * 4;
 }
 constexpr size_t LDS_LIMIT = 65536;
-// Sphere slots per link the fused kernels are instantiated for.
-constexpr int FUSED_MAX_SLOTS = 8;
+// Sphere slots per link the fused kernels are instantiated for: 1 to 8, and
+// 12 (links of up to 12 spheres are padded to 12 slots).
+constexpr int FUSED_MAX_SLOTS = 12;
 
 // States per workgroup of the self-collision kernel (LDS tile).
 int self_collision_tile(int L, int nmax, int list_cap);

@@ -107,9 +107,12 @@ def test_rejects_unsupported_sizes(abi):
     with pytest.raises(abi.WbError) as e:
         Robot(rb)
     assert e.value.code == abi.WB_ERR_UNSUPPORTED
-    # nine per link are fine, padded to 12 slots; the fused iteration takes at most 8
+    # nine per link are fine, padded to 12 slots, which the fused iteration takes;
+    # thirteen pad to 16, which only the per-operation calls take
     r = Robot(synth.serial_chain(3, 9, seed=0))
-    assert r.max_spheres_per_link == 9 and not r.fused_supported
+    assert r.max_spheres_per_link == 9 and r.fused_supported
+    r = Robot(synth.serial_chain(3, 13, seed=0))
+    assert r.max_spheres_per_link == 13 and not r.fused_supported
 
 
 def test_paper_scale_humanoid_sizes(abi):
@@ -117,6 +120,7 @@ def test_paper_scale_humanoid_sizes(abi):
     r = Robot(synth.humanoid48_paper_scale())
     assert (r.n_links, r.n_dof, r.n_spheres) == (49, 48, 588)
     assert r.n_pairs == 162432 and r.max_spheres_per_link == 12 and r.n_blocks == 1128
+    assert r.fused_supported
 
 
 def test_asymmetric_allow_rejected(abi):

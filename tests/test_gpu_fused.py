@@ -61,6 +61,8 @@ def check_fused(O, rb, st, label, w=None, torque_weight=1e-3, margin=0.01, sampl
     ("tree12_B4096", lambda: synth.random_tree(12, 6, seed=1), 4096, np.pi, False),
     ("tree23_B2048", lambda: synth.random_tree(23, 6, seed=2), 2048, np.pi, False),
     ("tree48_B1024", lambda: synth.random_tree(48, 6, seed=3), 1024, np.pi, False),
+    ("humanoid48_paper_scale_B1000", synth.humanoid48_paper_scale, 1000, 1.5, False),
+    ("chain3_9spheres_B512", lambda: synth.serial_chain(3, 9, seed=4), 512, np.pi, True),
 ])
 def test_fused_parity(oracle, label, factory, B, qr, weighted):
     rb = factory()
