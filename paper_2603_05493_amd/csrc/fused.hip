@@ -235,8 +235,10 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
         const float tj = __shfl(taub, revolute ? li[3 * 64 + gl] : gl, G);
         taub = revolute ? mult * tj : 0.f;
     }
-    // ---- VJP, with the terms of W added as soon as their factors exist
-    W += taub * crf(S, F);
+    // ---- VJP, with the terms of W added as soon as their factors exist;
+    // the terms crf(S, .) are linear in their second argument, so they are
+    // gathered in X and crossed with S once at the end
+    SV X = taub * F;
     const SV fb = path_sum(taub * S, parent_lane, glane, fz.jsteps, G);
     SV ab = iw_apply(J, fb);
     W = W - (crf(fb, Ia) + crf(a, ab));
@@ -247,14 +249,15 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     W += crf(vxfb, Iv) + crf(v, Ivxfb);
     if (!act) ab = zsv();
     const SV Acc = subtree_sum(ab, glane, sub_end, G);
-    vb += crf(Sqd, Acc);
+    vb += thd * crf(S, Acc);   // crf(S qd, Acc)
     if (!act) vb = zsv();
     const SV vxA = crf(v, Acc);
     const float thdd_b = dot(S, Acc);
-    W += thdd * crf(S, Acc) - thd * crf(S, vxA);
+    X += thdd * Acc - thd * vxA;
     const SV V = subtree_sum(vb, glane, sub_end, G);
     const float thd_b = dot(S, V) - dot(S, vxA);
-    W += thd * crf(S, V);
+    X += thd * V;
+    W += crf(S, X);
     if (!act) W = zsv();
     const SV Ws = subtree_sum(W, glane, sub_end, G);
     float th_b = dot(S, Ws);

@@ -291,10 +291,12 @@ def main():
         robots.append((r, desc, B))
         print(desc.name, r.topology_key(),
               {k: v for k, v in res.items() if k not in ("candidates", "sweep_us", "fk_us", "fk_pose_us")}, flush=True)
-    # the paper-scale humanoid (the fused iteration takes up to 8 spheres per link: the sweep split only)
+    # the paper-scale humanoid: the fused iteration's shape at one GPU's 3072-state share, and the
+    # per-operation thresholds
     desc = synth.humanoid48_paper_scale()
     r = wb.Robot(desc).to_device()
-    e = tune_sweep_split(r, desc)
+    e = tune_robot(r, desc, 3072, reps=args.reps)
+    e.update(tune_sweep_split(r, desc))
     e.update(tune_fk_groups(r, desc))
     e.update(tune_fk_groups(r, desc, pose=True))
     table[r.topology_key()] = e
