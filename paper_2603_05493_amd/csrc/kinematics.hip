@@ -56,12 +56,14 @@ __device__ __forceinline__ V3 scan3(V3 v, int G) {
 // and subtree end once for all tools, then takes each tool point (and, for
 // the gradient, the tool rotation) from the lanes that formed it.
 // Forward: writes the poses and Jacobians.  BWD: returns this column's
-// dL/dq_j = sum_t J_t[:, j] . [g_x; w_t].
-template <bool BWD>
+// dL/dq_j = sum_t J_t[:, j] . [g_x; w_t].  GC: the lanes per state, known
+// at compile time (16, 32 or 64; it equals k.G).
+template <bool BWD, int GC>
 __device__ __forceinline__ float tool_frames(const DevKin &k, int64_t B, int64_t b, bool valid, int gl, const M3 &R,
                                              V3 p, V3 s_w, float mult, int sub_end, const KinOut &o,
                                              const float *__restrict__ g_tool) {
-    const int G = k.G, n = k.n;
+    constexpr int G = GC;
+    const int n = k.n;
     const bool col_lane = gl < n;
     const int lk0 = k.conn[gl];
     const int src0 = lk0 >= 0 ? lk0 : gl;
@@ -138,10 +140,10 @@ __device__ __forceinline__ float tool_frames(const DevKin &k, int64_t B, int64_t
     return gq;
 }
 
-template <bool BWD>
+template <bool BWD, int GC>
 __device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b, bool valid, int gl,
                                           const float *__restrict__ q, const KinOut &o, const KinGrad &g) {
-    const int G = k.G;
+    constexpr int G = GC;
     const int *li = k.li;
     const float *lf = k.lf;
     const bool act = gl < k.L;
@@ -251,7 +253,7 @@ __device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b,
     }
     // ---- tool frames: poses and Jacobians, or their gradient
     if (BWD ? g.g_tool != nullptr : (o.tool_pose != nullptr || o.jac != nullptr))
-        gq += tool_frames<BWD>(k, B, b, valid, gl, R, p, s_w, mult, sub_end, o, g.g_tool);
+        gq += tool_frames<BWD, GC>(k, B, b, valid, gl, R, p, s_w, mult, sub_end, o, g.g_tool);
     if (BWD && valid && col_lane) g.g_q[(int64_t)gl * B + b] = gq;
 }
 
@@ -259,11 +261,11 @@ __device__ __forceinline__ void kin_state(const DevKin &k, int64_t B, int64_t b,
 // groups), so the rows of every [k][B] output are written in runs of
 // consecutive states by one workgroup.
 // nb: states; B: row length of the [k][B] arrays (>= nb).
-template <bool BWD>
+template <bool BWD, int GC>
 __global__ void __launch_bounds__(KIN_WG, 5) k_kinematics(DevKin k, int64_t nb_states, int64_t B,
                                                        const float *__restrict__ q, KinOut o, KinGrad g,
                                                        int32_t spb) {
-    const int G = k.G;
+    constexpr int G = GC;
     const int gl = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int gpw = KIN_WG / G;
@@ -278,7 +280,7 @@ __global__ void __launch_bounds__(KIN_WG, 5) k_kinematics(DevKin k, int64_t nb_s
         if (b0 >= nb_states) break;   // uniform over the workgroup
         const int64_t br = b0 + grp;
         const bool valid = br < nb_states;
-        kin_state<BWD>(k, B, valid ? br : nb_states - 1, valid, gl, q, o, g);
+        kin_state<BWD, GC>(k, B, valid ? br : nb_states - 1, valid, gl, q, o, g);
     }
 }
 
@@ -300,7 +302,12 @@ hipError_t launch_kinematics(const DevKin &k, int64_t B, int64_t ld, const float
     if (B == 0) return hipSuccess;
     const int32_t spb = states_per_block(k, B);
     const dim3 grid((unsigned)((B + spb - 1) / spb));
-    hipLaunchKernelGGL(k_kinematics<false>, grid, dim3(KIN_WG), 0, s, k, B, ld, q, o, KinGrad{}, spb);
+    switch (k.G) {   // one kernel per lane count: the group width is a compile-time constant
+        case 16: hipLaunchKernelGGL((k_kinematics<false, 16>), grid, dim3(KIN_WG), 0, s, k, B, ld, q, o, KinGrad{}, spb); break;
+        case 32: hipLaunchKernelGGL((k_kinematics<false, 32>), grid, dim3(KIN_WG), 0, s, k, B, ld, q, o, KinGrad{}, spb); break;
+        case 64: hipLaunchKernelGGL((k_kinematics<false, 64>), grid, dim3(KIN_WG), 0, s, k, B, ld, q, o, KinGrad{}, spb); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -309,7 +316,12 @@ hipError_t launch_kinematics_backward(const DevKin &k, int64_t B, const float *q
     if (B == 0) return hipSuccess;
     const int32_t spb = states_per_block(k, B);
     const dim3 grid((unsigned)((B + spb - 1) / spb));
-    hipLaunchKernelGGL(k_kinematics<true>, grid, dim3(KIN_WG), 0, s, k, B, B, q, KinOut{}, g, spb);
+    switch (k.G) {
+        case 16: hipLaunchKernelGGL((k_kinematics<true, 16>), grid, dim3(KIN_WG), 0, s, k, B, B, q, KinOut{}, g, spb); break;
+        case 32: hipLaunchKernelGGL((k_kinematics<true, 32>), grid, dim3(KIN_WG), 0, s, k, B, B, q, KinOut{}, g, spb); break;
+        case 64: hipLaunchKernelGGL((k_kinematics<true, 64>), grid, dim3(KIN_WG), 0, s, k, B, B, q, KinOut{}, g, spb); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
