@@ -48,15 +48,15 @@ PEAK_HBM_GBPS = 8000.0
 # and the launch shape (states per workgroup) it was measured with; reported
 # as null once either changes.
 TRAFFIC_MEASURED = {"sources_sha1": "76f2ecde9bd34c9a8c14b709d49a0cd622e51abd", "states": 24576,
-                    "states_per_item": 8, "bytes_per_launch": (14322.8 + 14221.1) * 1024}
+                    "states_per_item": 8, "bytes_per_launch": (14323.1 + 14739.6) * 1024}
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "tree.h", "spline.h", "spatial.h", "wb_internal.h")
 
 
 # HBM traffic of the kinematics-outputs kernel, measured the same way
 # (profiles/k_kinematics_humanoid48_B24576.md; 4 tool frames), per launch.
-KIN_TRAFFIC_MEASURED = {"sources_sha1": "4cf287ad7c8192a0fc0220a7704305d41f0540f5", "states": 24576, "tools": 4,
-                        "forward_bytes": (5505.7 + 133205.8) * 1024,
-                        "backward_bytes": (9684.9 + 4608.0) * 1024}
+KIN_TRAFFIC_MEASURED = {"sources_sha1": "847396f22bc075c7b3b829618cad7203b2673d32", "states": 24576, "tools": 4,
+                        "forward_bytes": (5608.1 + 133088.2) * 1024,
+                        "backward_bytes": (9675.9 + 4608.0) * 1024}
 KIN_SOURCES = ("kinematics.hip", "kin.h", "lanes.h", "spatial.h", "wb_internal.h")
 # ... and of the three distance-transform launches on the 256 x 256 x 128 room
 # (profiles/edt_room256_kernel_trace.md), summed per transform.
