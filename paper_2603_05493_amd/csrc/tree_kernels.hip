@@ -30,9 +30,10 @@
 
 namespace wb {
 
-// nb: states; B: row length of every [k][B] array (the ABI's ld >= nb).
-template <bool BACKWARD>
-__global__ void __launch_bounds__(256) k_rnea_lanes(DevRobot rb, DevFused fz, int64_t nb, int64_t B, int G,
+// nb: states; B: row length of every [k][B] array (the ABI's ld >= nb);
+// G: lanes per state, a compile-time constant (one kernel per lane count).
+template <bool BACKWARD, int G>
+__global__ void __launch_bounds__(256) k_rnea_lanes(DevRobot rb, DevFused fz, int64_t nb, int64_t B,
                                                     const float *__restrict__ q, const float *__restrict__ qd,
                                                     const float *__restrict__ qdd, const float *__restrict__ f_ext,
                                                     float *__restrict__ tau, const float *__restrict__ g_tau,
@@ -163,7 +164,8 @@ __global__ void __launch_bounds__(256) k_rnea_lanes(DevRobot rb, DevFused fz, in
 // is the joint's gradient (a rotation about s moves every point and frame
 // of the subtree).  Transforms are recomputed by pointer jumping; nothing is
 // stored.  Mimic joints gather m_l times their links' values.
-__global__ void __launch_bounds__(256) k_fk_backward_lanes(DevRobot rb, DevFused fz, int64_t nb, int64_t B, int G,
+template <int G>
+__global__ void __launch_bounds__(256) k_fk_backward_lanes(DevRobot rb, DevFused fz, int64_t nb, int64_t B,
                                                            const float *__restrict__ q,
                                                            const float *__restrict__ g_pose,
                                                            const float *__restrict__ g_sph,
@@ -238,7 +240,11 @@ hipError_t launch_fk_backward_lanes(const DevRobot &rb, const DevFused &fz, int6
     const int G = lanes_for(rb.L);
     const int64_t per_wg = 4 * (64 / G);
     const dim3 grid((unsigned)((B + per_wg - 1) / per_wg));
-    hipLaunchKernelGGL(k_fk_backward_lanes, grid, dim3(256), 0, s, rb, fz, B, ld, G, q, g_pose, g_sph, g_q);
+    switch (G) {
+        case 16: hipLaunchKernelGGL(k_fk_backward_lanes<16>, grid, dim3(256), 0, s, rb, fz, B, ld, q, g_pose, g_sph, g_q); break;
+        case 32: hipLaunchKernelGGL(k_fk_backward_lanes<32>, grid, dim3(256), 0, s, rb, fz, B, ld, q, g_pose, g_sph, g_q); break;
+        default: hipLaunchKernelGGL(k_fk_backward_lanes<64>, grid, dim3(256), 0, s, rb, fz, B, ld, q, g_pose, g_sph, g_q); break;
+    }
     return hipGetLastError();
 }
 
@@ -248,9 +254,13 @@ hipError_t launch_rnea_lanes(const DevRobot &rb, const DevFused &fz, int64_t B, 
     const int G = lanes_for(rb.L);
     const int64_t per_wg = 4 * (64 / G);
     const dim3 grid((unsigned)((B + per_wg - 1) / per_wg));
-    hipLaunchKernelGGL(k_rnea_lanes<false>, grid, dim3(256), 0, s, rb, fz, B, ld, G, q, qd, qdd, f_ext, tau,
-                       (const float *)nullptr, (float *)nullptr, (float *)nullptr, (float *)nullptr,
-                       (float *)nullptr);
+    const float *no = nullptr;
+    float *nw = nullptr;
+    switch (G) {
+        case 16: hipLaunchKernelGGL((k_rnea_lanes<false, 16>), grid, dim3(256), 0, s, rb, fz, B, ld, q, qd, qdd, f_ext, tau, no, nw, nw, nw, nw); break;
+        case 32: hipLaunchKernelGGL((k_rnea_lanes<false, 32>), grid, dim3(256), 0, s, rb, fz, B, ld, q, qd, qdd, f_ext, tau, no, nw, nw, nw, nw); break;
+        default: hipLaunchKernelGGL((k_rnea_lanes<false, 64>), grid, dim3(256), 0, s, rb, fz, B, ld, q, qd, qdd, f_ext, tau, no, nw, nw, nw, nw); break;
+    }
     return hipGetLastError();
 }
 
@@ -262,8 +272,12 @@ hipError_t launch_rnea_backward_lanes(const DevRobot &rb, const DevFused &fz, in
     const int G = lanes_for(rb.L);
     const int64_t per_wg = 4 * (64 / G);
     const dim3 grid((unsigned)((B + per_wg - 1) / per_wg));
-    hipLaunchKernelGGL(k_rnea_lanes<true>, grid, dim3(256), 0, s, rb, fz, B, ld, G, q, qd, qdd, f_ext,
-                       (float *)nullptr, g_tau, g_q, g_qd, g_qdd, g_fext);
+    float *nw = nullptr;
+    switch (G) {
+        case 16: hipLaunchKernelGGL((k_rnea_lanes<true, 16>), grid, dim3(256), 0, s, rb, fz, B, ld, q, qd, qdd, f_ext, nw, g_tau, g_q, g_qd, g_qdd, g_fext); break;
+        case 32: hipLaunchKernelGGL((k_rnea_lanes<true, 32>), grid, dim3(256), 0, s, rb, fz, B, ld, q, qd, qdd, f_ext, nw, g_tau, g_q, g_qd, g_qdd, g_fext); break;
+        default: hipLaunchKernelGGL((k_rnea_lanes<true, 64>), grid, dim3(256), 0, s, rb, fz, B, ld, q, qd, qdd, f_ext, nw, g_tau, g_q, g_qd, g_qdd, g_fext); break;
+    }
     return hipGetLastError();
 }
 
