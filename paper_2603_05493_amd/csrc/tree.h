@@ -37,8 +37,8 @@ __device__ __forceinline__ SV path_sum(SV x, int parent_lane, int glane, int ste
 // difference of two values of the group's inclusive scan.  Lanes outside the
 // robot must hold zero.
 __device__ __forceinline__ SV subtree_sum(SV x, int glane, int sub_end, int G) {
-    const SV s = sv(v3(group_scan(x.w.x, G), group_scan(x.w.y, G), group_scan(x.w.z, G)),
-                    v3(group_scan(x.l.x, G), group_scan(x.l.y, G), group_scan(x.l.z, G)));
+    SV s = x;
+    group_scan6(s.w.x, s.w.y, s.w.z, s.l.x, s.l.y, s.l.z, G);
     const SV hi = shfl_sv(s, sub_end, G);
     const SV lo = sv(v3(lane_prev(s.w.x), lane_prev(s.w.y), lane_prev(s.w.z)),
                      v3(lane_prev(s.l.x), lane_prev(s.l.y), lane_prev(s.l.z)));
