@@ -168,17 +168,24 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
                             key, cnt);
     const float hmarg = M + k.margin;
     const bool hinge_on = key != INT_MAX && hmarg > 0.f && k.hinge_weight != 0.f;
-    SV W = zsv();   // adjoint of the lane's joint rotation, before the subtree sum
-    if (hinge_on) {
-        const int s = key / rb.S, t = key - s * rb.S;
+    // W: adjoint of the lane's joint rotation, before the subtree sum.  The
+    // hinge force is formed without branches: a state without it reads the
+    // pair (0, 0) and selects zero.  A checked pair joins two different
+    // links, so a lane takes at most one of the two sphere forces.
+    SV W = zsv();
+    if (rb.S > 0) {
+        const int hk = hinge_on ? key : 0;
+        const int s = (int)((unsigned)hk / (unsigned)rb.S), t = hk - s * rb.S;
         const float4 cs = P[rb.sph_slot[s]], ct = P[rb.sph_slot[t]];
         const V3 d = v3(cs.x - ct.x, cs.y - ct.y, cs.z - ct.z);
-        const float n = sqrtf(dot(d, d));
-        if (n > 0.f) {
-            const V3 g = (k.hinge_weight / n) * d;   // gradient on c_t; -g on c_s
-            if (act && link == rb.sph_link[s]) W += sv(cross(v3(cs.x, cs.y, cs.z), -g), -g);
-            if (act && link == rb.sph_link[t]) W += sv(cross(v3(ct.x, ct.y, ct.z), g), g);
-        }
+        const float d2 = dot(d, d);
+        // 1/n as the reciprocal of the rounded root (n >= 2^-75 for any d2 > 0)
+        const bool on = hinge_on && d2 > 0.f;
+        const V3 g = on ? (k.hinge_weight * __builtin_amdgcn_rcpf(sqrtf(d2))) * d : v3(0.f, 0.f, 0.f);
+        const bool on_s = act && link == rb.sph_link[s], on_t = act && link == rb.sph_link[t];
+        const V3 c = on_s ? v3(cs.x, cs.y, cs.z) : v3(ct.x, ct.y, ct.z);
+        const V3 f = on_s ? -g : g;   // gradient on c_t is g, on c_s -g
+        if (on_s || on_t) W = sv(cross(c, f), f);
     }
     // ---- world axis and inertia
     SV S = zsv();
@@ -203,7 +210,10 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
         const V3 Rf = mul(R, v3(fx[3 * B], fx[4 * B], fx[5 * B]));
         fe = sv(mul(R, v3(fx[0], fx[B], fx[2 * B])) + cross(p, Rf), Rf);
     }
-    // ---- RNEA forward
+    // ---- RNEA forward.  A lane past the robot is a massless link without a
+    // joint whose parent is the fixed root (zero velocity and acceleration),
+    // so every force and adjoint it forms below is exactly zero and the
+    // subtree scans take it unguarded.
     const SV Sqd = thd * S;
     const SV v = path_sum(Sqd, parent_lane, glane, fz.jsteps, G);
     SV a = path_sum(thdd * S + crm(v, Sqd), parent_lane, glane, fz.jsteps, G);
@@ -211,7 +221,6 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     const SV Ia = iw_apply(J, a), Iv = iw_apply(J, v);
     SV F = Ia + crf(v, Iv);
     if (EXT) F = F - fe;
-    if (!act) F = zsv();
     F = subtree_sum(F, glane, sub_end, G);
     float tau = revolute ? dot(S, F) : 0.f;
     // with mimic joints, joint lane j (j < n) holds joint j from here to the cost head
@@ -247,10 +256,8 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     const SV Ivxfb = iw_apply(J, vxfb);
     SV vb = zsv() - (crf(fb, Iv) + Ivxfb);
     W += crf(vxfb, Iv) + crf(v, Ivxfb);
-    if (!act) ab = zsv();
     const SV Acc = subtree_sum(ab, glane, sub_end, G);
     vb += thd * crf(S, Acc);   // crf(S qd, Acc)
-    if (!act) vb = zsv();
     const SV vxA = crf(v, Acc);
     const float thdd_b = dot(S, Acc);
     X += thdd * Acc - thd * vxA;
@@ -258,7 +265,6 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     const float thd_b = dot(S, V) - dot(S, vxA);
     X += thd * V;
     W += crf(S, X);
-    if (!act) W = zsv();
     const SV Ws = subtree_sum(W, glane, sub_end, G);
     float th_b = dot(S, Ws);
     float thd_o = thd_b, thdd_o = thdd_b;

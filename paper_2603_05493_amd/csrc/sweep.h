@@ -517,7 +517,7 @@ __device__ __forceinline__ void sweep_state_wg(const DevRobot &rb, const E *tab,
 // Pair index (lexicographic in (s, t)) of a sphere key s*S + t.
 __device__ __forceinline__ int32_t pair_index(const DevRobot &rb, int key) {
     if (key == INT_MAX) return -1;
-    const int s = key / rb.S, t = key - s * rb.S;
+    const int s = (int)((unsigned)key / (unsigned)rb.S), t = key - s * rb.S;
     const int a = rb.sph_link[s], bt = rb.sph_link[t];
     return rb.pair_off[s] + rb.pair_cnt[a * rb.L + bt] + (t - rb.li[bt].sph_first);
 }
