@@ -47,16 +47,16 @@ PEAK_HBM_GBPS = 8000.0
 # calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
 # and the launch shape (states per workgroup) it was measured with; reported
 # as null once either changes.
-TRAFFIC_MEASURED = {"sources_sha1": "76f2ecde9bd34c9a8c14b709d49a0cd622e51abd", "states": 24576,
-                    "states_per_item": 8, "bytes_per_launch": (14323.1 + 14739.6) * 1024}
+TRAFFIC_MEASURED = {"sources_sha1": "511157a0f7f7c074e0c2c3937fd5c5b779d42383", "states": 24576,
+                    "states_per_item": 8, "bytes_per_launch": (14296.8 + 14273.5) * 1024}
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "tree.h", "spline.h", "spatial.h", "wb_internal.h")
 
 
 # HBM traffic of the kinematics-outputs kernel, measured the same way
 # (profiles/k_kinematics_humanoid48_B24576.md; 4 tool frames), per launch.
-KIN_TRAFFIC_MEASURED = {"sources_sha1": "847396f22bc075c7b3b829618cad7203b2673d32", "states": 24576, "tools": 4,
-                        "forward_bytes": (5608.1 + 133088.2) * 1024,
-                        "backward_bytes": (9675.9 + 4608.0) * 1024}
+KIN_TRAFFIC_MEASURED = {"sources_sha1": "38509660bc700118f01cfe70ded607abb3b22724", "states": 24576, "tools": 4,
+                        "forward_bytes": (5606.6 + 133142.4) * 1024,
+                        "backward_bytes": (9674.9 + 4608.0) * 1024}
 KIN_SOURCES = ("kinematics.hip", "kin.h", "lanes.h", "spatial.h", "wb_internal.h")
 # ... and of the three distance-transform launches on the 256 x 256 x 128 room
 # (profiles/edt_room256_kernel_trace.md), summed per transform.
@@ -425,39 +425,63 @@ def main():
         assert torch.isfinite(q).all() and torch.isfinite(it.cost).all()
         return dt
 
-    def timed_eager(form, events=False):
+    def timed_eager(form):
         q, qd, qdd = q0.clone(), qd0.clone(), qdd0.clone()
         it = make(form)
         for _ in range(args.warmup):
             it.run(q, qd, qdd)
         torch.cuda.synchronize()
-        stream = torch.cuda.current_stream()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
         t0 = time.perf_counter()
-        for k in range(args.steps):
-            if events:
-                ev[k][0].record(stream)
+        for _ in range(args.steps):
             it.run(q, qd, qdd)
-            if events:
-                ev[k][1].record(stream)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        kernel_ms = [a.elapsed_time(b) for a, b in ev] if events else None
-        return dt, kernel_ms
+        return (time.perf_counter() - t0) / args.steps
+
+    def timed_kernel_graph():
+        """Duration of one lean fused launch: K back-to-back launches captured
+        in one graph, each of `replays` replays bracketed by HIP events on
+        the stream it is replayed on, divided by K.  (HIP events around each
+        of K eager launches read up to 10 % more once the host falls behind
+        the launch queue: the interval then holds the launch's submission.)"""
+        q, qd, qdd = q0.clone(), qd0.clone(), qdd0.clone()
+        it = make("fused")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            it.run(q, qd, qdd)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for _ in range(args.steps):
+                it.run(q, qd, qdd)
+        graph.replay()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.replays)]
+        for e0, e1 in ev:
+            e0.record(s)
+            graph.replay()
+            e1.record(s)
+        torch.cuda.synchronize()
+        assert torch.isfinite(q).all()
+        return [e0.elapsed_time(e1) / args.steps for e0, e1 in ev]
 
     replay_ms = None
+    fused_all = None
     for form in forms:
         if form == "fused_graph":
             res[form], replay_ms = timed_optimizer_graph()
         elif "_graph" in form:
             res[form] = timed_graph(form)
         else:
-            res[form] = timed_eager(form)[0]
-    fused_ms = None
-    if robot.fused_supported and any(f.startswith("fused") for f in forms):
-        _, fused_all = timed_eager("fused", events=True)
-        fused_ms = float(np.mean(fused_all))
+            res[form] = timed_eager(form)
+        # the fused kernel's own launches, timed right after the first fused
+        # form (before the plain forms' memory-bound launches)
+        if fused_all is None and form.startswith("fused") and robot.fused_supported:
+            fused_all = timed_kernel_graph()
+    fused_ms = float(np.mean(fused_all)) if fused_all is not None else None
 
     head = "fused_graph" if "fused_graph" in res else forms[0]
     L, S, P, n = robot.n_links, robot.n_spheres, robot.n_pairs, robot.n_dof
@@ -502,7 +526,11 @@ def main():
                            "nonpacked_peak": PEAK_FP32_NONPACKED_TFLOPS,
                            "work": "algorithmic: every checked pair once, no pruning credited; VJP 500 FLOP/link",
                            "kernel_ms": fused_ms, "kernel_ms_median": float(np.median(fused_all)),
-                           "kernel_ms_min": float(np.min(fused_all)), "flop_per_launch": flop, "traffic": traffic,
+                           "kernel_ms_min": float(np.min(fused_all)),
+                           "kernel_timing": f"{args.steps} back-to-back launches captured in one graph, HIP events "
+                                            f"on the replaying stream around each of {len(fused_all)} replays, "
+                                            "per launch; taken right after the optimizer-graph form",
+                           "flop_per_launch": flop, "traffic": traffic,
                            "algorithmic_bytes_per_launch": alg_bytes,
                            "hbm_gbps_algorithmic": alg_bytes / (fused_ms * 1e-3) / 1e9}
         out["roofline"]["executed"] = executed_roofline(robot, rb, q0, fused_ms)
