@@ -249,6 +249,15 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
     // gathered in X and crossed with S once at the end
     SV X = taub * F;
     const SV fb = path_sum(taub * S, parent_lane, glane, fz.jsteps, G);
+    if (EXT && io.g_fext && act && valid) {
+        // the external-force gradient needs only fb, so it leaves here and the
+        // link's pose is dead for the rest of the adjoint: -X*^T fb, moment
+        // part -R^T fb_w, force part -R^T (fb_l + fb_w x p)
+        const V3 gn = mulT(R, fb.w), gf = mulT(R, fb.l + cross(fb.w, p));
+        float *gx = io.g_fext + (int64_t)(link * 6) * B + b;
+        gx[0] = -gn.x; gx[B] = -gn.y; gx[2 * B] = -gn.z;
+        gx[3 * B] = -gf.x; gx[4 * B] = -gf.y; gx[5 * B] = -gf.z;
+    }
     SV ab = iw_apply(J, fb);
     W = W - (crf(fb, Ia) + crf(a, ab));
     if (EXT) W += crf(fb, fe);
@@ -285,13 +294,6 @@ __device__ __forceinline__ void iterate_state(const DevRobot &rb, const uint16_t
         row[1] += r1;
         row[2] += r2;
         row[3] += r3;
-    }
-    if (EXT && io.g_fext && act) {
-        // -X*^T fb: moment part -R^T fb_w, force part -R^T (fb_l + fb_w x p)
-        const V3 gn = mulT(R, fb.w), gf = mulT(R, fb.l + cross(fb.w, p));
-        float *gx = io.g_fext + (int64_t)(link * 6) * B + b;
-        gx[0] = -gn.x; gx[B] = -gn.y; gx[2 * B] = -gn.z;
-        gx[3 * B] = -gf.x; gx[4 * B] = -gf.y; gx[5 * B] = -gf.z;
     }
     if (jlane) {
         if (io.tau) io.tau[jrow] = tau;
