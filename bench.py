@@ -47,14 +47,14 @@ PEAK_HBM_GBPS = 8000.0
 # calibration (FETCH x2.000, WRITE x1.000).  Valid only for the kernel sources
 # and the launch shape (states per workgroup) it was measured with; reported
 # as null once either changes.
-TRAFFIC_MEASURED = {"sources_sha1": "8c4ab4ae5bd69aa2d809c76f7961a44da774becd", "states": 24576,
+TRAFFIC_MEASURED = {"sources_sha1": "34f9acce194059b226ed12f33803f5f3be188970", "states": 24576,
                     "states_per_item": 8, "bytes_per_launch": (14296.8 + 14273.5) * 1024}
 FUSED_SOURCES = ("fused.hip", "sweep.h", "lanes.h", "tree.h", "spline.h", "spatial.h", "wb_internal.h")
 
 
 # HBM traffic of the kinematics-outputs kernel, measured the same way
 # (profiles/k_kinematics_humanoid48_B24576.md; 4 tool frames), per launch.
-KIN_TRAFFIC_MEASURED = {"sources_sha1": "38509660bc700118f01cfe70ded607abb3b22724", "states": 24576, "tools": 4,
+KIN_TRAFFIC_MEASURED = {"sources_sha1": "b54a8297dcd08b42f655f85c518d89b665149710", "states": 24576, "tools": 4,
                         "forward_bytes": (5606.6 + 133142.4) * 1024,
                         "backward_bytes": (9674.9 + 4608.0) * 1024}
 KIN_SOURCES = ("kinematics.hip", "kin.h", "lanes.h", "spatial.h", "wb_internal.h")

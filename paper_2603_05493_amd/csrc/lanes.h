@@ -58,7 +58,9 @@ __device__ __forceinline__ float group_scan(float x, int G) {
 // or six instructions after its last write.  The compiler's hazard checks
 // do not look into inline asm: the block opens with the 5 wait states a DPP
 // read needs after a VALU write of EXEC (2 after one of its source) and
-// closes with the 2 that a DPP read of its results needs.
+// closes with the 2 that a DPP read of its results needs.  The blocks are
+// volatile, so they stay where they are written: their results depend on
+// other lanes' values and on EXEC.
 #define WB_DPP4(op)                                  \
     "v_add_f32_dpp %0, %0, %0 " op "\n\t"             \
     "v_add_f32_dpp %1, %1, %1 " op "\n\t"             \
@@ -74,15 +76,15 @@ __device__ __forceinline__ float group_scan(float x, int G) {
 #define WB_SCAN(D, G, ...)                                                                                \
     do {                                                                                                 \
         if (G >= 64)                                                                                     \
-            asm("s_nop 4\n\t" D(WB_SHR(1)) D(WB_SHR(2)) D(WB_SHR(4)) D(WB_SHR(8)) D(WB_BC15) D(WB_BC31)     \
+            asm volatile("s_nop 4\n\t" D(WB_SHR(1)) D(WB_SHR(2)) D(WB_SHR(4)) D(WB_SHR(8)) D(WB_BC15) D(WB_BC31)     \
                 "s_nop 1"                                                                                \
                 : __VA_ARGS__);                                                                 \
         else if (G >= 32)                                                                                \
-            asm("s_nop 4\n\t" D(WB_SHR(1)) D(WB_SHR(2)) D(WB_SHR(4)) D(WB_SHR(8)) D(WB_BC15)       \
+            asm volatile("s_nop 4\n\t" D(WB_SHR(1)) D(WB_SHR(2)) D(WB_SHR(4)) D(WB_SHR(8)) D(WB_BC15)       \
                              "s_nop 1"                                                                   \
                          : __VA_ARGS__);                                                                 \
         else                                                                                             \
-            asm("s_nop 4\n\t" D(WB_SHR(1)) D(WB_SHR(2)) D(WB_SHR(4)) D(WB_SHR(8)) "s_nop 1"     \
+            asm volatile("s_nop 4\n\t" D(WB_SHR(1)) D(WB_SHR(2)) D(WB_SHR(4)) D(WB_SHR(8)) "s_nop 1"     \
                          : __VA_ARGS__);                                                                 \
     } while (0)
 __device__ __forceinline__ void group_scan4(float &a, float &b, float &c, float &d, int G) {
