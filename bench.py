@@ -210,6 +210,8 @@ def parse():
     ap.add_argument("--forms", default="fused_graph,fused_graph1,plain_graph,plain")
     ap.add_argument("--no-uneven", dest="uneven", action="store_false",
                     help="skip the uneven multi-tree batch measurement")
+    ap.add_argument("--no-rnea-b256", dest="rnea_b256", action="store_false",
+                    help="skip RNEA forward + VJP at 256 states (7-joint chain, 12-DoF tree, humanoid)")
     ap.add_argument("--no-kinematics", dest="kinematics", action="store_false",
                     help="skip the kinematics-outputs line (tool poses, CoM, Jacobians)")
     ap.add_argument("--no-ext", dest="ext", action="store_false",
@@ -558,6 +560,8 @@ def main():
         out["paper_scale_selfcollision"] = bench_paper_scale(args)
     if args.kinematics and robot.kinematics_supported:
         out["kinematics"] = bench_kinematics(args, robot, q0)
+    if args.rnea_b256:
+        out["rnea_fwd_bwd_B256"] = bench_rnea_b256(args)
     if args.edt:
         out["edt"] = bench_edt(args)
     if args.bspline and B % 48 == 0:
@@ -789,6 +793,64 @@ def bench_ext_variant(args, st, reps: int = 50):
     return {"robot": "humanoid48 with coupled fingers (40 joints, 48 links)", "states": B, "kernel_us": t * 1e6,
             "states_per_s": B / t, "features": "mimic joints, external link forces and their gradient, step",
             "states_per_workgroup": r.get_tune()["states_per_item"]}
+
+
+def bench_rnea_b256(args, reps: int = 100, B: int = 256):
+    """RNEA forward and its VJP (torques, then the gradient of w . tau with
+    respect to q, qd and qdd) at 256 states for a 7-joint chain, a 12-DoF
+    tree and the 48-DoF humanoid, in both per-operation forms: one state per
+    lane with the forward's cache, and one group of lanes per state that
+    recomputes the forward in the VJP.  `reps` forward + VJP pairs captured
+    in one graph (launch-bound at this size when issued eagerly), HIP events
+    around its replays on the replaying stream."""
+    import torch
+    from paper_2603_05493_amd import synth, wb
+    out = {"states": B, "timing": f"{reps} forward + VJP pairs in one graph, HIP events around 10 replays"}
+    for name, rb in (("chain7", synth.serial_chain(7)), ("tree12", synth.random_tree(12)),
+                     ("humanoid48", synth.humanoid48(seed=0))):
+        r = wb.Robot(rb).to_device("cuda:0")
+        st = synth.states(rb, B, seed=5)
+        T = lambda x: torch.from_numpy(np.ascontiguousarray(x.T.astype(np.float32))).cuda()
+        q, qd, qdd = T(st.q), T(st.qd), T(st.qdd)
+        gt = torch.randn(q.shape, generator=torch.Generator().manual_seed(6)).cuda()
+        tau, gq, gqd, gqdd = (torch.empty_like(q) for _ in range(4))
+        cache = torch.empty((r.n_links, 18, B), device="cuda")
+        ws = r.workspace(B)
+
+        def cached():
+            wb.wb_rnea(r, q, qd, qdd, tau=tau, cache=cache)
+            wb.wb_rnea_backward(r, q, qd, qdd, cache, gt, gq, gqd, gqdd, workspace=ws)
+
+        def recomputed():
+            wb.wb_rnea(r, q, qd, qdd, tau=tau, want_cache=False)
+            wb.wb_rnea_backward(r, q, qd, qdd, None, gt, gq, gqd, gqdd)
+
+        res = {"dof": r.n_dof}
+        for form, fn in (("one_state_per_lane_cached", cached), ("lane_group_recomputed", recomputed)):
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                fn()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                for _ in range(reps):
+                    fn()
+            graph.replay()
+            torch.cuda.synchronize()
+            s = torch.cuda.current_stream()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+            for e0, e1 in ev:
+                e0.record(s)
+                graph.replay()
+                e1.record(s)
+            torch.cuda.synchronize()
+            us = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev])) / reps * 1e3
+            assert torch.isfinite(gq).all()
+            res[form] = {"us": us, "states_per_s": B / (us * 1e-6)}
+        out[name] = res
+    return out
 
 
 def bench_kinematics(args, robot, q, reps: int = 50):
